@@ -1,0 +1,209 @@
+"""ctypes front end of the plain FP64 CPU oracle (``smoe_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may use this module; the product path (the HIP library and its
+Python binding) never imports it.
+
+All model arrays are float64 rows in the layouts documented in
+``smoe_oracle.cpp`` (materialized: mu_x, mu_y, l11, l21, l22, rho, a, wx, wy;
+raw: mu_x, mu_y, s1, l21, s2, rho, a, wx, wy).  float32 inputs are widened
+exactly.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_DIR = Path(__file__).resolve().parent
+_SRC = _DIR / "smoe_oracle.cpp"
+_LIB = _DIR / "liboracle.so"
+
+# -ffp-contract=off: the binary32 truncation rule must be evaluated op by op, with
+# no fused multiply-adds.  No -march: the library must run on any x86-64 host.
+CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+            "-pthread"]
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle into ``oracle/liboracle.so``."""
+    if force or not _LIB.exists():
+        tmp = _LIB.with_suffix(".so.tmp")
+        subprocess.check_call(["g++", *CXXFLAGS, str(_SRC), "-o", str(tmp)])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_lib_path = None
+
+
+def use_library(path=None):
+    """Bind to another build of the oracle source (tests that plant mistakes in a copy);
+    None restores the default library."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, (None if path is None else Path(path))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _lib_path or _LIB
+        if path == _LIB and not _LIB.exists():
+            build()
+        L = ct.CDLL(str(path))
+        dp, fp = ct.POINTER(ct.c_double), ct.POINTER(ct.c_float)
+        i32p, u32p = ct.POINTER(ct.c_int32), ct.POINTER(ct.c_uint32)
+        I, F, D, I64 = ct.c_int, ct.c_float, ct.c_double, ct.c_int64
+        L.oracle_num_params.argtypes = [I, I]
+        L.oracle_num_params.restype = I
+        L.oracle_bin.argtypes = [I, I, I, dp, I, I, I, I, I, F, i32p, i32p, i32p, I64, u32p, u32p, i32p]
+        L.oracle_bin.restype = I64
+        L.oracle_render.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I64, i32p, dp, dp, I]
+        L.oracle_render.restype = None
+        L.oracle_loss_grad.argtypes = [I, I, I, dp, I, I, I, I, I, F, dp, dp, I, i32p, dp, I]
+        L.oracle_loss_grad.restype = D
+        L.oracle_materialize.argtypes = [I, I, I, dp, dp]
+        L.oracle_materialize.restype = None
+        L.oracle_step_lrs.argtypes = [I, I, D, D, D, D, D, dp]
+        L.oracle_step_lrs.restype = None
+        L.oracle_adam.argtypes = [I, I, I, dp, dp, dp, dp, I, dp, D, D, D]
+        L.oracle_adam.restype = None
+        L.oracle_fit.argtypes = [I, I, I, dp, I, I, F, dp, I, I, D, D, D, D, D, D, D, D, dp, dp, I]
+        L.oracle_fit.restype = None
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    n = os.environ.get("OMP_NUM_THREADS")
+    if n and n.isdigit() and int(n) > 0:
+        return min(int(n), os.cpu_count() or 1)
+    return os.cpu_count() or 1
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(ct.POINTER(t))
+
+
+def num_params(C: int, order: int) -> int:
+    return int(lib().oracle_num_params(C, order))
+
+
+def _KC(model, C, order):
+    model = _d(model)
+    NP = num_params(C, order)
+    assert model.ndim == 2 and model.shape[1] == NP, (model.shape, NP)
+    return model, model.shape[0]
+
+
+def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None):
+    """Block lists.  Returns dict(tile_rects, pix_rects, counts, P, keys, vals, ranges)."""
+    model, K = _KC(model, C, order)
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    tr = np.zeros((K, 4), np.int32)
+    pr = np.zeros((K, 4), np.int32)
+    cnt = np.zeros(K, np.int32)
+    rng = np.zeros((T, 2), np.int32)
+    if capacity is None:
+        P = lib().oracle_bin(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r,
+                             _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
+                             0, None, None, _ptr(rng, ct.c_int32))
+        capacity = P
+    keys = np.zeros(max(capacity, 1), np.uint32)
+    vals = np.zeros(max(capacity, 1), np.uint32)
+    P = lib().oracle_bin(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r,
+                         _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
+                         capacity, _ptr(keys, ct.c_uint32), _ptr(vals, ct.c_uint32),
+                         _ptr(rng, ct.c_int32))
+    n = min(P, capacity)
+    return dict(tile_rects=tr, pix_rects=pr, counts=cnt, P=int(P), keys=keys[:n], vals=vals[:n],
+                ranges=rng)
+
+
+def render(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, truncated=True, pixels=None,
+           threads=None):
+    """y [H, W, C] and D [H, W] (or [n, C], [n] at the listed (u, v) pixels)."""
+    model, K = _KC(model, C, order)
+    threads = threads or default_threads()
+    if pixels is None:
+        y = np.zeros((H, W, C), np.float64)
+        D = np.zeros((H, W), np.float64)
+        lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r,
+                            int(truncated), 0, None, _ptr(y, ct.c_double), _ptr(D, ct.c_double),
+                            threads)
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        y = np.zeros((pix.shape[0], C), np.float64)
+        D = np.zeros(pix.shape[0], np.float64)
+        lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r,
+                            int(truncated), pix.shape[0], _ptr(pix, ct.c_int32),
+                            _ptr(y, ct.c_double), _ptr(D, ct.c_double), threads)
+    return y, D
+
+
+def loss_grad(model, C, order, W, H, target=None, grad_y=None, kernels=None, s=1, ox=0, oy=0,
+              r=3.0, threads=None):
+    """(loss, grads [K or len(kernels), NP]) in raw-parameter order."""
+    model, K = _KC(model, C, order)
+    NP = model.shape[1]
+    assert (target is None) != (grad_y is None)
+    t = None if target is None else _d(target).reshape(H, W, C)
+    gy = None if grad_y is None else _d(grad_y).reshape(H, W, C)
+    sel = None if kernels is None else np.ascontiguousarray(kernels, dtype=np.int32)
+    nout = K if sel is None else sel.shape[0]
+    g = np.zeros((nout, NP), np.float64)
+    loss = lib().oracle_loss_grad(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r,
+                                  _ptr(t, ct.c_double), _ptr(gy, ct.c_double),
+                                  0 if sel is None else sel.shape[0], _ptr(sel, ct.c_int32),
+                                  _ptr(g, ct.c_double), threads or default_threads())
+    return float(loss), g
+
+
+def materialize(raw, C, order):
+    raw, K = _KC(raw, C, order)
+    out = np.zeros_like(raw)
+    lib().oracle_materialize(K, C, order, _ptr(raw, ct.c_double), _ptr(out, ct.c_double))
+    return out
+
+
+def step_lrs(step_index, total_steps, lr_mu, lr_mu_final, lr_chol, lr_rho, lr_expert):
+    out = np.zeros(4, np.float64)
+    lib().oracle_step_lrs(step_index, total_steps, lr_mu, lr_mu_final, lr_chol, lr_rho,
+                          lr_expert, _ptr(out, ct.c_double))
+    return out
+
+
+def adam(p, g, m, v, t, lrs4, C, order, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays p, m, v (gradient g), 1-based step t."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _d(g)
+    lrs4 = _d(lrs4)
+    K = p.shape[0]
+    lib().oracle_adam(K, C, order, _ptr(p, ct.c_double), _ptr(g, ct.c_double),
+                      _ptr(m, ct.c_double), _ptr(v, ct.c_double), t, _ptr(lrs4, ct.c_double),
+                      beta1, beta2, eps)
+
+
+def fit(raw0, C, order, target, steps, total_steps=None, lr_mu=1e-2, lr_mu_final=None,
+        lr_chol=1e-2, lr_rho=1e-2, lr_expert=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, r=3.0,
+        threads=None):
+    """FP64 fit.  Returns (loss history [steps], final raw params [K, NP])."""
+    raw0, K = _KC(raw0, C, order)
+    t = _d(target)
+    H, W = t.shape[:2]
+    hist = np.zeros(steps, np.float64)
+    out = np.zeros_like(raw0)
+    lib().oracle_fit(K, C, order, _ptr(raw0, ct.c_double), W, H, r, _ptr(t, ct.c_double), steps,
+                     total_steps or steps, lr_mu, lr_mu if lr_mu_final is None else lr_mu_final,
+                     lr_chol, lr_rho, lr_expert, beta1, beta2, eps, _ptr(hist, ct.c_double),
+                     _ptr(out, ct.c_double), threads or default_threads())
+    return hist, out

@@ -1,0 +1,89 @@
+"""Planted mistakes: each plausible slip in the oracle must fail at least one pin.
+
+Every case copies the oracle source, applies one textual change (a dropped term, a
+flipped sign, swapped axes, a wrong index or normalisation), builds the copy into a
+temporary library, re-binds the oracle module to it and runs the pins named for that
+case.  The test passes when at least one of those pins fails.  Everything happens on
+the CPU; the real oracle library is rebound afterwards.
+"""
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = oracle._SRC.read_text()
+
+# (label, original text, planted text, pins expected to catch it)
+MUTANTS = [
+    ("drop rho in the gate", "t.e = std::exp(r[5] - 0.5 * q);", "t.e = std::exp(-0.5 * q);",
+     [pins.test_denominator_is_pi_times_gaussian_eq2_eq4]),
+    ("sign of l21 in forward substitution", "t.z2 = (t.dy - r[3] * t.z1) / r[4];",
+     "t.z2 = (t.dy + r[3] * t.z1) / r[4];", [pins.test_denominator_is_pi_times_gaussian_eq2_eq4]),
+    ("l11 and l22 swapped", "t.z1 = t.dx / r[2];", "t.z1 = t.dx / r[4];",
+     [pins.test_denominator_is_pi_times_gaussian_eq2_eq4]),
+    ("pixel centre not at +0.5", "return ((float)(o + u) + 0.5f) * inv_s;",
+     "return ((float)(o + u) + 0.0f) * inv_s;", [pins.test_hand_computed_single_kernel]),
+    ("expert slopes transposed",
+     "if (order == 1) m += r[6 + C + c] * dx + r[6 + 2 * C + c] * dy;",
+     "if (order == 1) m += r[6 + C + c] * dy + r[6 + 2 * C + c] * dx;",
+     [pins.test_single_kernel_reproduces_linear_expert]),
+    ("box from sxx instead of lambda_max", "const float lam = h + std::sqrt(d * d + sxy * sxy);",
+     "const float lam = sxx;", [pins.test_box_half_side_is_r_sqrt_lambda_max]),
+    ("ellipse radius off", "return q <= r2;", "return q <= 1.1f * r2;",
+     [pins.test_truncation_rule_matches_ellipse_and_stays_in_box]),
+    ("block rect off by one", "rc.tx1 = rc.u1 >> 4;", "rc.tx1 = (rc.u1 + 1) >> 4;",
+     [pins.test_box_half_side_is_r_sqrt_lambda_max]),
+    ("no normalisation of the gates", "y[c] = (Dsum > 0.0) ? N[c] / Dsum : 0.0;",
+     "y[c] = (Dsum > 0.0) ? N[c] : 0.0;", [pins.test_untruncated_gates_are_softmax]),
+    ("z2 chain term sign in the gradient", "const double bz1 = -Hh * t.z1 - bz2 * r[3] / r[4];",
+     "const double bz1 = -Hh * t.z1 + bz2 * r[3] / r[4];", [pins.test_gradient_central_differences]),
+    ("expert slope dropped from d/dmu", "const double bdx = bz1 / r[2] + ex;",
+     "const double bdx = bz1 / r[2];", [pins.test_gradient_central_differences]),
+    ("l21 gradient missing 1/l22", "out[3] += -bz2 * t.z1 / r[4];", "out[3] += -bz2 * t.z1;",
+     [pins.test_gradient_central_differences]),
+    ("gradient of y_c uses y of another channel",
+     "Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - y[c]);",
+     "Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - y[0]);",
+     [pins.test_gradient_central_differences]),
+    ("loss mean over H*W only", "const double inv_n = 1.0 / ((double)W * H * C);",
+     "const double inv_n = 1.0 / ((double)W * H);", [pins.test_upstream_gradient_mode_and_subsets]),
+    ("Adam without bias correction", "const double mhat = m[i] / bc1;", "const double mhat = m[i];",
+     [pins.test_adam_matches_torch_optim_adam]),
+    ("centre-rate decay exponent inverted",
+     "f = std::pow(lr_mu_final / lr_mu, (double)step_index / (double)total_steps);",
+     "f = std::pow(lr_mu / lr_mu_final, (double)step_index / (double)total_steps);",
+     [pins.test_adam_matches_torch_optim_adam]),
+    ("block list not in kernel order",
+     "for (int j = 0; j < K; ++j) {\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",
+     "for (int jj = 0; jj < K; ++jj) {\n    const int j = K - 1 - jj;\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",
+     [pins.test_bins_bruteforce_tiny]),
+]
+
+
+@pytest.fixture(scope="module")
+def workdir(tmp_path_factory):
+    yield tmp_path_factory.mktemp("mutants")
+    oracle.use_library(None)
+
+
+@pytest.mark.parametrize("label,old,new,catchers", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(workdir, label, old, new, catchers):
+    assert SRC.count(old) == 1, f"mutation anchor not unique or missing: {label}"
+    idx = MUTANTS.index(next(m for m in MUTANTS if m[0] == label))
+    src = workdir / f"m{idx}.cpp"
+    so = workdir / f"m{idx}.so"
+    src.write_text(SRC.replace(old, new))
+    subprocess.check_call(["g++", *oracle.CXXFLAGS, str(src), "-o", str(so)])
+    oracle.use_library(so)
+    try:
+        caught = False
+        for pin in catchers:
+            try:
+                pin()
+            except AssertionError:
+                caught = True
+        assert caught, f"planted mistake not detected: {label}"
+    finally:
+        oracle.use_library(None)

@@ -1,0 +1,419 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests compares the oracle with itself or with the GPU path.  Each
+one checks a value against an independent route to it: a library routine
+(numpy.linalg, scipy.special.softmax, torch.optim.Adam), a closed form, brute
+force on tiny inputs, an invariant of the model, or central finite differences.
+A dropped term, a sign error, a swapped axis or a transposed operand anywhere in
+the oracle makes at least one of them fail (see test_planted_mistakes_are_caught).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+R = 3.0
+
+
+def sigma_of(model):
+    """Covariances Sigma = L L^T from materialized rows."""
+    L = np.zeros((model.shape[0], 2, 2))
+    L[:, 0, 0] = model[:, 2]
+    L[:, 1, 0] = model[:, 3]
+    L[:, 1, 1] = model[:, 4]
+    return L @ np.transpose(L, (0, 2, 1))
+
+
+def maha_np(model, xs, ys):
+    """(x-mu)^T Sigma^-1 (x-mu) for every kernel and point, via numpy.linalg.solve."""
+    S = sigma_of(model.astype(np.float64))
+    d = np.stack([xs[None, :] - model[:, 0:1].astype(np.float64),
+                  ys[None, :] - model[:, 1:2].astype(np.float64)], axis=1)  # [K, 2, n]
+    sol = np.linalg.solve(S, d)
+    return np.einsum("kin,kin->kn", d, sol)
+
+
+def centres(W, H):
+    v, u = np.mgrid[0:H, 0:W]
+    return u.ravel(), v.ravel(), u.ravel() + 0.5, v.ravel() + 0.5
+
+
+# --------------------------------------------------------------------------- geometry
+
+
+def test_denominator_is_pi_times_gaussian_eq2_eq4():
+    """D(x) = sum_j pi_j K_j(x) (Eq. 2, 4): one kernel at a time, untruncated, against
+    the Mahalanobis form computed by numpy.linalg.solve on Sigma = L L^T."""
+    W, H = 23, 19
+    m = wl.random_model(6, 1, 0, W, H, seed=11, margin=0.0)
+    u, v, x, y = centres(W, H)
+    q = maha_np(m, x, y)
+    for j in range(m.shape[0]):
+        _, D = oracle.render(m[j:j + 1], 1, 0, W, H, truncated=False)
+        ref = np.exp(m[j, 5].astype(np.float64) - 0.5 * q[j]).reshape(H, W)
+        np.testing.assert_allclose(D, ref, rtol=1e-12, atol=0)
+
+
+def test_hand_computed_single_kernel():
+    """Closed form by hand: mu = (8, 8), L = 4 I, rho = 0.  Pixel (11, 7) has its centre at
+    (11.5, 7.5): q = (3.5^2 + 0.5^2)/16 = 0.78125, so D = exp(-0.390625)."""
+    m = np.array([[8.0, 8.0, 4.0, 0.0, 4.0, 0.0, 0.25]])
+    y, D = oracle.render(m, 1, 0, 16, 16, pixels=[(11, 7)])
+    assert D[0] == pytest.approx(math.exp(-0.390625), rel=1e-15)
+    assert y[0, 0] == pytest.approx(0.25, rel=1e-15)
+    # pixel (14, 8): centre (14.5, 8.5), q = (6.5^2 + 0.5^2)/16 = 2.65625 -> inside r = 3
+    # pixel (8, 0):  centre (8.5, 0.5),  q = (0.25 + 56.25)/16 = 3.53125 -> inside
+    # pixel (0, 0):  q = (56.25 + 56.25)/16 = 7.03125 -> inside;  r = 2.5 excludes it
+    _, D2 = oracle.render(m, 1, 0, 16, 16, pixels=[(14, 8), (8, 0), (0, 0)])
+    np.testing.assert_allclose(D2, np.exp(-0.5 * np.array([2.65625, 3.53125, 7.03125])), rtol=1e-15)
+    _, D3 = oracle.render(m, 1, 0, 16, 16, pixels=[(0, 0)], r=2.5)
+    assert D3[0] == 0.0
+
+
+def test_box_half_side_is_r_sqrt_lambda_max():
+    """The square box of Fig. 3b has half-side r*sqrt(lambda_max(Sigma)); the oracle's pixel
+    rect must be exactly the pixel centres inside it (eigvalsh in FP64), except where a
+    centre sits within 1e-3 px of an edge (binary32 rounding may go either way there)."""
+    W, H = 97, 83
+    m = wl.random_model(400, 1, 0, W, H, seed=12)
+    lam = np.linalg.eigvalsh(sigma_of(m.astype(np.float64)))[:, -1]
+    Rh = R * np.sqrt(lam)
+    b = oracle.bin(m, 1, 0, W, H)
+    checked = 0
+    for j in range(m.shape[0]):
+        lo_x, hi_x = m[j, 0] - Rh[j], m[j, 0] + Rh[j]
+        lo_y, hi_y = m[j, 1] - Rh[j], m[j, 1] + Rh[j]
+        cx = np.arange(W) + 0.5
+        cy = np.arange(H) + 0.5
+        near = (np.min(np.abs(np.concatenate([cx - lo_x, cx - hi_x]))) < 1e-3 or
+                np.min(np.abs(np.concatenate([cy - lo_y, cy - hi_y]))) < 1e-3)
+        if near:
+            continue
+        inx = np.nonzero((cx >= lo_x) & (cx <= hi_x))[0]
+        iny = np.nonzero((cy >= lo_y) & (cy <= hi_y))[0]
+        pr = b["pix_rects"][j]
+        if inx.size == 0 or iny.size == 0:
+            assert pr[2] < pr[0] and b["counts"][j] == 0
+            assert list(b["tile_rects"][j]) == [0, 0, -1, -1]
+        else:
+            assert list(pr) == [inx[0], iny[0], inx[-1], iny[-1]], j
+            tr = b["tile_rects"][j]
+            assert list(tr) == [inx[0] >> 4, iny[0] >> 4, inx[-1] >> 4, iny[-1] >> 4]
+            assert b["counts"][j] == (tr[2] - tr[0] + 1) * (tr[3] - tr[1] + 1)
+        checked += 1
+    assert checked > 350
+
+
+def test_box_contains_ellipse_boundary():
+    """Every point of the r-ellipse boundary lies in the square box (Sec. IV-B): 10^4
+    boundary points per kernel, mu + r L (cos t, sin t)."""
+    m = wl.random_model(200, 1, 0, 400, 400, seed=13, sig_lo=0.5, sig_hi=40.0, margin=0.0)
+    lam = np.linalg.eigvalsh(sigma_of(m.astype(np.float64)))[:, -1]
+    t = np.linspace(0, 2 * np.pi, 10000, endpoint=False)
+    circ = np.stack([np.cos(t), np.sin(t)])
+    for j in range(m.shape[0]):
+        Lj = np.array([[m[j, 2], 0.0], [m[j, 3], m[j, 4]]], dtype=np.float64)
+        pts = R * (Lj @ circ)
+        assert np.max(np.abs(pts)) <= R * math.sqrt(lam[j]) * (1 + 1e-12)
+
+
+def test_truncation_rule_matches_ellipse_and_stays_in_box():
+    """Brute force over every pixel, one kernel at a time: the oracle's participation set
+    {D > 0} equals {q <= r^2} (numpy FP64) away from a 1e-5 band, and lies inside the
+    kernel's pixel rect, so the block conjunct of the rule never removes a pixel."""
+    W, H = 61, 45
+    m = wl.random_model(60, 1, 0, W, H, seed=14, sig_lo=0.7, sig_hi=8.0)
+    u, v, x, y = centres(W, H)
+    q = maha_np(m, x, y)
+    b = oracle.bin(m, 1, 0, W, H)
+    for j in range(m.shape[0]):
+        _, D = oracle.render(m[j:j + 1], 1, 0, W, H)
+        on = D.ravel() > 0
+        band = np.abs(q[j] - R * R) < 1e-5
+        assert np.array_equal(on[~band], (q[j] <= R * R)[~band]), j
+        pr = b["pix_rects"][j]
+        assert np.all((u[on] >= pr[0]) & (u[on] <= pr[2]) & (v[on] >= pr[1]) & (v[on] <= pr[3]))
+
+
+def test_bins_bruteforce_tiny():
+    """Block lists (Sec. IV-C) against a tile x kernel double loop, and the pair order
+    against Python's sort of (block, kernel) tuples."""
+    for (W, H, K, seed) in [(33, 47, 30, 21), (16, 16, 5, 22), (80, 20, 70, 23), (7, 5, 3, 24)]:
+        m = wl.random_model(K, 3, 1, W, H, seed=seed, sig_hi=14.0)
+        b = oracle.bin(m, 3, 1, W, H)
+        ntx, nty = (W + 15) // 16, (H + 15) // 16
+        keys, vals, rng = [], [], []
+        for t in range(ntx * nty):
+            tx, ty = t % ntx, t // ntx
+            start = len(keys)
+            for j in range(K):
+                r = b["tile_rects"][j]
+                if r[0] <= tx <= r[2] and r[1] <= ty <= r[3]:
+                    keys.append(t)
+                    vals.append(j)
+            rng.append((start, len(keys)))
+        assert b["P"] == len(keys) == int(b["counts"].sum())
+        assert np.array_equal(b["keys"], keys) and np.array_equal(b["vals"], vals)
+        assert np.array_equal(b["ranges"], np.array(rng).reshape(-1, 2))
+        pairs = sorted(zip(keys, vals))
+        assert pairs == list(zip(b["keys"].tolist(), b["vals"].tolist()))
+
+
+# --------------------------------------------------------------------------- gates
+
+
+def test_untruncated_gates_are_softmax():
+    """Untruncated gates w_j = softmax_j(rho_j - q_j/2) (Eq. 4 with pi = e^rho), checked
+    with scipy.special.softmax: one-hot constant experts over C = K channels make
+    y_c = w_c."""
+    from scipy.special import softmax
+
+    W, H, K = 20, 14, 7
+    m1 = wl.random_model(K, 1, 0, W, H, seed=31, margin=0.0)
+    m = np.zeros((K, 6 + K))
+    m[:, :6] = m1[:, :6]
+    m[:, 6:] = np.eye(K)
+    y, D = oracle.render(m, K, 0, W, H, truncated=False)
+    u, v, x, yy = centres(W, H)
+    q = maha_np(m1, x, yy)
+    ref = softmax(m1[:, 5:6].astype(np.float64) - 0.5 * q, axis=0).T.reshape(H, W, K)
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(y.sum(-1), 1.0, rtol=1e-14)
+
+
+def test_two_kernel_logistic_edge():
+    """Two round kernels with equal sigma and pi: w_1 = logistic((q_2 - q_1)/2), exactly
+    1/2 on the bisector (the 2D version of the step edge of Fig. 2)."""
+    s = 3.0
+    m = np.array([[10.5, 8.0, s, 0.0, s, 0.2, 1.0], [16.5, 8.0, s, 0.0, s, 0.2, 0.0]])
+    W, H = 27, 16
+    y, _ = oracle.render(m, 1, 0, W, H, truncated=False)
+    u, v, x, yy = centres(W, H)
+    q1 = ((x - 10.5) ** 2 + (yy - 8.0) ** 2) / s ** 2
+    q2 = ((x - 16.5) ** 2 + (yy - 8.0) ** 2) / s ** 2
+    ref = 1.0 / (1.0 + np.exp(-(q2 - q1) / 2.0))
+    np.testing.assert_allclose(y[..., 0].ravel(), ref, rtol=1e-13)
+    assert np.all(y[:, 13, 0] == 0.5)  # centre x = 13.5 is the bisector
+
+
+# --------------------------------------------------------------------------- invariants
+
+
+def test_gates_sum_to_one_all_ones_experts():
+    W, H = 45, 38
+    m = wl.random_model(50, 3, 1, W, H, seed=41)
+    m[:, 6:9] = 1.0
+    m[:, 9:] = 0.0
+    y, D = oracle.render(m, 3, 1, W, H)
+    cov = D > 0
+    assert cov.any() and (~cov).any()
+    np.testing.assert_allclose(y[cov], 1.0, rtol=1e-14)
+    assert np.all(y[~cov] == 0.0)
+
+
+def test_single_kernel_reproduces_linear_expert():
+    """K = 1: the gate is 1 on the kernel's support, so y = a + W (x - mu) there (linear,
+    steered expert), with wx multiplying the column offset and wy the row offset."""
+    W, H = 40, 33
+    m = np.array([[17.3, 15.8, 5.0, 1.5, 3.0, -0.4, 0.2, 0.5, 0.9, 0.011, -0.02, 0.004,
+                   -0.013, 0.007, 0.03]])
+    y, D = oracle.render(m, 3, 1, W, H)
+    u, v, x, yy = centres(W, H)
+    on = D.ravel() > 0
+    ref = m[0, 6:9] + np.outer(x - m[0, 0], m[0, 9:12]) + np.outer(yy - m[0, 1], m[0, 12:15])
+    np.testing.assert_allclose(y.reshape(-1, 3)[on], ref[on], rtol=1e-13, atol=1e-15)
+    assert on.sum() > 100
+
+
+def test_equal_constant_experts_render_the_constant():
+    W, H = 31, 29
+    m = wl.random_model(40, 1, 0, W, H, seed=42)
+    m[:, 6] = 0.3125
+    y, D = oracle.render(m, 1, 0, W, H)
+    np.testing.assert_allclose(y[D > 0], 0.3125, rtol=1e-14)
+
+
+def test_integer_translation_equivariance():
+    """mu on a 2^-8 grid, integer shift t: render(mu + t)[p + t] = render(mu)[p]."""
+    W, H = 64, 48
+    m = wl.random_model(30, 3, 1, W, H, seed=43, margin=-8.0).astype(np.float64)
+    m[:, :2] = np.round(m[:, :2] * 256) / 256
+    y0, D0 = oracle.render(m, 3, 1, W, H)
+    tx, ty = 5, 3
+    m2 = m.copy()
+    m2[:, 0] += tx
+    m2[:, 1] += ty
+    y1, D1 = oracle.render(m2, 3, 1, W + tx, H + ty)
+    np.testing.assert_allclose(y1[ty:, tx:], y0, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(D1[ty:, tx:], D0, rtol=1e-12, atol=1e-300)
+
+
+def test_subpixel_sampling_scale3():
+    """Super-resolution (Sec. II-B): at s = 3 output pixel 3i+1 samples native i + 0.5, the
+    same point as native pixel i; scale 1 with origin 0 is the native raster."""
+    W, H = 30, 26
+    m = wl.random_model(25, 3, 1, W, H, seed=44)
+    y1, _ = oracle.render(m, 3, 1, W, H)
+    y3, _ = oracle.render(m, 3, 1, 3 * W, 3 * H, s=3)
+    np.testing.assert_allclose(y3[1::3, 1::3], y1, atol=1e-5)
+    # an origin shift by whole output pixels is a crop
+    yc, _ = oracle.render(m, 3, 1, 40, 35, s=3, ox=11, oy=7)
+    np.testing.assert_array_equal(yc, y3[7:42, 11:51])
+
+
+def test_common_pi_scale_invariance():
+    W, H = 33, 27
+    m = wl.random_model(30, 3, 1, W, H, seed=45).astype(np.float64)
+    y0, _ = oracle.render(m, 3, 1, W, H)
+    m[:, 5] += 1.75
+    y1, _ = oracle.render(m, 3, 1, W, H)
+    np.testing.assert_allclose(y1, y0, rtol=1e-12, atol=1e-14)
+
+
+def test_sampled_pixels_equal_full_raster():
+    W, H = 37, 21
+    m = wl.random_model(20, 3, 1, W, H, seed=46)
+    y, D = oracle.render(m, 3, 1, W, H)
+    pix = [(0, 0), (36, 20), (17, 3), (5, 19)]
+    ys, Ds = oracle.render(m, 3, 1, W, H, pixels=pix)
+    for i, (u, v) in enumerate(pix):
+        assert np.array_equal(ys[i], y[v, u]) and Ds[i] == D[v, u]
+
+
+# --------------------------------------------------------------------------- gradients
+
+
+def _fd_guard(model, W, H, margin=1e-4):
+    u, v, x, y = centres(W, H)
+    q = maha_np(model, x, y)
+    assert np.min(np.abs(q - R * R)) > margin, "a (pixel, kernel) pair sits on the truncation edge"
+
+
+def test_gradient_central_differences():
+    """Analytic gradient of the MSE (raw parameters, Cholesky log-diagonal) against FP64
+    central differences, h = 1e-6, on a 32x32 crop with K = 16 linear experts."""
+    tgt, raw = wl.fd_crop_case()
+    H, W, C = tgt.shape
+    raw = raw.astype(np.float64)
+    model = oracle.materialize(raw, 3, 1)
+    _fd_guard(model, W, H)
+    loss, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt)
+    h = 1e-6
+    fd = np.zeros_like(g)
+    for j in range(raw.shape[0]):
+        for k in range(raw.shape[1]):
+            rp = raw.copy(); rp[j, k] += h
+            rm = raw.copy(); rm[j, k] -= h
+            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt)
+            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt)
+            fd[j, k] = (lp - lm) / (2 * h)
+    groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
+              "wx": [9, 10, 11], "wy": [12, 13, 14]}
+    for name, cols in groups.items():
+        ref = fd[:, cols]
+        err = np.max(np.abs(g[:, cols] - ref)) / np.max(np.abs(ref))
+        assert err < 2e-5, (name, err)
+        assert np.max(np.abs(ref)) > 0
+
+
+def test_gradient_rho_sums_to_zero():
+    """Gates sum to one at every covered pixel, so a common shift of all rho changes
+    nothing: sum_j dL/drho_j = 0."""
+    tgt, raw = wl.fd_crop_case(seed=7)
+    H, W, _ = tgt.shape
+    model = oracle.materialize(raw.astype(np.float64), 3, 1)
+    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt)
+    assert abs(g[:, 5].sum()) < 1e-12 * np.abs(g[:, 5]).sum()
+    assert np.abs(g[:, 5]).max() > 1e-6
+
+
+def test_gradient_constant_expert_sum_closed_form():
+    """Constant experts: sum_j dL/da_jc = sum over covered pixels of dL/dy_c = 2 (y_c - t_c)/N."""
+    img = wl.config1_image()
+    raw, model = wl.grid_init(img, 8, 8, 4.0, order=0)
+    model = model.astype(np.float64)
+    rng = np.random.default_rng(5)
+    model[:, :2] += rng.uniform(-2, 2, size=(64, 2))
+    model[:, 6] += rng.uniform(-0.1, 0.1, size=64)
+    H, W, _ = img.shape
+    y, D = oracle.render(model, 1, 0, W, H)
+    loss, g = oracle.loss_grad(model, 1, 0, W, H, target=img)
+    gy = 2 * (y - img) / (H * W)
+    assert g[:, 6].sum() == pytest.approx(gy[D > 0].sum(), rel=1e-11)
+    assert loss == pytest.approx(np.mean((y - img) ** 2), rel=1e-13)
+
+
+def test_upstream_gradient_mode_and_subsets():
+    """grad_y mode with dL/dy = 2(y - t)/N equals the fused-MSE gradient, and requesting a
+    subset of kernels returns the same rows."""
+    tgt, raw = wl.fd_crop_case(seed=9)
+    H, W, _ = tgt.shape
+    model = oracle.materialize(raw.astype(np.float64), 3, 1)
+    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt)
+    y, _ = oracle.render(model, 3, 1, W, H)
+    _, g2 = oracle.loss_grad(model, 3, 1, W, H, grad_y=2 * (y - tgt) / y.size)
+    np.testing.assert_allclose(g2, g, rtol=1e-12, atol=1e-18)
+    sel = [3, 0, 11]
+    _, g3 = oracle.loss_grad(model, 3, 1, W, H, target=tgt, kernels=sel)
+    np.testing.assert_allclose(g3, g[sel], rtol=1e-12, atol=1e-18)
+
+
+# --------------------------------------------------------------------------- optimizer
+
+
+def test_adam_matches_torch_optim_adam():
+    """Adam with per-group learning rates and the exponential centre-rate decay, against
+    torch.optim.Adam in float64 fed the same gradients."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    K, C, order = 9, 3, 1
+    NP = 15
+    p = rng.normal(size=(K, NP))
+    grads = [rng.normal(size=(K, NP)) * 10.0 ** rng.uniform(-4, 0) for _ in range(6)]
+    lr = dict(mu=1e-2, mu_final=1e-5, chol=1e-3, rho=2e-3, expert=5e-3)
+    total = 6
+    tp = torch.tensor(p.copy(), dtype=torch.float64)
+    cols = {"mu": [0, 1], "chol": [2, 3, 4], "rho": [5], "expert": list(range(6, NP))}
+    params = {k: tp[:, c].clone().requires_grad_(True) for k, c in cols.items()}
+    opt = torch.optim.Adam([{"params": [params[k]], "lr": lr[k]} for k in cols],
+                           betas=(0.9, 0.999), eps=1e-8)
+    pp, m, v = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    for t, g in enumerate(grads):
+        lrs = oracle.step_lrs(t, total, lr["mu"], lr["mu_final"], lr["chol"], lr["rho"], lr["expert"])
+        oracle.adam(pp, g, m, v, t + 1, lrs, C, order)
+        opt.param_groups[0]["lr"] = lr["mu"] * (lr["mu_final"] / lr["mu"]) ** (t / total)
+        for k, c in cols.items():
+            params[k].grad = torch.tensor(g[:, c], dtype=torch.float64)
+        opt.step()
+    out = np.zeros_like(p)
+    for k, c in cols.items():
+        out[:, c] = params[k].detach().numpy()
+    np.testing.assert_allclose(pp, out, rtol=1e-12, atol=1e-14)
+
+
+def test_fit_one_step_equals_materialize_grad_adam():
+    """oracle_fit is materialize -> loss/gradient -> Adam; one step reproduces the pieces."""
+    img = wl.config1_image()
+    raw, _ = wl.grid_init(img, 8, 8, 4.0, order=0)
+    raw = raw.astype(np.float64)
+    hist, out = oracle.fit(raw, 1, 0, img, steps=1, lr_mu=1e-2, lr_chol=1e-2, lr_rho=1e-2,
+                           lr_expert=1e-2)
+    model = oracle.materialize(raw, 1, 0)
+    loss, g = oracle.loss_grad(model, 1, 0, 64, 64, target=img)
+    p, m, v = raw.copy(), np.zeros_like(raw), np.zeros_like(raw)
+    oracle.adam(p, g, m, v, 1, [1e-2] * 4, 1, 0)
+    assert hist[0] == pytest.approx(loss, rel=1e-14)
+    np.testing.assert_allclose(out, p, rtol=1e-14, atol=1e-15)
+
+
+def test_fit_reduces_loss_workload1():
+    """100 Adam steps on the 64x64 grey workload lower the MSE (trajectory itself is
+    parity-unpinned: FP32 and FP64 runs legitimately diverge)."""
+    w = wl.workload(1)
+    hist, out = oracle.fit(w.raw0, 1, 0, w.target, steps=100, lr_mu=1e-2, lr_chol=1e-2,
+                           lr_rho=1e-2, lr_expert=1e-2)
+    assert hist[-1] < 0.7 * hist[0]
+    assert np.all(np.isfinite(out))
