@@ -1,0 +1,200 @@
+/*
+ * smoe.h -- C ABI of the MI355X (gfx950) rasterized Steered Mixture of Experts library.
+ *
+ * The library evaluates the SMoE image regression of Eq. (3)-(4) -- K anisotropic 2D
+ * Gaussian gates (Eq. 2) with Cholesky-factored covariances (Sec. VI-B) and mixing
+ * weights, normalised per pixel into soft gates over constant or linear experts --
+ * restricted per 16x16 block to the kernels whose bounding box covers the block
+ * (Eq. 5, Sec. IV-B/IV-C), together with the gradient of the reconstruction loss with
+ * respect to every kernel parameter, which drives an Adam fitting loop (Sec. VI-B).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers marked "device" are HIP device pointers; all buffers are owned by the
+ *    caller.  The library allocates no device memory and keeps no global state.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*; NULL = the
+ *    null stream) and returns a status.  Arguments are validated on the host before
+ *    anything is launched; on SMOE_ERR_INVALID nothing was enqueued.
+ *  - Coordinates are pixels, x = column, y = row; native pixel (c, r) has its centre at
+ *    (c + 0.5, r + 0.5).  An output raster (smoe_grid) samples output pixel (u, v) at
+ *    the native point (((ox + u) + 0.5) * inv_s, ((oy + v) + 0.5) * inv_s), where
+ *    inv_s = 1/scale rounded to binary32 once: scale > 1 is super-resolution by
+ *    re-sampling the continuous regression (Sec. II-B, Sec. VII-C).
+ *  - Images are float32 [height][width][C] (channel-interleaved); per-pixel scalars
+ *    are float32 [height][width].  Blocks (tiles) are 16x16 output pixels numbered
+ *    row-major, T = ceil(width/16) * ceil(height/16).
+ *  - Kernel parameter rows are float32 [K][NP], NP = 6 + C * (1 + 2 * order):
+ *      materialized row: mu_x, mu_y, l11, l21, l22, rho, a[C], wx[C], wy[C]
+ *      raw row:          mu_x, mu_y, s1,  l21, s2,  rho, a[C], wx[C], wy[C]
+ *    L = [[l11, 0], [l21, l22]] (l11, l22 > 0) is the Cholesky factor of Sigma,
+ *    s1 = ln l11, s2 = ln l22, rho = ln pi (Eq. 4), and the expert is
+ *    m(x) = a + wx (x - mu_x) + wy (y - mu_y) (order 1) or m = a (order 0).
+ *    Gradients are reported in the raw order (d/ds1 = l11 d/dl11, d/ds2 = l22 d/dl22).
+ *  - Truncation rule (Eq. 5 with the ellipse discard of Sec. IV-B): kernel j takes part
+ *    at output pixel p iff p's block lies in j's block rectangle AND
+ *    q_j(p) = |L_j^-1 (p - mu_j)|^2 <= r^2.  The block rectangle comes from the square
+ *    box of half-side r * sqrt(lambda_max(Sigma_j)) (side = major axis of the ellipse,
+ *    Fig. 3b).  Both decisions are exactly specified binary32 computations:
+ *      i11 = 1/l11, i22 = 1/l22; dx = x - mu_x, dy = y - mu_y; z1 = dx*i11;
+ *      z2 = (dy - l21*z1)*i22; q = z1*z1 + z2*z2 (each op rounded, no fma); q <= r*r;
+ *      sxx = l11*l11, sxy = l11*l21, syy = l21*l21 + l22*l22;
+ *      lam = (sxx+syy)/2 + sqrt(((sxx-syy)/2)^2 + sxy^2); R = r*sqrt(lam);
+ *      X0 = (mu_x - R)*scale - ox, X1 = (mu_x + R)*scale - ox;
+ *      u0 = max(0, ceil(X0 - 0.5)), u1 = min(width-1, floor(X1 - 0.5)) (rows alike);
+ *      block rect = [u0>>4, u1>>4] x [v0>>4, v1>>4], empty if u0 > u1 or v0 > v1.
+ *    Within a block, kernels are visited in increasing kernel id, which is also the
+ *    summation order of every per-pixel sum (renders are bitwise reproducible).
+ *  - A pixel where no kernel takes part renders 0 and receives no gradient.
+ *
+ * Status codes are negative on error.  Asynchronous conditions detected on the device
+ * (pair-capacity overflow) are reported through the workspace status words and read
+ * back with smoe_read_status(), so that a whole fit step stays free of host syncs.
+ */
+#ifndef SMOE_H_
+#define SMOE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smoe_status;
+#define SMOE_OK 0
+#define SMOE_ERR_INVALID (-1)   /* bad argument: nothing was launched */
+#define SMOE_ERR_CAPACITY (-2)  /* pair capacity too small (from smoe_read_status) */
+#define SMOE_ERR_HIP (-3)       /* a HIP launch or copy failed */
+#define SMOE_ERR_TOO_LARGE (-4) /* raster needs more blocks than the workspace holds */
+
+#define SMOE_TILE 16
+
+/* Materialized model (device, read-only). */
+typedef struct smoe_model {
+  int32_t K;            /* number of kernels, >= 0 */
+  int32_t C;            /* channels, 1 or 3 */
+  int32_t order;        /* 0 = constant experts, 1 = linear (steered) experts */
+  const float* params;  /* device [K][NP] materialized rows */
+} smoe_model;
+
+/* Output raster. */
+typedef struct smoe_grid {
+  int32_t width, height;       /* output pixels, 1 .. 65536 each */
+  int32_t scale;               /* integer upscale factor, 1 .. 64 */
+  int32_t origin_x, origin_y;  /* raster origin in output pixels, |.| <= 2^22 */
+  float radius;                /* Mahalanobis truncation radius r > 0 (3 = 98.9 % mass) */
+} smoe_grid;
+
+/* Binning workspace: the block lists of Sec. IV-C and the scratch of the backward.
+ * Laid out by smoe_bins_layout() inside one caller-allocated device buffer. */
+typedef struct smoe_bins {
+  int32_t K, C, order;     /* model shape the workspace was laid out for */
+  int32_t max_tiles;       /* largest block count T a raster may have */
+  int32_t capacity;        /* largest number of (block, kernel) pairs P */
+  int32_t* tile_rects;     /* [K][4] (tx0, ty0, tx1, ty1); empty = (0, 0, -1, -1) */
+  int32_t* counts;         /* [K] blocks covered by each kernel */
+  float* records;          /* [K][record_stride] per-kernel render records */
+  int32_t record_stride;   /* floats per record */
+  int32_t* tile_counts;    /* [max_tiles] per-block counters (scratch) */
+  int32_t* ranges;         /* [max_tiles][2] [begin, end) of each block's list */
+  uint32_t* keys;          /* [capacity] block id of each pair, ascending */
+  uint32_t* vals;          /* [capacity] kernel id of each pair, ascending within a block */
+  uint32_t* vals_alt;      /* [capacity] scratch for very long block lists */
+  float* pair_grads;       /* [capacity][NP] per-(block, kernel) gradient partials */
+  float* tile_loss;        /* [max_tiles] per-block squared error */
+  int32_t* status;         /* [4]: pairs needed P, overflow flag, longest list, spare */
+} smoe_bins;
+
+/* Bytes of workspace needed for the given shape and limits (host only). */
+size_t smoe_bins_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t max_tiles,
+                                 int32_t capacity);
+
+/* Carves `workspace` (device, >= smoe_bins_workspace_bytes(...) bytes, 256-byte aligned)
+ * into `out`.  Host only; nothing is launched and the memory is not touched. */
+smoe_status smoe_bins_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K, int32_t C,
+                             int32_t order, int32_t max_tiles, int32_t capacity);
+
+/* Binning (Sec. IV-B, IV-C): per-kernel square box -> block rectangle and count, the
+ * per-kernel render record, then the (block, kernel) pairs ordered by block and, within a
+ * block, by kernel id, and each block's [begin, end) range.  The order is the one a
+ * stable radix sort by block id of the kernel-major pair list gives.  If P exceeds
+ * bins->capacity the status words record the needed P and the overflow flag, every
+ * range is written empty, and later calls on these bins render zeros and skip updates. */
+smoe_status smoe_bin(const smoe_model* model, const smoe_grid* grid, smoe_bins* bins,
+                     void* stream);
+
+/* Forward render (Eq. 3-5): image (device [H][W][C]) and, if denom != NULL, the
+ * per-pixel gate denominator D = sum_j pi_j K_j (device [H][W]) that the backward reuses.
+ * If target (device [H][W][C]) and loss_out (device float[1]) are both non-NULL, also
+ * writes loss_out[0] = mean over H*W*C of (image - target)^2.  `bins` must come from
+ * smoe_bin() with the same model and grid. */
+smoe_status smoe_render(const smoe_model* model, const smoe_grid* grid, const smoe_bins* bins,
+                        float* image, float* denom, const float* target, float* loss_out,
+                        void* stream);
+
+/* Backward (adjoint of smoe_render): writes grads (device [K][NP], raw order) =
+ * dL/dparams, recomputing every gate from the saved image and denom.  Exactly one of
+ * grad_image (device [H][W][C], upstream dL/dimage) and target (device [H][W][C]: L = the
+ * mean squared error of image against target) must be non-NULL.  Gradients are
+ * written, not accumulated.  Uses bins->pair_grads as scratch. */
+smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
+                                 const smoe_bins* bins, const float* image, const float* denom,
+                                 const float* grad_image, const float* target, float* grads,
+                                 void* stream);
+
+/* raw -> materialized rows (l11 = exp(s1), l22 = exp(s2), the rest copied), device. */
+smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw,
+                             float* model, void* stream);
+
+/* Adam settings of a fit (Sec. VI-B).  The centre learning rate decays exponentially
+ * from lr_mu to lr_mu_final over total_steps: lr_mu(t) = lr_mu*(lr_mu_final/lr_mu)^(t/total);
+ * the Cholesky parameters (s1, l21, s2), rho and the experts use fixed rates. */
+typedef struct smoe_adam_config {
+  float lr_mu, lr_mu_final, lr_chol, lr_rho, lr_expert;
+  float beta1, beta2, eps;
+  int32_t total_steps;
+} smoe_adam_config;
+
+/* State of one fit.  Every pointer is device memory owned by the caller; `raw`, `adam_m`,
+ * `adam_v` must be initialised (m = v = 0 for a fresh fit) and `model` must hold
+ * smoe_materialize(raw) before the first step; `step` holds the number of completed
+ * steps (0 for a fresh fit). */
+typedef struct smoe_fit_state {
+  int32_t K, C, order;
+  smoe_grid grid;            /* the target raster: scale 1, origin 0 */
+  smoe_adam_config adam;
+  float* raw;                /* [K][NP] raw parameters, updated in place */
+  float* adam_m;             /* [K][NP] */
+  float* adam_v;             /* [K][NP] */
+  float* model;              /* [K][NP] materialized rows of `raw` */
+  float* grads;              /* [K][NP] gradient of the last step (raw order), or NULL */
+  float* image;              /* [H][W][C] render of the last step */
+  float* denom;              /* [H][W] */
+  float* loss_history;       /* [max_steps] loss before each update, or NULL */
+  int32_t max_steps;
+  int32_t* step;             /* [1] completed steps */
+  float* scalars;            /* [4] per-step scratch */
+  smoe_bins bins;            /* laid out for (K, C, order) and this grid */
+} smoe_fit_state;
+
+/* One fit iteration on `stream` with no host synchronisation: binning, forward render
+ * with the fused squared-error loss, backward, then per kernel the deterministic
+ * reduction of its block partials, the Adam update of the raw row and its
+ * re-materialization.  loss_out (device float[1], may be NULL) and
+ * loss_history[step] receive the loss before the update.  After a capacity overflow the
+ * step changes nothing (the step counter included); smoe_read_status() reports it. */
+smoe_status smoe_fit_step(smoe_fit_state* state, const float* target, float* loss_out,
+                          void* stream);
+
+/* Synchronises `stream`, copies the status words (P needed, overflow flag, longest list,
+ * spare) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an overflow. */
+smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int32_t smoe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMOE_H_ */

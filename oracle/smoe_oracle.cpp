@@ -345,9 +345,9 @@ void oracle_render(int K, int C, int order, const double* model, int W, int H, i
 //   or grad_y [H][W][C]: upstream dL/dy (target ignored, loss reported as 0)
 //   sel [nsel]: kernel ids whose gradients are wanted (NULL = all K, nsel ignored);
 //     only pixels in the requested kernels' blocks are visited, which is exact because
-//     a kernel contributes nothing outside its blocks.
+//     a kernel contributes nothing outside its blocks; the loss is then not available.
 //   grads [nsel or K][NP] raw-parameter order, overwritten.
-// Returns the loss (0 in grad_y mode).
+// Returns the loss (NaN in grad_y mode or with a kernel subset).
 double oracle_loss_grad(int K, int C, int order, const double* model, int W, int H, int s, int ox,
                         int oy, float r, const double* target, const double* grad_y, int nsel,
                         const int32_t* sel, double* grads, int threads) {
@@ -379,7 +379,7 @@ double oracle_loss_grad(int K, int C, int order, const double* model, int W, int
     for (int u = 0; u < W; ++u) {
       const size_t p = (size_t)v * W + u;
       const bool want = !sel || need[p];
-      if (!want && !target) continue;
+      if (!want) continue;
       double D;
       eval_pixel(M, g, true, u, (int)v, y.data(), &D);
       for (int c = 0; c < C; ++c) {
@@ -401,7 +401,9 @@ double oracle_loss_grad(int K, int C, int order, const double* model, int W, int
     for (size_t i = 0; i < (size_t)nout * NP; ++i) grads[i] += Gt[t][i];
   double loss = 0.0;
   for (int v = 0; v < H; ++v) loss += loss_row[v];
-  return grad_y ? 0.0 : loss * inv_n;
+  // The loss needs every pixel; with a kernel subset only some were evaluated.
+  if (grad_y || sel) return std::nan("");
+  return loss * inv_n;
 }
 
 // Raw parameters -> materialized model (l11 = e^s1, l22 = e^s2, the rest copied).

@@ -1,0 +1,255 @@
+"""Device-memory plumbing around the C ABI: workspaces, fit state, convenience calls.
+
+PyTorch provides device memory (tensors from its caching allocator) and the
+current HIP stream; every computation is a call into ``libsmoe.so``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _capi as C
+
+TILE = C.TILE
+
+
+def num_params(C_: int, order: int) -> int:
+    """Floats per kernel row: mu(2) + Cholesky(3) + rho(1) + expert."""
+    return 6 + C_ * (1 + 2 * order)
+
+
+def tiles(width: int, height: int) -> int:
+    return ((width + TILE - 1) // TILE) * ((height + TILE - 1) // TILE)
+
+
+def make_grid(width, height, scale=1, origin_x=0, origin_y=0, radius=3.0) -> C.SmoeGrid:
+    return C.SmoeGrid(int(width), int(height), int(scale), int(origin_x), int(origin_y),
+                      float(radius))
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check_params(params, C_, order):
+    NP = num_params(C_, order)
+    if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()
+            and params.dim() == 2 and params.shape[1] == NP):
+        raise ValueError(f"params must be a contiguous cuda float32 [K, {NP}] tensor")
+
+
+def model_struct(params: torch.Tensor, C_: int, order: int) -> C.SmoeModel:
+    _check_params(params, C_, order)
+    return C.SmoeModel(params.shape[0], C_, order, params.data_ptr())
+
+
+class Bins:
+    """A binning workspace (block lists, records, backward scratch) in one device buffer."""
+
+    def __init__(self, K: int, C_: int, order: int, max_tiles: int, capacity: int,
+                 device="cuda"):
+        self.K, self.C, self.order = K, C_, order
+        self.max_tiles, self.capacity = int(max_tiles), int(capacity)
+        n = C.smoe_bins_workspace_bytes(K, C_, order, self.max_tiles, self.capacity)
+        if n == 0:
+            raise ValueError("invalid workspace shape")
+        self.nbytes = n
+        self.ws = torch.zeros(n, dtype=torch.uint8, device=device)
+        self.c = C.SmoeBins()
+        C.smoe_bins_layout(self.c, self.ws.data_ptr(), n, K, C_, order, self.max_tiles,
+                           self.capacity)
+
+    def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
+        off = ptr - self.ws.data_ptr()
+        size = torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + count * size].view(dtype)
+
+    def tile_rects(self):
+        return self._view(self.c.tile_rects, 4 * self.K, torch.int32).view(self.K, 4)
+
+    def counts(self):
+        return self._view(self.c.counts, self.K, torch.int32)
+
+    def ranges(self, T: int):
+        return self._view(self.c.ranges, 2 * T, torch.int32).view(T, 2)
+
+    def keys(self, P: int):
+        return self._view(self.c.keys, P, torch.int32)
+
+    def vals(self, P: int):
+        return self._view(self.c.vals, P, torch.int32)
+
+    def read_status(self, stream=None):
+        """Synchronises the stream; returns (overflowed, [P needed, overflow, longest, 0])."""
+        code, st = C.smoe_read_status(self.c, _stream(stream))
+        return code == C.SMOE_ERR_CAPACITY, st
+
+
+def initial_capacity(K: int, T: int) -> int:
+    return max(1024, 8 * K + 2 * T)
+
+
+def bin(params: torch.Tensor, C_: int, order: int, grid: C.SmoeGrid, bins: Bins | None = None,
+        capacity: int | None = None, stream=None, grow: bool = True) -> Bins:
+    """smoe_bin; with grow=True the workspace is re-made until the pairs fit (host sync)."""
+    m = model_struct(params, C_, order)
+    T = tiles(grid.width, grid.height)
+    if bins is None:
+        bins = Bins(m.K, C_, order, T, capacity or initial_capacity(m.K, T), params.device)
+    C.smoe_bin(m, grid, bins.c, _stream(stream))
+    if grow:
+        over, st = bins.read_status(stream)
+        if over:
+            bins = Bins(m.K, C_, order, max(T, bins.max_tiles), int(st[0] * 1.25) + 1024,
+                        params.device)
+            C.smoe_bin(m, grid, bins.c, _stream(stream))
+    return bins
+
+
+def render(params: torch.Tensor, C_: int, order: int, grid: C.SmoeGrid, bins: Bins | None = None,
+           target: torch.Tensor | None = None, stream=None):
+    """Bins (if not given) and renders.  Returns (image [H, W, C], denom [H, W], loss or
+    None, bins)."""
+    if bins is None:
+        bins = bin(params, C_, order, grid, stream=stream)
+    m = model_struct(params, C_, order)
+    dev = params.device
+    image = torch.empty((grid.height, grid.width, C_), dtype=torch.float32, device=dev)
+    denom = torch.empty((grid.height, grid.width), dtype=torch.float32, device=dev)
+    loss = None
+    if target is not None:
+        if not (target.is_cuda and target.dtype == torch.float32 and target.is_contiguous()
+                and tuple(target.shape) == (grid.height, grid.width, C_)):
+            raise ValueError("target must be a contiguous cuda float32 [H, W, C] tensor")
+        loss = torch.empty((1,), dtype=torch.float32, device=dev)
+    C.smoe_render(m, grid, bins.c, image.data_ptr(), denom.data_ptr(), _ptr(target), _ptr(loss),
+                  _stream(stream))
+    return image, denom, loss, bins
+
+
+def render_backward(params, C_, order, grid, bins: Bins, image, denom, grad_image=None,
+                    target=None, stream=None) -> torch.Tensor:
+    """dL/dparams [K, NP] in raw order (mu, s1, l21, s2, rho, a, wx, wy)."""
+    m = model_struct(params, C_, order)
+    grads = torch.empty_like(params)
+    for t in (image, denom, grad_image, target):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("image/denom/grad_image/target must be contiguous cuda float32")
+    C.smoe_render_backward(m, grid, bins.c, image.data_ptr(), denom.data_ptr(), _ptr(grad_image),
+                           _ptr(target), grads.data_ptr(), _stream(stream))
+    return grads
+
+
+def materialize(raw: torch.Tensor, C_: int, order: int, stream=None) -> torch.Tensor:
+    _check_params(raw, C_, order)
+    out = torch.empty_like(raw)
+    C.smoe_materialize(raw.shape[0], C_, order, raw.data_ptr(), out.data_ptr(), _stream(stream))
+    return out
+
+
+@dataclass
+class AdamConfig:
+    """Adam settings (Sec. VI-B): centre rate decays exponentially to lr_mu_final."""
+    lr_mu: float = 1e-2
+    lr_mu_final: float = 1e-5
+    lr_chol: float = 1e-3
+    lr_rho: float = 1e-3
+    lr_expert: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    total_steps: int = 10000
+
+    @classmethod
+    def constant(cls, lr: float, total_steps: int = 1):
+        return cls(lr, lr, lr, lr, lr, total_steps=total_steps)
+
+    def c(self) -> C.SmoeAdamConfig:
+        return C.SmoeAdamConfig(self.lr_mu, self.lr_mu_final, self.lr_chol, self.lr_rho,
+                                self.lr_expert, self.beta1, self.beta2, self.eps,
+                                int(self.total_steps))
+
+
+class FitState:
+    """Device state of one fit, driven by smoe_fit_step (one call = one iteration)."""
+
+    def __init__(self, target: torch.Tensor, raw0: torch.Tensor, order: int, adam: AdamConfig,
+                 max_steps: int = 0, capacity: int | None = None, radius: float = 3.0):
+        if not (target.is_cuda and target.dtype == torch.float32 and target.dim() == 3):
+            raise ValueError("target must be a cuda float32 [H, W, C] tensor")
+        self.target = target.contiguous()
+        H, W, C_ = self.target.shape
+        self.H, self.W, self.C, self.order = H, W, C_, order
+        self.K = raw0.shape[0]
+        dev = target.device
+        self.raw = raw0.to(device=dev, dtype=torch.float32).contiguous().clone()
+        _check_params(self.raw, C_, order)
+        self.m = torch.zeros_like(self.raw)
+        self.v = torch.zeros_like(self.raw)
+        self.model = materialize(self.raw, C_, order)
+        self.grads = torch.zeros_like(self.raw)
+        self.image = torch.zeros((H, W, C_), dtype=torch.float32, device=dev)
+        self.denom = torch.zeros((H, W), dtype=torch.float32, device=dev)
+        self.max_steps = int(max_steps)
+        self.loss_history = torch.zeros(max(1, self.max_steps), dtype=torch.float32, device=dev)
+        self.step_counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.scalars = torch.zeros(4, dtype=torch.float32, device=dev)
+        self.grid = make_grid(W, H, 1, 0, 0, radius)
+        self.adam = adam
+        T = tiles(W, H)
+        if capacity is None:
+            b = bin(self.model, C_, order, self.grid)
+            _, st = b.read_status()
+            capacity = int(st[0] * 1.5) + 4096
+        self.bins = Bins(self.K, C_, order, T, capacity, dev)
+        self._build_struct()
+
+    def _build_struct(self):
+        self.c = C.SmoeFitState(
+            self.K, self.C, self.order, self.grid, self.adam.c(), self.raw.data_ptr(),
+            self.m.data_ptr(), self.v.data_ptr(), self.model.data_ptr(), self.grads.data_ptr(),
+            self.image.data_ptr(), self.denom.data_ptr(), self.loss_history.data_ptr(),
+            self.max_steps, self.step_counter.data_ptr(), self.scalars.data_ptr(), self.bins.c)
+
+    def step(self, loss_out: torch.Tensor | None = None, stream=None):
+        C.smoe_fit_step(self.c, self.target.data_ptr(), _ptr(loss_out), _stream(stream))
+
+    def steps_done(self) -> int:
+        return int(self.step_counter.item())
+
+    def grow_if_needed(self, stream=None) -> bool:
+        """Host sync; after a pair-capacity overflow re-makes the workspace larger."""
+        over, st = self.bins.read_status(stream)
+        if over:
+            self.bins = Bins(self.K, self.C, self.order, self.bins.max_tiles,
+                             int(st[0] * 1.5) + 4096, self.target.device)
+            self._build_struct()
+        return over
+
+    def run(self, steps: int, check_every: int = 64, stream=None):
+        """Runs until `steps` more iterations have completed, re-sizing on overflow."""
+        goal = self.steps_done() + steps
+        while True:
+            todo = goal - self.steps_done()
+            if todo <= 0:
+                break
+            for _ in range(min(todo, check_every)):
+                self.step(stream=stream)
+            self.grow_if_needed(stream)
+        return self
+
+    def losses(self) -> torch.Tensor:
+        n = min(self.steps_done(), self.max_steps)
+        return self.loss_history[:n]
+
+
+def psnr(a: torch.Tensor, b: torch.Tensor, peak: float = 1.0) -> float:
+    mse = torch.mean((a.double() - b.double()) ** 2).item()
+    return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)

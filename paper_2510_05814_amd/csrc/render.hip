@@ -1,0 +1,161 @@
+// Forward rasterization of the SMoE regression (Eq. 3-5) on gfx950.
+//
+// One workgroup of 256 lanes (4 wave64) per 16x16 block, one output pixel per lane.  The
+// block's kernel list is staged through LDS in chunks of 256 render records (coalesced
+// float4 loads by the whole workgroup); every wave then reads each record with a
+// wave-uniform LDS address (a broadcast) and accumulates, in FP32 registers, the gate
+// denominator D = sum_j pi_j K_j(x) and the numerators N_c = sum_j pi_j K_j(x) m_jc(x)
+// in list order (increasing kernel id).  y_c = N_c / D.  No MFMA: there is no dense
+// contraction here, the work is FP32 VALU plus one v_exp_f32 per participating pair.
+//
+// Optional fused squared error against a target: each block writes its sum of squared
+// errors to tile_loss[block]; launch_loss_reduce() then reduces those in a fixed order.
+#include "smoe_internal.h"
+
+namespace smoe {
+namespace {
+
+constexpr int kThreads = kTilePixels;  // 256
+
+struct RenderArgs {
+  GridArgs g;
+  const float* __restrict__ records;
+  const int2* __restrict__ ranges;
+  const uint32_t* __restrict__ vals;
+  float* __restrict__ image;
+  float* __restrict__ denom;
+  const float* __restrict__ target;
+  float* __restrict__ tile_loss;
+};
+
+// Stages records vals[base .. base+n) into LDS as float4 rows of RS/4.
+template <int RS>
+__device__ __forceinline__ void stage_records(float4* __restrict__ srec,
+                                              const float* __restrict__ records,
+                                              const uint32_t* __restrict__ vals, int base, int n) {
+  constexpr int Q = RS / 4;
+  for (int i = threadIdx.x; i < n * Q; i += kThreads) {
+    const int k = i / Q, c = i - k * Q;
+    const uint32_t j = vals[base + k];
+    srec[i] = reinterpret_cast<const float4*>(records + (size_t)j * RS)[c];
+  }
+}
+
+template <int C, int ORDER>
+__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
+  constexpr int RS = record_stride(C, ORDER);
+  __shared__ float4 srec[kThreads * RS / 4];
+  __shared__ float sred[kThreads / 64];
+
+  const int tile = xcd_block(blockIdx.x, a.g.T);
+  const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
+  const int u = tx * kTile + (threadIdx.x & 15);
+  const int v = ty * kTile + (threadIdx.x >> 4);
+  const float x = sample_coord(u, a.g.ox, a.g.inv_s);
+  const float y = sample_coord(v, a.g.oy, a.g.inv_s);
+  const float r2 = a.g.r2;
+  const int2 rg = a.ranges[tile];
+
+  float D = 0.0f;
+  float N[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) N[c] = 0.0f;
+
+  for (int base = rg.x; base < rg.y; base += kThreads) {
+    const int n = min(kThreads, rg.y - base);
+    __syncthreads();
+    stage_records<RS>(srec, a.records, a.vals, base, n);
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      const float* r = reinterpret_cast<const float*>(&srec[k * (RS / 4)]);
+      // Truncation test: the binary32 sequence of the ABI contract (no contraction).
+      const float dx = x - r[0];
+      const float dy = y - r[1];
+      const float z1 = dx * r[2];
+      const float tt = r[3] * z1;
+      const float w = dy - tt;
+      const float z2 = w * r[4];
+      const float q = z1 * z1 + z2 * z2;
+      if (q <= r2) {
+        // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
+        const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+        D += e;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          float m = r[kRecExpert + c];
+          if (ORDER == 1) {
+            m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
+            m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+          }
+          N[c] = __builtin_fmaf(e, m, N[c]);
+        }
+      }
+    }
+  }
+
+  const bool inside = u < a.g.W && v < a.g.H;
+  float err = 0.0f;
+  if (inside) {
+    const size_t p = (size_t)v * a.g.W + u;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float yc = (D > 0.0f) ? N[c] / D : 0.0f;
+      a.image[p * C + c] = yc;
+      if (a.target) {
+        const float d = yc - a.target[p * C + c];
+        err = __builtin_fmaf(d, d, err);
+      }
+    }
+    if (a.denom) a.denom[p] = D;
+  }
+  if (a.tile_loss) {
+    for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = err;
+    __syncthreads();
+    if (threadIdx.x == 0) a.tile_loss[tile] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+  }
+}
+
+// One workgroup: loss = inv_n * sum of the per-block partials, in a fixed order.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __restrict__ part,
+                                                                int T, float inv_n,
+                                                                float* __restrict__ out) {
+  __shared__ float s[kReduceThreads / 64];
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < T; i += kReduceThreads) acc += part[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kReduceThreads / 64; ++w) t += s[w];
+    out[0] = t * inv_n;
+  }
+}
+
+template <int C, int ORDER>
+hipError_t launch(const RenderArgs& a, hipStream_t s) {
+  k_render<C, ORDER><<<a.g.T, kThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* image,
+                         float* denom, const float* target, hipStream_t s) {
+  RenderArgs a{g,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
+               target, target ? b.tile_loss : nullptr};
+  if (m.C == 1 && m.order == 0) return launch<1, 0>(a, s);
+  if (m.C == 1 && m.order == 1) return launch<1, 1>(a, s);
+  if (m.C == 3 && m.order == 0) return launch<3, 0>(a, s);
+  return launch<3, 1>(a, s);
+}
+
+hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,
+                              hipStream_t s) {
+  k_loss_reduce<<<1, kReduceThreads, 0, s>>>(b.tile_loss, T, inv_n, loss_out);
+  return hipGetLastError();
+}
+
+}  // namespace smoe
