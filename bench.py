@@ -1,0 +1,370 @@
+#!/usr/bin/env python3
+"""Benchmark of the rasterized SMoE fit step on one MI355X.
+
+Workload: fit of a 2048x2048 RGB float32 denoising target (Voronoi ramps + Gaussian noise
+of std 25/255) with K = 65536 linear-expert kernels initialised on a 256x256 grid
+(sigma 4 px), truncation radius 3, 16x16 blocks, Adam with the paper's learning rates.
+A step is one full iteration of the hot path: binning (box, block lists, ordering),
+forward render with the fused loss, backward, and the fused gradient-reduce/Adam/
+re-materialize update -- one smoe_fit_step call.  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line.  Besides throughput it reports the roofline of the dominant kernel
+(its duration from HIP events recorded around it in every timed step), the oracle's CPU
+throughput on a bounded sample of the same workload, per-stage times and pair counts.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 20]
+    python bench.py --summarize-profile DIR   # writes profiles/ summaries of rocprofv3 runs
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as ct
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SMoE fit iters/s (fwd+bwd) 2048² K=65536; render p50/p99 latency vs plain"
+WORKLOAD = "fit-2048x2048-rgb-K65536-linear-denoise"
+
+# Algorithmic FP32 work per (pixel, kernel) pair, in VALU operations (one add, mul, fma,
+# compare or exp each), C = 3 linear experts:
+#   tested pair (the truncation test):  dx, dy, z1, l21*z1, w, z2, z1^2, z2^2, q, compare = 10
+#   forward, participating pair: exponent fma, exp, D add, 6 fma expert, 3 fma numerators = 12
+#   backward, participating pair: exponent fma, exp, w, 6 expert fma, 3 G fma, 3 g*w,
+#     H, bz2, 2 bz1, 2 chain fma, 6 slope-chain fma, 6 slope products, s1, 2 l21, s2,
+#     15 accumulations = 52
+OPS_TESTED = 10
+OPS_ACTIVE_FWD = 12
+OPS_ACTIVE_BWD = 52
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s
+# (non-packed; packed FP32 is not used).
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+
+STAGES = ["bin", "render", "loss", "backward", "adam"]
+KERNEL_NAMES = {"backward": "k_backward", "render": "k_render"}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_fit2048.json")
+
+
+# ----------------------------------------------------------------------------- HIP events
+
+class HipEvents:
+    """hipEventCreate/ElapsedTime through the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        self.lib = ct.CDLL("libamdhip64.so.7")
+        self.lib.hipEventCreate.argtypes = [ct.POINTER(ct.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ct.POINTER(ct.c_float), ct.c_void_p, ct.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ct.c_void_p]
+        self.lib.hipEventSynchronize.argtypes = [ct.c_void_p]
+
+    def create(self, n):
+        out = []
+        for _ in range(n):
+            e = ct.c_void_p()
+            if self.lib.hipEventCreate(ct.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            out.append(e.value)
+        return out
+
+    def elapsed_ms(self, a, b):
+        self.lib.hipEventSynchronize(b)
+        f = ct.c_float()
+        if self.lib.hipEventElapsedTime(ct.byref(f), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(f.value)
+
+    def destroy(self, evs):
+        for e in evs:
+            self.lib.hipEventDestroy(e)
+
+
+def source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "backward": ["paper_2510_05814_amd/csrc/backward.hip", "paper_2510_05814_amd/csrc/smoe_internal.h"],
+    "render": ["paper_2510_05814_amd/csrc/render.hip", "paper_2510_05814_amd/csrc/smoe_internal.h"],
+}
+
+
+# ----------------------------------------------------------------------------- CPU baseline
+
+def cpu_baseline(target, raw0, budget_s=20.0):
+    """The FP64 oracle's loss + gradient on a band of image rows with all K kernels, scaled
+    to iterations/s of the whole 2048^2 image.  Every pixel of the band visits all K kernels
+    (the oracle's plain definition), exactly as a full-image call would."""
+    import numpy as np
+
+    import oracle
+
+    H, W, C = target.shape
+    threads = oracle.default_threads()
+    model = oracle.materialize(raw0.astype(np.float64), C, 1)
+    rows = 8
+    t_probe = None
+    while True:
+        t0 = time.perf_counter()
+        oracle.loss_grad(model, C, 1, W, rows, target=target[:rows], threads=threads)
+        dt = time.perf_counter() - t0
+        if t_probe is None and dt < 0.5 * budget_s / 8:
+            t_probe = dt
+            rows = int(min(H, max(rows + 8, rows * (budget_s / max(dt, 1e-3)) / 1.2)))
+            rows -= rows % 8
+            continue
+        break
+    full_s = dt * H / rows
+    return {"value": 1.0 / full_s, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 loss+gradient over rows 0..{rows - 1} (2048x{rows} px) with all "
+                      f"{raw0.shape[0]} kernels, {dt:.1f} s, scaled by {H}/{rows} rows",
+            "seconds_per_iter": full_s}
+
+
+# ----------------------------------------------------------------------------- main bench
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd import _capi
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    w = wl.workload(3)
+    H, W, C = w.target.shape
+    target = torch.from_numpy(w.target).cuda()
+    clean = torch.from_numpy(w.clean).cuda()
+    adam = smoe.AdamConfig(total_steps=10000)
+    raw0 = torch.from_numpy(w.raw0).cuda()
+    b0 = smoe.bin(smoe.materialize(raw0, C, 1), C, 1, smoe.make_grid(W, H))
+    P0 = b0.read_status()[1][0]
+    del b0
+    # generous pair capacity (HBM is plentiful): an overflowed step would be a no-op
+    st = smoe.FitState(target, raw0, 1, adam, max_steps=args.warmup + args.steps + 16,
+                       capacity=8 * P0 + 65536)
+    ev = HipEvents()
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    # warm-up (advances the fit), then make sure the pair capacity is sufficient
+    for _ in range(args.warmup):
+        st.step()
+    st.grow_if_needed()
+
+    # per-stage profile of a few steps (not part of the timed region)
+    nprof = 8
+    evs = ev.create(6 * nprof)
+    for i in range(nprof):
+        _capi.smoe_fit_step_timed(st.c, st.target.data_ptr(), None, evs[6 * i:6 * i + 6], sh)
+    torch.cuda.synchronize()
+    stage_ms = {s: [] for s in STAGES}
+    for i in range(nprof):
+        e = evs[6 * i:6 * i + 6]
+        for k, s in enumerate(STAGES):
+            stage_ms[s].append(ev.elapsed_ms(e[k], e[k + 1]))
+    ev.destroy(evs)
+    stage_avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
+    dominant = max(("render", "backward"), key=lambda s: stage_avg[s])
+    dom_idx = STAGES.index(dominant)
+
+    # timed region: K steps, HIP events around the dominant kernel in every step
+    evs = ev.create(2 * args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e6 = [None] * 6
+        e6[dom_idx], e6[dom_idx + 1] = evs[2 * i], evs[2 * i + 1]
+        _capi.smoe_fit_step_timed(st.c, st.target.data_ptr(), None, e6, sh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms = [ev.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(args.steps)]
+    ev.destroy(evs)
+    elapsed = t1 - t0
+    over, status = st.bins.read_status()
+    if over:
+        raise RuntimeError("pair capacity overflow inside the timed region")
+
+    # geometry at the end of the timed region
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    m = smoe.core.model_struct(st.model, C, 1)
+    _capi.smoe_pair_stats(m, st.grid, st.bins.c, stats.data_ptr(), sh)
+    tested, active = [int(x) for x in stats.tolist()]
+    P = status[0]
+    T = smoe.tiles(W, H)
+
+    dom_avg_s = float(np.mean(dom_ms)) * 1e-3
+    ops = tested * OPS_TESTED + active * (OPS_ACTIVE_BWD if dominant == "backward" else OPS_ACTIVE_FWD)
+    achieved = ops / dom_avg_s
+    roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dominant], "achieved": achieved / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (FP32 VALU lane-ops)",
+                "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                "avg_launch_ms": dom_avg_s * 1e3, "algorithmic_ops_per_launch": ops}
+    # HBM traffic per launch from committed rocprofv3 counters, if taken on this source
+    try:
+        with open(COUNTERS_FILE) as f:
+            k = json.load(f)["kernels"][KERNEL_NAMES[dominant]]
+        if k["source_digest"] == source_digest(KERNEL_SOURCES[dominant]):
+            roofline["traffic"] = k["fetch_bytes"] + k["write_bytes"]
+    except (OSError, ValueError, KeyError):
+        pass
+
+    psnr_clean = smoe.psnr(st.image, clean)
+    out = {
+        "metric": METRIC, "value": args.steps / elapsed, "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "image": f"{W}x{H}x{C}", "K": st.K, "experts": "linear",
+                   "tile": 16, "radius": 3.0, "fit_steps_before_timing": args.warmup},
+        "roofline": roofline,
+        "stages_ms": stage_avg,
+        "pairs": {"P_init": P0, "P": P, "mean_list": P / T, "longest_list": status[2], "tested": tested,
+                  "active": active, "active_per_px": active / (W * H)},
+        "gate_evals_per_s_tested": tested * args.steps / elapsed,
+        "psnr_vs_clean_db": psnr_clean,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
+        out["cpu_baseline"] = cb
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 4
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------------------- profiles
+
+def _rocpd_kernels(db_path):
+    """(name, calls, total ns, average ns, percent of kernel time) from a rocprofv3 SQLite output."""
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    try:
+        rows = con.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                           "group by name order by sum(duration) desc").fetchall()
+    finally:
+        con.close()
+    total = sum(r[2] for r in rows) or 1
+    return [(n, c, t, a, 100.0 * t / total) for n, c, t, a in rows]
+
+
+def _rocpd_counters(db_path, counter):
+    """{kernel name: [values per dispatch]} of one PMC counter in a rocprofv3 SQLite output."""
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    out = {}
+    try:
+        tabs = [r[0] for r in con.execute("select name from sqlite_master where type='view'")]
+        view = "counters_collection" if "counters_collection" in tabs else None
+        if view is None:
+            return out
+        cols = [r[1] for r in con.execute(f"pragma table_info({view})")]
+        name_col = "kernel_name" if "kernel_name" in cols else "name"
+        val_col = "value" if "value" in cols else "counter_value"
+        cn_col = "counter_name" if "counter_name" in cols else "counter"
+        disp = "dispatch_id" if "dispatch_id" in cols else None
+        q = f"select {name_col}, {cn_col}, {val_col}" + (f", {disp}" if disp else "") + f" from {view}"
+        acc = {}
+        for r in con.execute(q):
+            if r[1] != counter:
+                continue
+            key = (r[0], r[3] if disp else len(acc))
+            acc[key] = acc.get(key, 0.0) + float(r[2])   # sum over shader engines / instances
+        for (name, _), v in acc.items():
+            out.setdefault(name, []).append(v)
+    finally:
+        con.close()
+    return out
+
+
+def summarize_profile(prof_dir, cmd):
+    """Writes profiles/ summaries from rocprofv3 SQLite outputs under prof_dir:
+    trace/ (--kernel-trace --stats) and, if present, fetch_size/ and write_size/ (--pmc)."""
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    dbs = glob.glob(os.path.join(prof_dir, "trace", "**", "*_results.db"), recursive=True)
+    if dbs:
+        lines = ["# rocprofv3 kernel trace: fit step, 2048x2048 RGB, K=65536 linear experts", "",
+                 f"Command: `{cmd}`", "",
+                 "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
+        for name, calls, tot, avg, pct in _rocpd_kernels(dbs[0]):
+            short = name.replace("smoe::(anonymous namespace)::", "").split("(")[0]
+            if len(short) > 60:
+                short = short[:57] + "..."
+            lines.append(f"| `{short}` | {calls} | {avg / 1e3:.2f} | {tot / 1e3:.1f} | {pct:.1f} |")
+        with open(os.path.join(ROOT, "profiles", "kernels_fit2048.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    f_db = glob.glob(os.path.join(prof_dir, "fetch_size", "**", "*_results.db"), recursive=True)
+    w_db = glob.glob(os.path.join(prof_dir, "write_size", "**", "*_results.db"), recursive=True)
+    if not (f_db and w_db):
+        return
+    fetch, write = _rocpd_counters(f_db[0], "FETCH_SIZE"), _rocpd_counters(w_db[0], "WRITE_SIZE")
+
+    def pick(d, key):
+        return [x for k, v in d.items() if key in k for x in v]
+
+    copy_bytes = (64 << 20) * 4
+    cf, cw = pick(fetch, "direct_copy"), pick(write, "direct_copy")
+    f_scale = copy_bytes / (max(cf) * 1024.0) if cf else 1.0
+    w_scale = copy_bytes / (max(cw) * 1024.0) if cw else 1.0
+    out = {"calibration": {"copy_bytes": copy_bytes, "fetch_kib": max(cf) if cf else None,
+                           "write_kib": max(cw) if cw else None, "fetch_scale": f_scale,
+                           "write_scale": w_scale},
+           "kernels": {}, "command": cmd}
+    for stage, kname in KERNEL_NAMES.items():
+        fv, wv = pick(fetch, kname + "<"), pick(write, kname + "<")
+        if fv and wv:
+            out["kernels"][kname] = {
+                "fetch_bytes": sum(fv) / len(fv) * 1024.0 * f_scale,
+                "write_bytes": sum(wv) / len(wv) * 1024.0 * w_scale,
+                "dispatches": len(fv), "source_digest": source_digest(KERNEL_SOURCES[stage])}
+    with open(COUNTERS_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle CPU work")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain copy of known size (for PMC byte counters)")
+    ap.add_argument("--summarize-profile", metavar="DIR")
+    ap.add_argument("--profile-command", default="")
+    args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.profile_command)
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+    run(args)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

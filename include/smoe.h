@@ -186,6 +186,20 @@ typedef struct smoe_fit_state {
 smoe_status smoe_fit_step(smoe_fit_state* state, const float* target, float* loss_out,
                           void* stream);
 
+/* smoe_fit_step with HIP events recorded on `stream` at the stage boundaries, for timing:
+ * stage_events[0] before binning, [1] after binning, [2] after the forward render,
+ * [3] after the loss/step scalars, [4] after the backward, [5] after the Adam update.
+ * stage_events is a host array of 6 hipEvent_t; NULL entries are not recorded. */
+smoe_status smoe_fit_step_timed(smoe_fit_state* state, const float* target, float* loss_out,
+                                void* const* stage_events, void* stream);
+
+/* Diagnostic (not part of a fit step): counts, over the raster's in-image pixels, the
+ * (pixel, kernel) pairs a render tests -- every kernel of the pixel's block list -- and the
+ * pairs that take part (q <= r^2).  out2 is device uint64[2] = (tested, active) and is
+ * overwritten.  Uses atomics; the counts are exact integers. */
+smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
+                            const smoe_bins* bins, uint64_t* out2, void* stream);
+
 /* Synchronises `stream`, copies the status words (P needed, overflow flag, longest list,
  * spare) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an overflow. */
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream);

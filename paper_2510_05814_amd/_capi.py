@@ -85,6 +85,10 @@ def _load():
     L.smoe_materialize.restype = _i32
     L.smoe_fit_step.argtypes = [P(SmoeFitState), _vp, _vp, _vp]
     L.smoe_fit_step.restype = _i32
+    L.smoe_fit_step_timed.argtypes = [P(SmoeFitState), _vp, _vp, P(_vp), _vp]
+    L.smoe_fit_step_timed.restype = _i32
+    L.smoe_pair_stats.argtypes = [P(SmoeModel), P(SmoeGrid), P(SmoeBins), _vp, _vp]
+    L.smoe_pair_stats.restype = _i32
     L.smoe_read_status.argtypes = [P(SmoeBins), P(_i32), _vp]
     L.smoe_read_status.restype = _i32
     return L
@@ -95,7 +99,7 @@ lib = _load()
 # Symbols the header declares; the CPU test suite checks that each is exported.
 EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "smoe_bin",
             "smoe_render", "smoe_render_backward", "smoe_materialize", "smoe_fit_step",
-            "smoe_read_status"]
+            "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status"]
 
 
 def _check(fn: str, code: int, allow=()):
@@ -146,6 +150,18 @@ def smoe_materialize(K, C, order, raw_ptr, model_ptr, stream):
 def smoe_fit_step(state: SmoeFitState, target_ptr, loss_ptr, stream):
     return _check("smoe_fit_step", lib.smoe_fit_step(ct.byref(state), target_ptr, loss_ptr,
                                                      stream))
+
+
+def smoe_fit_step_timed(state: SmoeFitState, target_ptr, loss_ptr, events6, stream):
+    """events6: six hipEvent_t handles (ints) or None entries."""
+    arr = (_vp * 6)(*[e or None for e in events6])
+    return _check("smoe_fit_step_timed",
+                  lib.smoe_fit_step_timed(ct.byref(state), target_ptr, loss_ptr, arr, stream))
+
+
+def smoe_pair_stats(model, grid, bins, out2_ptr, stream):
+    return _check("smoe_pair_stats", lib.smoe_pair_stats(ct.byref(model), ct.byref(grid),
+                                                         ct.byref(bins), out2_ptr, stream))
 
 
 def smoe_read_status(bins: SmoeBins, stream):

@@ -207,7 +207,7 @@ class FitState:
         if capacity is None:
             b = bin(self.model, C_, order, self.grid)
             _, st = b.read_status()
-            capacity = int(st[0] * 1.5) + 4096
+            capacity = int(st[0] * 2) + 4096
         self.bins = Bins(self.K, C_, order, T, capacity, dev)
         self._build_struct()
 

@@ -166,8 +166,10 @@ smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* r
   return hip_status(launch_materialize(K, C, order, raw, model, static_cast<hipStream_t>(stream)));
 }
 
-smoe_status smoe_fit_step(smoe_fit_state* st, const float* target, float* loss_out,
-                          void* stream) {
+namespace {
+
+smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
+                     void* const* ev, void* stream) {
   if (!st || !target) return SMOE_ERR_INVALID;
   const smoe_model m{st->K, st->C, st->order, st->model};
   GridArgs g;
@@ -182,13 +184,44 @@ smoe_status smoe_fit_step(smoe_fit_state* st, const float* target, float* loss_o
   if (g.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float inv_n = (float)(1.0 / ((double)g.W * g.H * st->C));
-  hipError_t e = launch_bin(m, g, st->bins, s);
+  auto mark = [&](int i) -> hipError_t {
+    return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
+  };
+  hipError_t e = mark(0);
+  if (e == hipSuccess) e = launch_bin(m, g, st->bins, s);
+  if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_render(m, g, st->bins, st->image, st->denom, target, s);
+  if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = launch_step_begin(*st, g, inv_n, loss_out, s);
+  if (e == hipSuccess) e = mark(3);
   if (e == hipSuccess)
     e = launch_backward(m, g, st->bins, st->image, st->denom, nullptr, target, s);
+  if (e == hipSuccess) e = mark(4);
   if (e == hipSuccess) e = launch_adam(*st, g, s);
+  if (e == hipSuccess) e = mark(5);
   return hip_status(e);
+}
+
+}  // namespace
+
+smoe_status smoe_fit_step(smoe_fit_state* st, const float* target, float* loss_out,
+                          void* stream) {
+  return fit_step(st, target, loss_out, nullptr, stream);
+}
+
+smoe_status smoe_fit_step_timed(smoe_fit_state* st, const float* target, float* loss_out,
+                                void* const* stage_events, void* stream) {
+  if (!stage_events) return SMOE_ERR_INVALID;
+  return fit_step(st, target, loss_out, stage_events, stream);
+}
+
+smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
+                            const smoe_bins* bins, uint64_t* out2, void* stream) {
+  GridArgs g;
+  if (!valid_model(model) || !make_grid(grid, &g) || !bins_match(bins, model) || !out2)
+    return SMOE_ERR_INVALID;
+  if (g.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  return hip_status(launch_pair_stats(*model, g, *bins, out2, static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream) {

@@ -134,6 +134,48 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
   }
 }
 
+// Diagnostic: per block, the tested (pixel, kernel) pairs of in-image pixels and those with
+// q <= r^2, added atomically into out2 = (tested, active).
+__global__ __launch_bounds__(kThreads) void k_pair_stats(GridArgs g, const float* __restrict__ records,
+                                                         int rs, const int2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ vals,
+                                                         unsigned long long* __restrict__ out2) {
+  __shared__ unsigned long long s_act[kThreads / 64];
+  const int tile = blockIdx.x;
+  const int tx = tile % g.ntx, ty = tile / g.ntx;
+  const int u = tx * kTile + (threadIdx.x & 15);
+  const int v = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = u < g.W && v < g.H;
+  const float x = sample_coord(u, g.ox, g.inv_s);
+  const float y = sample_coord(v, g.oy, g.inv_s);
+  const int2 rg = ranges[tile];
+  unsigned long long act = 0;
+  for (int i = rg.x; i < rg.y && inside; ++i) {
+    const float* r = records + (size_t)vals[i] * rs;
+    const float dx = x - r[0];
+    const float dy = y - r[1];
+    const float z1 = dx * r[2];
+    const float tt = r[3] * z1;
+    const float w = dy - tt;
+    const float z2 = w * r[4];
+    const float q = z1 * z1 + z2 * z2;
+    act += (q <= g.r2) ? 1ull : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) act += __shfl_xor(act, off);
+  if ((threadIdx.x & 63) == 0) s_act[threadIdx.x >> 6] = act;
+  const unsigned long long n_in = inside ? 1ull : 0ull;
+  unsigned long long cnt = n_in;
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  __shared__ unsigned long long s_cnt[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long px = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    atomicAdd(&out2[0], px * (unsigned long long)(rg.y - rg.x));
+    atomicAdd(&out2[1], s_act[0] + s_act[1] + s_act[2] + s_act[3]);
+  }
+}
+
 template <int C, int ORDER>
 hipError_t launch(const RenderArgs& a, hipStream_t s) {
   k_render<C, ORDER><<<a.g.T, kThreads, 0, s>>>(a);
@@ -150,6 +192,17 @@ hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins
   if (m.C == 1 && m.order == 1) return launch<1, 1>(a, s);
   if (m.C == 3 && m.order == 0) return launch<3, 0>(a, s);
   return launch<3, 1>(a, s);
+}
+
+hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
+                             uint64_t* out2, hipStream_t s) {
+  (void)m;
+  hipError_t e = hipMemsetAsync(out2, 0, 2 * sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
+  k_pair_stats<<<g.T, kThreads, 0, s>>>(g, b.records, b.record_stride,
+                                        reinterpret_cast<const int2*>(b.ranges), b.vals,
+                                        reinterpret_cast<unsigned long long*>(out2));
+  return hipGetLastError();
 }
 
 hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,

@@ -92,6 +92,8 @@ __device__ __forceinline__ void gather_kernel_grads(int j, int ntx, const int4* 
 hipError_t launch_bin(const smoe_model& m, const GridArgs& g, const smoe_bins& b, hipStream_t s);
 hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* image,
                          float* denom, const float* target, hipStream_t s);
+hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
+                             uint64_t* out2, hipStream_t s);
 hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,
                               hipStream_t s);
 hipError_t launch_backward(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
