@@ -80,48 +80,88 @@ __global__ __launch_bounds__(128) void k_preprocess(int K, int C, int order,
 }
 
 // One workgroup: exclusive scan of the per-block counts into [begin, end) ranges, the total
-// P and the overflow flag; resets the counters to serve as scatter cursors.
+// P and the overflow flag; resets the counters to serve as scatter cursors.  Each pass
+// covers 16384 blocks: every thread holds 16 consecutive counts in registers (4 x int4
+// loads, contiguous across the wave), the thread totals are scanned with wave shuffles and
+// one exchange of the 16 wave totals through LDS, and a running carry links the passes.
 constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 16;
+__device__ __forceinline__ long long wave_incl_scan(long long x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long o = __shfl_up(x, off);
+    if (lane >= off) x += o;
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(int T, int32_t* __restrict__ tile_counts,
                                                        int2* __restrict__ ranges, int capacity,
                                                        int32_t* __restrict__ status) {
-  __shared__ long long s_sum[kScanThreads];
+  __shared__ long long s_wave[kScanThreads / 64];
   __shared__ int s_max[kScanThreads / 64];
-  const int tid = threadIdx.x;
-  const int per = (T + kScanThreads - 1) / kScanThreads;
-  const int b = min(T, tid * per), e = min(T, b + per);
-  long long sum = 0;
-  int mx = 0;
-  for (int t = b; t < e; ++t) {
-    const int c = tile_counts[t];
-    sum += c;
-    mx = max(mx, c);
-  }
-  s_sum[tid] = sum;
-  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
-  if ((tid & 63) == 0) s_max[tid >> 6] = mx;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const long long v = tid >= off ? s_sum[tid - off] : 0;
-    __syncthreads();
-    s_sum[tid] += v;
-    __syncthreads();
-  }
-  const long long P = s_sum[kScanThreads - 1];
-  const bool over = P > (long long)capacity;
-  long long off = s_sum[tid] - sum;
-  for (int t = b; t < e; ++t) {
-    const int c = tile_counts[t];
-    ranges[t] = over ? make_int2(0, 0) : make_int2((int)off, (int)(off + c));
-    off += c;
-    tile_counts[t] = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  long long carry = 0;
+  int mx_all = 0;
+  // First pass over all blocks computes P (needed before any range is written, so that an
+  // overflow writes every range empty); the second writes the ranges.
+  for (int write = 0; write < 2; ++write) {
+    const bool over = write && carry > (long long)capacity;
+    long long run = 0;
+    for (int base = 0; base < T; base += kScanThreads * kScanItems) {
+      const int b = base + tid * kScanItems;
+      int c[kScanItems];
+      if (b + kScanItems <= T) {
+        const int4* p4 = reinterpret_cast<const int4*>(tile_counts + b);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+          const int4 v = p4[q];
+          c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) c[q] = (b + q < T) ? tile_counts[b + q] : 0;
+      }
+      long long sum = 0;
+      int mx = 0;
+#pragma unroll
+      for (int q = 0; q < kScanItems; ++q) {
+        sum += c[q];
+        mx = max(mx, c[q]);
+      }
+      const long long incl = wave_incl_scan(sum, lane);
+      if (lane == 63) s_wave[wave] = incl;
+      for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+      if (lane == 0) s_max[wave] = mx;
+      __syncthreads();
+      long long wbase = 0, total = 0;
+      for (int w = 0; w < kScanThreads / 64; ++w) {
+        const long long t = s_wave[w];
+        if (w < wave) wbase += t;
+        total += t;
+      }
+      if (!write)
+        for (int w = 0; w < kScanThreads / 64; ++w) mx_all = max(mx_all, s_max[w]);
+      __syncthreads();
+      if (write) {
+        long long off = run + wbase + incl - sum;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+          if (b + q < T) {
+            ranges[b + q] = over ? make_int2(0, 0) : make_int2((int)off, (int)(off + c[q]));
+            tile_counts[b + q] = 0;
+          }
+          off += c[q];
+        }
+      }
+      run += total;
+    }
+    if (!write) carry = run;
   }
   if (tid == 0) {
-    int m = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) m = max(m, s_max[w]);
-    status[0] = (int)min(P, (long long)INT32_MAX);
-    status[1] = over ? 1 : 0;
-    status[2] = m;
+    status[0] = (int)min(carry, (long long)INT32_MAX);
+    status[1] = carry > (long long)capacity ? 1 : 0;
+    status[2] = mx_all;
     status[3] = 0;
   }
 }

@@ -84,32 +84,28 @@ struct AdamArgs {
   smoe_adam_config adam;
 };
 
-// One thread per kernel: its gradient row (sum of its block partials), Adam on each raw
-// parameter with the group's learning rate, and the new materialized row.
+// 16 lanes per kernel, lane i owning raw parameter i: its gradient (the sum of the
+// kernel's block partials), Adam with the group's learning rate, and the re-materialized
+// value.  Rows are read and written as contiguous 4*NP-byte runs.
 template <int NP>
-__global__ __launch_bounds__(128) void k_adam(AdamArgs a) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gid >> 4, i = gid & 15;
   if (j >= a.K || a.scalars[kSkip] != 0.0f) return;
-  float g[NP];
-  gather_kernel_grads<NP>(j, a.ntx, a.tile_rects, a.ranges, a.vals, a.pair_grads, g);
-  const float lr_mu = a.scalars[0];
-  const float bc1 = a.scalars[1], bc2 = a.scalars[2];
-  const float b1 = a.adam.beta1, b2 = a.adam.beta2, eps = a.adam.eps;
-  const size_t row = (size_t)j * NP;
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const float lr = i < 2 ? lr_mu : (i < 5 ? a.adam.lr_chol : (i == 5 ? a.adam.lr_rho
-                                                                       : a.adam.lr_expert));
-    const float gi = g[i];
-    const float mi = b1 * a.m[row + i] + (1.0f - b1) * gi;
-    const float vi = b2 * a.v[row + i] + (1.0f - b2) * gi * gi;
-    a.m[row + i] = mi;
-    a.v[row + i] = vi;
-    const float p = a.raw[row + i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-    a.raw[row + i] = p;
-    a.model[row + i] = (i == 2 || i == 4) ? expf(p) : p;
-    if (a.grads) a.grads[row + i] = gi;
-  }
+  const float gi = gather_param<NP>(j, i, a.ntx, a.tile_rects, a.ranges, a.vals, a.pair_grads);
+  if (i >= NP) return;
+  const float lr = i < 2 ? a.scalars[0]
+                         : (i < 5 ? a.adam.lr_chol : (i == 5 ? a.adam.lr_rho : a.adam.lr_expert));
+  const float b1 = a.adam.beta1, b2 = a.adam.beta2;
+  const size_t e = (size_t)j * NP + i;
+  const float mi = b1 * a.m[e] + (1.0f - b1) * gi;
+  const float vi = b2 * a.v[e] + (1.0f - b2) * gi * gi;
+  a.m[e] = mi;
+  a.v[e] = vi;
+  const float p = a.raw[e] - lr * (mi / a.scalars[1]) / (sqrtf(vi / a.scalars[2]) + a.adam.eps);
+  a.raw[e] = p;
+  a.model[e] = (i == 2 || i == 4) ? expf(p) : p;
+  if (a.grads) a.grads[e] = gi;
 }
 
 }  // namespace
@@ -147,11 +143,11 @@ hipError_t launch_adam(const smoe_fit_state& st, const GridArgs& g, hipStream_t 
              st.model,
              st.grads,
              st.adam};
-  const int blocks = (st.K + 127) / 128;
+  const int blocks = (int)(((long long)st.K * 16 + 255) / 256);
   const int NP = num_params(st.C, st.order);
-  if (NP == 7) k_adam<7><<<blocks, 128, 0, s>>>(a);
-  else if (NP == 9) k_adam<9><<<blocks, 128, 0, s>>>(a);  // (C, order) = (1, 1) or (3, 0)
-  else k_adam<15><<<blocks, 128, 0, s>>>(a);
+  if (NP == 7) k_adam<7><<<blocks, 256, 0, s>>>(a);
+  else if (NP == 9) k_adam<9><<<blocks, 256, 0, s>>>(a);  // (C, order) = (1, 1) or (3, 0)
+  else k_adam<15><<<blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

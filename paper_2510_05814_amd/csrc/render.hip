@@ -1,12 +1,14 @@
 // Forward rasterization of the SMoE regression (Eq. 3-5) on gfx950.
 //
-// One workgroup of 256 lanes (4 wave64) per 16x16 block, one output pixel per lane.  The
-// block's kernel list is staged through LDS in chunks of 256 render records (coalesced
-// float4 loads by the whole workgroup); every wave then reads each record with a
-// wave-uniform LDS address (a broadcast) and accumulates, in FP32 registers, the gate
-// denominator D = sum_j pi_j K_j(x) and the numerators N_c = sum_j pi_j K_j(x) m_jc(x)
-// in list order (increasing kernel id).  y_c = N_c / D.  No MFMA: there is no dense
-// contraction here, the work is FP32 VALU plus one v_exp_f32 per participating pair.
+// One wave (64 lanes) per 16x16 block.  Lane l owns column l & 15 and the four rows
+// (l >> 4) + 4i, i = 0..3, so the column-only terms of the exact truncation test (dx, z1,
+// l21 z1, z1^2) are computed once per kernel for four pixels.  The block's kernel list is
+// staged through LDS in chunks of 64 render records (coalesced float4 loads); the wave
+// reads each record with a uniform LDS address (a broadcast) and accumulates, in FP32
+// registers, the gate denominator D = sum_j pi_j K_j(x) and the numerators
+// N_c = sum_j pi_j K_j(x) m_jc(x) of each pixel in list order (increasing kernel id);
+// y_c = N_c / D.  No MFMA: there is no dense contraction here, the work is FP32 VALU plus
+// one v_exp_f32 per participating pair.
 //
 // Optional fused squared error against a target: each block writes its sum of squared
 // errors to tile_loss[block]; launch_loss_reduce() then reduces those in a fixed order.
@@ -15,7 +17,9 @@
 namespace smoe {
 namespace {
 
-constexpr int kThreads = kTilePixels;  // 256
+constexpr int kThreads = 64;                     // one wave per block
+constexpr int kChunk = 64;                       // records staged in LDS per chunk
+constexpr int kRows = kTilePixels / kThreads;    // pixels per lane (4)
 
 struct RenderArgs {
   GridArgs g;
@@ -28,91 +32,93 @@ struct RenderArgs {
   float* __restrict__ tile_loss;
 };
 
-// Stages records vals[base .. base+n) into LDS as float4 rows of RS/4.
-template <int RS>
-__device__ __forceinline__ void stage_records(float4* __restrict__ srec,
-                                              const float* __restrict__ records,
-                                              const uint32_t* __restrict__ vals, int base, int n) {
-  constexpr int Q = RS / 4;
-  for (int i = threadIdx.x; i < n * Q; i += kThreads) {
-    const int k = i / Q, c = i - k * Q;
-    const uint32_t j = vals[base + k];
-    srec[i] = reinterpret_cast<const float4*>(records + (size_t)j * RS)[c];
-  }
-}
-
 template <int C, int ORDER>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   constexpr int RS = record_stride(C, ORDER);
-  __shared__ float4 srec[kThreads * RS / 4];
-  __shared__ float sred[kThreads / 64];
+  constexpr int Q = RS / 4;
+  __shared__ float4 srec[kChunk * Q];
 
+  const int lane = threadIdx.x;
   const int tile = xcd_block(blockIdx.x, a.g.T);
   const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
-  const int u = tx * kTile + (threadIdx.x & 15);
-  const int v = ty * kTile + (threadIdx.x >> 4);
+  const int u = tx * kTile + (lane & 15);
   const float x = sample_coord(u, a.g.ox, a.g.inv_s);
-  const float y = sample_coord(v, a.g.oy, a.g.inv_s);
   const float r2 = a.g.r2;
   const int2 rg = a.ranges[tile];
-
-  float D = 0.0f;
-  float N[C];
+  float yv[kRows];
 #pragma unroll
-  for (int c = 0; c < C; ++c) N[c] = 0.0f;
+  for (int i = 0; i < kRows; ++i)
+    yv[i] = sample_coord(ty * kTile + (lane >> 4) + 4 * i, a.g.oy, a.g.inv_s);
 
-  for (int base = rg.x; base < rg.y; base += kThreads) {
-    const int n = min(kThreads, rg.y - base);
+  float D[kRows], N[kRows][C];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    D[i] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) N[i][c] = 0.0f;
+  }
+
+  for (int base = rg.x; base < rg.y; base += kChunk) {
+    const int n = min(kChunk, rg.y - base);
     __syncthreads();
-    stage_records<RS>(srec, a.records, a.vals, base, n);
+    for (int i = lane; i < n * Q; i += kThreads) {
+      const int k = i / Q, c = i - k * Q;
+      srec[i] = reinterpret_cast<const float4*>(a.records + (size_t)a.vals[base + k] * RS)[c];
+    }
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-      const float* r = reinterpret_cast<const float*>(&srec[k * (RS / 4)]);
-      // Truncation test: the binary32 sequence of the ABI contract (no contraction).
+      const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
+      // Truncation test: the binary32 sequence of the ABI contract (no contraction); the
+      // column terms are shared by the lane's four pixels.
       const float dx = x - r[0];
-      const float dy = y - r[1];
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
-      const float w = dy - tt;
-      const float z2 = w * r[4];
-      const float q = z1 * z1 + z2 * z2;
-      if (q <= r2) {
-        // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
-        const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
-        D += e;
+      const float zz1 = z1 * z1;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          float m = r[kRecExpert + c];
-          if (ORDER == 1) {
-            m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
-            m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+      for (int i = 0; i < kRows; ++i) {
+        const float dy = yv[i] - r[1];
+        const float w = dy - tt;
+        const float z2 = w * r[4];
+        const float q = zz1 + z2 * z2;
+        if (q <= r2) {
+          // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
+          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+          D[i] += e;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            float m = r[kRecExpert + c];
+            if (ORDER == 1) {
+              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
+              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+            }
+            N[i][c] = __builtin_fmaf(e, m, N[i][c]);
           }
-          N[c] = __builtin_fmaf(e, m, N[c]);
         }
       }
     }
   }
 
-  const bool inside = u < a.g.W && v < a.g.H;
   float err = 0.0f;
-  if (inside) {
-    const size_t p = (size_t)v * a.g.W + u;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const float yc = (D > 0.0f) ? N[c] / D : 0.0f;
-      a.image[p * C + c] = yc;
-      if (a.target) {
-        const float d = yc - a.target[p * C + c];
-        err = __builtin_fmaf(d, d, err);
+  for (int i = 0; i < kRows; ++i) {
+    const int v = ty * kTile + (lane >> 4) + 4 * i;
+    if (u < a.g.W && v < a.g.H) {
+      const size_t p = (size_t)v * a.g.W + u;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float yc = (D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f;
+        a.image[p * C + c] = yc;
+        if (a.target) {
+          const float d = yc - a.target[p * C + c];
+          err = __builtin_fmaf(d, d, err);
+        }
       }
+      if (a.denom) a.denom[p] = D[i];
     }
-    if (a.denom) a.denom[p] = D;
   }
   if (a.tile_loss) {
     for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = err;
-    __syncthreads();
-    if (threadIdx.x == 0) a.tile_loss[tile] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+    if (lane == 0) a.tile_loss[tile] = err;
   }
 }
 
@@ -136,11 +142,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
 
 // Diagnostic: per block, the tested (pixel, kernel) pairs of in-image pixels and those with
 // q <= r^2, added atomically into out2 = (tested, active).
-__global__ __launch_bounds__(kThreads) void k_pair_stats(GridArgs g, const float* __restrict__ records,
+constexpr int kStatThreads = kTilePixels;
+__global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const float* __restrict__ records,
                                                          int rs, const int2* __restrict__ ranges,
                                                          const uint32_t* __restrict__ vals,
                                                          unsigned long long* __restrict__ out2) {
-  __shared__ unsigned long long s_act[kThreads / 64];
+  __shared__ unsigned long long s_act[kStatThreads / 64];
   const int tile = blockIdx.x;
   const int tx = tile % g.ntx, ty = tile / g.ntx;
   const int u = tx * kTile + (threadIdx.x & 15);
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_stats(GridArgs g, const float
   const unsigned long long n_in = inside ? 1ull : 0ull;
   unsigned long long cnt = n_in;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-  __shared__ unsigned long long s_cnt[kThreads / 64];
+  __shared__ unsigned long long s_cnt[kStatThreads / 64];
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -199,7 +206,7 @@ hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_
   (void)m;
   hipError_t e = hipMemsetAsync(out2, 0, 2 * sizeof(uint64_t), s);
   if (e != hipSuccess) return e;
-  k_pair_stats<<<g.T, kThreads, 0, s>>>(g, b.records, b.record_stride,
+  k_pair_stats<<<g.T, kStatThreads, 0, s>>>(g, b.records, b.record_stride,
                                         reinterpret_cast<const int2*>(b.ranges), b.vals,
                                         reinterpret_cast<unsigned long long*>(out2));
   return hipGetLastError();

@@ -67,26 +67,25 @@ __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, i
   return (a < hi && vals[a] == j) ? a : -1;
 }
 
-// Sum of kernel j's per-block partial rows over its block rectangle in row-major order.
+// Gradient of parameter i of kernel j: the sum of its per-block partials over the kernel's
+// block rectangle in row-major order (a fixed order, so the result is reproducible).  Used
+// with 16 lanes per kernel, lane i reading element i of each partial row, so a group's
+// reads of one row are contiguous.
 template <int NP>
-__device__ __forceinline__ void gather_kernel_grads(int j, int ntx, const int4* __restrict__ rects,
-                                                    const int2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ vals,
-                                                    const float* __restrict__ pair_grads,
-                                                    float (&acc)[NP]) {
-#pragma unroll
-  for (int i = 0; i < NP; ++i) acc[i] = 0.0f;
+__device__ __forceinline__ float gather_param(int j, int i, int ntx, const int4* __restrict__ rects,
+                                              const int2* __restrict__ ranges,
+                                              const uint32_t* __restrict__ vals,
+                                              const float* __restrict__ pair_grads) {
+  float acc = 0.0f;
   const int4 rc = rects[j];
   for (int ty = rc.y; ty <= rc.w; ++ty)
     for (int tx = rc.x; tx <= rc.z; ++tx) {
       const int2 rg = ranges[ty * ntx + tx];
       if (rg.y <= rg.x) continue;
       const int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j);
-      if (p < 0) continue;
-      const float* row = pair_grads + (size_t)p * NP;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) acc[i] += row[i];
+      if (p >= 0 && i < NP) acc += pair_grads[(size_t)p * NP + i];
     }
+  return acc;
 }
 
 hipError_t launch_bin(const smoe_model& m, const GridArgs& g, const smoe_bins& b, hipStream_t s);
