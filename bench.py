@@ -6,8 +6,8 @@ of std 25/255) with K = 65536 linear-expert kernels initialised on a 256x256 gri
 (sigma 4 px), truncation radius 3, 16x16 blocks, Adam with the paper's learning rates.
 A step is one full iteration of the hot path: binning (box, block lists, ordering),
 forward render with the fused loss, backward, and the fused gradient-reduce/Adam/
-re-materialize update -- one smoe_fit_step call.  Inputs are resident in HBM before the
-timed region starts.
+re-materialize update -- one smoe_fit_step call; most timed steps replay from HIP graphs
+captured beforehand.  Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line.  Besides throughput it reports the roofline of the dominant kernel
 (its duration from HIP events recorded around it in every timed step), the oracle's CPU
@@ -49,9 +49,11 @@ OPS_ACTIVE_BWD = 52
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 
-STAGES = ["bin", "render", "loss", "backward", "adam"]
-KERNEL_NAMES = {"backward": "k_backward", "render": "k_render"}
+STAGES = ["bin", "render_backward", "adam"]
+DOMINANT = "render_backward"
+KERNEL_NAMES = {"render_backward": "k_fit_tile"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_fit2048.json")
+CALIB_BYTES = 1 << 30
 
 
 # ----------------------------------------------------------------------------- HIP events
@@ -96,8 +98,9 @@ def source_digest(files):
 
 
 KERNEL_SOURCES = {
-    "backward": ["paper_2510_05814_amd/csrc/backward.hip", "paper_2510_05814_amd/csrc/smoe_internal.h"],
-    "render": ["paper_2510_05814_amd/csrc/render.hip", "paper_2510_05814_amd/csrc/smoe_internal.h"],
+    "render_backward": ["paper_2510_05814_amd/csrc/fit.hip", "paper_2510_05814_amd/csrc/tile_math.h",
+                        "paper_2510_05814_amd/csrc/device_common.h",
+                        "paper_2510_05814_amd/csrc/smoe_internal.h"],
 }
 
 
@@ -167,52 +170,74 @@ def run(args):
 
     # per-stage profile of a few steps (not part of the timed region)
     nprof = 8
-    evs = ev.create(6 * nprof)
+    ne = len(STAGES) + 1
+    evs = ev.create(ne * nprof)
     for i in range(nprof):
-        _capi.smoe_fit_step_timed(st.c, st.target.data_ptr(), None, evs[6 * i:6 * i + 6], sh)
+        st.step_timed(evs[ne * i:ne * i + ne])
     torch.cuda.synchronize()
     stage_ms = {s: [] for s in STAGES}
     for i in range(nprof):
-        e = evs[6 * i:6 * i + 6]
+        e = evs[ne * i:ne * i + ne]
         for k, s in enumerate(STAGES):
             stage_ms[s].append(ev.elapsed_ms(e[k], e[k + 1]))
     ev.destroy(evs)
     stage_avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
-    dominant = max(("render", "backward"), key=lambda s: stage_avg[s])
+    dominant = DOMINANT
     dom_idx = STAGES.index(dominant)
 
-    # timed region: K steps, HIP events around the dominant kernel in every step
-    evs = ev.create(2 * args.steps)
+    # Timed region: K steps.  The first K - M replay from HIP graphs of up to 50 captured
+    # steps; the last M run eagerly with HIP events recorded around the dominant kernel on
+    # its launch stream (HIP does not time events recorded as graph nodes), which gives the
+    # kernel's average launch duration from inside the timed region.
+    m_ev = max(1, min(20, args.steps // 5))
+    n_graph = 0 if args.eager else args.steps - m_ev
+    m_ev = args.steps - n_graph
+    spg = max(1, min(n_graph, 50))
+    n_full, rem = divmod(n_graph, spg) if n_graph > 0 else (0, 0)
+    graph = st.capture(spg) if n_full else None
+    graph_rem = st.capture(rem) if rem else None
+    evs = ev.create(2 * m_ev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        e6 = [None] * 6
-        e6[dom_idx], e6[dom_idx + 1] = evs[2 * i], evs[2 * i + 1]
-        _capi.smoe_fit_step_timed(st.c, st.target.data_ptr(), None, e6, sh)
+    for _ in range(n_full):
+        st.replay(graph)
+    if graph_rem is not None:
+        st.replay(graph_rem)
+    for i in range(m_ev):
+        e4 = [None] * ne
+        e4[dom_idx], e4[dom_idx + 1] = evs[2 * i], evs[2 * i + 1]
+        st.step_timed(e4)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    dom_ms = [ev.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(args.steps)]
+    dom_ms = [ev.elapsed_ms(evs[2 * i], evs[2 * i + 1]) for i in range(m_ev)]
     ev.destroy(evs)
     elapsed = t1 - t0
     over, status = st.bins.read_status()
     if over:
         raise RuntimeError("pair capacity overflow inside the timed region")
 
-    # geometry at the end of the timed region
+    # geometry at the end of the timed region, from a standalone binning of the current model
+    # (the fit workspace already holds part of the next step's binning)
+    sb = smoe.bin(st.model, C, 1, st.grid)
+    _, sstat = sb.read_status()
     stats = torch.zeros(2, dtype=torch.int64, device="cuda")
     m = smoe.core.model_struct(st.model, C, 1)
-    _capi.smoe_pair_stats(m, st.grid, st.bins.c, stats.data_ptr(), sh)
+    _capi.smoe_pair_stats(m, st.grid, sb.c, stats.data_ptr(), sh)
     tested, active = [int(x) for x in stats.tolist()]
-    P = status[0]
+    P = sstat[0]
+    status = sstat
     T = smoe.tiles(W, H)
 
     dom_avg_s = float(np.mean(dom_ms)) * 1e-3
-    ops = tested * OPS_TESTED + active * (OPS_ACTIVE_BWD if dominant == "backward" else OPS_ACTIVE_FWD)
+    # the fused kernel tests every pair twice (forward, then the recomputing backward)
+    ops = tested * 2 * OPS_TESTED + active * (OPS_ACTIVE_FWD + OPS_ACTIVE_BWD)
     achieved = ops / dom_avg_s
     roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dominant], "achieved": achieved / 1e12,
                 "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (FP32 VALU lane-ops)",
                 "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                "avg_launch_ms": dom_avg_s * 1e3, "algorithmic_ops_per_launch": ops}
+                "avg_launch_ms": dom_avg_s * 1e3, "algorithmic_ops_per_launch": ops,
+                "duration_source": f"HIP events around the kernel in the last {m_ev} timed "
+                                   f"steps (eager); the other {n_graph} replay from graphs"}
     # HBM traffic per launch from committed rocprofv3 counters, if taken on this source
     try:
         with open(COUNTERS_FILE) as f:
@@ -242,13 +267,14 @@ def run(args):
         cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
         out["cpu_baseline"] = cb
     if args.copy_calibration:
-        # a plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
-        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
+        # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
+        a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = a.numel() * 4
+        out["copy_calibration_bytes"] = CALIB_BYTES
     print(json.dumps(out), flush=True)
 
 
@@ -269,32 +295,22 @@ def _rocpd_kernels(db_path):
 
 
 def _rocpd_counters(db_path, counter):
-    """{kernel name: [values per dispatch]} of one PMC counter in a rocprofv3 SQLite output."""
+    """{kernel name: [value per dispatch]} of one PMC counter in a rocprofv3 SQLite output
+    (rows of one dispatch, e.g. per shader-engine instances, are summed)."""
     import sqlite3
 
     con = sqlite3.connect(db_path)
-    out = {}
+    acc = {}
     try:
-        tabs = [r[0] for r in con.execute("select name from sqlite_master where type='view'")]
-        view = "counters_collection" if "counters_collection" in tabs else None
-        if view is None:
-            return out
-        cols = [r[1] for r in con.execute(f"pragma table_info({view})")]
-        name_col = "kernel_name" if "kernel_name" in cols else "name"
-        val_col = "value" if "value" in cols else "counter_value"
-        cn_col = "counter_name" if "counter_name" in cols else "counter"
-        disp = "dispatch_id" if "dispatch_id" in cols else None
-        q = f"select {name_col}, {cn_col}, {val_col}" + (f", {disp}" if disp else "") + f" from {view}"
-        acc = {}
-        for r in con.execute(q):
-            if r[1] != counter:
-                continue
-            key = (r[0], r[3] if disp else len(acc))
-            acc[key] = acc.get(key, 0.0) + float(r[2])   # sum over shader engines / instances
-        for (name, _), v in acc.items():
-            out.setdefault(name, []).append(v)
+        for name, disp, val in con.execute(
+                "select kernel_name, dispatch_id, value from counters_collection "
+                "where counter_name = ?", (counter,)):
+            acc[(name, disp)] = acc.get((name, disp), 0.0) + float(val)
     finally:
         con.close()
+    out = {}
+    for (name, _), v in acc.items():
+        out.setdefault(name, []).append(v)
     return out
 
 
@@ -323,10 +339,14 @@ def summarize_profile(prof_dir, cmd):
     def pick(d, key):
         return [x for k, v in d.items() if key in k for x in v]
 
-    copy_bytes = (64 << 20) * 4
-    cf, cw = pick(fetch, "direct_copy"), pick(write, "direct_copy")
-    f_scale = copy_bytes / (max(cf) * 1024.0) if cf else 1.0
-    w_scale = copy_bytes / (max(cw) * 1024.0) if cw else 1.0
+    copy_bytes = CALIB_BYTES
+    cf, cw = pick(fetch, "MulFunctor"), pick(write, "MulFunctor")
+    if not (cf and cw):
+        print("PMC runs lack the calibration kernel (profile with --copy-calibration); "
+              "counters not summarised", file=sys.stderr)
+        return
+    f_scale = copy_bytes / (max(cf) * 1024.0)
+    w_scale = copy_bytes / (max(cw) * 1024.0)
     out = {"calibration": {"copy_bytes": copy_bytes, "fetch_kib": max(cf) if cf else None,
                            "write_kib": max(cw) if cw else None, "fetch_scale": f_scale,
                            "write_scale": w_scale},
@@ -349,6 +369,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle CPU work")
+    ap.add_argument("--eager", action="store_true",
+                    help="no HIP graphs: every timed step is launched eagerly (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy of known size (for PMC byte counters)")
     ap.add_argument("--summarize-profile", metavar="DIR")

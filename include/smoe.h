@@ -102,7 +102,8 @@ typedef struct smoe_bins {
   uint32_t* vals_alt;      /* [capacity] scratch for very long block lists */
   float* pair_grads;       /* [capacity][NP] per-(block, kernel) gradient partials */
   float* tile_loss;        /* [max_tiles] per-block squared error */
-  int32_t* status;         /* [4]: pairs needed P, overflow flag, longest list, spare */
+  int32_t* status;         /* [8]: pairs needed P, overflow flag, longest list, spare,
+                              then internal counters (kept zero between calls) */
 } smoe_bins;
 
 /* Bytes of workspace needed for the given shape and limits (host only). */
@@ -172,6 +173,10 @@ typedef struct smoe_fit_state {
   float* denom;              /* [H][W] */
   float* loss_history;       /* [max_steps] loss before each update, or NULL */
   int32_t max_steps;
+  int32_t prepared;          /* host flag: 1 when the workspace already holds the block
+                                counts and ranges of `model` (each step leaves them for the
+                                next); set 0 for a fresh fit, a new workspace, or after
+                                changing raw/model outside smoe_fit_step */
   int32_t* step;             /* [1] completed steps */
   float* scalars;            /* [4] per-step scratch */
   smoe_bins bins;            /* laid out for (K, C, order) and this grid */
@@ -180,16 +185,22 @@ typedef struct smoe_fit_state {
 /* One fit iteration on `stream` with no host synchronisation: binning, forward render
  * with the fused squared-error loss, backward, then per kernel the deterministic
  * reduction of its block partials, the Adam update of the raw row and its
- * re-materialization.  loss_out (device float[1], may be NULL) and
- * loss_history[step] receive the loss before the update.  After a capacity overflow the
- * step changes nothing (the step counter included); smoe_read_status() reports it. */
+ * re-materialization.  The step runs as four kernels: the scan of the block counts into
+ * list ranges; the scatter into block buckets; one kernel that per 16x16 block orders the
+ * bucket, renders the block and runs its backward; and Adam, which also records the loss
+ * and computes the next step's boxes, records and block counts (so the first step,
+ * state->prepared == 0, computes those first and then sets state->prepared = 1).
+ * loss_out (device float[1], may be NULL) and loss_history[step] receive the loss before
+ * the update.  After a capacity overflow the step changes nothing (the step counter
+ * included); smoe_read_status() reports it.  image, denom and grads hold the last step's
+ * render, denominator and gradient. */
 smoe_status smoe_fit_step(smoe_fit_state* state, const float* target, float* loss_out,
                           void* stream);
 
 /* smoe_fit_step with HIP events recorded on `stream` at the stage boundaries, for timing:
- * stage_events[0] before binning, [1] after binning, [2] after the forward render,
- * [3] after the loss/step scalars, [4] after the backward, [5] after the Adam update.
- * stage_events is a host array of 6 hipEvent_t; NULL entries are not recorded. */
+ * stage_events[0] before binning, [1] after binning (scan and scatter), [2] after the fused
+ * per-block render + backward kernel, [3] after Adam (with the next step's binning front).
+ * stage_events is a host array of 4 hipEvent_t; NULL entries are not recorded. */
 smoe_status smoe_fit_step_timed(smoe_fit_state* state, const float* target, float* loss_out,
                                 void* const* stage_events, void* stream);
 

@@ -49,7 +49,8 @@ class SmoeFitState(ct.Structure):
     _fields_ = [("K", _i32), ("C", _i32), ("order", _i32), ("grid", SmoeGrid),
                 ("adam", SmoeAdamConfig), ("raw", _vp), ("adam_m", _vp), ("adam_v", _vp),
                 ("model", _vp), ("grads", _vp), ("image", _vp), ("denom", _vp),
-                ("loss_history", _vp), ("max_steps", _i32), ("step", _vp), ("scalars", _vp),
+                ("loss_history", _vp), ("max_steps", _i32), ("prepared", _i32), ("step", _vp),
+                ("scalars", _vp),
                 ("bins", SmoeBins)]
 
 
@@ -152,9 +153,9 @@ def smoe_fit_step(state: SmoeFitState, target_ptr, loss_ptr, stream):
                                                      stream))
 
 
-def smoe_fit_step_timed(state: SmoeFitState, target_ptr, loss_ptr, events6, stream):
-    """events6: six hipEvent_t handles (ints) or None entries."""
-    arr = (_vp * 6)(*[e or None for e in events6])
+def smoe_fit_step_timed(state: SmoeFitState, target_ptr, loss_ptr, events4, stream):
+    """events4: four hipEvent_t handles (ints) or None entries."""
+    arr = (_vp * 4)(*[e or None for e in events4])
     return _check("smoe_fit_step_timed",
                   lib.smoe_fit_step_timed(ct.byref(state), target_ptr, loss_ptr, arr, stream))
 

@@ -216,10 +216,61 @@ class FitState:
             self.K, self.C, self.order, self.grid, self.adam.c(), self.raw.data_ptr(),
             self.m.data_ptr(), self.v.data_ptr(), self.model.data_ptr(), self.grads.data_ptr(),
             self.image.data_ptr(), self.denom.data_ptr(), self.loss_history.data_ptr(),
-            self.max_steps, self.step_counter.data_ptr(), self.scalars.data_ptr(), self.bins.c)
+            self.max_steps, 0, self.step_counter.data_ptr(), self.scalars.data_ptr(), self.bins.c)
 
     def step(self, loss_out: torch.Tensor | None = None, stream=None):
         C.smoe_fit_step(self.c, self.target.data_ptr(), _ptr(loss_out), _stream(stream))
+
+    def step_timed(self, events4, stream=None):
+        """One step with hipEvent_t handles recorded at the stage boundaries (None = skip):
+        start, after binning, after the per-block render+backward kernel, after Adam."""
+        C.smoe_fit_step_timed(self.c, self.target.data_ptr(), None, events4, _stream(stream))
+
+    def capture(self, steps: int, events=None) -> "torch.cuda.CUDAGraph":
+        """Captures `steps` fit steps into one HIP graph (nothing runs during capture).
+        Each replay advances the fit by `steps` (the step counter lives on the device).
+        events: optional list of `steps` four-entry event lists for smoe_fit_step_timed.
+        A re-made workspace (grow_if_needed) invalidates the graph."""
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        prepared = self.c.prepared  # capture runs nothing: the device state is unchanged
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for i in range(steps):
+                    if events is None:
+                        self.step()
+                    else:
+                        self.step_timed(events[i])
+        torch.cuda.current_stream().wait_stream(side)
+        self.c.prepared = prepared
+        return g
+
+    def replay(self, graph: "torch.cuda.CUDAGraph"):
+        """Replays a graph from capture(); afterwards the workspace is prepared."""
+        graph.replay()
+        self.c.prepared = 1
+
+    def run_graphed(self, steps: int, steps_per_graph: int = 32, check_every: int = 4):
+        """Like run(), replaying captured graphs of steps_per_graph steps; re-captures after
+        a workspace re-size and finishes any remainder with eager steps."""
+        goal = self.steps_done() + steps
+        graph = None
+        while True:
+            todo = goal - self.steps_done()
+            if todo <= 0:
+                break
+            if todo < steps_per_graph:
+                for _ in range(todo):
+                    self.step()
+            else:
+                if graph is None:
+                    graph = self.capture(steps_per_graph)
+                for _ in range(min(check_every, todo // steps_per_graph)):
+                    self.replay(graph)
+            if self.grow_if_needed():
+                graph = None
+        return self
 
     def steps_done(self) -> int:
         return int(self.step_counter.item())

@@ -69,7 +69,7 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   L.vals_alt = o;   o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.pair_grads = o; o = align_up(o + (size_t)capacity * np * sizeof(float));
   L.tile_loss = o;  o = align_up(o + (size_t)max_tiles * sizeof(float));
-  L.status = o;     o = align_up(o + 4 * sizeof(int32_t));
+  L.status = o;     o = align_up(o + 8 * sizeof(int32_t));
   L.total = o;
   return L;
 }
@@ -183,22 +183,19 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
   if (st->max_steps < 0) return SMOE_ERR_INVALID;
   if (g.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const float inv_n = (float)(1.0 / ((double)g.W * g.H * st->C));
   auto mark = [&](int i) -> hipError_t {
     return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
   };
   hipError_t e = mark(0);
-  if (e == hipSuccess) e = launch_bin(m, g, st->bins, s);
+  if (e == hipSuccess && !st->prepared) e = launch_count(m, g, st->bins, s);
+  if (e == hipSuccess) e = launch_scan(g, st->bins, s, st->step);
+  if (e == hipSuccess) e = launch_scatter(m, g, st->bins, s);
   if (e == hipSuccess) e = mark(1);
-  if (e == hipSuccess) e = launch_render(m, g, st->bins, st->image, st->denom, target, s);
+  if (e == hipSuccess) e = launch_fit_tile(*st, g, target, s);
   if (e == hipSuccess) e = mark(2);
-  if (e == hipSuccess) e = launch_step_begin(*st, g, inv_n, loss_out, s);
+  if (e == hipSuccess) e = launch_adam_fit(*st, g, loss_out, s);
   if (e == hipSuccess) e = mark(3);
-  if (e == hipSuccess)
-    e = launch_backward(m, g, st->bins, st->image, st->denom, nullptr, target, s);
-  if (e == hipSuccess) e = mark(4);
-  if (e == hipSuccess) e = launch_adam(*st, g, s);
-  if (e == hipSuccess) e = mark(5);
+  if (e == hipSuccess) st->prepared = 1;
   return hip_status(e);
 }
 

@@ -1,0 +1,265 @@
+// Device building blocks shared by the standalone binning calls and the fused fit step:
+// the kernel box (Sec. IV-B), the render record, the per-block ordering of a bucket and the
+// block scan that turns per-block counts into list ranges (Sec. IV-C).  Internal header.
+#pragma once
+
+#include "smoe_internal.h"
+
+namespace smoe {
+
+// Status word holding the fit step counter as the step began (written by the scan).
+constexpr int kStepShadow = 4;
+
+// Output-pixel index range whose centres lie in [lo, hi] (output units), clamped to
+// [0, n-1]; false when empty.  NaN inputs give an empty range.
+__device__ __forceinline__ bool axis_range(float lo, float hi, int n, int& i0, int& i1) {
+  const float a = ceilf(lo - 0.5f);
+  const float b = floorf(hi - 0.5f);
+  const float last = (float)(n - 1);
+  if (!(a <= last) || !(b >= 0.0f)) return false;
+  i0 = (a < 0.0f) ? 0 : (int)a;
+  i1 = (b > last) ? n - 1 : (int)b;
+  return i0 <= i1;
+}
+
+// Block rectangle (tx0, ty0, tx1, ty1) of one kernel, (0, 0, -1, -1) when empty: the pixel
+// centres inside the square box of half-side R = r sqrt(lambda_max(L L^T)) around mu,
+// as the exact binary32 sequence of the ABI contract.
+__device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l11, float l21,
+                                                  float l22, const GridArgs& g) {
+  const float sxx = l11 * l11;
+  const float sxy = l11 * l21;
+  const float syy = l21 * l21 + l22 * l22;
+  const float h = 0.5f * (sxx + syy);
+  const float d = 0.5f * (sxx - syy);
+  const float lam = h + sqrtf(d * d + sxy * sxy);
+  const float R = g.r * sqrtf(lam);
+  const float fs = (float)g.scale;
+  const float X0 = (mux - R) * fs - (float)g.ox;
+  const float X1 = (mux + R) * fs - (float)g.ox;
+  const float Y0 = (muy - R) * fs - (float)g.oy;
+  const float Y1 = (muy + R) * fs - (float)g.oy;
+  int u0, u1, v0, v1;
+  const bool ok = axis_range(X0, X1, g.W, u0, u1) && axis_range(Y0, Y1, g.H, v0, v1);
+  return ok ? make_int4(u0 >> 4, v0 >> 4, u1 >> 4, v1 >> 4) : make_int4(0, 0, -1, -1);
+}
+
+__device__ __forceinline__ int rect_count(int4 rc) {
+  return rc.z < rc.x ? 0 : (rc.z - rc.x + 1) * (rc.w - rc.y + 1);
+}
+
+// One increment per covered block: the histogram of the block-id digit.
+__device__ __forceinline__ void count_blocks(int4 rc, int ntx, int32_t* __restrict__ tile_counts) {
+  for (int ty = rc.y; ty <= rc.w; ++ty)
+    for (int tx = rc.x; tx <= rc.z; ++tx) atomicAdd(&tile_counts[ty * ntx + tx], 1);
+}
+
+// Exclusive scan of per-block counts into [begin, end) ranges by one workgroup of NT
+// threads (NT = 1024), with P, the overflow flag and the longest list into status, and
+// the counters reset to zero (they serve as the scatter cursors).  Each pass covers a
+// chunk of 16*NT blocks: every thread holds 16 consecutive counts in registers (four
+// int4 loads, contiguous across the wave), thread totals are scanned with wave shuffles
+// and one exchange of wave totals, and the begins go through LDS so that ranges and
+// resets are stored with consecutive threads on consecutive blocks.  Rasters of at most
+// one chunk (16384 blocks, 2048^2 pixels) take a single pass; larger ones first sum all
+// counts (P must be known before any range is written, so that an overflow can write
+// every range empty).  s_begin: 16*NT ints; s_tot: NT/64 long longs.
+template <int NT>
+__device__ void block_scan_ranges(int T, int32_t* __restrict__ tile_counts,
+                                  int2* __restrict__ ranges, int capacity,
+                                  int32_t* __restrict__ status, int* s_begin, long long* s_tot) {
+  constexpr int ITEMS = 16;
+  constexpr int CHUNK = NT * ITEMS;
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int s_max[NW];
+  long long P = -1;  // unknown until summed
+  int longest = 0;
+  if (T > CHUNK) {
+    long long sum = 0;
+    int mx = 0;
+    for (int t0 = tid * 4; t0 < T; t0 += NT * 4) {
+      if (t0 + 4 <= T) {
+        const int4 v = *reinterpret_cast<const int4*>(tile_counts + t0);
+        sum += (long long)v.x + v.y + v.z + v.w;
+        mx = max(mx, max(max(v.x, v.y), max(v.z, v.w)));
+      } else {
+        for (int q = t0; q < T; ++q) {
+          sum += tile_counts[q];
+          mx = max(mx, tile_counts[q]);
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      sum += __shfl_xor(sum, off);
+      mx = max(mx, __shfl_xor(mx, off));
+    }
+    if (lane == 0) {
+      s_tot[wave] = sum;
+      s_max[wave] = mx;
+    }
+    __syncthreads();
+    P = 0;
+    for (int w = 0; w < NW; ++w) {
+      P += s_tot[w];
+      longest = max(longest, s_max[w]);
+    }
+    __syncthreads();
+  }
+  long long carry = 0;
+  bool over = P > (long long)capacity;
+  for (int base = 0; base < T; base += CHUNK) {
+    const int b = base + tid * ITEMS;
+    int c[ITEMS];
+    if (b + ITEMS <= T) {
+      const int4* p4 = reinterpret_cast<const int4*>(tile_counts + b);
+#pragma unroll
+      for (int q = 0; q < ITEMS / 4; ++q) {
+        const int4 v = p4[q];
+        c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) c[q] = (b + q < T) ? tile_counts[b + q] : 0;
+    }
+    long long local = 0;
+    int mx = 0;
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+      local += c[q];
+      mx = max(mx, c[q]);
+    }
+    long long incl = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+    if (lane == 63) s_tot[wave] = incl;
+    if (lane == 0) s_max[wave] = mx;
+    __syncthreads();
+    long long wbase = 0, ctot = 0;
+    for (int w = 0; w < NW; ++w) {
+      const long long t = s_tot[w];
+      if (w < wave) wbase += t;
+      ctot += t;
+    }
+    if (T <= CHUNK) {  // single pass: the chunk total is P
+      P = ctot;
+      over = P > (long long)capacity;
+      for (int w = 0; w < NW; ++w) longest = max(longest, s_max[w]);
+    }
+    // Begins relative to the chunk; they fit in int32 whenever ranges are written (P is
+    // then at most the int32 capacity).
+    long long run = wbase + incl - local;
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+      s_begin[tid * ITEMS + q] = (int)run;
+      run += c[q];
+    }
+    __syncthreads();
+    const int n = min(CHUNK, T - base);
+    for (int i = tid; i < n; i += NT) {
+      const int bg = (int)carry + s_begin[i];
+      const int en = (i + 1 < n) ? (int)carry + s_begin[i + 1] : (int)(carry + ctot);
+      ranges[base + i] = over ? make_int2(0, 0) : make_int2(bg, en);
+      tile_counts[base + i] = 0;
+    }
+    carry += ctot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    status[0] = (int)min(P, (long long)INT32_MAX);
+    status[1] = over ? 1 : 0;
+    status[2] = longest;
+  }
+}
+
+// The scan kernel's optional extra for the fit step: snapshot the step counter.
+__device__ __forceinline__ void snapshot_step(const int32_t* step, int32_t* status) {
+  if (step && threadIdx.x == 0) status[kStepShadow] = step[0];
+}
+
+// Sorts one bucket of n distinct kernel ids (seg[0, n)) ascending with the 64 lanes of one
+// wave: bitonic sort in LDS for runs of up to `run` ids (lds holds `run` u32), then
+// pairwise merges of sorted runs in global memory through alt[0, n) for longer buckets.
+// Only wave-level barriers are used (the caller's workgroup is this one wave).
+__device__ __forceinline__ void sort_bucket(uint32_t* __restrict__ seg, uint32_t* __restrict__ alt,
+                                            int n, uint32_t* lds, int run) {
+  const int lane = threadIdx.x & 63;
+  if (n <= 1) return;
+  for (int c0 = 0; c0 < n; c0 += run) {
+    const int m = min(run, n - c0);
+    int p2 = 1;
+    while (p2 < m) p2 <<= 1;
+    for (int i = lane; i < p2; i += 64) lds[i] = (i < m) ? seg[c0 + i] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = lane; i < p2; i += 64) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const uint32_t a = lds[i], c = lds[ixj];
+            if ((a > c) == ((i & k) == 0)) {
+              lds[i] = c;
+              lds[ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = lane; i < m; i += 64) seg[c0 + i] = lds[i];
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (n <= run) return;
+  // An element's output position is its index in its own run plus the number of smaller
+  // elements in the partner run.
+  uint32_t* src = seg;
+  uint32_t* dst = alt;
+  for (int width = run; width < n; width <<= 1) {
+    for (int i = lane; i < n; i += 64) {
+      const int r_i = i / width;
+      const int pair_lo = (r_i & ~1) * width;
+      const bool left = (r_i & 1) == 0;
+      const int o_lo = left ? min(n, pair_lo + width) : pair_lo;
+      const int o_hi = left ? min(n, pair_lo + 2 * width) : pair_lo + width;
+      const uint32_t v = src[i];
+      int lo = o_lo, hi = o_hi;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (src[mid] < v) lo = mid + 1;
+        else hi = mid;
+      }
+      dst[pair_lo + (i - r_i * width) + (lo - o_lo)] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+    uint32_t* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  if (src != seg) {
+    for (int i = lane; i < n; i += 64) seg[i] = src[i];
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Arguments the fit step's Adam kernel needs to record the loss and advance the step.
+struct StepScalarsArgs {
+  int32_t* step;
+  float* scalars;
+  float* loss_out;
+  float* loss_history;
+  int max_steps;
+  smoe_adam_config adam;
+};
+
+inline StepScalarsArgs make_step_scalars_args(const smoe_fit_state& st, float* loss_out) {
+  return StepScalarsArgs{st.step, st.scalars, loss_out, st.loss_history, st.max_steps, st.adam};
+}
+
+}  // namespace smoe

@@ -1,0 +1,297 @@
+// Fit-step kernels on gfx950 (Sec. VI-B: gradient descent with Adam on all kernel
+// parameters, the centre learning rate decaying exponentially).
+//
+// A fit step runs four kernels after the first: the scan of the block counters into list
+// ranges and the scatter into block buckets (binning.hip), then
+//   k_fit_tile: one wave per 16x16 block orders the block's bucket, renders the block
+//     (image, D, squared error) and runs the backward over the same list while the
+//     pixels' y, D and dL/dy are still in its registers -- the backward of a block needs
+//     only that block's pixels, so nothing round-trips through HBM between the two;
+//   k_adam_fit: per kernel, the sum of its block partials, Adam, re-materialization, and
+//     the next step's box, render record and block counts.
+// Cross-workgroup handoffs happen only at kernel boundaries: the 8 XCD L2 caches are not
+// coherent with each other, so a device-scope fence per workgroup would cost more than a
+// launch.  The step counter is read by every Adam workgroup and advanced by one: the scan
+// (the step's first kernel) copies it into a shadow status word that Adam reads, so the
+// single writer never races the readers.
+#include "tile_math.h"
+
+namespace smoe {
+namespace {
+
+struct FitTileArgs {
+  GridArgs g;
+  const float* __restrict__ records;
+  const int2* __restrict__ ranges;
+  uint32_t* __restrict__ vals;
+  uint32_t* __restrict__ vals_alt;
+  int32_t* __restrict__ cursors;
+  const float* __restrict__ target;
+  float* __restrict__ image;
+  float* __restrict__ denom;
+  float* __restrict__ tile_loss;
+  float* __restrict__ pair_grads;
+  float inv_n2;  // 2 / (W H C)
+};
+
+template <int C, int ORDER>
+__global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
+  constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
+  __shared__ float4 srec[LDS_FLOATS / 4];
+  const int tile = xcd_block(blockIdx.x, a.g.T);
+  const int2 rg = a.ranges[tile];
+  // Order the bucket (the scatter appended in arbitrary order) and reset its cursor.
+  if (threadIdx.x == 0) a.cursors[tile] = 0;
+  constexpr int run = LDS_FLOATS >= 1024 ? 1024 : (LDS_FLOATS >= 512 ? 512 : 256);
+  sort_bucket(a.vals + rg.x, a.vals_alt + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec),
+              run);
+
+  const PixelCoords px = lane_pixels(a.g, tile);
+  float D[kRows], N[kRows][C];
+  forward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, rg, srec, D, N);
+
+  PixelSeed<C> sd;
+  float err = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const int v = px.v0 + 4 * i;
+    sd.valid[i] = false;
+    sd.invD[i] = 0.0f;
+    sd.gy[i] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sd.g[i][c] = 0.0f;
+    if (px.u < a.g.W && v < a.g.H) {
+      const size_t p = (size_t)v * a.g.W + px.u;
+      const bool cov = D[i] > 0.0f;
+      const float invD = cov ? 1.0f / D[i] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float yc = cov ? N[i][c] / D[i] : 0.0f;
+        a.image[p * C + c] = yc;
+        const float d = yc - a.target[p * C + c];
+        err = __builtin_fmaf(d, d, err);
+        if (cov) {
+          sd.g[i][c] = d * a.inv_n2;
+          sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
+        }
+      }
+      a.denom[p] = D[i];
+      sd.valid[i] = cov;
+      sd.invD[i] = invD;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
+  if (threadIdx.x == 0) a.tile_loss[tile] = err;
+
+  backward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, rg, srec, true, sd, a.pair_grads);
+}
+
+struct AdamFitArgs {
+  int K;
+  GridArgs g;
+  const int4* __restrict__ tile_rects_in;
+  const int2* __restrict__ ranges;
+  const uint32_t* __restrict__ vals;
+  const float* __restrict__ pair_grads;
+  const float* __restrict__ tile_loss;
+  float inv_n;
+  int32_t* __restrict__ status;
+  StepScalarsArgs step;
+  float* __restrict__ raw;
+  float* __restrict__ m;
+  float* __restrict__ v;
+  float* __restrict__ model;
+  float* __restrict__ grads;
+  float* __restrict__ records;
+  int4* __restrict__ tile_rects_out;
+  int32_t* __restrict__ counts;
+  int32_t* __restrict__ tile_counts;
+};
+
+
+// Fit-step Adam fused with the next step's binning front end.  16 lanes per kernel: lane i
+// owns raw parameter i -- its gradient (the sum of the kernel's block partials), Adam with
+// the group's learning rate, the re-materialized value -- and writes field i of the new
+// render record; lane 0 also writes the new block rectangle and count and increments the
+// covered blocks' counters, which the next step scans.  Block 0 also reduces the
+// per-block squared errors into the loss.  After an overflow the parameters stay as they
+// are, but the binning front end still runs so that the state stays consistent.
+constexpr int kAdamThreads = 256;
+template <int C, int ORDER>
+__global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
+  constexpr int NP = num_params(C, ORDER);
+  constexpr int NE = expert_floats(C, ORDER);
+  constexpr int RS = record_stride(C, ORDER);
+  __shared__ int s_t0;
+  __shared__ float s_sc[3];
+  __shared__ float s_red[kAdamThreads / 64];
+  const bool skip = f.status[1] != 0;
+  const smoe_adam_config& ad = f.step.adam;
+  if (threadIdx.x == 0) {
+    const int t0 = f.status[kStepShadow];  // completed steps, copied by this step's scan
+    float lr_mu = ad.lr_mu;
+    if (ad.total_steps > 0 && ad.lr_mu > 0.0f && ad.lr_mu_final > 0.0f)
+      lr_mu = ad.lr_mu * powf(ad.lr_mu_final / ad.lr_mu, (float)t0 / (float)ad.total_steps);
+    s_t0 = t0;
+    s_sc[0] = lr_mu;
+    s_sc[1] = 1.0f - powf(ad.beta1, (float)(t0 + 1));
+    s_sc[2] = 1.0f - powf(ad.beta2, (float)(t0 + 1));
+  }
+  __syncthreads();
+  const int t0 = s_t0;
+  if (blockIdx.x == 0 && !skip) {
+    // Loss: the whole workgroup sums the per-block squared errors in a fixed order, four
+    // independent float4 streams per thread so that the loads overlap.
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int T4 = f.g.T >> 2;
+    const float4* tl4 = reinterpret_cast<const float4*>(f.tile_loss);
+    for (int q = threadIdx.x; q < T4; q += 4 * kAdamThreads) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int qq = q + u * kAdamThreads;
+        if (qq < T4) {
+          const float4 v = tl4[qq];
+          acc[u] += (v.x + v.y) + (v.z + v.w);
+        }
+      }
+    }
+    for (int t = (T4 << 2) + threadIdx.x; t < f.g.T; t += kAdamThreads) acc[0] += f.tile_loss[t];
+    float tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float sum = 0.0f;
+      for (int w = 0; w < kAdamThreads / 64; ++w) sum += s_red[w];
+      const float loss = sum * f.inv_n;
+      if (f.step.loss_out) f.step.loss_out[0] = loss;
+      if (f.step.loss_history && t0 < f.step.max_steps) f.step.loss_history[t0] = loss;
+    }
+  }
+
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gid >> 4, i = gid & 15;
+  const bool live = j < f.K;
+  float pm = 0.0f;  // materialized value of parameter i after the step
+  if (live && skip && i < NP) pm = f.model[(size_t)j * NP + i];
+  const float gi = (live && !skip) ? gather_param<NP>(j, i, f.g.ntx, f.tile_rects_in, f.ranges,
+                                                      f.vals, f.pair_grads)
+                                   : 0.0f;
+  if (live && !skip && i < NP) {
+    const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
+    const size_t e = (size_t)j * NP + i;
+    const float mi = ad.beta1 * f.m[e] + (1.0f - ad.beta1) * gi;
+    const float vi = ad.beta2 * f.v[e] + (1.0f - ad.beta2) * gi * gi;
+    f.m[e] = mi;
+    f.v[e] = vi;
+    const float p = f.raw[e] - lr * (mi / s_sc[1]) / (sqrtf(vi / s_sc[2]) + ad.eps);
+    f.raw[e] = p;
+    pm = (i == 2 || i == 4) ? expf(p) : p;
+    f.model[e] = pm;
+    if (f.grads) f.grads[e] = gi;
+  }
+  // The kernel's new row, shared inside its group of 16 lanes.
+  const float mux = __shfl(pm, 0, 16), muy = __shfl(pm, 1, 16), l11 = __shfl(pm, 2, 16);
+  const float l21 = __shfl(pm, 3, 16), l22 = __shfl(pm, 4, 16), rho = __shfl(pm, 5, 16);
+  const float prev = __shfl_up(pm, 1, 16);  // parameter i - 1
+  if (live) {
+    if (i < RS) {
+      const float i22 = 1.0f / l22;
+      float fld;
+      if (i == 0) fld = mux;
+      else if (i == 1) fld = muy;
+      else if (i == 2) fld = 1.0f / l11;
+      else if (i == 3) fld = l21;
+      else if (i == 4) fld = i22;
+      else if (i == 5) fld = rho * kLog2e;
+      else if (i == 6) fld = l21 * i22;
+      else if (i < kRecExpert + NE) fld = prev;
+      else fld = 0.0f;
+      f.records[(size_t)j * RS + i] = fld;
+    }
+    if (i == 0) {
+      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, f.g);
+      f.tile_rects_out[j] = rc;
+      f.counts[j] = rect_count(rc);
+      count_blocks(rc, f.g.ntx, f.tile_counts);
+    }
+  }
+  // The counter itself is written once; every workgroup read the shadow copy instead.
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !skip) f.step.step[0] = t0 + 1;
+}
+
+__global__ __launch_bounds__(128) void k_materialize(int n_rows, int NP,
+                                                     const float* __restrict__ raw,
+                                                     float* __restrict__ model) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows * NP) return;
+  const int k = i % NP;
+  const float x = raw[i];
+  model[i] = (k == 2 || k == 4) ? expf(x) : x;
+}
+
+}  // namespace
+
+hipError_t launch_fit_tile(const smoe_fit_state& st, const GridArgs& g, const float* target,
+                           hipStream_t s) {
+  const smoe_bins& b = st.bins;
+  FitTileArgs a{g,
+                b.records,
+                reinterpret_cast<const int2*>(b.ranges),
+                b.vals,
+                b.vals_alt,
+                b.tile_counts,
+                target,
+                st.image,
+                st.denom,
+                b.tile_loss,
+                b.pair_grads,
+                2.0f / ((float)g.W * (float)g.H * (float)st.C)};
+  if (st.C == 1 && st.order == 0) k_fit_tile<1, 0><<<g.T, kWave, 0, s>>>(a);
+  else if (st.C == 1 && st.order == 1) k_fit_tile<1, 1><<<g.T, kWave, 0, s>>>(a);
+  else if (st.C == 3 && st.order == 0) k_fit_tile<3, 0><<<g.T, kWave, 0, s>>>(a);
+  else k_fit_tile<3, 1><<<g.T, kWave, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_fit(const smoe_fit_state& st, const GridArgs& g, float* loss_out,
+                           hipStream_t s) {
+  const smoe_bins& b = st.bins;
+  AdamFitArgs f{st.K,
+                g,
+                reinterpret_cast<const int4*>(b.tile_rects),
+                reinterpret_cast<const int2*>(b.ranges),
+                b.vals,
+                b.pair_grads,
+                b.tile_loss,
+                (float)(1.0 / ((double)g.W * g.H * st.C)),
+                b.status,
+                make_step_scalars_args(st, loss_out),
+                st.raw,
+                st.adam_m,
+                st.adam_v,
+                st.model,
+                st.grads,
+                b.records,
+                reinterpret_cast<int4*>(b.tile_rects),
+                b.counts,
+                b.tile_counts};
+  // at least one workgroup, so that the loss and the step counter advance even for K = 0
+  const int blocks = max(1, (int)(((long long)st.K * 16 + kAdamThreads - 1) / kAdamThreads));
+  if (st.C == 1 && st.order == 0) k_adam_fit<1, 0><<<blocks, kAdamThreads, 0, s>>>(f);
+  else if (st.C == 1 && st.order == 1) k_adam_fit<1, 1><<<blocks, kAdamThreads, 0, s>>>(f);
+  else if (st.C == 3 && st.order == 0) k_adam_fit<3, 0><<<blocks, kAdamThreads, 0, s>>>(f);
+  else k_adam_fit<3, 1><<<blocks, kAdamThreads, 0, s>>>(f);
+  return hipGetLastError();
+}
+
+hipError_t launch_materialize(int K, int C, int order, const float* raw, float* model,
+                              hipStream_t s) {
+  const int NP = num_params(C, order);
+  const long long n = (long long)K * NP;
+  if (n == 0) return hipSuccess;
+  k_materialize<<<(int)((n + 127) / 128), 128, 0, s>>>(K, NP, raw, model);
+  return hipGetLastError();
+}
+
+}  // namespace smoe

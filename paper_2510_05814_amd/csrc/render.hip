@@ -1,10 +1,8 @@
-// Forward rasterization of the SMoE regression (Eq. 3-5) on gfx950.
+// Forward rasterization of the SMoE regression (Eq. 3-5) on gfx950: the standalone render.
 //
-// One wave (64 lanes) per 16x16 block.  Lane l owns column l & 15 and the four rows
-// (l >> 4) + 4i, i = 0..3, so the column-only terms of the exact truncation test (dx, z1,
-// l21 z1, z1^2) are computed once per kernel for four pixels.  The block's kernel list is
-// staged through LDS in chunks of 64 render records (coalesced float4 loads); the wave
-// reads each record with a uniform LDS address (a broadcast) and accumulates, in FP32
+// One wave (64 lanes) per 16x16 block (lane layout in tile_math.h).  The block's kernel
+// list is staged through LDS in chunks of 64 render records (coalesced float4 loads); the
+// wave reads each record with a uniform LDS address (a broadcast) and accumulates, in FP32
 // registers, the gate denominator D = sum_j pi_j K_j(x) and the numerators
 // N_c = sum_j pi_j K_j(x) m_jc(x) of each pixel in list order (increasing kernel id);
 // y_c = N_c / D.  No MFMA: there is no dense contraction here, the work is FP32 VALU plus
@@ -12,14 +10,10 @@
 //
 // Optional fused squared error against a target: each block writes its sum of squared
 // errors to tile_loss[block]; launch_loss_reduce() then reduces those in a fixed order.
-#include "smoe_internal.h"
+#include "tile_math.h"
 
 namespace smoe {
 namespace {
-
-constexpr int kThreads = 64;                     // one wave per block
-constexpr int kChunk = 64;                       // records staged in LDS per chunk
-constexpr int kRows = kTilePixels / kThreads;    // pixels per lane (4)
 
 struct RenderArgs {
   GridArgs g;
@@ -33,77 +27,18 @@ struct RenderArgs {
 };
 
 template <int C, int ORDER>
-__global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
-  constexpr int RS = record_stride(C, ORDER);
-  constexpr int Q = RS / 4;
-  __shared__ float4 srec[kChunk * Q];
-
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
+  __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
   const int tile = xcd_block(blockIdx.x, a.g.T);
-  const int tx = tile % a.g.ntx, ty = tile / a.g.ntx;
-  const int u = tx * kTile + (lane & 15);
-  const float x = sample_coord(u, a.g.ox, a.g.inv_s);
-  const float r2 = a.g.r2;
-  const int2 rg = a.ranges[tile];
-  float yv[kRows];
-#pragma unroll
-  for (int i = 0; i < kRows; ++i)
-    yv[i] = sample_coord(ty * kTile + (lane >> 4) + 4 * i, a.g.oy, a.g.inv_s);
-
+  const PixelCoords px = lane_pixels(a.g, tile);
   float D[kRows], N[kRows][C];
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    D[i] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < C; ++c) N[i][c] = 0.0f;
-  }
-
-  for (int base = rg.x; base < rg.y; base += kChunk) {
-    const int n = min(kChunk, rg.y - base);
-    __syncthreads();
-    for (int i = lane; i < n * Q; i += kThreads) {
-      const int k = i / Q, c = i - k * Q;
-      srec[i] = reinterpret_cast<const float4*>(a.records + (size_t)a.vals[base + k] * RS)[c];
-    }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-      const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      // Truncation test: the binary32 sequence of the ABI contract (no contraction); the
-      // column terms are shared by the lane's four pixels.
-      const float dx = x - r[0];
-      const float z1 = dx * r[2];
-      const float tt = r[3] * z1;
-      const float zz1 = z1 * z1;
-#pragma unroll
-      for (int i = 0; i < kRows; ++i) {
-        const float dy = yv[i] - r[1];
-        const float w = dy - tt;
-        const float z2 = w * r[4];
-        const float q = zz1 + z2 * z2;
-        if (q <= r2) {
-          // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
-          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
-          D[i] += e;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            float m = r[kRecExpert + c];
-            if (ORDER == 1) {
-              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
-              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
-            }
-            N[i][c] = __builtin_fmaf(e, m, N[i][c]);
-          }
-        }
-      }
-    }
-  }
-
+  forward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, a.ranges[tile], srec, D, N);
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
-    const int v = ty * kTile + (lane >> 4) + 4 * i;
-    if (u < a.g.W && v < a.g.H) {
-      const size_t p = (size_t)v * a.g.W + u;
+    const int v = px.v0 + 4 * i;
+    if (px.u < a.g.W && v < a.g.H) {
+      const size_t p = (size_t)v * a.g.W + px.u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const float yc = (D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f;
@@ -118,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   }
   if (a.tile_loss) {
     for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
-    if (lane == 0) a.tile_loss[tile] = err;
+    if (threadIdx.x == 0) a.tile_loss[tile] = err;
   }
 }
 
@@ -144,10 +79,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
 // q <= r^2, added atomically into out2 = (tested, active).
 constexpr int kStatThreads = kTilePixels;
 __global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const float* __restrict__ records,
-                                                         int rs, const int2* __restrict__ ranges,
-                                                         const uint32_t* __restrict__ vals,
-                                                         unsigned long long* __restrict__ out2) {
+                                                             int rs, const int2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ vals,
+                                                             unsigned long long* __restrict__ out2) {
   __shared__ unsigned long long s_act[kStatThreads / 64];
+  __shared__ unsigned long long s_cnt[kStatThreads / 64];
   const int tile = blockIdx.x;
   const int tx = tile % g.ntx, ty = tile / g.ntx;
   const int u = tx * kTile + (threadIdx.x & 15);
@@ -168,13 +104,15 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const f
     const float q = z1 * z1 + z2 * z2;
     act += (q <= g.r2) ? 1ull : 0ull;
   }
-  for (int off = 32; off > 0; off >>= 1) act += __shfl_xor(act, off);
-  if ((threadIdx.x & 63) == 0) s_act[threadIdx.x >> 6] = act;
-  const unsigned long long n_in = inside ? 1ull : 0ull;
-  unsigned long long cnt = n_in;
-  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-  __shared__ unsigned long long s_cnt[kStatThreads / 64];
-  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+  unsigned long long cnt = inside ? 1ull : 0ull;
+  for (int off = 32; off > 0; off >>= 1) {
+    act += __shfl_xor(act, off);
+    cnt += __shfl_xor(cnt, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_act[threadIdx.x >> 6] = act;
+    s_cnt[threadIdx.x >> 6] = cnt;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long px = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
@@ -183,10 +121,8 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const f
   }
 }
 
-template <int C, int ORDER>
-hipError_t launch(const RenderArgs& a, hipStream_t s) {
-  k_render<C, ORDER><<<a.g.T, kThreads, 0, s>>>(a);
-  return hipGetLastError();
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 }  // namespace
@@ -195,20 +131,20 @@ hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins
                          float* denom, const float* target, hipStream_t s) {
   RenderArgs a{g,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
                target, target ? b.tile_loss : nullptr};
-  if (m.C == 1 && m.order == 0) return launch<1, 0>(a, s);
-  if (m.C == 1 && m.order == 1) return launch<1, 1>(a, s);
-  if (m.C == 3 && m.order == 0) return launch<3, 0>(a, s);
-  return launch<3, 1>(a, s);
+  if (m.C == 1 && m.order == 0) k_render<1, 0><<<g.T, kWave, 0, s>>>(a);
+  else if (m.C == 1 && m.order == 1) k_render<1, 1><<<g.T, kWave, 0, s>>>(a);
+  else if (m.C == 3 && m.order == 0) k_render<3, 0><<<g.T, kWave, 0, s>>>(a);
+  else k_render<3, 1><<<g.T, kWave, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
                              uint64_t* out2, hipStream_t s) {
   (void)m;
-  hipError_t e = hipMemsetAsync(out2, 0, 2 * sizeof(uint64_t), s);
-  if (e != hipSuccess) return e;
+  k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(out2), 2);
   k_pair_stats<<<g.T, kStatThreads, 0, s>>>(g, b.records, b.record_stride,
-                                        reinterpret_cast<const int2*>(b.ranges), b.vals,
-                                        reinterpret_cast<unsigned long long*>(out2));
+                                            reinterpret_cast<const int2*>(b.ranges), b.vals,
+                                            reinterpret_cast<unsigned long long*>(out2));
   return hipGetLastError();
 }
 

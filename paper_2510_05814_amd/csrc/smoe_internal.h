@@ -89,6 +89,21 @@ __device__ __forceinline__ float gather_param(int j, int i, int ntx, const int4*
 }
 
 hipError_t launch_bin(const smoe_model& m, const GridArgs& g, const smoe_bins& b, hipStream_t s);
+// Fit-step pieces: block counters, boxes and records of the current model (fill,
+// preprocess); the scan of the counters into ranges; the scatter into buckets; the fused
+// per-block sort + render + backward; Adam fused with the next step's boxes, records and
+// counters.
+hipError_t launch_count(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
+                        hipStream_t s);
+// fit_step (the fit step only): the step counter to snapshot for the step's Adam kernel.
+hipError_t launch_scan(const GridArgs& g, const smoe_bins& b, hipStream_t s,
+                       const int32_t* fit_step = nullptr);
+hipError_t launch_scatter(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
+                          hipStream_t s);
+hipError_t launch_fit_tile(const smoe_fit_state& st, const GridArgs& g, const float* target,
+                           hipStream_t s);
+hipError_t launch_adam_fit(const smoe_fit_state& st, const GridArgs& g, float* loss_out,
+                           hipStream_t s);
 hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* image,
                          float* denom, const float* target, hipStream_t s);
 hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
@@ -102,8 +117,5 @@ hipError_t launch_gather(const smoe_model& m, const GridArgs& g, const smoe_bins
                          hipStream_t s);
 hipError_t launch_materialize(int K, int C, int order, const float* raw, float* model,
                               hipStream_t s);
-hipError_t launch_step_begin(const smoe_fit_state& st, const GridArgs& g, float inv_n,
-                             float* loss_out, hipStream_t s);
-hipError_t launch_adam(const smoe_fit_state& st, const GridArgs& g, hipStream_t s);
 
 }  // namespace smoe

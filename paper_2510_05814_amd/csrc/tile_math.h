@@ -1,0 +1,241 @@
+// Per-block math of the rasterized SMoE on gfx950, shared by the standalone render and
+// backward calls and the fused fit-step kernel.  Internal header.
+//
+// Lane layout: one wave per 16x16 block; lane l owns column l & 15 and the four rows
+// (l >> 4) + 4i, i = 0..3.  The column-only terms of the exact truncation test (dx, z1,
+// l21 z1, z1^2) are then computed once per kernel for the lane's four pixels, and a wave
+// iteration i covers one 16x4 strip of the block.
+#pragma once
+
+#include "device_common.h"
+
+namespace smoe {
+
+constexpr int kWave = 64;
+constexpr int kChunk = 64;                     // records staged in LDS per chunk
+constexpr int kRows = kTilePixels / kWave;     // pixels per lane (4)
+
+struct PixelCoords {
+  int u;            // output column of the lane
+  int v0;           // output row of the lane's first pixel (rows v0 + 4i)
+  float x;          // sampling coordinates
+  float y[kRows];
+};
+
+__device__ __forceinline__ PixelCoords lane_pixels(const GridArgs& g, int tile) {
+  PixelCoords p;
+  const int lane = threadIdx.x & 63;
+  const int tx = tile % g.ntx, ty = tile / g.ntx;
+  p.u = tx * kTile + (lane & 15);
+  p.v0 = ty * kTile + (lane >> 4);
+  p.x = sample_coord(p.u, g.ox, g.inv_s);
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) p.y[i] = sample_coord(p.v0 + 4 * i, g.oy, g.inv_s);
+  return p;
+}
+
+// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS.
+template <int RS>
+__device__ __forceinline__ void stage_records(float4* __restrict__ srec,
+                                              const float* __restrict__ records,
+                                              const uint32_t* __restrict__ vals, int base, int n) {
+  constexpr int Q = RS / 4;
+  __syncthreads();
+  for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
+    const int k = i / Q, c = i - k * Q;
+    srec[i] = reinterpret_cast<const float4*>(records + (size_t)vals[base + k] * RS)[c];
+  }
+  __syncthreads();
+}
+
+// Forward accumulation over a block's list [rg.x, rg.y) in list order:
+// D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers).
+template <int C, int ORDER>
+__device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
+                                                   const float* __restrict__ records,
+                                                   const uint32_t* __restrict__ vals, int2 rg,
+                                                   float4* srec, float (&D)[kRows],
+                                                   float (&N)[kRows][C]) {
+  constexpr int RS = record_stride(C, ORDER);
+  constexpr int Q = RS / 4;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    D[i] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) N[i][c] = 0.0f;
+  }
+  for (int base = rg.x; base < rg.y; base += kChunk) {
+    const int n = min(kChunk, rg.y - base);
+    stage_records<RS>(srec, records, vals, base, n);
+    for (int k = 0; k < n; ++k) {
+      const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
+      // Truncation test: the binary32 sequence of the ABI contract (no contraction).
+      const float dx = px.x - r[0];
+      const float z1 = dx * r[2];
+      const float tt = r[3] * z1;
+      const float zz1 = z1 * z1;
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        const float dy = px.y[i] - r[1];
+        const float w = dy - tt;
+        const float z2 = w * r[4];
+        const float q = zz1 + z2 * z2;
+        if (q <= r2) {
+          // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
+          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+          D[i] += e;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            float m = r[kRecExpert + c];
+            if (ORDER == 1) {
+              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
+              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+            }
+            N[i][c] = __builtin_fmaf(e, m, N[i][c]);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Transposed wave reduction of 16 values: on return lane l holds the sum over all 64 lanes
+// of v[(l >> 2) & 15].  Each stage pairs every lane with one whose index differs in the next
+// bit (5, 4, 3, 2); a lane keeps the half of its values selected by that bit and adds the
+// partner's copy of the same half, halving the values per lane.  Bits 1 and 0 are then a
+// plain butterfly.  About 40 instructions for 16 sums instead of 6 per sum.
+__device__ __forceinline__ float wave_reduce16_transposed(float (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  // bit 5: v_permlane32_swap exchanges lanes 32-63 of its first operand with lanes 0-31 of
+  // its second, so (a + b) of the two results holds sum(v[i]) in the low half and
+  // sum(v[i + 8]) in the high half.
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]),
+                                                    false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // bit 4: v_permlane16_swap exchanges the odd 16-lane rows of its first operand with the
+  // even rows of its second.
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]),
+                                                    false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // bit 3: DPP row_ror:8 pairs lane l with l ^ 8 inside each row of 16.
+  const bool b3 = (lane & 8) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = b3 ? v[i + 2] : v[i];
+    const float send = b3 ? v[i] : v[i + 2];
+    v[i] = keep + dpp<0x128>(send);
+  }
+  // bit 2: DPP row_half_mirror pairs lane l with 7 - l inside each group of 8.
+  const bool b2 = (lane & 4) != 0;
+  {
+    const float keep = b2 ? v[1] : v[0];
+    const float send = b2 ? v[0] : v[1];
+    v[0] = keep + dpp<0x141>(send);
+  }
+  v[0] += dpp<0x4E>(v[0]);  // quad_perm [2, 3, 0, 1]: bit 1
+  v[0] += dpp<0xB1>(v[0]);  // quad_perm [1, 0, 3, 2]: bit 0
+  return v[0];
+}
+
+// Adjoint seed of one pixel: dL/dy (g), 1/D, sum_c g_c y_c; `valid` false where D = 0 or the
+// pixel lies outside the raster (no gradient flows there).
+template <int C>
+struct PixelSeed {
+  float g[kRows][C];
+  float invD[kRows];
+  float gy[kRows];
+  bool valid[kRows];
+};
+
+// Backward over a block's list [rg.x, rg.y): for every kernel the wave forms, per pixel, the
+// adjoints of its 6 + 3C raw parameters (recomputing pi K from the record, w = pi K / D),
+// sums them over the block's 256 pixels with the transposed reduction, and writes the
+// per-(block, kernel) partial row pair_grads[list position].  `staged`: the records of a
+// single-chunk list are already in srec (the fused fit kernel rendered from them).
+//   G = sum_c g_c (m_c - y_c),  H = w G                       (dL/drho)
+//   dL/da_c = g_c w,  dL/dwx_c = g_c w dx,  dL/dwy_c = g_c w dy
+//   bz2 = -H z2,  bz1 = -H z1 - bz2 l21/l22                  (through q = z1^2 + z2^2)
+//   dL/dmu_x = -(bz1/l11 + sum_c g_c w wx_c),  dL/dmu_y = -(bz2/l22 + sum_c g_c w wy_c)
+//   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
+template <int C, int ORDER>
+__device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
+                                                    const float* __restrict__ records,
+                                                    const uint32_t* __restrict__ vals, int2 rg,
+                                                    float4* srec, bool staged,
+                                                    const PixelSeed<C>& sd,
+                                                    float* __restrict__ pair_grads) {
+  constexpr int RS = record_stride(C, ORDER);
+  constexpr int Q = RS / 4;
+  constexpr int NP = num_params(C, ORDER);
+  static_assert(NP <= 16, "16 accumulators per kernel");
+  const int lane = threadIdx.x & 63;
+  for (int base = rg.x; base < rg.y; base += kChunk) {
+    const int n = min(kChunk, rg.y - base);
+    if (!staged || rg.y - rg.x > kChunk) stage_records<RS>(srec, records, vals, base, n);
+    for (int k = 0; k < n; ++k) {
+      const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
+      float acc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+      const float dx = px.x - r[0];
+      const float z1 = dx * r[2];
+      const float tt = r[3] * z1;
+      const float zz1 = z1 * z1;
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        const float dy = px.y[i] - r[1];
+        const float w_ = dy - tt;
+        const float z2 = w_ * r[4];
+        const float q = zz1 + z2 * z2;
+        if (sd.valid[i] && q <= r2) {
+          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+          const float w = e * sd.invD[i];
+          float Gs = -sd.gy[i];
+          float ex = 0.0f, ey = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            float m = r[kRecExpert + c];
+            if (ORDER == 1) {
+              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
+              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+            }
+            Gs = __builtin_fmaf(sd.g[i][c], m, Gs);
+            const float gw = sd.g[i][c] * w;
+            acc[6 + c] += gw;
+            if (ORDER == 1) {
+              acc[6 + C + c] = __builtin_fmaf(gw, dx, acc[6 + C + c]);
+              acc[6 + 2 * C + c] = __builtin_fmaf(gw, dy, acc[6 + 2 * C + c]);
+              ex = __builtin_fmaf(gw, r[kRecExpert + C + c], ex);
+              ey = __builtin_fmaf(gw, r[kRecExpert + 2 * C + c], ey);
+            }
+          }
+          const float Hh = w * Gs;
+          const float bz2 = -Hh * z2;
+          const float bz1 = __builtin_fmaf(-bz2, r[6], -Hh * z1);
+          acc[0] -= __builtin_fmaf(bz1, r[2], ex);
+          acc[1] -= __builtin_fmaf(bz2, r[4], ey);
+          acc[2] = __builtin_fmaf(-bz1, z1, acc[2]);
+          acc[3] = __builtin_fmaf(-bz2 * z1, r[4], acc[3]);
+          acc[4] = __builtin_fmaf(-bz2, z2, acc[4]);
+          acc[5] += Hh;
+        }
+      }
+      const float tot = wave_reduce16_transposed(acc);
+      const int idx = lane >> 2;
+      if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = tot;
+    }
+  }
+}
+
+}  // namespace smoe

@@ -1,0 +1,95 @@
+"""The autograd.Function path: gradients against the FP64 oracle and against the fused fit
+step; it composes with torch optimizers and upstream gradients of any loss."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_autograd_mse_gradient_matches_oracle(record_error):
+    import torch
+
+    from paper_2510_05814_amd.autograd import smoe_render
+    print("[case] autograd vs oracle, crop", flush=True)
+    tgt, raw = wl.fd_crop_case(seed=17)
+    H, W, C = tgt.shape
+    r = _dev(raw).requires_grad_(True)
+    img = smoe_render(r, C, 1, W, H)
+    loss = torch.mean((img - _dev(tgt)) ** 2)
+    loss.backward()
+    model = oracle.materialize(raw.astype(np.float64), C, 1)
+    l_o, g_o = oracle.loss_grad(model, C, 1, W, H, target=tgt)
+    g = r.grad.cpu().numpy()
+    assert abs(loss.item() - l_o) <= 1e-5 * l_o
+    err = np.max(np.abs(g - g_o)) / np.max(np.abs(g_o))
+    record_error("autograd grad rel (all params)", err, 1e-3)
+    assert err <= 1e-3
+
+
+def test_autograd_arbitrary_upstream_gradient(record_error):
+    """A non-MSE loss: L = sum(weights * image) -> upstream gradient = weights."""
+    import torch
+
+    from paper_2510_05814_amd.autograd import smoe_render
+    print("[case] autograd upstream", flush=True)
+    W, H = 41, 35
+    m = wl.random_model(60, 3, 1, W, H, seed=91)
+    raw = m.astype(np.float64).copy()
+    raw[:, 2] = np.log(raw[:, 2])
+    raw[:, 4] = np.log(raw[:, 4])
+    wts = np.random.default_rng(2).normal(size=(H, W, 3))
+    r = _dev(raw).requires_grad_(True)
+    (smoe_render(r, 3, 1, W, H) * _dev(wts)).sum().backward()
+    _, g_o = oracle.loss_grad(oracle.materialize(raw, 3, 1), 3, 1, W, H, grad_y=wts)
+    err = np.max(np.abs(r.grad.cpu().numpy() - g_o)) / np.max(np.abs(g_o))
+    record_error("autograd upstream grad rel", err, 1e-3)
+    assert err <= 1e-3
+
+
+def test_autograd_equals_fused_fit_step_gradient(record_error):
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.autograd import smoe_render
+    print("[case] autograd vs fit step", flush=True)
+    w = wl.workload(2)
+    H, W, C = w.target.shape
+    t = _dev(w.target)
+    st = smoe.FitState(t, _dev(w.raw0), 1, smoe.AdamConfig(total_steps=100), max_steps=2)
+    st.step()
+    r = _dev(w.raw0).requires_grad_(True)
+    loss = torch.mean((smoe_render(r, C, 1, W, H) - t) ** 2)
+    loss.backward()
+    gf = st.grads
+    err = (torch.max(torch.abs(r.grad - gf)) / torch.max(torch.abs(gf))).item()
+    record_error("autograd vs fused fit-step grad rel", err, 1e-5)
+    assert err <= 1e-5
+    assert abs(loss.item() - st.losses()[0].item()) <= 1e-6 * loss.item()
+
+
+def test_autograd_with_torch_adam_reduces_loss():
+    import torch
+
+    from paper_2510_05814_amd.autograd import smoe_render
+    print("[case] autograd + torch.optim.Adam", flush=True)
+    w = wl.workload(1)
+    H, W, C = w.target.shape
+    t = _dev(w.target)
+    r = _dev(w.raw0).requires_grad_(True)
+    opt = torch.optim.Adam([r], lr=1e-2)
+    losses = []
+    for _ in range(30):
+        opt.zero_grad()
+        loss = torch.mean((smoe_render(r, C, 0, W, H) - t) ** 2)
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    assert losses[-1] < 0.8 * losses[0]

@@ -410,3 +410,26 @@ def test_capacity_overflow_is_reported_and_harmless(smoe):
     assert fs.grow_if_needed()
     fs.step()
     assert fs.steps_done() == 1 and not torch.equal(fs.raw, raw_before)
+
+
+def test_fused_fit_step_equals_standalone_calls(smoe):
+    """The fit step's fused kernels (bucket sort inside the render, next-step binning inside
+    Adam) give bitwise the image and gradient of smoe_bin + smoe_render +
+    smoe_render_backward, on the first step (prologue binning) and on later steps (binning
+    left by the previous step's Adam)."""
+    import torch
+    say("fused vs standalone")
+    w = wl.workload(2)
+    H, W, C = w.target.shape
+    t = dev(w.target)
+    st = smoe.FitState(t, dev(w.raw0), 1, smoe.AdamConfig(total_steps=2000), max_steps=8)
+    grid = smoe.make_grid(W, H)
+    for k in range(3):
+        model = st.model.clone()
+        img, D, _, b = smoe.render(model, C, 1, grid)
+        g = smoe.render_backward(model, C, 1, grid, b, img, D, target=t)
+        st.step()
+        torch.cuda.synchronize()
+        assert torch.equal(st.image, img), k
+        assert torch.equal(st.denom, D), k
+        assert torch.equal(st.grads, g), k
