@@ -266,6 +266,10 @@ def run(args):
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
         out["cpu_baseline"] = cb
+    if not args.no_serving:
+        out["serving"] = run_serving(args)
+    if not args.no_batched_fit:
+        out["batched_fit"] = run_batched_fit(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -276,6 +280,113 @@ def run(args):
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = CALIB_BYTES
     print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------------------- serving
+
+def run_serving(args):
+    """Serving workload: 16 resident fitted models (K 256 .. 65536, native 256^2 .. 2048^2,
+    linear experts), a Poisson stream of render requests at 200 req/s, each at an upscale
+    factor in {1, 2, 3, 4} with outputs up to 4096^2 RGB, admitted under an 8 GB budget.
+    Reports p50/p99 latency and pixels/s of continuous batching against one launch
+    sequence per request, at the Poisson rate and at saturation (all requests at t = 0)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.serve import ModelBank, PlainServer, Server
+    import workloads as wl
+
+    t_setup = time.perf_counter()
+    ms = wl.serving_models()
+    st = smoe.FitState([torch.from_numpy(m["image"]).cuda() for m in ms],
+                       [torch.from_numpy(m["raw0"]).cuda() for m in ms], 1,
+                       smoe.AdamConfig(total_steps=args.serve_fit_steps),
+                       max_steps=args.serve_fit_steps)
+    for _ in range(args.serve_fit_steps):
+        st.step()
+    st.grow_if_needed()
+    models = [st.model[sg.kernel_offset:sg.kernel_offset + sg.num_kernels]
+              for sg in st.segments.host]
+    bank = ModelBank(models, 3, 1)
+    del st
+    torch.cuda.empty_cache()
+    sides = [m["side"] for m in ms]
+    reqs = wl.serving_requests(sides, args.serve_requests, rate=200.0)
+    warm = wl.serving_requests(sides, 24, rate=1e6, seed=7)
+    setup_s = time.perf_counter() - t_setup
+    out = {"models": len(ms), "K": [m["K"] for m in ms], "native_side": sides,
+           "requests": len(reqs), "rate_hz": 200.0, "scales": [1, 2, 3, 4], "max_side": 4096,
+           "budget_bytes": 8 << 30, "mean_output_px": float(np.mean([r["width"] * r["height"]
+                                                                    for r in reqs])),
+           "setup_s": setup_s, "fit_steps_per_model": args.serve_fit_steps}
+    srv = Server(bank, budget_bytes=8 << 30, streams=2)
+    plain = PlainServer(bank)
+    srv.serve(warm, realtime=False)
+    plain.serve(warm, realtime=False)
+    _, out["batched"] = srv.serve(reqs)
+    _, out["plain"] = plain.serve(reqs)
+    sat = reqs[:args.serve_saturation]
+    _, out["batched_saturated"] = srv.serve(sat, realtime=False)
+    _, out["plain_saturated"] = plain.serve(sat, realtime=False)
+    return out
+
+
+def run_batched_fit(args):
+    """Batched fit: 64 RGB images of uneven sizes (sides log-uniform in [128, 1024]), each
+    with K = pixels / 64 linear experts, fitted together -- one binning + render + backward
+    + Adam launch sequence per step for all images, steps replayed from a HIP graph.
+    Reports aggregate iterations/s and every image's PSNR against its own unbatched fit
+    (the same steps run image by image)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    imgs = wl.config5_images()
+    raws = wl.batched_fit_inits(imgs)
+    steps = args.bfit_steps
+    adam = smoe.AdamConfig(total_steps=steps)
+    tg = [torch.from_numpy(i).cuda() for i in imgs]
+    rg = [torch.from_numpy(r).cuda() for r in raws]
+    probe = smoe.FitState(tg, rg, 1, adam, max_steps=1)
+    cap = 4 * probe.bins.capacity        # graph replays cannot re-size the workspace
+    del probe
+    st = smoe.FitState(tg, rg, 1, adam, max_steps=steps + 1, capacity=cap)
+    st.step()                     # first step eagerly (prologue), then graphs
+    spg = 50
+    n_full, rem = divmod(steps - 1, spg)
+    g = st.capture(spg) if n_full else None
+    g_rem = st.capture(rem) if rem else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_full):
+        st.replay(g)
+    if g_rem is not None:
+        st.replay(g_rem)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if st.bins.read_status()[0]:
+        raise RuntimeError("pair capacity overflow in the batched fit")
+    psnr_b = [smoe.psnr(im, t) for im, t in zip(st.images(), tg)]
+    # the unbatched path: every image fitted alone for the same steps
+    psnr_u = []
+    t0 = time.perf_counter()
+    for t, r in zip(tg, raws):
+        s1 = smoe.FitState(t, torch.from_numpy(r).cuda(), 1, adam, max_steps=steps + 1)
+        s1.run(steps)
+        psnr_u.append(smoe.psnr(s1.image, t))
+    torch.cuda.synchronize()
+    t_unb = time.perf_counter() - t0
+    d = np.abs(np.array(psnr_b) - np.array(psnr_u))
+    px = sum(i.shape[0] * i.shape[1] for i in imgs)
+    return {"images": len(imgs), "pixels": int(px), "K": int(st.K), "steps": steps,
+            "timed_steps": steps - 1, "iters_per_s": (steps - 1) / elapsed,
+            "ms_per_step": 1e3 * elapsed / (steps - 1),
+            "unbatched_iters_per_s": steps / t_unb,
+            "psnr_mean_db": float(np.mean(psnr_b)), "psnr_min_db": float(np.min(psnr_b)),
+            "psnr_max_abs_diff_vs_unbatched_db": float(d.max())}
 
 
 # ----------------------------------------------------------------------------- profiles
@@ -373,6 +484,12 @@ def main():
                     help="no HIP graphs: every timed step is launched eagerly (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain copy of known size (for PMC byte counters)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-saturation", type=int, default=300)
+    ap.add_argument("--serve-fit-steps", type=int, default=50)
+    ap.add_argument("--no-batched-fit", action="store_true")
+    ap.add_argument("--bfit-steps", type=int, default=1000)
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()

@@ -85,6 +85,41 @@ typedef struct smoe_grid {
   float radius;                /* Mahalanobis truncation radius r > 0 (3 = 98.9 % mass) */
 } smoe_grid;
 
+/* One raster of a batched call: an image of a batched fit, or one render request (the
+ * model rows params[param_offset, param_offset + num_kernels) rendered on this raster).
+ * Rasters are numbered consecutively: kernel_offset, tile_offset and pixel_offset are the
+ * raster's first row in the per-kernel workspace arrays, first block in the global block
+ * numbering, and first pixel in the concatenated images; smoe_segments_layout() sets them. */
+typedef struct smoe_segment {
+  int32_t width, height;       /* output pixels, 1 .. 65536 each */
+  int32_t scale;               /* integer upscale factor, 1 .. 64 */
+  int32_t origin_x, origin_y;  /* raster origin in output pixels, |.| <= 2^22 */
+  int32_t num_kernels;         /* rows of this raster's model */
+  int32_t param_offset;        /* first row of the model in the params array */
+  int32_t kernel_offset;       /* set by smoe_segments_layout */
+  int32_t tile_offset;         /* set by smoe_segments_layout */
+  int32_t reserved;
+  int64_t pixel_offset;        /* set by smoe_segments_layout */
+} smoe_segment;
+
+/* Host only: sets kernel_offset, tile_offset and pixel_offset of segs[0, n) to the running
+ * sums of num_kernels, blocks and pixels, and returns the totals (any output may be NULL).
+ * Fails with SMOE_ERR_INVALID on an invalid raster or if a total exceeds int32 (blocks,
+ * kernels). */
+smoe_status smoe_segments_layout(smoe_segment* segs, int32_t n, int32_t* total_kernels,
+                                 int32_t* total_tiles, int64_t* total_pixels);
+
+/* A batch of rasters sharing one parameter array, expert shape and truncation radius. */
+typedef struct smoe_batch {
+  int32_t C, order;                   /* as in smoe_model */
+  const float* params;                /* device, materialized rows addressed by param_offset */
+  int32_t num_params_rows;            /* rows in params (for validation) */
+  int32_t num_segments;               /* >= 1 */
+  const smoe_segment* segments;       /* device copy of the laid-out table */
+  const smoe_segment* segments_host;  /* host copy of the same table */
+  float radius;                       /* Mahalanobis truncation radius */
+} smoe_batch;
+
 /* Binning workspace: the block lists of Sec. IV-C and the scratch of the backward.
  * Laid out by smoe_bins_layout() inside one caller-allocated device buffer. */
 typedef struct smoe_bins {
@@ -115,6 +150,16 @@ size_t smoe_bins_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t ma
 smoe_status smoe_bins_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K, int32_t C,
                              int32_t order, int32_t max_tiles, int32_t capacity);
 
+/* A render-only workspace: the same layout without the per-pair gradient partials
+ * (pair_grads = NULL), for callers that bin and render but never run the backward -- a
+ * serving loop.  smoe_render_backward and smoe_fit_step reject such bins with
+ * SMOE_ERR_INVALID.  Host only, as smoe_bins_workspace_bytes / smoe_bins_layout. */
+size_t smoe_render_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t max_tiles,
+                                   int32_t capacity);
+smoe_status smoe_render_workspace_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K,
+                                         int32_t C, int32_t order, int32_t max_tiles,
+                                         int32_t capacity);
+
 /* Binning (Sec. IV-B, IV-C): per-kernel square box -> block rectangle and count, the
  * per-kernel render record, then the (block, kernel) pairs ordered by block and, within a
  * block, by kernel id, and each block's [begin, end) range.  The order is the one a
@@ -142,6 +187,15 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
                                  const smoe_bins* bins, const float* image, const float* denom,
                                  const float* grad_image, const float* target, float* grads,
                                  void* stream);
+
+/* Batched binning and render: every segment of `batch` is binned into one workspace (laid
+ * out for K = total kernels, max_tiles >= total blocks) and rendered into the concatenated
+ * images (device [total pixels][C]) and denominators ([total pixels], may be NULL), exactly
+ * as smoe_bin + smoe_render of each raster alone would.  One launch per stage serves all
+ * segments (render requests of a serving loop, images of a batched fit). */
+smoe_status smoe_bin_batched(const smoe_batch* batch, smoe_bins* bins, void* stream);
+smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, float* images,
+                                float* denoms, void* stream);
 
 /* raw -> materialized rows (l11 = exp(s1), l22 = exp(s2), the rest copied), device. */
 smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw,
@@ -179,7 +233,15 @@ typedef struct smoe_fit_state {
                                 changing raw/model outside smoe_fit_step */
   int32_t* step;             /* [1] completed steps */
   float* scalars;            /* [4] per-step scratch */
-  smoe_bins bins;            /* laid out for (K, C, order) and this grid */
+  /* Batched fit (num_segments > 0): num_segments images fitted together, each with its own
+   * kernels, as independent fits stepped in lock-step (the loss is the sum of the images'
+   * MSEs, so every image's gradient is its own).  Segments laid out by
+   * smoe_segments_layout with scale 1, origin 0 and param_offset == kernel_offset; target,
+   * image and denom are the concatenated images; K = total kernels; `grid` is unused. */
+  int32_t num_segments;
+  const smoe_segment* segments;       /* device copy, or NULL for one image */
+  const smoe_segment* segments_host;  /* host copy, or NULL */
+  smoe_bins bins;            /* laid out for (K, C, order) and all blocks */
 } smoe_fit_state;
 
 /* One fit iteration on `stream` with no host synchronisation: binning, forward render
@@ -210,6 +272,10 @@ smoe_status smoe_fit_step_timed(smoe_fit_state* state, const float* target, floa
  * overwritten.  Uses atomics; the counts are exact integers. */
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
                             const smoe_bins* bins, uint64_t* out2, void* stream);
+
+/* Reporting: out (device float[max(1, num_segments)]) = each image's MSE at the state's last
+ * fit step. */
+smoe_status smoe_fit_segment_losses(const smoe_fit_state* state, float* out, void* stream);
 
 /* Synchronises `stream`, copies the status words (P needed, overflow flag, longest list,
  * spare) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an overflow. */

@@ -31,6 +31,19 @@ class SmoeGrid(ct.Structure):
                 ("origin_y", _i32), ("radius", _f32)]
 
 
+class SmoeSegment(ct.Structure):
+    _fields_ = [("width", _i32), ("height", _i32), ("scale", _i32), ("origin_x", _i32),
+                ("origin_y", _i32), ("num_kernels", _i32), ("param_offset", _i32),
+                ("kernel_offset", _i32), ("tile_offset", _i32), ("reserved", _i32),
+                ("pixel_offset", ct.c_int64)]
+
+
+class SmoeBatch(ct.Structure):
+    _fields_ = [("C", _i32), ("order", _i32), ("params", _vp), ("num_params_rows", _i32),
+                ("num_segments", _i32), ("segments", _vp), ("segments_host", _vp),
+                ("radius", _f32)]
+
+
 class SmoeBins(ct.Structure):
     _fields_ = [("K", _i32), ("C", _i32), ("order", _i32), ("max_tiles", _i32),
                 ("capacity", _i32), ("tile_rects", _vp), ("counts", _vp), ("records", _vp),
@@ -50,8 +63,8 @@ class SmoeFitState(ct.Structure):
                 ("adam", SmoeAdamConfig), ("raw", _vp), ("adam_m", _vp), ("adam_v", _vp),
                 ("model", _vp), ("grads", _vp), ("image", _vp), ("denom", _vp),
                 ("loss_history", _vp), ("max_steps", _i32), ("prepared", _i32), ("step", _vp),
-                ("scalars", _vp),
-                ("bins", SmoeBins)]
+                ("scalars", _vp), ("num_segments", _i32), ("segments", _vp),
+                ("segments_host", _vp), ("bins", SmoeBins)]
 
 
 class SmoeError(RuntimeError):
@@ -75,6 +88,10 @@ def _load():
     L.smoe_bins_workspace_bytes.restype = _sz
     L.smoe_bins_layout.argtypes = [P(SmoeBins), _vp, _sz, _i32, _i32, _i32, _i32, _i32]
     L.smoe_bins_layout.restype = _i32
+    L.smoe_render_workspace_bytes.argtypes = [_i32, _i32, _i32, _i32, _i32]
+    L.smoe_render_workspace_bytes.restype = _sz
+    L.smoe_render_workspace_layout.argtypes = [P(SmoeBins), _vp, _sz, _i32, _i32, _i32, _i32, _i32]
+    L.smoe_render_workspace_layout.restype = _i32
     L.smoe_bin.argtypes = [P(SmoeModel), P(SmoeGrid), P(SmoeBins), _vp]
     L.smoe_bin.restype = _i32
     L.smoe_render.argtypes = [P(SmoeModel), P(SmoeGrid), P(SmoeBins), _vp, _vp, _vp, _vp, _vp]
@@ -92,6 +109,14 @@ def _load():
     L.smoe_pair_stats.restype = _i32
     L.smoe_read_status.argtypes = [P(SmoeBins), P(_i32), _vp]
     L.smoe_read_status.restype = _i32
+    L.smoe_segments_layout.argtypes = [P(SmoeSegment), _i32, P(_i32), P(_i32), P(ct.c_int64)]
+    L.smoe_segments_layout.restype = _i32
+    L.smoe_bin_batched.argtypes = [P(SmoeBatch), P(SmoeBins), _vp]
+    L.smoe_bin_batched.restype = _i32
+    L.smoe_render_batched.argtypes = [P(SmoeBatch), P(SmoeBins), _vp, _vp, _vp]
+    L.smoe_render_batched.restype = _i32
+    L.smoe_fit_segment_losses.argtypes = [P(SmoeFitState), _vp, _vp]
+    L.smoe_fit_segment_losses.restype = _i32
     return L
 
 
@@ -100,7 +125,9 @@ lib = _load()
 # Symbols the header declares; the CPU test suite checks that each is exported.
 EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "smoe_bin",
             "smoe_render", "smoe_render_backward", "smoe_materialize", "smoe_fit_step",
-            "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status"]
+            "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status", "smoe_segments_layout",
+            "smoe_bin_batched", "smoe_render_batched", "smoe_fit_segment_losses",
+            "smoe_render_workspace_bytes", "smoe_render_workspace_layout"]
 
 
 def _check(fn: str, code: int, allow=()):
@@ -122,6 +149,17 @@ def smoe_bins_layout(bins: SmoeBins, workspace_ptr: int, nbytes: int, K, C, orde
     return _check("smoe_bins_layout",
                   lib.smoe_bins_layout(ct.byref(bins), workspace_ptr, nbytes, K, C, order,
                                        max_tiles, capacity))
+
+
+def smoe_render_workspace_bytes(K, C, order, max_tiles, capacity) -> int:
+    return int(lib.smoe_render_workspace_bytes(K, C, order, max_tiles, capacity))
+
+
+def smoe_render_workspace_layout(bins: SmoeBins, workspace_ptr: int, nbytes: int, K, C, order,
+                                 max_tiles, capacity):
+    return _check("smoe_render_workspace_layout",
+                  lib.smoe_render_workspace_layout(ct.byref(bins), workspace_ptr, nbytes, K, C,
+                                                   order, max_tiles, capacity))
 
 
 def smoe_bin(model: SmoeModel, grid: SmoeGrid, bins: SmoeBins, stream: int | None):
@@ -171,3 +209,25 @@ def smoe_read_status(bins: SmoeBins, stream):
     code = _check("smoe_read_status", lib.smoe_read_status(ct.byref(bins), out, stream),
                   allow=(SMOE_ERR_CAPACITY,))
     return code, list(out)
+
+
+def smoe_segments_layout(segs):
+    """segs: ctypes array of SmoeSegment, filled in place; returns (K, T, pixels)."""
+    k, t, px = _i32(), _i32(), ct.c_int64()
+    _check("smoe_segments_layout", lib.smoe_segments_layout(segs, len(segs), ct.byref(k),
+                                                            ct.byref(t), ct.byref(px)))
+    return k.value, t.value, px.value
+
+
+def smoe_bin_batched(batch: SmoeBatch, bins: SmoeBins, stream):
+    return _check("smoe_bin_batched", lib.smoe_bin_batched(ct.byref(batch), ct.byref(bins), stream))
+
+
+def smoe_render_batched(batch: SmoeBatch, bins: SmoeBins, images_ptr, denoms_ptr, stream):
+    return _check("smoe_render_batched", lib.smoe_render_batched(ct.byref(batch), ct.byref(bins),
+                                                                 images_ptr, denoms_ptr, stream))
+
+
+def smoe_fit_segment_losses(state: SmoeFitState, out_ptr, stream):
+    return _check("smoe_fit_segment_losses", lib.smoe_fit_segment_losses(ct.byref(state), out_ptr,
+                                                                         stream))

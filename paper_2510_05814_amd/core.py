@@ -5,6 +5,7 @@ current HIP stream; every computation is a call into ``libsmoe.so``.
 """
 from __future__ import annotations
 
+import ctypes as ct
 import math
 from dataclasses import dataclass
 
@@ -54,17 +55,21 @@ class Bins:
     """A binning workspace (block lists, records, backward scratch) in one device buffer."""
 
     def __init__(self, K: int, C_: int, order: int, max_tiles: int, capacity: int,
-                 device="cuda"):
+                 device="cuda", render_only: bool = False, zero: bool = True):
+        """render_only: no per-pair gradient scratch (bin + render only).  zero=False leaves
+        the buffer uninitialised, which the binning and render calls allow (they write
+        every word they read)."""
         self.K, self.C, self.order = K, C_, order
         self.max_tiles, self.capacity = int(max_tiles), int(capacity)
-        n = C.smoe_bins_workspace_bytes(K, C_, order, self.max_tiles, self.capacity)
+        size = C.smoe_render_workspace_bytes if render_only else C.smoe_bins_workspace_bytes
+        n = size(K, C_, order, self.max_tiles, self.capacity)
         if n == 0:
             raise ValueError("invalid workspace shape")
         self.nbytes = n
-        self.ws = torch.zeros(n, dtype=torch.uint8, device=device)
+        self.ws = (torch.zeros if zero else torch.empty)(n, dtype=torch.uint8, device=device)
         self.c = C.SmoeBins()
-        C.smoe_bins_layout(self.c, self.ws.data_ptr(), n, K, C_, order, self.max_tiles,
-                           self.capacity)
+        lay = C.smoe_render_workspace_layout if render_only else C.smoe_bins_layout
+        lay(self.c, self.ws.data_ptr(), n, K, C_, order, self.max_tiles, self.capacity)
 
     def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
         off = ptr - self.ws.data_ptr()
@@ -154,6 +159,76 @@ def materialize(raw: torch.Tensor, C_: int, order: int, stream=None) -> torch.Te
     return out
 
 
+class Segments:
+    """A laid-out segment table (host ctypes array + device copy) for batched calls.
+
+    rasters: list of dicts with width, height and optionally scale, origin_x, origin_y,
+    num_kernels, param_offset (default: the running sum of num_kernels)."""
+
+    def __init__(self, rasters, device="cuda", stream=None):
+        n = len(rasters)
+        if n < 1:
+            raise ValueError("at least one raster")
+        self.host = (C.SmoeSegment * n)()
+        k = 0
+        for i, r in enumerate(rasters):
+            sg = self.host[i]
+            sg.width, sg.height = int(r["width"]), int(r["height"])
+            sg.scale = int(r.get("scale", 1))
+            sg.origin_x, sg.origin_y = int(r.get("origin_x", 0)), int(r.get("origin_y", 0))
+            sg.num_kernels = int(r.get("num_kernels", 0))
+            sg.param_offset = int(r.get("param_offset", k))
+            k += sg.num_kernels
+        self.K, self.T, self.pixels = C.smoe_segments_layout(self.host)
+        # device copy: staged through pinned memory and copied on `stream` (no host wait)
+        nbytes = ct.sizeof(self.host)
+        pinned = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        ct.memmove(pinned.data_ptr(), ct.addressof(self.host), nbytes)
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            self.dev = pinned.to(device, non_blocking=True)
+        self.n = n
+
+    def __len__(self):
+        return self.n
+
+    def pixel_slices(self):
+        """(start, stop, height, width) of every raster in the concatenated images."""
+        return [(sg.pixel_offset, sg.pixel_offset + sg.width * sg.height, sg.height, sg.width)
+                for sg in self.host]
+
+
+def bin_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, radius: float = 3.0,
+                bins: Bins | None = None, capacity: int | None = None, stream=None,
+                grow: bool = True) -> Bins:
+    """smoe_bin_batched over every segment; with grow=True the workspace is re-made until the
+    pairs fit (host sync)."""
+    _check_params(params, C_, order)
+    batch = C.SmoeBatch(C_, order, params.data_ptr(), params.shape[0], segs.n, segs.dev.data_ptr(),
+                        ct.addressof(segs.host), float(radius))
+    if bins is None:
+        bins = Bins(segs.K, C_, order, segs.T, capacity or initial_capacity(segs.K, segs.T),
+                    params.device)
+    C.smoe_bin_batched(batch, bins.c, _stream(stream))
+    if grow:
+        over, st = bins.read_status(stream)
+        if over:
+            bins = Bins(segs.K, C_, order, max(segs.T, bins.max_tiles), int(st[0] * 1.25) + 1024,
+                        params.device)
+            C.smoe_bin_batched(batch, bins.c, _stream(stream))
+    return bins
+
+
+def render_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, bins: Bins,
+                   images: torch.Tensor, denoms: torch.Tensor | None = None, radius: float = 3.0,
+                   stream=None):
+    """smoe_render_batched into the concatenated images [total pixels, C]."""
+    _check_params(params, C_, order)
+    batch = C.SmoeBatch(C_, order, params.data_ptr(), params.shape[0], segs.n, segs.dev.data_ptr(),
+                        ct.addressof(segs.host), float(radius))
+    C.smoe_render_batched(batch, bins.c, images.data_ptr(), _ptr(denoms), _stream(stream))
+    return images
+
+
 @dataclass
 class AdamConfig:
     """Adam settings (Sec. VI-B): centre rate decays exponentially to lr_mu_final."""
@@ -178,45 +253,96 @@ class AdamConfig:
 
 
 class FitState:
-    """Device state of one fit, driven by smoe_fit_step (one call = one iteration)."""
+    """Device state of one fit, driven by smoe_fit_step (one call = one iteration).
 
-    def __init__(self, target: torch.Tensor, raw0: torch.Tensor, order: int, adam: AdamConfig,
-                 max_steps: int = 0, capacity: int | None = None, radius: float = 3.0):
-        if not (target.is_cuda and target.dtype == torch.float32 and target.dim() == 3):
-            raise ValueError("target must be a cuda float32 [H, W, C] tensor")
-        self.target = target.contiguous()
-        H, W, C_ = self.target.shape
-        self.H, self.W, self.C, self.order = H, W, C_, order
-        self.K = raw0.shape[0]
-        dev = target.device
-        self.raw = raw0.to(device=dev, dtype=torch.float32).contiguous().clone()
+    target: one cuda float32 [H, W, C] image with raw0 [K, NP] -- or, for a batched fit, a
+    list of images with a list of raw0 arrays (one per image): the images are fitted together
+    in lock-step, each by its own kernels, with one launch per stage for all of them."""
+
+    def __init__(self, target, raw0, order: int, adam: AdamConfig, max_steps: int = 0,
+                 capacity: int | None = None, radius: float = 3.0):
+        batched = isinstance(target, (list, tuple))
+        targets = list(target) if batched else [target]
+        raws = list(raw0) if batched else [raw0]
+        if len(targets) != len(raws) or not targets:
+            raise ValueError("one raw parameter array per target image")
+        for t in targets:
+            if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 3):
+                raise ValueError("targets must be cuda float32 [H, W, C] tensors")
+        C_ = targets[0].shape[2]
+        dev = targets[0].device
+        self.C, self.order, self.batched = C_, order, batched
+        self.shapes = [tuple(t.shape[:2]) for t in targets]
+        self.raw = torch.cat([r.to(device=dev, dtype=torch.float32) for r in raws]).contiguous()
         _check_params(self.raw, C_, order)
+        self.K = self.raw.shape[0]
+        self.segments = None
+        if batched:
+            self.segments = Segments([{"width": w, "height": h, "num_kernels": r.shape[0]}
+                                      for (h, w), r in zip(self.shapes, raws)], device=dev)
+            self.target = torch.cat([t.reshape(-1, C_) for t in targets]).contiguous()
+            npx = self.target.shape[0]
+            self.image = torch.zeros((npx, C_), dtype=torch.float32, device=dev)
+            self.denom = torch.zeros((npx,), dtype=torch.float32, device=dev)
+            T = self.segments.T
+            self.H = self.W = None
+        else:
+            self.target = targets[0].contiguous()
+            H, W = self.shapes[0]
+            self.H, self.W = H, W
+            self.image = torch.zeros((H, W, C_), dtype=torch.float32, device=dev)
+            self.denom = torch.zeros((H, W), dtype=torch.float32, device=dev)
+            T = tiles(W, H)
         self.m = torch.zeros_like(self.raw)
         self.v = torch.zeros_like(self.raw)
         self.model = materialize(self.raw, C_, order)
         self.grads = torch.zeros_like(self.raw)
-        self.image = torch.zeros((H, W, C_), dtype=torch.float32, device=dev)
-        self.denom = torch.zeros((H, W), dtype=torch.float32, device=dev)
         self.max_steps = int(max_steps)
         self.loss_history = torch.zeros(max(1, self.max_steps), dtype=torch.float32, device=dev)
         self.step_counter = torch.zeros(1, dtype=torch.int32, device=dev)
         self.scalars = torch.zeros(4, dtype=torch.float32, device=dev)
-        self.grid = make_grid(W, H, 1, 0, 0, radius)
+        H0, W0 = self.shapes[0]
+        self.grid = make_grid(W0, H0, 1, 0, 0, radius)
         self.adam = adam
-        T = tiles(W, H)
         if capacity is None:
-            b = bin(self.model, C_, order, self.grid)
+            if batched:
+                b = bin_batched(self.model, C_, order, self.segments, radius)
+            else:
+                b = bin(self.model, C_, order, self.grid)
             _, st = b.read_status()
             capacity = int(st[0] * 2) + 4096
         self.bins = Bins(self.K, C_, order, T, capacity, dev)
         self._build_struct()
 
     def _build_struct(self):
+        seg = self.segments
         self.c = C.SmoeFitState(
             self.K, self.C, self.order, self.grid, self.adam.c(), self.raw.data_ptr(),
             self.m.data_ptr(), self.v.data_ptr(), self.model.data_ptr(), self.grads.data_ptr(),
             self.image.data_ptr(), self.denom.data_ptr(), self.loss_history.data_ptr(),
-            self.max_steps, 0, self.step_counter.data_ptr(), self.scalars.data_ptr(), self.bins.c)
+            self.max_steps, 0, self.step_counter.data_ptr(), self.scalars.data_ptr(),
+            0 if seg is None else seg.n, None if seg is None else seg.dev.data_ptr(),
+            None if seg is None else ct.addressof(seg.host), self.bins.c)
+
+    def segment_losses(self, stream=None) -> torch.Tensor:
+        """Each image's MSE at the last step (a single-image fit gives one value)."""
+        n = 1 if self.segments is None else self.segments.n
+        out = torch.zeros(n, dtype=torch.float32, device=self.raw.device)
+        C.smoe_fit_segment_losses(self.c, out.data_ptr(), _stream(stream))
+        return out
+
+    def images(self):
+        """The last step's render, one [H, W, C] view per image."""
+        if self.segments is None:
+            return [self.image]
+        return [self.image[a:b].view(h, w, self.C) for a, b, h, w in self.segments.pixel_slices()]
+
+    def raw_rows(self):
+        """The raw parameter rows of each image."""
+        if self.segments is None:
+            return [self.raw]
+        return [self.raw[sg.kernel_offset:sg.kernel_offset + sg.num_kernels]
+                for sg in self.segments.host]
 
     def step(self, loss_out: torch.Tensor | None = None, stream=None):
         C.smoe_fit_step(self.c, self.target.data_ptr(), _ptr(loss_out), _stream(stream))
@@ -280,7 +406,7 @@ class FitState:
         over, st = self.bins.read_status(stream)
         if over:
             self.bins = Bins(self.K, self.C, self.order, self.bins.max_tiles,
-                             int(st[0] * 1.5) + 4096, self.target.device)
+                             int(st[0] * 1.5) + 4096, self.raw.device)
             self._build_struct()
         return over
 

@@ -17,7 +17,8 @@ namespace smoe {
 namespace {
 
 struct BackwardArgs {
-  GridArgs g;
+  Segs S;
+  int C;
   const float* __restrict__ records;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -25,15 +26,17 @@ struct BackwardArgs {
   const float* __restrict__ denom;
   const float* __restrict__ grad_image;  // upstream dL/dy, or null
   const float* __restrict__ target;      // MSE target, or null
-  float inv_n2;                          // 2 / (W H C) for the MSE
   float* __restrict__ pair_grads;
 };
 
 template <int C, int ORDER>
 __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  const int tile = xcd_block(blockIdx.x, a.g.T);
-  const PixelCoords px = lane_pixels(a.g, tile);
+  const int tile = xcd_block(blockIdx.x, a.S.T);
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
+  // MSE of this raster: dL/dy = 2 (y - t) / (W H C)
+  const float inv_n2 = 2.0f / ((float)sg.W * (float)sg.H * (float)C);
   PixelSeed<C> sd;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
@@ -43,8 +46,8 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
     sd.gy[i] = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) sd.g[i][c] = 0.0f;
-    if (px.u < a.g.W && v < a.g.H) {
-      const size_t p = (size_t)v * a.g.W + px.u;
+    if (px.u < sg.W && v < sg.H) {
+      const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const float D = a.denom[p];
       if (D > 0.0f) {
         sd.valid[i] = true;
@@ -52,19 +55,18 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const float yc = a.image[p * C + c];
-          sd.g[i][c] = a.target ? (yc - a.target[p * C + c]) * a.inv_n2 : a.grad_image[p * C + c];
+          sd.g[i][c] = a.target ? (yc - a.target[p * C + c]) * inv_n2 : a.grad_image[p * C + c];
           sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
         }
       }
     }
   }
-  backward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, a.ranges[tile], srec, false, sd,
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, false, sd,
                                 a.pair_grads);
 }
 
 struct GatherArgs {
-  int K;
-  int ntx;
+  Segs S;
   const int4* __restrict__ tile_rects;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -78,48 +80,39 @@ template <int NP>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = gid >> 4, i = gid & 15;
-  if (j >= a.K) return;
-  const float g = a.status[1] != 0
-                      ? 0.0f
-                      : gather_param<NP>(j, i, a.ntx, a.tile_rects, a.ranges, a.vals, a.pair_grads);
+  if (j >= a.S.K) return;
+  const float g = a.status[1] != 0 ? 0.0f
+                                   : gather_param<NP>(j, i, seg_of_kernel(a.S, j), a.tile_rects,
+                                                      a.ranges, a.vals, a.pair_grads);
   if (i < NP) a.grads[(size_t)j * NP + i] = g;
 }
 
 }  // namespace
 
-hipError_t launch_backward(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
+hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
                            const float* image, const float* denom, const float* grad_image,
                            const float* target, hipStream_t s) {
-  BackwardArgs a{g,
-                 b.records,
-                 reinterpret_cast<const int2*>(b.ranges),
-                 b.vals,
-                 image,
-                 denom,
-                 grad_image,
-                 target,
-                 2.0f / ((float)g.W * (float)g.H * (float)m.C),
-                 b.pair_grads};
-  if (m.C == 1 && m.order == 0) k_backward<1, 0><<<g.T, kWave, 0, s>>>(a);
-  else if (m.C == 1 && m.order == 1) k_backward<1, 1><<<g.T, kWave, 0, s>>>(a);
-  else if (m.C == 3 && m.order == 0) k_backward<3, 0><<<g.T, kWave, 0, s>>>(a);
-  else k_backward<3, 1><<<g.T, kWave, 0, s>>>(a);
+  BackwardArgs a{S,     C,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals,
+                 image, denom, grad_image, target, b.pair_grads};
+  if (C == 1 && order == 0) k_backward<1, 0><<<S.T, kWave, 0, s>>>(a);
+  else if (C == 1 && order == 1) k_backward<1, 1><<<S.T, kWave, 0, s>>>(a);
+  else if (C == 3 && order == 0) k_backward<3, 0><<<S.T, kWave, 0, s>>>(a);
+  else k_backward<3, 1><<<S.T, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* grads,
+hipError_t launch_gather(int C, int order, const Segs& S, const smoe_bins& b, float* grads,
                          hipStream_t s) {
-  if (m.K == 0) return hipSuccess;
-  GatherArgs a{m.K,
-               g.ntx,
+  if (S.K == 0) return hipSuccess;
+  GatherArgs a{S,
                reinterpret_cast<const int4*>(b.tile_rects),
                reinterpret_cast<const int2*>(b.ranges),
                b.vals,
                b.pair_grads,
                b.status,
                grads};
-  const int blocks = (int)(((long long)m.K * 16 + 255) / 256);
-  const int NP = num_params(m.C, m.order);
+  const int blocks = (int)(((long long)S.K * 16 + 255) / 256);
+  const int NP = num_params(C, order);
   if (NP == 7) k_gather<7><<<blocks, 256, 0, s>>>(a);
   else if (NP == 9) k_gather<9><<<blocks, 256, 0, s>>>(a);  // (C, order) = (1, 1) or (3, 0)
   else k_gather<15><<<blocks, 256, 0, s>>>(a);

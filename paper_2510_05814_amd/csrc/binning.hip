@@ -15,36 +15,24 @@
 namespace smoe {
 namespace {
 
-// One thread per kernel: block rectangle, count, render record, and one atomic increment
-// per covered block.
-__global__ __launch_bounds__(128) void k_preprocess(int K, int C, int order,
-                                                    const float* __restrict__ params, GridArgs g,
+// One thread per kernel row: block rectangle, count, render record, and one atomic
+// increment per covered block.
+__global__ __launch_bounds__(128) void k_preprocess(int C, int order,
+                                                    const float* __restrict__ params, Segs S,
                                                     int4* __restrict__ tile_rects,
                                                     int32_t* __restrict__ counts,
                                                     float* __restrict__ records, int rs,
                                                     int32_t* __restrict__ tile_counts) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= K) return;
+  if (j >= S.K) return;
+  const SegGrid sg = seg_of_kernel(S, j);
   const int ne = expert_floats(C, order);
-  const float* p = params + (size_t)j * (6 + ne);
-  const float mux = p[0], muy = p[1], l11 = p[2], l21 = p[3], l22 = p[4], rho = p[5];
-  const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, g);
+  const float* p = params + (size_t)(sg.param_offset + (j - sg.kernel_offset)) * (6 + ne);
+  const int4 rc = kernel_block_rect(p[0], p[1], p[2], p[3], p[4], sg, S.r);
   tile_rects[j] = rc;
   counts[j] = rect_count(rc);
-
-  float* rec = records + (size_t)j * rs;
-  const float i11 = 1.0f / l11;
-  const float i22 = 1.0f / l22;
-  rec[0] = mux;
-  rec[1] = muy;
-  rec[2] = i11;
-  rec[3] = l21;
-  rec[4] = i22;
-  rec[5] = rho * kLog2e;
-  rec[6] = l21 * i22;
-  for (int i = 0; i < ne; ++i) rec[kRecExpert + i] = p[6 + i];
-  for (int i = kRecExpert + ne; i < rs; ++i) rec[i] = 0.0f;
-  count_blocks(rc, g.ntx, tile_counts);
+  write_record(records + (size_t)j * rs, p, ne, rs);
+  count_blocks(rc, sg, tile_counts);
 }
 
 constexpr int kScanThreads = 1024;
@@ -62,19 +50,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int T, int32_t* __restric
 // covered blocks q, q + 4, ... (row-major inside its block rectangle), so the cursor
 // atomics of one kernel run in parallel rather than one after another.
 constexpr int kScatterLanes = 4;
-__global__ __launch_bounds__(256) void k_scatter(int K, const int4* __restrict__ tile_rects,
-                                                 int ntx, const int2* __restrict__ ranges,
+__global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict__ tile_rects,
+                                                 const int2* __restrict__ ranges,
                                                  int32_t* __restrict__ cursors,
                                                  uint32_t* __restrict__ vals,
                                                  const int32_t* __restrict__ status) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = gid / kScatterLanes, q0 = gid % kScatterLanes;
-  if (j >= K || status[1] != 0) return;
+  if (j >= S.K || status[1] != 0) return;
   const int4 rc = tile_rects[j];
-  const int w = rc.z - rc.x + 1;
   const int n = rect_count(rc);
+  if (n == 0) return;
+  const SegGrid sg = seg_of_kernel(S, j);
+  const int w = rc.z - rc.x + 1;
   for (int q = q0; q < n; q += kScatterLanes) {
-    const int t = (rc.y + q / w) * ntx + rc.x + q % w;
+    const int t = sg.tile_offset + (rc.y + q / w) * sg.ntx + rc.x + q % w;
     const int pos = atomicAdd(&cursors[t], 1);
     const int2 rg = ranges[t];
     if (rg.x + pos < rg.y) vals[rg.x + pos] = (uint32_t)j;
@@ -108,43 +98,41 @@ inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_count(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                        hipStream_t s) {
+hipError_t launch_count(int C, int order, const float* params, const Segs& S,
+                        const smoe_bins& b, hipStream_t s) {
   // Counters start from zero (a fill kernel rather than a memset node, so that the step
   // can be captured into a graph).
-  k_fill_i32<<<cdiv(g.T, 256), 256, 0, s>>>(b.tile_counts, g.T, 0);
-  if (m.K > 0) {
-    k_preprocess<<<cdiv(m.K, 128), 128, 0, s>>>(m.K, m.C, m.order, m.params, g,
+  k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
+  if (S.K > 0) {
+    k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects), b.counts,
                                                  b.records, b.record_stride, b.tile_counts);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const GridArgs& g, const smoe_bins& b, hipStream_t s,
-                       const int32_t* fit_step) {
-  k_scan<<<1, kScanThreads, 0, s>>>(g.T, b.tile_counts, reinterpret_cast<int2*>(b.ranges),
+hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s, const int32_t* fit_step) {
+  k_scan<<<1, kScanThreads, 0, s>>>(S.T, b.tile_counts, reinterpret_cast<int2*>(b.ranges),
                                     b.capacity, b.status, fit_step);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                          hipStream_t s) {
-  if (m.K > 0) {
-    k_scatter<<<cdiv((long long)m.K * kScatterLanes, 256), 256, 0, s>>>(
-        m.K, reinterpret_cast<const int4*>(b.tile_rects),
-                                             g.ntx, reinterpret_cast<const int2*>(b.ranges),
-                                             b.tile_counts, b.vals, b.status);
+hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s) {
+  if (S.K > 0) {
+    k_scatter<<<cdiv((long long)S.K * kScatterLanes, 256), 256, 0, s>>>(
+        S, reinterpret_cast<const int4*>(b.tile_rects), reinterpret_cast<const int2*>(b.ranges),
+        b.tile_counts, b.vals, b.status);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const smoe_model& m, const GridArgs& g, const smoe_bins& b, hipStream_t s) {
-  hipError_t e = launch_count(m, g, b, s);
-  if (e == hipSuccess) e = launch_scan(g, b, s);
-  if (e == hipSuccess) e = launch_scatter(m, g, b, s);
+hipError_t launch_bin(int C, int order, const float* params, const Segs& S, const smoe_bins& b,
+                      hipStream_t s) {
+  hipError_t e = launch_count(C, order, params, S, b, s);
+  if (e == hipSuccess) e = launch_scan(S, b, s);
+  if (e == hipSuccess) e = launch_scatter(S, b, s);
   if (e != hipSuccess) return e;
-  k_sort_buckets<<<g.T, 64, 0, s>>>(reinterpret_cast<const int2*>(b.ranges), b.vals, b.vals_alt,
+  k_sort_buckets<<<S.T, 64, 0, s>>>(reinterpret_cast<const int2*>(b.ranges), b.vals, b.vals_alt,
                                     b.keys, b.tile_counts);
   return hipGetLastError();
 }

@@ -22,31 +22,81 @@ bool valid_model(const smoe_model* m) {
   return m && valid_shape(m->K, m->C, m->order) && (m->K == 0 || m->params);
 }
 
-bool make_grid(const smoe_grid* g, GridArgs* out) {
-  if (!g) return false;
-  if (g->width < 1 || g->height < 1 || g->width > 65536 || g->height > 65536) return false;
-  if (g->scale < 1 || g->scale > 64) return false;
-  if (std::abs(g->origin_x) > (1 << 22) || std::abs(g->origin_y) > (1 << 22)) return false;
-  if (!(g->radius > 0.0f) || !std::isfinite(g->radius)) return false;
-  GridArgs a;
-  a.W = g->width;
-  a.H = g->height;
-  a.scale = g->scale;
-  a.ox = g->origin_x;
-  a.oy = g->origin_y;
-  a.r = g->radius;
-  a.r2 = g->radius * g->radius;
-  a.inv_s = 1.0f / (float)g->scale;
-  a.ntx = (g->width + kTile - 1) / kTile;
-  a.nty = (g->height + kTile - 1) / kTile;
-  a.T = a.ntx * a.nty;
-  *out = a;
+bool valid_raster(int32_t W, int32_t H, int32_t scale, int32_t ox, int32_t oy) {
+  if (W < 1 || H < 1 || W > 65536 || H > 65536) return false;
+  if (scale < 1 || scale > 64) return false;
+  return std::abs(ox) <= (1 << 22) && std::abs(oy) <= (1 << 22);
+}
+
+bool valid_radius(float r) { return r > 0.0f && std::isfinite(r); }
+
+long long raster_tiles(int32_t W, int32_t H) {
+  return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+}
+
+// The single raster of a non-batched call as a one-segment Segs.
+bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
+  if (!valid_model(m) || !g ||
+      !valid_raster(g->width, g->height, g->scale, g->origin_x, g->origin_y) ||
+      !valid_radius(g->radius))
+    return false;
+  Segs S;
+  std::memset(&S, 0, sizeof(S));
+  smoe_segment& o = S.one;
+  o.width = g->width;
+  o.height = g->height;
+  o.scale = g->scale;
+  o.origin_x = g->origin_x;
+  o.origin_y = g->origin_y;
+  o.num_kernels = m->K;
+  S.r = g->radius;
+  S.r2 = g->radius * g->radius;
+  S.T = (int)raster_tiles(g->width, g->height);
+  S.K = m->K;
+  *out = S;
   return true;
 }
 
-bool bins_match(const smoe_bins* b, const smoe_model* m) {
-  return b && b->K == m->K && b->C == m->C && b->order == m->order && b->status &&
-         b->ranges && b->vals && b->records;
+// Checks a host segment table (rasters valid, offsets equal to their running sums, model
+// rows inside [0, rows)) and returns its totals.
+bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int* K) {
+  if (!h || n < 1) return false;
+  long long t = 0, k = 0, px = 0;
+  for (int i = 0; i < n; ++i) {
+    const smoe_segment& s = h[i];
+    if (!valid_raster(s.width, s.height, s.scale, s.origin_x, s.origin_y)) return false;
+    if (s.num_kernels < 0 || s.param_offset < 0) return false;
+    if ((long long)s.param_offset + s.num_kernels > rows) return false;
+    if (s.kernel_offset != k || s.tile_offset != t || s.pixel_offset != px) return false;
+    k += s.num_kernels;
+    t += raster_tiles(s.width, s.height);
+    px += (long long)s.width * s.height;
+  }
+  if (t >= (1LL << 31) || k * 16 >= (1LL << 31)) return false;
+  *T = (int)t;
+  *K = (int)k;
+  return true;
+}
+
+bool batch_segs(const smoe_batch* b, Segs* out) {
+  if (!b || !valid_shape(0, b->C, b->order) || !b->params || !b->segments ||
+      b->num_params_rows < 0 || !valid_radius(b->radius))
+    return false;
+  Segs S;
+  std::memset(&S, 0, sizeof(S));
+  if (!check_segments(b->segments_host, b->num_segments, b->num_params_rows, &S.T, &S.K))
+    return false;
+  S.tab = b->segments;
+  S.n = b->num_segments;
+  S.r = b->radius;
+  S.r2 = b->radius * b->radius;
+  *out = S;
+  return true;
+}
+
+bool bins_match(const smoe_bins* b, int K, int C, int order) {
+  return b && b->K == K && b->C == C && b->order == order && b->status && b->ranges && b->vals &&
+         b->records;
 }
 
 struct Layout {
@@ -54,7 +104,9 @@ struct Layout {
       tile_loss, status, total;
 };
 
-Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t capacity) {
+// grads = false: a render-only workspace, without the per-pair gradient partials.
+Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t capacity,
+                 bool grads = true) {
   const size_t rs = (size_t)record_stride(C, order);
   const size_t np = (size_t)num_params(C, order);
   Layout L;
@@ -67,7 +119,7 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   L.keys = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals_alt = o;   o = align_up(o + (size_t)capacity * sizeof(uint32_t));
-  L.pair_grads = o; o = align_up(o + (size_t)capacity * np * sizeof(float));
+  L.pair_grads = o; o = align_up(o + (grads ? (size_t)capacity * np * sizeof(float) : 0));
   L.tile_loss = o;  o = align_up(o + (size_t)max_tiles * sizeof(float));
   L.status = o;     o = align_up(o + 8 * sizeof(int32_t));
   L.total = o;
@@ -75,6 +127,58 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
 }
 
 inline smoe_status hip_status(hipError_t e) { return e == hipSuccess ? SMOE_OK : SMOE_ERR_HIP; }
+
+// The rasters of a fit state: its segment table (batched fit) or its single grid.
+bool fit_segs(const smoe_fit_state* st, Segs* S) {
+  if (st->num_segments > 0) {
+    if (!st->segments || !st->segments_host || !valid_radius(st->grid.radius)) return false;
+    std::memset(S, 0, sizeof(*S));
+    if (!check_segments(st->segments_host, st->num_segments, st->K, &S->T, &S->K)) return false;
+    for (int i = 0; i < st->num_segments; ++i) {
+      const smoe_segment& s = st->segments_host[i];
+      if (s.scale != 1 || s.origin_x != 0 || s.origin_y != 0 || s.param_offset != s.kernel_offset)
+        return false;
+    }
+    if (S->K != st->K) return false;
+    S->tab = st->segments;
+    S->n = st->num_segments;
+    S->r = st->grid.radius;
+    S->r2 = st->grid.radius * st->grid.radius;
+    return true;
+  }
+  const smoe_model m{st->K, st->C, st->order, st->model};
+  if (!single_segs(&m, &st->grid, S)) return false;
+  return st->grid.scale == 1 && st->grid.origin_x == 0 && st->grid.origin_y == 0;
+}
+
+smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
+                     void* const* ev, void* stream) {
+  if (!st || !target) return SMOE_ERR_INVALID;
+  Segs S;
+  if (!valid_shape(st->K, st->C, st->order) || (st->K > 0 && !st->model) || !fit_segs(st, &S) ||
+      !bins_match(&st->bins, S.K, st->C, st->order))
+    return SMOE_ERR_INVALID;
+  if (!st->raw || !st->adam_m || !st->adam_v || !st->image || !st->denom || !st->step ||
+      !st->scalars || !st->bins.pair_grads || !st->bins.tile_loss || st->max_steps < 0)
+    return SMOE_ERR_INVALID;
+  if (S.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto mark = [&](int i) -> hipError_t {
+    return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
+  };
+  hipError_t e = mark(0);
+  if (e == hipSuccess && !st->prepared)
+    e = launch_count(st->C, st->order, st->model, S, st->bins, s);
+  if (e == hipSuccess) e = launch_scan(S, st->bins, s, st->step);
+  if (e == hipSuccess) e = launch_scatter(S, st->bins, s);
+  if (e == hipSuccess) e = mark(1);
+  if (e == hipSuccess) e = launch_fit_tile(*st, S, target, s);
+  if (e == hipSuccess) e = mark(2);
+  if (e == hipSuccess) e = launch_adam_fit(*st, S, loss_out, s);
+  if (e == hipSuccess) e = mark(3);
+  if (e == hipSuccess) st->prepared = 1;
+  return hip_status(e);
+}
 
 }  // namespace
 
@@ -88,12 +192,14 @@ size_t smoe_bins_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t ma
   return layout_of(K, C, order, max_tiles, capacity).total;
 }
 
-smoe_status smoe_bins_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K, int32_t C,
-                             int32_t order, int32_t max_tiles, int32_t capacity) {
+namespace {
+
+smoe_status layout_into(smoe_bins* out, void* workspace, size_t bytes, int32_t K, int32_t C,
+                        int32_t order, int32_t max_tiles, int32_t capacity, bool grads) {
   if (!out || !workspace || !valid_shape(K, C, order) || max_tiles < 1 || capacity < 0)
     return SMOE_ERR_INVALID;
   if (((uintptr_t)workspace & (kAlign - 1)) != 0) return SMOE_ERR_INVALID;
-  const Layout L = layout_of(K, C, order, max_tiles, capacity);
+  const Layout L = layout_of(K, C, order, max_tiles, capacity, grads);
   if (bytes < L.total) return SMOE_ERR_INVALID;
   char* base = static_cast<char*>(workspace);
   smoe_bins b;
@@ -112,35 +218,81 @@ smoe_status smoe_bins_layout(smoe_bins* out, void* workspace, size_t bytes, int3
   b.keys = reinterpret_cast<uint32_t*>(base + L.keys);
   b.vals = reinterpret_cast<uint32_t*>(base + L.vals);
   b.vals_alt = reinterpret_cast<uint32_t*>(base + L.vals_alt);
-  b.pair_grads = reinterpret_cast<float*>(base + L.pair_grads);
+  b.pair_grads = grads ? reinterpret_cast<float*>(base + L.pair_grads) : nullptr;
   b.tile_loss = reinterpret_cast<float*>(base + L.tile_loss);
   b.status = reinterpret_cast<int32_t*>(base + L.status);
   *out = b;
   return SMOE_OK;
 }
 
+}  // namespace
+
+smoe_status smoe_bins_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K, int32_t C,
+                             int32_t order, int32_t max_tiles, int32_t capacity) {
+  return layout_into(out, workspace, bytes, K, C, order, max_tiles, capacity, true);
+}
+
+size_t smoe_render_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t max_tiles,
+                                   int32_t capacity) {
+  if (!valid_shape(K, C, order) || max_tiles < 1 || capacity < 0) return 0;
+  return layout_of(K, C, order, max_tiles, capacity, false).total;
+}
+
+smoe_status smoe_render_workspace_layout(smoe_bins* out, void* workspace, size_t bytes, int32_t K,
+                                         int32_t C, int32_t order, int32_t max_tiles,
+                                         int32_t capacity) {
+  return layout_into(out, workspace, bytes, K, C, order, max_tiles, capacity, false);
+}
+
+smoe_status smoe_segments_layout(smoe_segment* segs, int32_t n, int32_t* total_kernels,
+                                 int32_t* total_tiles, int64_t* total_pixels) {
+  if (!segs || n < 1) return SMOE_ERR_INVALID;
+  long long t = 0, k = 0, px = 0;
+  for (int i = 0; i < n; ++i) {
+    smoe_segment& s = segs[i];
+    if (!valid_raster(s.width, s.height, s.scale, s.origin_x, s.origin_y) || s.num_kernels < 0 ||
+        s.param_offset < 0)
+      return SMOE_ERR_INVALID;
+    s.kernel_offset = (int32_t)k;
+    s.tile_offset = (int32_t)t;
+    s.pixel_offset = px;
+    s.reserved = 0;
+    k += s.num_kernels;
+    t += raster_tiles(s.width, s.height);
+    px += (long long)s.width * s.height;
+    if (t >= (1LL << 31) || k * 16 >= (1LL << 31)) return SMOE_ERR_INVALID;
+  }
+  if (total_kernels) *total_kernels = (int32_t)k;
+  if (total_tiles) *total_tiles = (int32_t)t;
+  if (total_pixels) *total_pixels = px;
+  return SMOE_OK;
+}
+
 smoe_status smoe_bin(const smoe_model* model, const smoe_grid* grid, smoe_bins* bins,
                      void* stream) {
-  GridArgs g;
-  if (!valid_model(model) || !make_grid(grid, &g) || !bins_match(bins, model))
+  Segs S;
+  if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order))
     return SMOE_ERR_INVALID;
-  if (g.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
-  return hip_status(launch_bin(*model, g, *bins, static_cast<hipStream_t>(stream)));
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  return hip_status(launch_bin(model->C, model->order, model->params, S, *bins,
+                               static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_render(const smoe_model* model, const smoe_grid* grid, const smoe_bins* bins,
                         float* image, float* denom, const float* target, float* loss_out,
                         void* stream) {
-  GridArgs g;
-  if (!valid_model(model) || !make_grid(grid, &g) || !bins_match(bins, model) || !image)
+  Segs S;
+  if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
+      !image)
     return SMOE_ERR_INVALID;
-  if (g.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
   const bool loss = target && loss_out;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_render(*model, g, *bins, image, denom, loss ? target : nullptr, s);
+  hipError_t e =
+      launch_render(model->C, model->order, S, *bins, image, denom, loss ? target : nullptr, s);
   if (e == hipSuccess && loss) {
-    const float inv_n = (float)(1.0 / ((double)g.W * g.H * model->C));
-    e = launch_loss_reduce(*bins, g.T, inv_n, loss_out, s);
+    const float inv_n = (float)(1.0 / ((double)grid->width * grid->height * model->C));
+    e = launch_loss_reduce(*bins, S.T, inv_n, loss_out, s);
   }
   return hip_status(e);
 }
@@ -149,15 +301,36 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
                                  const smoe_bins* bins, const float* image, const float* denom,
                                  const float* grad_image, const float* target, float* grads,
                                  void* stream) {
-  GridArgs g;
-  if (!valid_model(model) || !make_grid(grid, &g) || !bins_match(bins, model) || !image ||
-      !denom || !grads || (grad_image == nullptr) == (target == nullptr) || !bins->pair_grads)
+  Segs S;
+  if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
+      !image || !denom || !grads || (grad_image == nullptr) == (target == nullptr) ||
+      !bins->pair_grads)
     return SMOE_ERR_INVALID;
-  if (g.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_backward(*model, g, *bins, image, denom, grad_image, target, s);
-  if (e == hipSuccess) e = launch_gather(*model, g, *bins, grads, s);
+  hipError_t e =
+      launch_backward(model->C, model->order, S, *bins, image, denom, grad_image, target, s);
+  if (e == hipSuccess) e = launch_gather(model->C, model->order, S, *bins, grads, s);
   return hip_status(e);
+}
+
+smoe_status smoe_bin_batched(const smoe_batch* batch, smoe_bins* bins, void* stream) {
+  Segs S;
+  if (!batch_segs(batch, &S) || !bins_match(bins, S.K, batch->C, batch->order))
+    return SMOE_ERR_INVALID;
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  return hip_status(launch_bin(batch->C, batch->order, batch->params, S, *bins,
+                               static_cast<hipStream_t>(stream)));
+}
+
+smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, float* images,
+                                float* denoms, void* stream) {
+  Segs S;
+  if (!batch_segs(batch, &S) || !bins_match(bins, S.K, batch->C, batch->order) || !images)
+    return SMOE_ERR_INVALID;
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  return hip_status(launch_render(batch->C, batch->order, S, *bins, images, denoms, nullptr,
+                                  static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw, float* model,
@@ -165,41 +338,6 @@ smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* r
   if (!valid_shape(K, C, order) || (K > 0 && (!raw || !model))) return SMOE_ERR_INVALID;
   return hip_status(launch_materialize(K, C, order, raw, model, static_cast<hipStream_t>(stream)));
 }
-
-namespace {
-
-smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
-                     void* const* ev, void* stream) {
-  if (!st || !target) return SMOE_ERR_INVALID;
-  const smoe_model m{st->K, st->C, st->order, st->model};
-  GridArgs g;
-  if (!valid_model(&m) || !make_grid(&st->grid, &g) || !bins_match(&st->bins, &m))
-    return SMOE_ERR_INVALID;
-  if (st->grid.scale != 1 || st->grid.origin_x != 0 || st->grid.origin_y != 0)
-    return SMOE_ERR_INVALID;
-  if (!st->raw || !st->adam_m || !st->adam_v || !st->image || !st->denom || !st->step ||
-      !st->scalars || !st->bins.pair_grads || !st->bins.tile_loss)
-    return SMOE_ERR_INVALID;
-  if (st->max_steps < 0) return SMOE_ERR_INVALID;
-  if (g.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  auto mark = [&](int i) -> hipError_t {
-    return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
-  };
-  hipError_t e = mark(0);
-  if (e == hipSuccess && !st->prepared) e = launch_count(m, g, st->bins, s);
-  if (e == hipSuccess) e = launch_scan(g, st->bins, s, st->step);
-  if (e == hipSuccess) e = launch_scatter(m, g, st->bins, s);
-  if (e == hipSuccess) e = mark(1);
-  if (e == hipSuccess) e = launch_fit_tile(*st, g, target, s);
-  if (e == hipSuccess) e = mark(2);
-  if (e == hipSuccess) e = launch_adam_fit(*st, g, loss_out, s);
-  if (e == hipSuccess) e = mark(3);
-  if (e == hipSuccess) st->prepared = 1;
-  return hip_status(e);
-}
-
-}  // namespace
 
 smoe_status smoe_fit_step(smoe_fit_state* st, const float* target, float* loss_out,
                           void* stream) {
@@ -212,13 +350,20 @@ smoe_status smoe_fit_step_timed(smoe_fit_state* st, const float* target, float* 
   return fit_step(st, target, loss_out, stage_events, stream);
 }
 
+smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* stream) {
+  Segs S;
+  if (!st || !out || !st->bins.tile_loss || !fit_segs(st, &S)) return SMOE_ERR_INVALID;
+  return hip_status(launch_segment_losses(S, st->bins, out, static_cast<hipStream_t>(stream)));
+}
+
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
                             const smoe_bins* bins, uint64_t* out2, void* stream) {
-  GridArgs g;
-  if (!valid_model(model) || !make_grid(grid, &g) || !bins_match(bins, model) || !out2)
+  Segs S;
+  if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
+      !out2)
     return SMOE_ERR_INVALID;
-  if (g.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
-  return hip_status(launch_pair_stats(*model, g, *bins, out2, static_cast<hipStream_t>(stream)));
+  if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
+  return hip_status(launch_pair_stats(S, *bins, out2, static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream) {

@@ -26,14 +26,14 @@ __device__ __forceinline__ bool axis_range(float lo, float hi, int n, int& i0, i
 // centres inside the square box of half-side R = r sqrt(lambda_max(L L^T)) around mu,
 // as the exact binary32 sequence of the ABI contract.
 __device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l11, float l21,
-                                                  float l22, const GridArgs& g) {
+                                                  float l22, const SegGrid& g, float r) {
   const float sxx = l11 * l11;
   const float sxy = l11 * l21;
   const float syy = l21 * l21 + l22 * l22;
   const float h = 0.5f * (sxx + syy);
   const float d = 0.5f * (sxx - syy);
   const float lam = h + sqrtf(d * d + sxy * sxy);
-  const float R = g.r * sqrtf(lam);
+  const float R = r * sqrtf(lam);
   const float fs = (float)g.scale;
   const float X0 = (mux - R) * fs - (float)g.ox;
   const float X1 = (mux + R) * fs - (float)g.ox;
@@ -48,10 +48,30 @@ __device__ __forceinline__ int rect_count(int4 rc) {
   return rc.z < rc.x ? 0 : (rc.z - rc.x + 1) * (rc.w - rc.y + 1);
 }
 
-// One increment per covered block: the histogram of the block-id digit.
-__device__ __forceinline__ void count_blocks(int4 rc, int ntx, int32_t* __restrict__ tile_counts) {
+// One increment per covered block (global block ids): the histogram of the block-id digit.
+__device__ __forceinline__ void count_blocks(int4 rc, const SegGrid& g,
+                                             int32_t* __restrict__ tile_counts) {
   for (int ty = rc.y; ty <= rc.w; ++ty)
-    for (int tx = rc.x; tx <= rc.z; ++tx) atomicAdd(&tile_counts[ty * ntx + tx], 1);
+    for (int tx = rc.x; tx <= rc.z; ++tx)
+      atomicAdd(&tile_counts[g.tile_offset + ty * g.ntx + tx], 1);
+}
+
+// Render record of kernel row j from its materialized parameter row p (layout in
+// smoe_internal.h).
+__device__ __forceinline__ void write_record(float* __restrict__ rec, const float* __restrict__ p,
+                                             int ne, int rs) {
+  const float l11 = p[2], l21 = p[3], l22 = p[4];
+  const float i11 = 1.0f / l11;
+  const float i22 = 1.0f / l22;
+  rec[0] = p[0];
+  rec[1] = p[1];
+  rec[2] = i11;
+  rec[3] = l21;
+  rec[4] = i22;
+  rec[5] = p[5] * kLog2e;
+  rec[6] = l21 * i22;
+  for (int i = 0; i < ne; ++i) rec[kRecExpert + i] = p[6 + i];
+  for (int i = kRecExpert + ne; i < rs; ++i) rec[i] = 0.0f;
 }
 
 // Exclusive scan of per-block counts into [begin, end) ranges by one workgroup of NT

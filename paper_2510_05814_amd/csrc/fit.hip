@@ -20,7 +20,7 @@ namespace smoe {
 namespace {
 
 struct FitTileArgs {
-  GridArgs g;
+  Segs S;
   const float* __restrict__ records;
   const int2* __restrict__ ranges;
   uint32_t* __restrict__ vals;
@@ -31,24 +31,28 @@ struct FitTileArgs {
   float* __restrict__ denom;
   float* __restrict__ tile_loss;
   float* __restrict__ pair_grads;
-  float inv_n2;  // 2 / (W H C)
 };
 
 template <int C, int ORDER>
 __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
   __shared__ float4 srec[LDS_FLOATS / 4];
-  const int tile = xcd_block(blockIdx.x, a.g.T);
+  const int tile = xcd_block(blockIdx.x, a.S.T);
   const int2 rg = a.ranges[tile];
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  // MSE of this raster: dL/dy = 2 (y - t) / (W H C); its squared errors are stored already
+  // divided by W H C, so that the sum over all blocks is the sum of the rasters' MSEs.
+  const float inv_n2 = 2.0f / ((float)sg.W * (float)sg.H * (float)C);
+  const float inv_n = 1.0f / ((float)sg.W * (float)sg.H * (float)C);
   // Order the bucket (the scatter appended in arbitrary order) and reset its cursor.
   if (threadIdx.x == 0) a.cursors[tile] = 0;
   constexpr int run = LDS_FLOATS >= 1024 ? 1024 : (LDS_FLOATS >= 512 ? 512 : 256);
   sort_bucket(a.vals + rg.x, a.vals_alt + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec),
               run);
 
-  const PixelCoords px = lane_pixels(a.g, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, rg, srec, D, N);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, D, N);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -60,8 +64,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
     sd.gy[i] = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) sd.g[i][c] = 0.0f;
-    if (px.u < a.g.W && v < a.g.H) {
-      const size_t p = (size_t)v * a.g.W + px.u;
+    if (px.u < sg.W && v < sg.H) {
+      const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const bool cov = D[i] > 0.0f;
       const float invD = cov ? 1.0f / D[i] : 0.0f;
 #pragma unroll
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
         const float d = yc - a.target[p * C + c];
         err = __builtin_fmaf(d, d, err);
         if (cov) {
-          sd.g[i][c] = d * a.inv_n2;
+          sd.g[i][c] = d * inv_n2;
           sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
         }
       }
@@ -81,20 +85,18 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
     }
   }
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
-  if (threadIdx.x == 0) a.tile_loss[tile] = err;
+  if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  backward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, rg, srec, true, sd, a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, true, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {
-  int K;
-  GridArgs g;
+  Segs S;
   const int4* __restrict__ tile_rects_in;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
   const float* __restrict__ pair_grads;
-  const float* __restrict__ tile_loss;
-  float inv_n;
+  const float* __restrict__ tile_loss;  // per-block squared errors / (W H C)
   int32_t* __restrict__ status;
   StepScalarsArgs step;
   float* __restrict__ raw;
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
     // Loss: the whole workgroup sums the per-block squared errors in a fixed order, four
     // independent float4 streams per thread so that the loads overlap.
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const int T4 = f.g.T >> 2;
+    const int T4 = f.S.T >> 2;
     const float4* tl4 = reinterpret_cast<const float4*>(f.tile_loss);
     for (int q = threadIdx.x; q < T4; q += 4 * kAdamThreads) {
 #pragma unroll
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
         }
       }
     }
-    for (int t = (T4 << 2) + threadIdx.x; t < f.g.T; t += kAdamThreads) acc[0] += f.tile_loss[t];
+    for (int t = (T4 << 2) + threadIdx.x; t < f.S.T; t += kAdamThreads) acc[0] += f.tile_loss[t];
     float tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = tot;
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
     if (threadIdx.x == 0) {
       float sum = 0.0f;
       for (int w = 0; w < kAdamThreads / 64; ++w) sum += s_red[w];
-      const float loss = sum * f.inv_n;
+      const float loss = sum;
       if (f.step.loss_out) f.step.loss_out[0] = loss;
       if (f.step.loss_history && t0 < f.step.max_steps) f.step.loss_history[t0] = loss;
     }
@@ -171,11 +173,12 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
 
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = gid >> 4, i = gid & 15;
-  const bool live = j < f.K;
+  const bool live = j < f.S.K;
+  const SegGrid sg = seg_of_kernel(f.S, live ? j : 0);
   float pm = 0.0f;  // materialized value of parameter i after the step
   if (live && skip && i < NP) pm = f.model[(size_t)j * NP + i];
-  const float gi = (live && !skip) ? gather_param<NP>(j, i, f.g.ntx, f.tile_rects_in, f.ranges,
-                                                      f.vals, f.pair_grads)
+  const float gi = (live && !skip) ? gather_param<NP>(j, i, sg, f.tile_rects_in, f.ranges, f.vals,
+                                                      f.pair_grads)
                                    : 0.0f;
   if (live && !skip && i < NP) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
@@ -210,14 +213,30 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       f.records[(size_t)j * RS + i] = fld;
     }
     if (i == 0) {
-      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, f.g);
+      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, sg, f.S.r);
       f.tile_rects_out[j] = rc;
       f.counts[j] = rect_count(rc);
-      count_blocks(rc, f.g.ntx, f.tile_counts);
+      count_blocks(rc, sg, f.tile_counts);
     }
   }
   // The counter itself is written once; every workgroup read the shadow copy instead.
   if (blockIdx.x == 0 && threadIdx.x == 0 && !skip) f.step.step[0] = t0 + 1;
+}
+
+// Reporting: the loss of each raster of the last fit step (one workgroup per segment sums
+// its blocks' normalised squared errors in a fixed order).
+__global__ __launch_bounds__(256) void k_segment_losses(Segs S, const float* __restrict__ tile_loss,
+                                                        float* __restrict__ out) {
+  __shared__ float s_red[4];
+  const smoe_segment seg = S.tab ? S.tab[blockIdx.x] : S.one;
+  const int T0 = seg.tile_offset;
+  const int Ts = ((seg.width + 15) >> 4) * ((seg.height + 15) >> 4);
+  float acc = 0.0f;
+  for (int t = threadIdx.x; t < Ts; t += 256) acc += tile_loss[T0 + t];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
 __global__ __launch_bounds__(128) void k_materialize(int n_rows, int NP,
@@ -232,39 +251,29 @@ __global__ __launch_bounds__(128) void k_materialize(int n_rows, int NP,
 
 }  // namespace
 
-hipError_t launch_fit_tile(const smoe_fit_state& st, const GridArgs& g, const float* target,
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, const float* target,
                            hipStream_t s) {
   const smoe_bins& b = st.bins;
-  FitTileArgs a{g,
-                b.records,
-                reinterpret_cast<const int2*>(b.ranges),
-                b.vals,
-                b.vals_alt,
-                b.tile_counts,
-                target,
-                st.image,
-                st.denom,
-                b.tile_loss,
-                b.pair_grads,
-                2.0f / ((float)g.W * (float)g.H * (float)st.C)};
-  if (st.C == 1 && st.order == 0) k_fit_tile<1, 0><<<g.T, kWave, 0, s>>>(a);
-  else if (st.C == 1 && st.order == 1) k_fit_tile<1, 1><<<g.T, kWave, 0, s>>>(a);
-  else if (st.C == 3 && st.order == 0) k_fit_tile<3, 0><<<g.T, kWave, 0, s>>>(a);
-  else k_fit_tile<3, 1><<<g.T, kWave, 0, s>>>(a);
+  FitTileArgs a{S,        b.records, reinterpret_cast<const int2*>(b.ranges),
+                b.vals,   b.vals_alt, b.tile_counts,
+                target,   st.image,  st.denom,
+                b.tile_loss, b.pair_grads};
+  if (st.C == 1 && st.order == 0) k_fit_tile<1, 0><<<S.T, kWave, 0, s>>>(a);
+  else if (st.C == 1 && st.order == 1) k_fit_tile<1, 1><<<S.T, kWave, 0, s>>>(a);
+  else if (st.C == 3 && st.order == 0) k_fit_tile<3, 0><<<S.T, kWave, 0, s>>>(a);
+  else k_fit_tile<3, 1><<<S.T, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_adam_fit(const smoe_fit_state& st, const GridArgs& g, float* loss_out,
+hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_out,
                            hipStream_t s) {
   const smoe_bins& b = st.bins;
-  AdamFitArgs f{st.K,
-                g,
+  AdamFitArgs f{S,
                 reinterpret_cast<const int4*>(b.tile_rects),
                 reinterpret_cast<const int2*>(b.ranges),
                 b.vals,
                 b.pair_grads,
                 b.tile_loss,
-                (float)(1.0 / ((double)g.W * g.H * st.C)),
                 b.status,
                 make_step_scalars_args(st, loss_out),
                 st.raw,
@@ -277,11 +286,16 @@ hipError_t launch_adam_fit(const smoe_fit_state& st, const GridArgs& g, float* l
                 b.counts,
                 b.tile_counts};
   // at least one workgroup, so that the loss and the step counter advance even for K = 0
-  const int blocks = max(1, (int)(((long long)st.K * 16 + kAdamThreads - 1) / kAdamThreads));
+  const int blocks = max(1, (int)(((long long)S.K * 16 + kAdamThreads - 1) / kAdamThreads));
   if (st.C == 1 && st.order == 0) k_adam_fit<1, 0><<<blocks, kAdamThreads, 0, s>>>(f);
   else if (st.C == 1 && st.order == 1) k_adam_fit<1, 1><<<blocks, kAdamThreads, 0, s>>>(f);
   else if (st.C == 3 && st.order == 0) k_adam_fit<3, 0><<<blocks, kAdamThreads, 0, s>>>(f);
   else k_adam_fit<3, 1><<<blocks, kAdamThreads, 0, s>>>(f);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_losses(const Segs& S, const smoe_bins& b, float* out, hipStream_t s) {
+  k_segment_losses<<<S.tab ? S.n : 1, 256, 0, s>>>(S, b.tile_loss, out);
   return hipGetLastError();
 }
 

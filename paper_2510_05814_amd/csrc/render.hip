@@ -16,7 +16,7 @@ namespace smoe {
 namespace {
 
 struct RenderArgs {
-  GridArgs g;
+  Segs S;
   const float* __restrict__ records;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -29,16 +29,17 @@ struct RenderArgs {
 template <int C, int ORDER>
 __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  const int tile = xcd_block(blockIdx.x, a.g.T);
-  const PixelCoords px = lane_pixels(a.g, tile);
+  const int tile = xcd_block(blockIdx.x, a.S.T);
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.g.r2, a.records, a.vals, a.ranges[tile], srec, D, N);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, D, N);
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const int v = px.v0 + 4 * i;
-    if (px.u < a.g.W && v < a.g.H) {
-      const size_t p = (size_t)v * a.g.W + px.u;
+    if (px.u < sg.W && v < sg.H) {
+      const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const float yc = (D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f;
@@ -78,14 +79,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
 // Diagnostic: per block, the tested (pixel, kernel) pairs of in-image pixels and those with
 // q <= r^2, added atomically into out2 = (tested, active).
 constexpr int kStatThreads = kTilePixels;
-__global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const float* __restrict__ records,
+__global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float* __restrict__ records,
                                                              int rs, const int2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ vals,
                                                              unsigned long long* __restrict__ out2) {
   __shared__ unsigned long long s_act[kStatThreads / 64];
   __shared__ unsigned long long s_cnt[kStatThreads / 64];
   const int tile = blockIdx.x;
-  const int tx = tile % g.ntx, ty = tile / g.ntx;
+  const SegGrid g = seg_of_tile(S, tile);
+  const int lt = tile - g.tile_offset;
+  const int tx = lt % g.ntx, ty = lt / g.ntx;
   const int u = tx * kTile + (threadIdx.x & 15);
   const int v = ty * kTile + (threadIdx.x >> 4);
   const bool inside = u < g.W && v < g.H;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(GridArgs g, const f
     const float w = dy - tt;
     const float z2 = w * r[4];
     const float q = z1 * z1 + z2 * z2;
-    act += (q <= g.r2) ? 1ull : 0ull;
+    act += (q <= S.r2) ? 1ull : 0ull;
   }
   unsigned long long cnt = inside ? 1ull : 0ull;
   for (int off = 32; off > 0; off >>= 1) {
@@ -127,22 +130,20 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
-hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* image,
+hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, float* image,
                          float* denom, const float* target, hipStream_t s) {
-  RenderArgs a{g,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
+  RenderArgs a{S,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
                target, target ? b.tile_loss : nullptr};
-  if (m.C == 1 && m.order == 0) k_render<1, 0><<<g.T, kWave, 0, s>>>(a);
-  else if (m.C == 1 && m.order == 1) k_render<1, 1><<<g.T, kWave, 0, s>>>(a);
-  else if (m.C == 3 && m.order == 0) k_render<3, 0><<<g.T, kWave, 0, s>>>(a);
-  else k_render<3, 1><<<g.T, kWave, 0, s>>>(a);
+  if (C == 1 && order == 0) k_render<1, 0><<<S.T, kWave, 0, s>>>(a);
+  else if (C == 1 && order == 1) k_render<1, 1><<<S.T, kWave, 0, s>>>(a);
+  else if (C == 3 && order == 0) k_render<3, 0><<<S.T, kWave, 0, s>>>(a);
+  else k_render<3, 1><<<S.T, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                             uint64_t* out2, hipStream_t s) {
-  (void)m;
+hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out2, hipStream_t s) {
   k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(out2), 2);
-  k_pair_stats<<<g.T, kStatThreads, 0, s>>>(g, b.records, b.record_stride,
+  k_pair_stats<<<S.T, kStatThreads, 0, s>>>(S, b.records, b.record_stride,
                                             reinterpret_cast<const int2*>(b.ranges), b.vals,
                                             reinterpret_cast<unsigned long long*>(out2));
   return hipGetLastError();

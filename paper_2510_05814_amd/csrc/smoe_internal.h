@@ -27,16 +27,69 @@ __host__ __device__ constexpr int record_stride(int C, int order) {
 }
 constexpr int kRecExpert = 7;
 
-// Raster description derived from smoe_grid on the host.
-struct GridArgs {
-  int W, H;        // output pixels
-  int scale;       // integer upscale
-  int ox, oy;      // origin in output pixels
-  float r;         // truncation radius
-  float r2;        // r*r, binary32
-  float inv_s;     // 1/scale, binary32
-  int ntx, nty, T; // blocks
+// The rasters of one call.  A batched call (several images of a batched fit, or several
+// render requests) numbers the blocks of all its rasters consecutively (segment s owns
+// blocks [tile_offset, tile_offset + T_s)) and its kernel rows likewise; each kernel and
+// each block then finds its segment by a binary search on those offsets.  A single-raster
+// call has no table (tab == null) and uses `one`.
+struct Segs {
+  const smoe_segment* __restrict__ tab;  // device table of n segments, or null
+  int n;
+  smoe_segment one;                      // the single raster when tab is null
+  float r, r2;                           // truncation radius and r*r (binary32)
+  int T;                                 // blocks of all segments
+  int K;                                 // kernel rows of all segments
 };
+
+// One segment's raster, as the kernels use it.
+struct SegGrid {
+  int W, H, scale, ox, oy, ntx;
+  float inv_s;                 // 1/scale, binary32
+  int tile_offset, kernel_offset, param_offset, K;
+  long long pixel_offset;
+};
+
+__host__ __device__ inline SegGrid seg_grid_of(const smoe_segment& s) {
+  SegGrid g;
+  g.W = s.width;
+  g.H = s.height;
+  g.scale = s.scale;
+  g.ox = s.origin_x;
+  g.oy = s.origin_y;
+  g.ntx = (s.width + 15) >> 4;
+  g.inv_s = 1.0f / (float)s.scale;
+  g.tile_offset = s.tile_offset;
+  g.kernel_offset = s.kernel_offset;
+  g.param_offset = s.param_offset;
+  g.K = s.num_kernels;
+  g.pixel_offset = s.pixel_offset;
+  return g;
+}
+
+// Segment of global block t: the last segment whose tile_offset <= t.
+__device__ __forceinline__ SegGrid seg_of_tile(const Segs& S, int t) {
+  if (!S.tab) return seg_grid_of(S.one);
+  int lo = 0, hi = S.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.tab[mid].tile_offset <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return seg_grid_of(S.tab[lo]);
+}
+
+// Segment of global kernel row j: the last segment whose kernel_offset <= j (segments
+// without kernels share their offset with the next one and are skipped by "last").
+__device__ __forceinline__ SegGrid seg_of_kernel(const Segs& S, int j) {
+  if (!S.tab) return seg_grid_of(S.one);
+  int lo = 0, hi = S.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.tab[mid].kernel_offset <= j) lo = mid;
+    else hi = mid - 1;
+  }
+  return seg_grid_of(S.tab[lo]);
+}
 
 // Output pixel index -> native sampling coordinate, the exact binary32 sequence of the
 // ABI contract: ((o + u) + 0.5) * inv_s.
@@ -67,12 +120,13 @@ __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, i
   return (a < hi && vals[a] == j) ? a : -1;
 }
 
-// Gradient of parameter i of kernel j: the sum of its per-block partials over the kernel's
-// block rectangle in row-major order (a fixed order, so the result is reproducible).  Used
-// with 16 lanes per kernel, lane i reading element i of each partial row, so a group's
-// reads of one row are contiguous.
+// Gradient of parameter i of kernel row j: the sum of its per-block partials over the
+// kernel's block rectangle in row-major order (a fixed order, so the result is
+// reproducible).  Used with 16 lanes per kernel, lane i reading element i of each partial
+// row, so a group's reads of one row are contiguous.
 template <int NP>
-__device__ __forceinline__ float gather_param(int j, int i, int ntx, const int4* __restrict__ rects,
+__device__ __forceinline__ float gather_param(int j, int i, const SegGrid& sg,
+                                              const int4* __restrict__ rects,
                                               const int2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals,
                                               const float* __restrict__ pair_grads) {
@@ -80,7 +134,7 @@ __device__ __forceinline__ float gather_param(int j, int i, int ntx, const int4*
   const int4 rc = rects[j];
   for (int ty = rc.y; ty <= rc.w; ++ty)
     for (int tx = rc.x; tx <= rc.z; ++tx) {
-      const int2 rg = ranges[ty * ntx + tx];
+      const int2 rg = ranges[sg.tile_offset + ty * sg.ntx + tx];
       if (rg.y <= rg.x) continue;
       const int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j);
       if (p >= 0 && i < NP) acc += pair_grads[(size_t)p * NP + i];
@@ -88,34 +142,36 @@ __device__ __forceinline__ float gather_param(int j, int i, int ntx, const int4*
   return acc;
 }
 
-hipError_t launch_bin(const smoe_model& m, const GridArgs& g, const smoe_bins& b, hipStream_t s);
+// Launchers.  `params` rows are addressed through each segment's param_offset; every
+// per-kernel workspace array through kernel_offset; images through pixel_offset.
+hipError_t launch_bin(int C, int order, const float* params, const Segs& S, const smoe_bins& b,
+                      hipStream_t s);
+hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, float* image,
+                         float* denom, const float* target, hipStream_t s);
+hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out2, hipStream_t s);
+hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,
+                              hipStream_t s);
+hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
+                           const float* image, const float* denom, const float* grad_image,
+                           const float* target, hipStream_t s);
+hipError_t launch_gather(int C, int order, const Segs& S, const smoe_bins& b, float* grads,
+                         hipStream_t s);
+hipError_t launch_materialize(int K, int C, int order, const float* raw, float* model,
+                              hipStream_t s);
 // Fit-step pieces: block counters, boxes and records of the current model (fill,
 // preprocess); the scan of the counters into ranges; the scatter into buckets; the fused
 // per-block sort + render + backward; Adam fused with the next step's boxes, records and
 // counters.
-hipError_t launch_count(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                        hipStream_t s);
+hipError_t launch_count(int C, int order, const float* params, const Segs& S,
+                        const smoe_bins& b, hipStream_t s);
 // fit_step (the fit step only): the step counter to snapshot for the step's Adam kernel.
-hipError_t launch_scan(const GridArgs& g, const smoe_bins& b, hipStream_t s,
+hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s,
                        const int32_t* fit_step = nullptr);
-hipError_t launch_scatter(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                          hipStream_t s);
-hipError_t launch_fit_tile(const smoe_fit_state& st, const GridArgs& g, const float* target,
+hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s);
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, const float* target,
                            hipStream_t s);
-hipError_t launch_adam_fit(const smoe_fit_state& st, const GridArgs& g, float* loss_out,
+hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_out,
                            hipStream_t s);
-hipError_t launch_render(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* image,
-                         float* denom, const float* target, hipStream_t s);
-hipError_t launch_pair_stats(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                             uint64_t* out2, hipStream_t s);
-hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,
-                              hipStream_t s);
-hipError_t launch_backward(const smoe_model& m, const GridArgs& g, const smoe_bins& b,
-                           const float* image, const float* denom, const float* grad_image,
-                           const float* target, hipStream_t s);
-hipError_t launch_gather(const smoe_model& m, const GridArgs& g, const smoe_bins& b, float* grads,
-                         hipStream_t s);
-hipError_t launch_materialize(int K, int C, int order, const float* raw, float* model,
-                              hipStream_t s);
+hipError_t launch_segment_losses(const Segs& S, const smoe_bins& b, float* out, hipStream_t s);
 
 }  // namespace smoe

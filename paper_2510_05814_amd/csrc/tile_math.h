@@ -16,13 +16,14 @@ constexpr int kChunk = 64;                     // records staged in LDS per chun
 constexpr int kRows = kTilePixels / kWave;     // pixels per lane (4)
 
 struct PixelCoords {
-  int u;            // output column of the lane
+  int u;            // output column of the lane (within its raster)
   int v0;           // output row of the lane's first pixel (rows v0 + 4i)
   float x;          // sampling coordinates
   float y[kRows];
 };
 
-__device__ __forceinline__ PixelCoords lane_pixels(const GridArgs& g, int tile) {
+// `tile` is the block index inside the segment's raster.
+__device__ __forceinline__ PixelCoords lane_pixels(const SegGrid& g, int tile) {
   PixelCoords p;
   const int lane = threadIdx.x & 63;
   const int tx = tile % g.ntx, ty = tile / g.ntx;

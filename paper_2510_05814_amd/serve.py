@@ -1,0 +1,371 @@
+"""Serving render: fitted SMoE models kept resident in HBM and rendered on request.
+
+A request names a resident model, an integer upscale factor s and an output window
+(width, height, origin) in the upscaled raster.  Output pixel (u, v) samples the
+continuous regression (Eq. 3-5) at native coordinate ((origin + u) + 0.5) / s, so every
+factor is a native super-resolution of the same model, not an interpolation of a render.
+
+Two servers share the request format and the report:
+
+* ``Server`` -- continuous batching.  Requests that have arrived wait in a FIFO queue.
+  Whenever one of its streams is free, the server takes the queue's head requests whose
+  memory (output image + their share of the binning workspace) fits the HBM budget
+  beside the batches still in flight, lays them out as segments of one raster table, and
+  issues one batched binning and ONE render launch over the concatenated (request,
+  block) list on that stream.  Batches on different streams overlap on the device;
+  finished batches release their memory and stream, and the queue is admitted again.
+  Nothing waits on the device except to learn which batches have finished.
+* ``PlainServer`` -- the baseline: one bin + render launch sequence per request, in
+  arrival order on one stream, the host waiting for each request before the next.
+
+Latency of a request = device completion time of its render - arrival time, both on the
+host clock (the completion time is the request's completion event measured against a
+reference event recorded at the start).  The workspace of a batch is sized from an upper
+bound of its (block, kernel) pairs computed on the host from the resident models' box
+sizes (Sec. IV-B), so no batch needs a host round-trip to learn its pair count.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _capi as C
+from .core import Bins, Segments, _check_params, make_grid, model_struct
+
+TILE = 16
+
+
+@dataclass
+class RenderRequest:
+    model: int
+    scale: int
+    width: int
+    height: int
+    origin_x: int = 0
+    origin_y: int = 0
+    arrival: float = 0.0      # seconds from the start of the run
+
+
+@dataclass
+class RenderResult:
+    request: RenderRequest
+    done: float               # device completion, seconds from the start of the run
+    batch: int
+    image: torch.Tensor | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.request.arrival
+
+
+class BoxSpans:
+    """Host-side upper bounds of the (block, kernel) pairs a render creates, from each
+    kernel's square box (half-side r sqrt(lambda_max) of its covariance, Sec. IV-B).
+
+    models: float64/float32 [K_i, NP] materialized rows, one array per model."""
+
+    def __init__(self, models, radius: float = 3.0):
+        self.radius = float(radius)
+        self._R = []
+        for m in models:
+            m = np.asarray(m, dtype=np.float64)
+            l11, l21, l22 = m[:, 2], m[:, 3], m[:, 4]
+            sxx, sxy, syy = l11 * l11, l11 * l21, l21 * l21 + l22 * l22
+            lam = 0.5 * (sxx + syy) + np.sqrt((0.5 * (sxx - syy)) ** 2 + sxy * sxy)
+            self._R.append(self.radius * np.sqrt(lam))
+        self._spans = {}
+
+    def _span_table(self, i: int, scale: int):
+        """Sorted per-kernel bound on the blocks its box spans per axis, with prefix sums."""
+        key = (i, scale)
+        if key not in self._spans:
+            # pixels spanned <= floor(2 R s) + 1; 2 more absorb the binary32 rounding of the
+            # box edges; n pixels at any alignment touch <= ceil((n - 1) / 16) + 1 blocks.
+            n = np.floor(2.0 * self._R[i] * scale * (1.0 + 1e-5)).astype(np.int64) + 3
+            b = np.sort((n + TILE - 2) // TILE + 1)
+            self._spans[key] = (b, np.concatenate([[0], np.cumsum(b)]),
+                                np.concatenate([[0], np.cumsum(b * b)]))
+        return self._spans[key]
+
+    def pair_bound(self, i: int, scale: int, width: int, height: int) -> int:
+        """Sum over model i's kernels of min(span, blocks across) * min(span, blocks down)."""
+        b, s1, s2 = self._span_table(i, scale)
+        a = (width + TILE - 1) // TILE
+        c = (height + TILE - 1) // TILE
+        a, c = min(a, c), max(a, c)
+        ia = int(np.searchsorted(b, a, side="right"))
+        ic = int(np.searchsorted(b, c, side="right"))
+        return int(s2[ia] + a * (s1[ic] - s1[ia]) + a * c * (len(b) - ic))
+
+
+class ModelBank:
+    """Materialized rows of every resident model in one device array [sum K, NP], with the
+    host-side pair bounds of their renders.  models: float32 [K_i, NP] materialized rows
+    (numpy arrays or tensors)."""
+
+    def __init__(self, models, C_: int, order: int, radius: float = 3.0, device="cuda"):
+        rows = [m.detach().float().cpu() if torch.is_tensor(m) else
+                torch.as_tensor(np.asarray(m, dtype=np.float32)) for m in models]
+        self.C, self.order, self.radius = C_, order, float(radius)
+        self.K = [int(r.shape[0]) for r in rows]
+        self.offset = [int(x) for x in np.concatenate([[0], np.cumsum(self.K)[:-1]])]
+        self.params = torch.cat(rows).to(device).contiguous()
+        _check_params(self.params, C_, order)
+        self.spans = BoxSpans([r.numpy() for r in rows], radius)
+
+    def __len__(self):
+        return len(self.K)
+
+    def rows(self, i: int) -> torch.Tensor:
+        return self.params[self.offset[i]:self.offset[i] + self.K[i]]
+
+    def pair_bound(self, i: int, scale: int, width: int, height: int) -> int:
+        return self.spans.pair_bound(i, scale, width, height)
+
+
+def admit(pending, in_use: int, budget: int, footprint, max_batch: int, max_pixels: int):
+    """Admission: pops from the FIFO `pending` the longest head run of requests whose
+    footprint(batch) fits `budget - in_use`, at most max_batch requests and (beyond the
+    first) max_pixels output pixels.  A request is never skipped for a later one.  Raises
+    if the head alone exceeds the whole budget."""
+    batch = []
+    px = 0
+    while pending and len(batch) < max_batch:
+        r = pending[0]
+        npx = px + r.width * r.height
+        if batch and npx > max_pixels:
+            break
+        need = footprint(batch + [r])
+        if in_use + need > budget:
+            if not batch and need > budget:
+                raise ValueError(f"request needs {need} bytes, over the {budget}-byte budget")
+            break
+        batch.append(pending.popleft())
+        px = npx
+    return batch
+
+
+def _tiles(w: int, h: int) -> int:
+    return ((w + TILE - 1) // TILE) * ((h + TILE - 1) // TILE)
+
+
+def _to_requests(reqs):
+    return [r if isinstance(r, RenderRequest) else RenderRequest(**r) for r in reqs]
+
+
+def _summary(results, name: str, extra=None):
+    lat = np.array([r.latency for r in results]) * 1e3
+    px = sum(r.request.width * r.request.height for r in results)
+    t0 = min(r.request.arrival for r in results)
+    t1 = max(r.done for r in results)
+    out = {"server": name, "requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+           "max_ms": float(lat.max()), "pixels": int(px), "makespan_s": float(t1 - t0),
+           "pixels_per_s": float(px / max(t1 - t0, 1e-9)),
+           "requests_per_s": float(len(results) / max(t1 - t0, 1e-9))}
+    if extra:
+        out.update(extra)
+    return out
+
+
+class _Clock:
+    """Host clock and a reference event: maps device events to host seconds."""
+
+    def __init__(self, stream):
+        torch.cuda.synchronize()
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record(stream)
+        self.t0 = time.perf_counter()
+        self.ref.synchronize()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def at(self, ev) -> float:
+        return self.ref.elapsed_time(ev) * 1e-3
+
+
+def _wait_until(clock, t):
+    while True:
+        d = t - clock.now()
+        if d <= 0:
+            return
+        if d > 2e-3:
+            time.sleep(d - 1e-3)
+
+
+@dataclass
+class _Batch:
+    bid: int
+    stream_index: int
+    reqs: list
+    nbytes: int
+    done: object = None
+    keep: list = field(default_factory=list)   # tensors that must live until done
+    slices: list = field(default_factory=list)
+    status: torch.Tensor | None = None
+
+
+class Server:
+    """Continuous batching over `streams` streams under an HBM budget (bytes)."""
+
+    def __init__(self, bank: ModelBank, budget_bytes: int = 8 << 30, streams: int = 2,
+                 max_batch: int = 32, max_batch_pixels: int = 1 << 26):
+        if streams < 1:
+            raise ValueError("at least one stream")
+        self.bank = bank
+        self.budget = int(budget_bytes)
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.max_batch = int(max_batch)
+        self.max_batch_pixels = int(max_batch_pixels)
+        self.nbytes_px = 4 * bank.C
+
+    def footprint(self, reqs) -> tuple[int, int, int, int]:
+        """(bytes, kernels, blocks, pair bound) of one batch of requests."""
+        b = self.bank
+        K = sum(b.K[r.model] for r in reqs)
+        T = sum(_tiles(r.width, r.height) for r in reqs)
+        P = sum(b.pair_bound(r.model, r.scale, r.width, r.height) for r in reqs)
+        ws = C.smoe_render_workspace_bytes(max(K, 0), b.C, b.order, T, P)
+        px = sum(r.width * r.height for r in reqs)
+        return ws + px * self.nbytes_px + 64 * len(reqs), K, T, P
+
+    def _launch(self, batch: _Batch, keep_outputs: bool):
+        b = self.bank
+        st = self.streams[batch.stream_index]
+        rasters = [dict(width=r.width, height=r.height, scale=r.scale, origin_x=r.origin_x,
+                        origin_y=r.origin_y, num_kernels=b.K[r.model],
+                        param_offset=b.offset[r.model]) for r in batch.reqs]
+        _, K, T, P = self.footprint(batch.reqs)
+        with torch.cuda.stream(st):
+            segs = Segments(rasters, stream=st)
+            bins = Bins(K, b.C, b.order, T, P, device=b.params.device, render_only=True,
+                        zero=False)
+            images = torch.empty((segs.pixels, b.C), dtype=torch.float32, device=b.params.device)
+            cb = C.SmoeBatch(b.C, b.order, b.params.data_ptr(), b.params.shape[0], segs.n,
+                             segs.dev.data_ptr(), ct.addressof(segs.host), b.radius)
+            C.smoe_bin_batched(cb, bins.c, st.cuda_stream)
+            C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
+            status = torch.empty(4, dtype=torch.int32, pin_memory=True)
+            status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
+            batch.done = torch.cuda.Event(enable_timing=True)
+            batch.done.record(st)
+        batch.keep = [segs, bins, images]
+        batch.status = status
+        if keep_outputs:
+            batch.slices = [images[a:e].view(h, w, b.C) for a, e, h, w in segs.pixel_slices()]
+
+    def serve(self, requests, realtime: bool = True, keep_outputs: bool = False):
+        """Serves every request; returns (results in request order, summary dict).  With
+        realtime=False every request is taken as arrived at time 0 (saturation)."""
+        reqs = _to_requests(requests)
+        order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
+        if not realtime:
+            reqs = [RenderRequest(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+        results = [None] * len(reqs)
+        index = {id(r): i for i, r in enumerate(reqs)}
+        pending = deque()
+        inflight = []
+        free = list(range(len(self.streams)))
+        in_use = peak = 0
+        nxt = nb = overflow = 0
+        sizes = []
+        clock = _Clock(self.streams[0])
+        while nxt < len(order) or pending or inflight:
+            now = clock.now()
+            while nxt < len(order) and reqs[order[nxt]].arrival <= now:
+                pending.append(reqs[order[nxt]])
+                nxt += 1
+            for bt in list(inflight):
+                if bt.done.query():
+                    t = clock.at(bt.done)
+                    if int(bt.status[1]) != 0:
+                        overflow += 1
+                        raise RuntimeError("pair bound exceeded: batch overflowed its workspace")
+                    for j, r in enumerate(bt.reqs):
+                        results[index[id(r)]] = RenderResult(
+                            r, t, bt.bid, bt.slices[j] if keep_outputs else None)
+                    in_use -= bt.nbytes
+                    free.append(bt.stream_index)
+                    inflight.remove(bt)
+            launched = False
+            while free and pending:
+                got = admit(pending, in_use, self.budget, lambda q: self.footprint(q)[0],
+                            self.max_batch, self.max_batch_pixels)
+                if not got:
+                    break
+                need = self.footprint(got)[0]
+                bt = _Batch(nb, free.pop(0), got, need)
+                nb += 1
+                self._launch(bt, keep_outputs)
+                inflight.append(bt)
+                in_use += need
+                peak = max(peak, in_use)
+                sizes.append(len(got))
+                launched = True
+            if not launched and not inflight and not pending and nxt < len(order):
+                _wait_until(clock, reqs[order[nxt]].arrival)
+        torch.cuda.synchronize()
+        return results, _summary(results, "batched", {
+            "batches": nb, "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+            "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.streams),
+            "peak_bytes": int(peak), "budget_bytes": self.budget, "overflows": overflow})
+
+
+class PlainServer:
+    """One launch sequence (bin, render) per request on one stream, host-synchronised."""
+
+    def __init__(self, bank: ModelBank):
+        self.bank = bank
+        self.stream = torch.cuda.Stream()
+
+    def serve(self, requests, realtime: bool = True, keep_outputs: bool = False):
+        b = self.bank
+        reqs = _to_requests(requests)
+        if not realtime:
+            reqs = [RenderRequest(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+        order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
+        results = [None] * len(reqs)
+        st = self.stream
+        clock = _Clock(st)
+        for i in order:
+            r = reqs[i]
+            _wait_until(clock, r.arrival)
+            grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius)
+            rows = b.rows(r.model)
+            m = model_struct(rows, b.C, b.order)
+            with torch.cuda.stream(st):
+                bins = Bins(b.K[r.model], b.C, b.order, _tiles(r.width, r.height),
+                            b.pair_bound(r.model, r.scale, r.width, r.height),
+                            device=rows.device, render_only=True, zero=False)
+                image = torch.empty((r.height, r.width, b.C), dtype=torch.float32,
+                                    device=rows.device)
+                C.smoe_bin(m, grid, bins.c, st.cuda_stream)
+                C.smoe_render(m, grid, bins.c, image.data_ptr(), None, None, None, st.cuda_stream)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(st)
+            code, status = C.smoe_read_status(bins.c, st.cuda_stream)
+            if code == C.SMOE_ERR_CAPACITY:
+                raise RuntimeError("pair bound exceeded: request overflowed its workspace")
+            results[i] = RenderResult(r, clock.at(ev), i, image if keep_outputs else None)
+        torch.cuda.synchronize()
+        return results, _summary(results, "plain")
+
+
+def latency_table(summaries) -> str:
+    """A small text table of serving summaries."""
+    keys = ["server", "requests", "p50_ms", "p99_ms", "mean_ms", "pixels_per_s"]
+    lines = [" | ".join(keys)]
+    for s in summaries:
+        lines.append(" | ".join(f"{s[k]:.4g}" if isinstance(s[k], float) else str(s[k])
+                                for k in keys))
+    return "\n".join(lines)
+
+
+__all__ = ["RenderRequest", "RenderResult", "BoxSpans", "ModelBank", "admit", "Server",
+           "PlainServer", "latency_table"]

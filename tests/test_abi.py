@@ -36,7 +36,8 @@ def test_struct_layouts_match_c(tmp_path):
     from paper_2510_05814_amd import _capi as C
 
     structs = {"smoe_model": C.SmoeModel, "smoe_grid": C.SmoeGrid, "smoe_bins": C.SmoeBins,
-               "smoe_adam_config": C.SmoeAdamConfig, "smoe_fit_state": C.SmoeFitState}
+               "smoe_adam_config": C.SmoeAdamConfig, "smoe_fit_state": C.SmoeFitState,
+               "smoe_segment": C.SmoeSegment, "smoe_batch": C.SmoeBatch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "smoe.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -110,3 +111,19 @@ def test_invalid_arguments_rejected_before_launch():
                                     None) == C.SMOE_ERR_INVALID
     assert lib.smoe_materialize(4, 3, 1, None, None, None) == C.SMOE_ERR_INVALID
     assert lib.smoe_fit_step(None, p, None, None) == C.SMOE_ERR_INVALID
+
+
+def test_segments_layout_host_only():
+    from paper_2510_05814_amd import _capi as C
+
+    segs = (C.SmoeSegment * 3)()
+    for i, (w, h, k, sc) in enumerate([(33, 17, 5, 1), (16, 16, 0, 2), (100, 40, 7, 3)]):
+        segs[i].width, segs[i].height, segs[i].num_kernels, segs[i].scale = w, h, k, sc
+    K, T, px = C.smoe_segments_layout(segs)
+    assert (K, T, px) == (12, 3 * 2 + 1 + 7 * 3, 33 * 17 + 256 + 4000)
+    assert [s.kernel_offset for s in segs] == [0, 5, 5]
+    assert [s.tile_offset for s in segs] == [0, 6, 7]
+    assert [s.pixel_offset for s in segs] == [0, 561, 817]
+    segs[1].scale = 0
+    with pytest.raises(C.SmoeError):
+        C.smoe_segments_layout(segs)

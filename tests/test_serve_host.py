@@ -1,0 +1,75 @@
+"""Host logic of the serving loop (no GPU): the pair bound that sizes a batch's workspace
+never falls below the pairs the oracle's binning produces, and admission is FIFO, within
+the budget and the batch limits."""
+from collections import deque
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from paper_2510_05814_amd.serve import BoxSpans, admit
+
+
+def test_pair_bound_covers_oracle_pairs():
+    rng = np.random.default_rng(5)
+    models = [wl.random_model(150, 3, 1, 48, 40, seed=300 + i, sig_lo=0.5, sig_hi=14.0)
+              for i in range(3)]
+    spans = BoxSpans(models, 3.0)
+    ratios = []
+    for _ in range(40):
+        i = int(rng.integers(3))
+        s = int(rng.integers(1, 5))
+        W = int(rng.integers(1, 48 * s + 1))
+        H = int(rng.integers(1, 40 * s + 1))
+        ox = int(rng.integers(-20, 48 * s - W + 21))
+        oy = int(rng.integers(-20, 40 * s - H + 21))
+        P = oracle.bin(models[i].astype(np.float64), 3, 1, W, H, s, ox, oy)["P"]
+        bound = spans.pair_bound(i, s, W, H)
+        assert bound >= P, (i, s, W, H, ox, oy)
+        if P:
+            ratios.append(bound / P)
+    # a bound, not a wild over-estimate, for windows that contain most kernels
+    assert np.median(ratios) < 8.0
+
+
+def test_pair_bound_single_kernel_closed_form():
+    # one round kernel, l = 2: R = 6, box 12 px at s = 1 -> n <= 15 px -> <= 2 blocks/axis
+    m = np.zeros((1, 15), np.float64)
+    m[0, 2] = m[0, 4] = 2.0
+    spans = BoxSpans([m], 3.0)
+    assert spans.pair_bound(0, 1, 256, 256) == 4
+    assert spans.pair_bound(0, 1, 16, 256) == 2      # one block across
+    assert spans.pair_bound(0, 4, 256, 256) == 5 * 5  # 48 px box -> n <= 51 -> 5 blocks
+    for ox in range(16):
+        P = oracle.bin(np.array([[8.0 + ox / 4, 8.0, 2.0, 0.0, 2.0, 0.0] + [0.5] * 9]), 3, 1,
+                       64, 64)["P"]
+        assert P <= 4
+
+
+def _req(w, h):
+    return SimpleNamespace(width=w, height=h)
+
+
+def test_admit_fifo_budget_and_limits():
+    fp = lambda b: sum(r.width * r.height for r in b)  # noqa: E731  bytes = pixels here
+    q = deque([_req(10, 10), _req(20, 20), _req(5, 5), _req(1, 1)])
+    got = admit(q, 0, 1000, fp, 8, 10 ** 9)
+    assert [r.width for r in got] == [10, 20, 5, 1]   # 100 + 400 + 25 + 1 fits
+    assert not q
+    q = deque([_req(10, 10), _req(20, 20), _req(25, 25)])
+    got = admit(q, 0, 1000, fp, 8, 10 ** 9)
+    assert [r.width for r in got] == [10, 20]         # + 625 would exceed 1000
+    q = deque([_req(10, 10), _req(31, 31), _req(1, 1)])
+    got = admit(q, 0, 1000, fp, 8, 10 ** 9)
+    assert [r.width for r in got] == [10]             # 31x31 does not fit: never skipped
+    assert [r.width for r in q] == [31, 1]
+    assert admit(q, 200, 1000, fp, 8, 10 ** 9) == []  # head waits for memory
+    q = deque([_req(1, 1)] * 5)
+    assert len(admit(q, 0, 1000, fp, 2, 10 ** 9)) == 2
+    q = deque([_req(10, 10)] * 5)
+    assert len(admit(q, 0, 10 ** 6, fp, 8, 250)) == 2  # pixel cap
+    q = deque([_req(100, 100)])
+    with pytest.raises(ValueError):
+        admit(q, 0, 1000, fp, 8, 10 ** 9)

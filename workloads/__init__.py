@@ -33,7 +33,8 @@ import numpy as np
 __all__ = [
     "num_params", "voronoi_ramps", "config1_image", "config2_image",
     "config3_images", "config5_images", "grid_init", "random_model",
-    "fd_crop_case", "Workload", "SEEDS",
+    "fd_crop_case", "Workload", "SEEDS", "serving_models", "serving_requests",
+    "batched_fit_inits",
 ]
 
 SEEDS = {1: 1, 2: 2, 3: 3, 4: 4, 5: 5}
@@ -220,6 +221,69 @@ def fd_crop_case(seed: int = SEEDS[3], size: int = 32, g: int = 4, order: int = 
     if order == 1:
         raw[:, 6 + C:6 + 3 * C] = rng.uniform(-0.03, 0.03, size=(K, 2 * C))
     return tgt, raw.astype(np.float32)
+
+
+SERVING_KS = (256, 1024, 4096, 16384, 65536)
+
+
+def serving_models(seed: int = SEEDS[4], n: int = 16, small: bool = False):
+    """The resident models of the serving workload, as fit inputs: n RGB images and their
+    grid initialisations with linear experts.  Model i has K = SERVING_KS[i % 5] kernels
+    and a square native raster of side clip(sqrt(64 K), 256, 2048) (one kernel per 8x8
+    pixels, as the batched fit), or a quarter of that side with small=True.  Returns a
+    list of dicts (image f32 [H, W, 3], raw0 f32 [K, NP], K, side)."""
+    rng = _rng(seed)
+    out = []
+    for i in range(n):
+        K = SERVING_KS[i % len(SERVING_KS)]
+        side = int(min(2048, max(256, round(math.sqrt(64.0 * K)))))
+        g = int(round(math.sqrt(K)))
+        if small:
+            side //= 4
+            g = max(2, g // 4)
+        cells = max(1, int(round(6.0 * side * side / 4096.0)))
+        img = voronoi_ramps(side, side, 3, cells, rng)
+        img = np.clip(img + rng.normal(0.0, 0.01, size=img.shape), 0.0, 1.0).astype(np.float32)
+        raw, _ = grid_init(img, g, g, sigma=0.5 * side / g, order=1)
+        out.append(dict(image=img, raw0=raw, K=g * g, side=side))
+    return out
+
+
+def serving_requests(sides, n: int, rate: float = 200.0, seed: int = SEEDS[4] + 100,
+                     scales=(1, 2, 3, 4), max_side: int = 4096, poisson: bool = True):
+    """A render request stream over resident models with native sides `sides`.
+
+    Each request picks a model uniformly, an upscale factor uniformly from `scales`, and
+    an output window of min(max_side, side * scale) pixels per axis at a uniform origin
+    inside the upscaled raster.  Arrival times (seconds) are a Poisson process of the
+    given rate (exponential gaps), or all zero with poisson=False.  Returns a list of
+    dicts (model, scale, width, height, origin_x, origin_y, arrival)."""
+    rng = _rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n):
+        m = int(rng.integers(len(sides)))
+        s = int(scales[int(rng.integers(len(scales)))])
+        full = sides[m] * s
+        w = h = min(max_side, full)
+        ox = int(rng.integers(full - w + 1))
+        oy = int(rng.integers(full - h + 1))
+        if poisson:
+            t += float(rng.exponential(1.0 / rate))
+        out.append(dict(model=m, scale=s, width=w, height=h, origin_x=ox, origin_y=oy,
+                        arrival=t if poisson else 0.0))
+    return out
+
+
+def batched_fit_inits(images, order: int = 1):
+    """Grid initialisations for a batch of images, one kernel per 8x8 pixels
+    (K = H W / 64, grid W/8 x H/8, sigma 4 px)."""
+    out = []
+    for img in images:
+        H, W, _ = img.shape
+        raw, _ = grid_init(img, max(1, W // 8), max(1, H // 8), sigma=4.0, order=order)
+        out.append(raw)
+    return out
 
 
 @dataclass
