@@ -405,72 +405,126 @@ def _rocpd_kernels(db_path):
     return [(n, c, t, a, 100.0 * t / total) for n, c, t, a in rows]
 
 
-def _rocpd_counters(db_path, counter):
-    """{kernel name: [value per dispatch]} of one PMC counter in a rocprofv3 SQLite output
-    (rows of one dispatch, e.g. per shader-engine instances, are summed)."""
+def _rocpd_counters(db_path):
+    """{(kernel name, counter): [value per dispatch]} of every PMC counter in a rocprofv3
+    SQLite output (rows of one dispatch, e.g. per shader-engine instances, are summed)."""
     import sqlite3
 
     con = sqlite3.connect(db_path)
     acc = {}
     try:
-        for name, disp, val in con.execute(
-                "select kernel_name, dispatch_id, value from counters_collection "
-                "where counter_name = ?", (counter,)):
-            acc[(name, disp)] = acc.get((name, disp), 0.0) + float(val)
+        for name, disp, ctr, val in con.execute(
+                "select kernel_name, dispatch_id, counter_name, value from counters_collection"):
+            acc[(name, ctr, disp)] = acc.get((name, ctr, disp), 0.0) + float(val)
     finally:
         con.close()
     out = {}
-    for (name, _), v in acc.items():
-        out.setdefault(name, []).append(v)
+    for (name, ctr, _), v in acc.items():
+        out.setdefault((name, ctr), []).append(v)
     return out
 
 
+# Kernels of the fit step, with the sources whose digest tags their counters.
+STEP_KERNELS = {"k_fit_tile": KERNEL_SOURCES["render_backward"],
+                "k_adam_fit": KERNEL_SOURCES["render_backward"],
+                "k_scan": ["paper_2510_05814_amd/csrc/binning.hip",
+                           "paper_2510_05814_amd/csrc/device_common.h"],
+                "k_scatter": ["paper_2510_05814_amd/csrc/binning.hip",
+                              "paper_2510_05814_amd/csrc/device_common.h"]}
+# CDNA issue model: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles, and a
+# binary32 transcendental (v_exp_f32, v_rcp_f32, ...) for 16 cycles (quarter rate).
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
+
+
 def summarize_profile(prof_dir, cmd):
-    """Writes profiles/ summaries from rocprofv3 SQLite outputs under prof_dir:
-    trace/ (--kernel-trace --stats) and, if present, fetch_size/ and write_size/ (--pmc)."""
+    """Writes profiles/ summaries from rocprofv3 SQLite outputs under prof_dir: trace/
+    (--kernel-trace --stats) and, if present, one pmc_*/ directory per --pmc run
+    (FETCH_SIZE and WRITE_SIZE runs need the calibration kernel, --copy-calibration)."""
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     dbs = glob.glob(os.path.join(prof_dir, "trace", "**", "*_results.db"), recursive=True)
+    durations = {}
     if dbs:
         lines = ["# rocprofv3 kernel trace: fit step, 2048x2048 RGB, K=65536 linear experts", "",
                  f"Command: `{cmd}`", "",
                  "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
         for name, calls, tot, avg, pct in _rocpd_kernels(dbs[0]):
             short = name.replace("smoe::(anonymous namespace)::", "").split("(")[0]
+            for k in STEP_KERNELS:
+                if short.startswith(k) or short.startswith("void " + k):
+                    durations[k] = avg * 1e-9
             if len(short) > 60:
                 short = short[:57] + "..."
             lines.append(f"| `{short}` | {calls} | {avg / 1e3:.2f} | {tot / 1e3:.1f} | {pct:.1f} |")
         with open(os.path.join(ROOT, "profiles", "kernels_fit2048.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
-    f_db = glob.glob(os.path.join(prof_dir, "fetch_size", "**", "*_results.db"), recursive=True)
-    w_db = glob.glob(os.path.join(prof_dir, "write_size", "**", "*_results.db"), recursive=True)
-    if not (f_db and w_db):
+    ctr = {}
+    for d in sorted(glob.glob(os.path.join(prof_dir, "pmc_*"))):
+        for db in glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True):
+            ctr.update(_rocpd_counters(db))
+    if not ctr:
         return
-    fetch, write = _rocpd_counters(f_db[0], "FETCH_SIZE"), _rocpd_counters(w_db[0], "WRITE_SIZE")
 
-    def pick(d, key):
-        return [x for k, v in d.items() if key in k for x in v]
+    def per_kernel(key, counter):
+        v = [x for (n, c), vals in ctr.items() if key in n and c == counter for x in vals]
+        return sum(v) / len(v) if v else None
 
-    copy_bytes = CALIB_BYTES
-    cf, cw = pick(fetch, "MulFunctor"), pick(write, "MulFunctor")
-    if not (cf and cw):
-        print("PMC runs lack the calibration kernel (profile with --copy-calibration); "
-              "counters not summarised", file=sys.stderr)
-        return
-    f_scale = copy_bytes / (max(cf) * 1024.0)
-    w_scale = copy_bytes / (max(cw) * 1024.0)
-    out = {"calibration": {"copy_bytes": copy_bytes, "fetch_kib": max(cf) if cf else None,
-                           "write_kib": max(cw) if cw else None, "fetch_scale": f_scale,
-                           "write_scale": w_scale},
-           "kernels": {}, "command": cmd}
-    for stage, kname in KERNEL_NAMES.items():
-        fv, wv = pick(fetch, kname + "<"), pick(write, kname + "<")
-        if fv and wv:
-            out["kernels"][kname] = {
-                "fetch_bytes": sum(fv) / len(fv) * 1024.0 * f_scale,
-                "write_bytes": sum(wv) / len(wv) * 1024.0 * w_scale,
-                "dispatches": len(fv), "source_digest": source_digest(KERNEL_SOURCES[stage])}
+    out = {"command": cmd, "calibration": None, "kernels": {}}
+    f_scale = w_scale = None
+    cf, cw = per_kernel("MulFunctor", "FETCH_SIZE"), per_kernel("MulFunctor", "WRITE_SIZE")
+    if cf and cw:
+        f_scale = CALIB_BYTES / (cf * 1024.0)
+        w_scale = CALIB_BYTES / (cw * 1024.0)
+        out["calibration"] = {"copy_bytes": CALIB_BYTES, "fetch_kib": cf, "write_kib": cw,
+                              "fetch_scale": f_scale, "write_scale": w_scale}
+    elif any(c in ("FETCH_SIZE", "WRITE_SIZE") for (_, c) in ctr):
+        print("PMC byte counters lack the calibration kernel (--copy-calibration); "
+              "bytes not summarised", file=sys.stderr)
+    counters = sorted({c for (_, c) in ctr})
+    rows = ["| kernel | avg us | fetch MB | write MB | HBM GB/s | VALU instr | VALU busy | "
+            "trans busy |", "|---|---|---|---|---|---|---|---|"]
+    for k, srcs in STEP_KERNELS.items():
+        e = {"source_digest": source_digest(srcs), "counters": {}}
+        for c in counters:
+            v = per_kernel(k + "<", c) or per_kernel(k, c)
+            if v is not None:
+                e["counters"][c] = v
+        fv, wv = e["counters"].get("FETCH_SIZE"), e["counters"].get("WRITE_SIZE")
+        if f_scale and fv is not None and wv is not None:
+            e["fetch_bytes"] = fv * 1024.0 * f_scale
+            e["write_bytes"] = wv * 1024.0 * w_scale
+        dur = durations.get(k)
+        if dur:
+            e["avg_duration_s"] = dur
+            if "fetch_bytes" in e:
+                e["hbm_gbps"] = (e["fetch_bytes"] + e["write_bytes"]) / dur / 1e9
+            nv = e["counters"].get("SQ_INSTS_VALU")
+            nt = e["counters"].get("SQ_INSTS_VALU_TRANS_F32")
+            slots = N_SIMD * CLOCK_HZ * dur
+            if nv is not None:
+                e["valu_busy_frac"] = nv * 4 / slots
+            if nt is not None:
+                e["trans_busy_frac"] = nt * 16 / slots
+        if e["counters"]:
+            out["kernels"][k] = e
+
+        def f(x, scale=1.0, fmt="{:.3g}"):
+            return fmt.format(x * scale) if x is not None else "-"
+        rows.append(f"| `{k}` | {f(e.get('avg_duration_s'), 1e6)} | "
+                    f"{f(e.get('fetch_bytes'), 1e-6)} | {f(e.get('write_bytes'), 1e-6)} | "
+                    f"{f(e.get('hbm_gbps'))} | {f(e['counters'].get('SQ_INSTS_VALU'))} | "
+                    f"{f(e.get('valu_busy_frac'))} | {f(e.get('trans_busy_frac'))} |")
     with open(COUNTERS_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
+    md = ["# rocprofv3 counters: fit step, 2048x2048 RGB, K=65536 linear experts", "",
+          f"Command (trace; each pmc_* run is the same program under `--pmc <counters>`): "
+          f"`{cmd}`", "",
+          "Bytes: FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB elementwise kernel of "
+          "known traffic.  VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x "
+          "duration); trans busy = SQ_INSTS_VALU_TRANS_F32 x 16 cycles / the same.", "",
+          *rows, "", "Counters collected: " + ", ".join(counters), ""]
+    with open(os.path.join(ROOT, "profiles", "counters_fit2048.md"), "w") as fh:
+        fh.write("\n".join(md))
 
 
 def main():

@@ -75,16 +75,16 @@ struct GatherArgs {
   float* __restrict__ grads;
 };
 
-// 16 lanes per kernel: lane i of the group reduces parameter i.
+// 16 lanes per kernel (one 16-lane row of the wave); lane i ends with parameter i.
 template <int NP>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = gid >> 4, i = gid & 15;
-  if (j >= a.S.K) return;
-  const float g = a.status[1] != 0 ? 0.0f
-                                   : gather_param<NP>(j, i, seg_of_kernel(a.S, j), a.tile_rects,
-                                                      a.ranges, a.vals, a.pair_grads);
-  if (i < NP) a.grads[(size_t)j * NP + i] = g;
+  const bool live = j < a.S.K;
+  // every lane takes part in the gather's row reduction
+  const float g = gather_param<NP>(j, live && a.status[1] == 0, seg_of_kernel(a.S, live ? j : 0),
+                                   a.tile_rects, a.ranges, a.vals, a.pair_grads);
+  if (live && i < NP) a.grads[(size_t)j * NP + i] = g;
 }
 
 }  // namespace

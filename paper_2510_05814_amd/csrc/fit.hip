@@ -177,9 +177,9 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const SegGrid sg = seg_of_kernel(f.S, live ? j : 0);
   float pm = 0.0f;  // materialized value of parameter i after the step
   if (live && skip && i < NP) pm = f.model[(size_t)j * NP + i];
-  const float gi = (live && !skip) ? gather_param<NP>(j, i, sg, f.tile_rects_in, f.ranges, f.vals,
-                                                      f.pair_grads)
-                                   : 0.0f;
+  // every lane takes part in the gather's row reduction
+  const float gi = gather_param<NP>(j, live && !skip, sg, f.tile_rects_in, f.ranges, f.vals,
+                                    f.pair_grads);
   if (live && !skip && i < NP) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const size_t e = (size_t)j * NP + i;

@@ -120,28 +120,6 @@ __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, i
   return (a < hi && vals[a] == j) ? a : -1;
 }
 
-// Gradient of parameter i of kernel row j: the sum of its per-block partials over the
-// kernel's block rectangle in row-major order (a fixed order, so the result is
-// reproducible).  Used with 16 lanes per kernel, lane i reading element i of each partial
-// row, so a group's reads of one row are contiguous.
-template <int NP>
-__device__ __forceinline__ float gather_param(int j, int i, const SegGrid& sg,
-                                              const int4* __restrict__ rects,
-                                              const int2* __restrict__ ranges,
-                                              const uint32_t* __restrict__ vals,
-                                              const float* __restrict__ pair_grads) {
-  float acc = 0.0f;
-  const int4 rc = rects[j];
-  for (int ty = rc.y; ty <= rc.w; ++ty)
-    for (int tx = rc.x; tx <= rc.z; ++tx) {
-      const int2 rg = ranges[sg.tile_offset + ty * sg.ntx + tx];
-      if (rg.y <= rg.x) continue;
-      const int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j);
-      if (p >= 0 && i < NP) acc += pair_grads[(size_t)p * NP + i];
-    }
-  return acc;
-}
-
 // Launchers.  `params` rows are addressed through each segment's param_offset; every
 // per-kernel workspace array through kernel_offset; images through pixel_offset.
 hipError_t launch_bin(int C, int order, const float* params, const Segs& S, const smoe_bins& b,

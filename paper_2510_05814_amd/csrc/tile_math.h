@@ -149,6 +149,68 @@ __device__ __forceinline__ float wave_reduce16_transposed(float (&v)[16]) {
   return v[0];
 }
 
+// Transposed reduction inside each 16-lane row: on return lane l holds the sum over the
+// row's 16 lanes of v[l & 15].  Stages pair lane l with l ^ 8 (row_ror:8), with 7 - l in its
+// group of 8 (row_half_mirror), then l ^ 2 and l ^ 1 (quad_perm); at each stage a lane keeps
+// the half of its values selected by that bit of its index and adds the partner's copy.
+// Every lane of the row must be active.
+__device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0,
+             b0 = (lane & 1) != 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
+    v[i] = keep + dpp<0x128>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
+    v[i] = keep + dpp<0x141>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
+    v[i] = keep + dpp<0x4E>(send);
+  }
+  const float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
+  return keep + dpp<0xB1>(send);
+}
+
+// Gradient of kernel row j: the sum of its per-block partial rows over its block rectangle.
+// A group of 16 lanes (one 16-lane row of the wave) serves one kernel: lane b finds the
+// kernel's position in the lists of blocks b, b + 16, ... of the rectangle (row-major) by a
+// binary search and adds those partial rows; the row reduction then leaves parameter i's
+// gradient in lane i.  The summation order is fixed, so the result is reproducible.  All 16
+// lanes must call it (live = false: the kernel contributes nothing).
+template <int NP>
+__device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& sg,
+                                              const int4* __restrict__ rects,
+                                              const int2* __restrict__ ranges,
+                                              const uint32_t* __restrict__ vals,
+                                              const float* __restrict__ pair_grads) {
+  static_assert(NP <= 16, "16 lanes per kernel");
+  float v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = 0.0f;
+  if (live) {
+    const int4 rc = rects[j];
+    const int n = rect_count(rc);
+    const int w = rc.z - rc.x + 1;
+    for (int b = threadIdx.x & 15; b < n; b += 16) {
+      const int dy = b / w;
+      const int2 rg = ranges[sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w)];
+      if (rg.y <= rg.x) continue;
+      const int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j);
+      if (p < 0) continue;
+      const float* row = pair_grads + (size_t)p * NP;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) v[q] += row[q];
+    }
+  }
+  return row_reduce16_transposed(v);
+}
+
 // Adjoint seed of one pixel: dL/dy (g), 1/D, sum_c g_c y_c; `valid` false where D = 0 or the
 // pixel lies outside the raster (no gradient flows there).
 template <int C>
