@@ -282,6 +282,11 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* state, float* out, voi
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream);
 
 /* Library version, e.g. 100 for 0.1.0. */
+/* Name and description of the HIP error behind this thread's last SMOE_ERR_HIP ("no
+ * error" if none).  The string is owned by the library and valid until the next failing
+ * call on the thread. */
+const char* smoe_last_error(void);
+
 int32_t smoe_version(void);
 
 #ifdef __cplusplus

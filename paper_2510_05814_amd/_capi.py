@@ -10,6 +10,12 @@ from __future__ import annotations
 import ctypes as ct
 from pathlib import Path
 
+# torch first: it loads its HIP runtime (libamdhip64.so.7), and libsmoe.so, whose dependency
+# carries the same soname, then binds to that one.  Loaded the other way round the process
+# would hold two HIP runtimes, and the library's could see a different set of devices than
+# the one that owns torch's memory and streams.
+import torch  # noqa: F401,E402
+
 _LIB_PATH = Path(__file__).resolve().parent / "libsmoe.so"
 
 SMOE_OK = 0
@@ -71,7 +77,13 @@ class SmoeError(RuntimeError):
     def __init__(self, fn: str, code: int):
         names = {SMOE_ERR_INVALID: "SMOE_ERR_INVALID", SMOE_ERR_CAPACITY: "SMOE_ERR_CAPACITY",
                  SMOE_ERR_HIP: "SMOE_ERR_HIP", SMOE_ERR_TOO_LARGE: "SMOE_ERR_TOO_LARGE"}
-        super().__init__(f"{fn} failed: {names.get(code, code)}")
+        msg = f"{fn} failed: {names.get(code, code)}"
+        if code == SMOE_ERR_HIP:
+            try:
+                msg += f" ({lib.smoe_last_error().decode()})"
+            except Exception:  # noqa: BLE001  (the message is best effort)
+                pass
+        super().__init__(msg)
         self.code = code
 
 
@@ -107,6 +119,8 @@ def _load():
     L.smoe_fit_step_timed.restype = _i32
     L.smoe_pair_stats.argtypes = [P(SmoeModel), P(SmoeGrid), P(SmoeBins), _vp, _vp]
     L.smoe_pair_stats.restype = _i32
+    L.smoe_last_error.argtypes = []
+    L.smoe_last_error.restype = ct.c_char_p
     L.smoe_read_status.argtypes = [P(SmoeBins), P(_i32), _vp]
     L.smoe_read_status.restype = _i32
     L.smoe_segments_layout.argtypes = [P(SmoeSegment), _i32, P(_i32), P(_i32), P(ct.c_int64)]
@@ -127,7 +141,7 @@ EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "sm
             "smoe_render", "smoe_render_backward", "smoe_materialize", "smoe_fit_step",
             "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status", "smoe_segments_layout",
             "smoe_bin_batched", "smoe_render_batched", "smoe_fit_segment_losses",
-            "smoe_render_workspace_bytes", "smoe_render_workspace_layout"]
+            "smoe_render_workspace_bytes", "smoe_render_workspace_layout", "smoe_last_error"]
 
 
 def _check(fn: str, code: int, allow=()):

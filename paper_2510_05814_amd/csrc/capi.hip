@@ -1,6 +1,7 @@
 // The C ABI of include/smoe.h: host-side validation, workspace layout and the launch
 // sequences of each call.  No device memory is allocated here.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "smoe_internal.h"
@@ -126,7 +127,20 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   return L;
 }
 
-inline smoe_status hip_status(hipError_t e) { return e == hipSuccess ? SMOE_OK : SMOE_ERR_HIP; }
+// The HIP error behind the last SMOE_ERR_HIP of this thread, for smoe_last_error().
+thread_local char g_last_error[256] = "no error";
+
+inline smoe_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return SMOE_OK;
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", hipGetErrorName(e),
+                hipGetErrorString(e));
+  return SMOE_ERR_HIP;
+}
+
+// hipGetLastError() reports the last failure of any HIP call on the thread, including
+// calls made by other code before ours; a launching entry point clears it first so that
+// the status it returns is about its own launches only.
+inline void clear_stale_error() { (void)hipGetLastError(); }
 
 // The rasters of a fit state: its segment table (batched fit) or its single grid.
 bool fit_segs(const smoe_fit_state* st, Segs* S) {
@@ -153,6 +167,7 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
 
 smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
                      void* const* ev, void* stream) {
+  clear_stale_error();
   if (!st || !target) return SMOE_ERR_INVALID;
   Segs S;
   if (!valid_shape(st->K, st->C, st->order) || (st->K > 0 && !st->model) || !fit_segs(st, &S) ||
@@ -185,6 +200,8 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
 extern "C" {
 
 int32_t smoe_version(void) { return 100; }
+
+const char* smoe_last_error(void) { return g_last_error; }
 
 size_t smoe_bins_workspace_bytes(int32_t K, int32_t C, int32_t order, int32_t max_tiles,
                                  int32_t capacity) {
@@ -270,6 +287,7 @@ smoe_status smoe_segments_layout(smoe_segment* segs, int32_t n, int32_t* total_k
 
 smoe_status smoe_bin(const smoe_model* model, const smoe_grid* grid, smoe_bins* bins,
                      void* stream) {
+  clear_stale_error();
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order))
     return SMOE_ERR_INVALID;
@@ -281,6 +299,7 @@ smoe_status smoe_bin(const smoe_model* model, const smoe_grid* grid, smoe_bins* 
 smoe_status smoe_render(const smoe_model* model, const smoe_grid* grid, const smoe_bins* bins,
                         float* image, float* denom, const float* target, float* loss_out,
                         void* stream) {
+  clear_stale_error();
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
       !image)
@@ -301,6 +320,7 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
                                  const smoe_bins* bins, const float* image, const float* denom,
                                  const float* grad_image, const float* target, float* grads,
                                  void* stream) {
+  clear_stale_error();
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
       !image || !denom || !grads || (grad_image == nullptr) == (target == nullptr) ||
@@ -315,6 +335,7 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
 }
 
 smoe_status smoe_bin_batched(const smoe_batch* batch, smoe_bins* bins, void* stream) {
+  clear_stale_error();
   Segs S;
   if (!batch_segs(batch, &S) || !bins_match(bins, S.K, batch->C, batch->order))
     return SMOE_ERR_INVALID;
@@ -325,6 +346,7 @@ smoe_status smoe_bin_batched(const smoe_batch* batch, smoe_bins* bins, void* str
 
 smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, float* images,
                                 float* denoms, void* stream) {
+  clear_stale_error();
   Segs S;
   if (!batch_segs(batch, &S) || !bins_match(bins, S.K, batch->C, batch->order) || !images)
     return SMOE_ERR_INVALID;
@@ -335,6 +357,7 @@ smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, 
 
 smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw, float* model,
                              void* stream) {
+  clear_stale_error();
   if (!valid_shape(K, C, order) || (K > 0 && (!raw || !model))) return SMOE_ERR_INVALID;
   return hip_status(launch_materialize(K, C, order, raw, model, static_cast<hipStream_t>(stream)));
 }
@@ -351,6 +374,7 @@ smoe_status smoe_fit_step_timed(smoe_fit_state* st, const float* target, float* 
 }
 
 smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* stream) {
+  clear_stale_error();
   Segs S;
   if (!st || !out || !st->bins.tile_loss || !fit_segs(st, &S)) return SMOE_ERR_INVALID;
   return hip_status(launch_segment_losses(S, st->bins, out, static_cast<hipStream_t>(stream)));
@@ -358,6 +382,7 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* 
 
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
                             const smoe_bins* bins, uint64_t* out2, void* stream) {
+  clear_stale_error();
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
       !out2)

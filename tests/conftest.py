@@ -22,6 +22,9 @@ def pytest_collection_modifyitems(config, items):
     import torch
 
     if torch.cuda.is_available():
+        p = torch.cuda.get_device_properties(0)
+        print(f"\n[device] {p.name} {getattr(p, 'gcnArchName', '?')} "
+              f"{p.total_memory >> 20} MiB, {p.multi_processor_count} CUs", flush=True)
         return
     skip = pytest.mark.skip(reason="no GPU in this environment")
     for it in items:

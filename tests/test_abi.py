@@ -4,6 +4,7 @@ arguments before anything is launched.  No compute call is made."""
 import ctypes as ct
 import re
 import subprocess
+import sys
 from pathlib import Path
 
 import pytest
@@ -127,3 +128,15 @@ def test_segments_layout_host_only():
     segs[1].scale = 0
     with pytest.raises(C.SmoeError):
         C.smoe_segments_layout(segs)
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the package before torch must not load a second HIP runtime: the library
+    binds to the libamdhip64 torch loads."""
+    code = ("import paper_2510_05814_amd.serve, torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "libs = {ln.split()[-1] for ln in maps if 'libamdhip64' in ln}\n"
+            "print(len(libs), sorted(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                         check=True).stdout
+    assert out.startswith("1 "), out
