@@ -220,10 +220,12 @@ def run(args):
     # (the fit workspace already holds part of the next step's binning)
     sb = smoe.bin(st.model, C, 1, st.grid)
     _, sstat = sb.read_status()
-    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
     m = smoe.core.model_struct(st.model, C, 1)
     _capi.smoe_pair_stats(m, st.grid, sb.c, stats.data_ptr(), sh)
-    tested, active = [int(x) for x in stats.tolist()]
+    tested, active, culled_active = [int(x) for x in stats.tolist()]
+    if culled_active:
+        raise RuntimeError("strip culling skipped participating pairs")
     P = sstat[0]
     status = sstat
     T = smoe.tiles(W, H)
@@ -405,6 +407,29 @@ def _rocpd_kernels(db_path):
     return [(n, c, t, a, 100.0 * t / total) for n, c, t, a in rows]
 
 
+def _rocpd_gaps(db_path, names):
+    """Idle time between consecutive dispatches of the fit step's kernels (end of one to
+    start of the next, in dispatch order): {"prev->next": [ns, ...]}."""
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    try:
+        rows = con.execute('select name, start, "end" from kernels order by start').fetchall()
+    except sqlite3.Error:
+        return {}
+    finally:
+        con.close()
+    short = []
+    for name, t0, t1 in rows:
+        k = next((n for n in names if n in name), None)
+        short.append((k, t0, t1))
+    gaps = {}
+    for (a, _, a1), (b, b0, _) in zip(short, short[1:]):
+        if a and b:
+            gaps.setdefault(f"{a}->{b}", []).append(b0 - a1)
+    return gaps
+
+
 def _rocpd_counters(db_path):
     """{(kernel name, counter): [value per dispatch]} of every PMC counter in a rocprofv3
     SQLite output (rows of one dispatch, e.g. per shader-engine instances, are summed)."""
@@ -456,6 +481,15 @@ def summarize_profile(prof_dir, cmd):
             if len(short) > 60:
                 short = short[:57] + "..."
             lines.append(f"| `{short}` | {calls} | {avg / 1e3:.2f} | {tot / 1e3:.1f} | {pct:.1f} |")
+        gaps = _rocpd_gaps(dbs[0], list(STEP_KERNELS))
+        if gaps:
+            lines += ["", "Idle time between consecutive step kernels (end of one dispatch to the "
+                      "start of the next):", "", "| boundary | count | median us | mean us |",
+                      "|---|---|---|---|"]
+            for key, v in sorted(gaps.items()):
+                v = sorted(v)
+                lines.append(f"| {key} | {len(v)} | {v[len(v) // 2] / 1e3:.2f} | "
+                             f"{sum(v) / len(v) / 1e3:.2f} |")
         with open(os.path.join(ROOT, "profiles", "kernels_fit2048.md"), "w") as fh:
             fh.write("\n".join(lines) + "\n")
     ctr = {}

@@ -5,7 +5,8 @@ device memory around it; ``autograd`` exposes the render as a torch.autograd.Fun
 Importing the package requires the built library: there is no CPU fallback.
 """
 from . import _capi  # noqa: F401  (fails loudly when libsmoe.so is missing)
-from .core import (AdamConfig, Bins, FitState, bin, make_grid, materialize, num_params,  # noqa: F401
-                   psnr, render, render_backward, tiles)
+from .core import (AdamConfig, Bins, FitState, Segments, bin, bin_batched,  # noqa: F401
+                   make_grid, materialize, num_params, psnr, render, render_backward,
+                   render_batched, tiles)
 
 __version__ = "0.1.0"
