@@ -220,12 +220,10 @@ def run(args):
     # (the fit workspace already holds part of the next step's binning)
     sb = smoe.bin(st.model, C, 1, st.grid)
     _, sstat = sb.read_status()
-    stats = torch.zeros(3, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
     m = smoe.core.model_struct(st.model, C, 1)
     _capi.smoe_pair_stats(m, st.grid, sb.c, stats.data_ptr(), sh)
-    tested, active, culled_active = [int(x) for x in stats.tolist()]
-    if culled_active:
-        raise RuntimeError("strip culling skipped participating pairs")
+    tested, active = [int(x) for x in stats.tolist()]
     P = sstat[0]
     status = sstat
     T = smoe.tiles(W, H)

@@ -267,14 +267,11 @@ smoe_status smoe_fit_step_timed(smoe_fit_state* state, const float* target, floa
                                 void* const* stage_events, void* stream);
 
 /* Diagnostic (not part of a fit step): counts, over the raster's in-image pixels, the
- * (pixel, kernel) pairs a render tests -- every kernel of the pixel's block list, except in
- * the 16x4 strips of a block that the kernel's ellipse extents provably miss (those tests
- * are skipped; their q exceeds r^2 by a margin) -- the pairs that take part (q <= r^2),
- * and the pairs that take part inside a skipped strip (0 unless the skipping is wrong).
- * out3 is device uint64[3] = (tested, active, active in skipped strips), overwritten.
- * Uses atomics; the counts are exact integers. */
+ * (pixel, kernel) pairs a render tests -- every kernel of the pixel's block list -- and the
+ * pairs that take part (q <= r^2).  out2 is device uint64[2] = (tested, active) and is
+ * overwritten.  Uses atomics; the counts are exact integers. */
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
-                            const smoe_bins* bins, uint64_t* out3, void* stream);
+                            const smoe_bins* bins, uint64_t* out2, void* stream);
 
 /* Reporting: out (device float[max(1, num_segments)]) = each image's MSE at the state's last
  * fit step. */

@@ -30,10 +30,8 @@ struct BackwardArgs {
 };
 
 template <int C, int ORDER>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_backward(
-    BackwardArgs a) {
+__global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
@@ -63,8 +61,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
       }
     }
   }
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, smask,
-                                false, sd, a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, false, sd,
+                                a.pair_grads);
 }
 
 struct GatherArgs {

@@ -381,14 +381,14 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* 
 }
 
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
-                            const smoe_bins* bins, uint64_t* out3, void* stream) {
+                            const smoe_bins* bins, uint64_t* out2, void* stream) {
   clear_stale_error();
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
-      !out3)
+      !out2)
     return SMOE_ERR_INVALID;
   if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
-  return hip_status(launch_pair_stats(S, *bins, out3, static_cast<hipStream_t>(stream)));
+  return hip_status(launch_pair_stats(S, *bins, out2, static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream) {

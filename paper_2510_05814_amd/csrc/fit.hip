@@ -34,11 +34,9 @@ struct FitTileArgs {
 };
 
 template <int C, int ORDER>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void k_fit_tile(
-    FitTileArgs a) {
+__global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
   __shared__ float4 srec[LDS_FLOATS / 4];
-  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const int2 rg = a.ranges[tile];
   const SegGrid sg = seg_of_tile(a.S, tile);
@@ -54,7 +52,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
 
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, smask, D, N);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, D, N);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -89,8 +87,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7))) void
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, smask, true, sd,
-                                a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, true, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {

@@ -29,13 +29,11 @@ struct RenderArgs {
 template <int C, int ORDER>
 __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, smask, D,
-                               N);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, D, N);
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
@@ -78,17 +76,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
   }
 }
 
-// Diagnostic: per block, over in-image pixels, the (pixel, kernel) pairs the render tests
-// (those in strips the culling keeps), the pairs with q <= r^2, and the pairs with
-// q <= r^2 in culled strips (must be 0), added atomically into out3.
+// Diagnostic: per block, the tested (pixel, kernel) pairs of in-image pixels and those with
+// q <= r^2, added atomically into out2 = (tested, active).
 constexpr int kStatThreads = kTilePixels;
 __global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float* __restrict__ records,
                                                              int rs, const int2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ vals,
-                                                             unsigned long long* __restrict__ out3) {
+                                                             unsigned long long* __restrict__ out2) {
   __shared__ unsigned long long s_act[kStatThreads / 64];
-  __shared__ unsigned long long s_tst[kStatThreads / 64];
-  __shared__ unsigned long long s_bad[kStatThreads / 64];
+  __shared__ unsigned long long s_cnt[kStatThreads / 64];
   const int tile = blockIdx.x;
   const SegGrid g = seg_of_tile(S, tile);
   const int lt = tile - g.tile_offset;
@@ -98,13 +94,10 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float
   const bool inside = u < g.W && v < g.H;
   const float x = sample_coord(u, g.ox, g.inv_s);
   const float y = sample_coord(v, g.oy, g.inv_s);
-  const StripBounds sb = strip_bounds(g, lt);
-  const int strip = (threadIdx.x >> 4) >> 2;
   const int2 rg = ranges[tile];
-  unsigned long long act = 0, tst = 0, bad = 0;
+  unsigned long long act = 0;
   for (int i = rg.x; i < rg.y && inside; ++i) {
     const float* r = records + (size_t)vals[i] * rs;
-    const bool kept = (strip_mask(make_float4(r[0], r[1], r[2], r[3]), r[4], sb, S.r2) >> strip) & 1u;
     const float dx = x - r[0];
     const float dy = y - r[1];
     const float z1 = dx * r[2];
@@ -113,24 +106,21 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float
     const float z2 = w * r[4];
     const float q = z1 * z1 + z2 * z2;
     act += (q <= S.r2) ? 1ull : 0ull;
-    tst += kept ? 1ull : 0ull;
-    bad += (q <= S.r2 && !kept) ? 1ull : 0ull;
   }
+  unsigned long long cnt = inside ? 1ull : 0ull;
   for (int off = 32; off > 0; off >>= 1) {
     act += __shfl_xor(act, off);
-    tst += __shfl_xor(tst, off);
-    bad += __shfl_xor(bad, off);
+    cnt += __shfl_xor(cnt, off);
   }
   if ((threadIdx.x & 63) == 0) {
     s_act[threadIdx.x >> 6] = act;
-    s_tst[threadIdx.x >> 6] = tst;
-    s_bad[threadIdx.x >> 6] = bad;
+    s_cnt[threadIdx.x >> 6] = cnt;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(&out3[0], s_tst[0] + s_tst[1] + s_tst[2] + s_tst[3]);
-    atomicAdd(&out3[1], s_act[0] + s_act[1] + s_act[2] + s_act[3]);
-    atomicAdd(&out3[2], s_bad[0] + s_bad[1] + s_bad[2] + s_bad[3]);
+    const unsigned long long px = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    atomicAdd(&out2[0], px * (unsigned long long)(rg.y - rg.x));
+    atomicAdd(&out2[1], s_act[0] + s_act[1] + s_act[2] + s_act[3]);
   }
 }
 
@@ -151,11 +141,11 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
   return hipGetLastError();
 }
 
-hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out3, hipStream_t s) {
-  k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(out3), 3);
+hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out2, hipStream_t s) {
+  k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(out2), 2);
   k_pair_stats<<<S.T, kStatThreads, 0, s>>>(S, b.records, b.record_stride,
                                             reinterpret_cast<const int2*>(b.ranges), b.vals,
-                                            reinterpret_cast<unsigned long long*>(out3));
+                                            reinterpret_cast<unsigned long long*>(out2));
   return hipGetLastError();
 }
 

@@ -126,7 +126,7 @@ hipError_t launch_bin(int C, int order, const float* params, const Segs& S, cons
                       hipStream_t s);
 hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, float* image,
                          float* denom, const float* target, hipStream_t s);
-hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out3, hipStream_t s);
+hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out2, hipStream_t s);
 hipError_t launch_loss_reduce(const smoe_bins& b, int T, float inv_n, float* loss_out,
                               hipStream_t s);
 hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,

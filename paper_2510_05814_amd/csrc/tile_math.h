@@ -35,77 +35,11 @@ __device__ __forceinline__ PixelCoords lane_pixels(const SegGrid& g, int tile) {
   return p;
 }
 
-// Sampling coordinates bounding a block: its first and last columns, and the first and
-// last rows of each 16x4 strip (the rows one wave iteration covers).
-struct StripBounds {
-  float x0, x1;
-  float y0[kRows], y3[kRows];
-};
-
-__device__ __forceinline__ StripBounds strip_bounds(const SegGrid& g, int tile) {
-  StripBounds b;
-  const int tx = tile % g.ntx, ty = tile / g.ntx;
-  b.x0 = sample_coord(tx * kTile, g.ox, g.inv_s);
-  b.x1 = sample_coord(tx * kTile + kTile - 1, g.ox, g.inv_s);
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    b.y0[i] = sample_coord(ty * kTile + 4 * i, g.oy, g.inv_s);
-    b.y3[i] = sample_coord(ty * kTile + 4 * i + 3, g.oy, g.inv_s);
-  }
-  return b;
-}
-
-// Strip culling.  With z = L'^-1 (x - mu) for L' = [[1/i11, 0], [l21, 1/i22]] (the factor
-// the binary32 test uses), q = |z|^2 >= dx^2 / S'xx and q >= dy^2 / S'yy, S' = L' L'^T: the
-// ellipse q <= r^2 lies within |dx| <= r sqrt(S'xx) and |dy| <= r sqrt(S'yy).  Bit i of the
-// mask is set unless every pixel of strip i is beyond those extents by a relative margin
-// of 1/64 -- far above the rounding of the binary32 q, so a culled pixel's q always exceeds
-// r^2 and the culling never changes a truncation decision, only skips tests whose answer is
-// known.  Mask 0: the kernel misses the block's columns or every strip.
-constexpr float kCullSlack = 1.0f + 1.0f / 64.0f;
-
-__device__ __forceinline__ uint32_t strip_mask(float4 r0, float i22, const StripBounds& b,
-                                               float r2) {
-  // r0 = (mu_x, mu_y, 1/l11, l21)
-  const float l11 = 1.0f / r0.z, l22 = 1.0f / i22;
-  const float lim_x = r2 * kCullSlack * (l11 * l11);
-  const float lim_y = r2 * kCullSlack * __builtin_fmaf(r0.w, r0.w, l22 * l22);
-  const float dx = fmaxf(fmaxf(b.x0 - r0.x, r0.x - b.x1), 0.0f);
-  if (!(dx * dx <= lim_x)) return 0u;
-  uint32_t m = 0u;
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    const float dy = fmaxf(fmaxf(b.y0[i] - r0.y, r0.y - b.y3[i]), 0.0f);
-    m |= (dy * dy <= lim_y ? 1u : 0u) << i;
-  }
-  return m;
-}
-
-__device__ __forceinline__ float lane_value(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// The same bounds read from the wave's own pixel coordinates (lane 0: column 0 and the first
-// row of each strip, lane 15: column 15, lane 48: the last row of each strip), as scalars.
-__device__ __forceinline__ StripBounds strip_bounds(const PixelCoords& px) {
-  StripBounds b;
-  b.x0 = lane_value(px.x, 0);
-  b.x1 = lane_value(px.x, 15);
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    b.y0[i] = lane_value(px.y[i], 0);
-    b.y3[i] = lane_value(px.y[i], 48);
-  }
-  return b;
-}
-
-// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS, and the strip
-// mask of each (lane k computes entry k's).
+// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS.
 template <int RS>
-__device__ __forceinline__ void stage_records(float4* __restrict__ srec, uint32_t* __restrict__ smask,
+__device__ __forceinline__ void stage_records(float4* __restrict__ srec,
                                               const float* __restrict__ records,
-                                              const uint32_t* __restrict__ vals, int base, int n,
-                                              const PixelCoords& px, float r2) {
+                                              const uint32_t* __restrict__ vals, int base, int n) {
   constexpr int Q = RS / 4;
   __syncthreads();
   for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
@@ -113,18 +47,15 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec, uint32_
     srec[i] = reinterpret_cast<const float4*>(records + (size_t)vals[base + k] * RS)[c];
   }
   __syncthreads();
-  const int l = threadIdx.x & 63;
-  const StripBounds sb = strip_bounds(px);
-  if (l < n) smask[l] = strip_mask(srec[l * Q], srec[l * Q + 1].x, sb, r2);
-  __syncthreads();
 }
 
 // Forward accumulation over a block's list [rg.x, rg.y) in list order:
 // D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers).
 template <int C, int ORDER>
-__device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2, const float* __restrict__ records,
+__device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
+                                                   const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int2 rg,
-                                                   float4* srec, uint32_t* smask, float (&D)[kRows],
+                                                   float4* srec, float (&D)[kRows],
                                                    float (&N)[kRows][C]) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
@@ -136,10 +67,8 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
   }
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    stage_records<RS>(srec, smask, records, vals, base, n, px, r2);
+    stage_records<RS>(srec, records, vals, base, n);
     for (int k = 0; k < n; ++k) {
-      const uint32_t cm = __builtin_amdgcn_readfirstlane(smask[k]);
-      if (cm == 0u) continue;
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
       // Truncation test: the binary32 sequence of the ABI contract (no contraction).
       const float dx = px.x - r[0];
@@ -148,7 +77,6 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
       const float zz1 = z1 * z1;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
-        if (!((cm >> i) & 1u)) continue;  // culled strip: q > r^2 for all its pixels
         const float dy = px.y[i] - r[1];
         const float w = dy - tt;
         const float z2 = w * r[4];
@@ -304,9 +232,10 @@ struct PixelSeed {
 //   dL/dmu_x = -(bz1/l11 + sum_c g_c w wx_c),  dL/dmu_y = -(bz2/l22 + sum_c g_c w wy_c)
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 template <int C, int ORDER>
-__device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2, const float* __restrict__ records,
+__device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
+                                                    const float* __restrict__ records,
                                                     const uint32_t* __restrict__ vals, int2 rg,
-                                                    float4* srec, uint32_t* smask, bool staged,
+                                                    float4* srec, bool staged,
                                                     const PixelSeed<C>& sd,
                                                     float* __restrict__ pair_grads) {
   constexpr int RS = record_stride(C, ORDER);
@@ -316,15 +245,8 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
   const int lane = threadIdx.x & 63;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    if (!staged || rg.y - rg.x > kChunk)
-      stage_records<RS>(srec, smask, records, vals, base, n, px, r2);
+    if (!staged || rg.y - rg.x > kChunk) stage_records<RS>(srec, records, vals, base, n);
     for (int k = 0; k < n; ++k) {
-      const uint32_t cm = __builtin_amdgcn_readfirstlane(smask[k]);
-      const int idx = lane >> 2;
-      if (cm == 0u) {  // no pixel of the block takes part: a zero partial row
-        if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = 0.0f;
-        continue;
-      }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
       float acc[16];
 #pragma unroll
@@ -335,7 +257,6 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
       const float zz1 = z1 * z1;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
-        if (!((cm >> i) & 1u)) continue;
         const float dy = px.y[i] - r[1];
         const float w_ = dy - tt;
         const float z2 = w_ * r[4];
@@ -374,6 +295,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         }
       }
       const float tot = wave_reduce16_transposed(acc);
+      const int idx = lane >> 2;
       if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = tot;
     }
   }

@@ -35,7 +35,7 @@ import numpy as np
 import torch
 
 from . import _capi as C
-from .core import Bins, Segments, _check_params, make_grid, model_struct
+from .core import Bins, _check_params, make_grid, model_struct
 
 TILE = 16
 
@@ -202,13 +202,25 @@ def _wait_until(clock, t):
 @dataclass
 class _Batch:
     bid: int
-    stream_index: int
+    slot: int
     reqs: list
     nbytes: int
     done: object = None
     keep: list = field(default_factory=list)   # tensors that must live until done
     slices: list = field(default_factory=list)
-    status: torch.Tensor | None = None
+
+
+class _Slot:
+    """Per-stream resources reused by every batch the stream runs: a pinned staging area and
+    a device copy of the segment table, and a pinned copy of the binning status words."""
+
+    def __init__(self, max_batch: int, device):
+        self.stream = torch.cuda.Stream()
+        nbytes = max_batch * ct.sizeof(C.SmoeSegment)
+        self.table_host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        self.table_dev = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        self.batch = None
 
 
 class Server:
@@ -216,105 +228,137 @@ class Server:
 
     def __init__(self, bank: ModelBank, budget_bytes: int = 8 << 30, streams: int = 2,
                  max_batch: int = 32, max_batch_pixels: int = 1 << 26):
-        if streams < 1:
-            raise ValueError("at least one stream")
+        if streams < 1 or max_batch < 1:
+            raise ValueError("at least one stream and one request per batch")
         self.bank = bank
         self.budget = int(budget_bytes)
-        self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.max_batch = int(max_batch)
         self.max_batch_pixels = int(max_batch_pixels)
         self.nbytes_px = 4 * bank.C
+        self.slots = [_Slot(self.max_batch, bank.params.device) for _ in range(streams)]
+        self.streams = [sl.stream for sl in self.slots]
+        self._models = [model_struct(bank.rows(i), bank.C, bank.order) for i in range(len(bank))]
+
+    def _info(self, r):
+        """(kernels, blocks, pair bound, pixels) of one request, computed once."""
+        inf = getattr(r, "_smoe_info", None)
+        if inf is None:
+            inf = (self.bank.K[r.model], _tiles(r.width, r.height),
+                   self.bank.pair_bound(r.model, r.scale, r.width, r.height), r.width * r.height)
+            r._smoe_info = inf
+        return inf
 
     def footprint(self, reqs) -> tuple[int, int, int, int]:
         """(bytes, kernels, blocks, pair bound) of one batch of requests."""
-        b = self.bank
-        K = sum(b.K[r.model] for r in reqs)
-        T = sum(_tiles(r.width, r.height) for r in reqs)
-        P = sum(b.pair_bound(r.model, r.scale, r.width, r.height) for r in reqs)
-        ws = C.smoe_render_workspace_bytes(max(K, 0), b.C, b.order, T, P)
-        px = sum(r.width * r.height for r in reqs)
+        K = T = P = px = 0
+        for r in reqs:
+            k, t, p, n = self._info(r)
+            K, T, P, px = K + k, T + t, P + p, px + n
+        ws = C.smoe_render_workspace_bytes(K, self.bank.C, self.bank.order, T, P)
         return ws + px * self.nbytes_px + 64 * len(reqs), K, T, P
 
     def _launch(self, batch: _Batch, keep_outputs: bool):
         b = self.bank
-        st = self.streams[batch.stream_index]
-        rasters = [dict(width=r.width, height=r.height, scale=r.scale, origin_x=r.origin_x,
-                        origin_y=r.origin_y, num_kernels=b.K[r.model],
-                        param_offset=b.offset[r.model]) for r in batch.reqs]
+        sl = self.slots[batch.slot]
+        st = sl.stream
         _, K, T, P = self.footprint(batch.reqs)
+        dev = b.params.device
         with torch.cuda.stream(st):
-            segs = Segments(rasters, stream=st)
-            bins = Bins(K, b.C, b.order, T, P, device=b.params.device, render_only=True,
-                        zero=False)
-            images = torch.empty((segs.pixels, b.C), dtype=torch.float32, device=b.params.device)
-            cb = C.SmoeBatch(b.C, b.order, b.params.data_ptr(), b.params.shape[0], segs.n,
-                             segs.dev.data_ptr(), ct.addressof(segs.host), b.radius)
-            C.smoe_bin_batched(cb, bins.c, st.cuda_stream)
-            C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
-            status = torch.empty(4, dtype=torch.int32, pin_memory=True)
-            status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
+            bins = Bins(K, b.C, b.order, T, P, device=dev, render_only=True, zero=False)
+            if len(batch.reqs) == 1:
+                # one request: the single-raster calls, no segment table
+                r = batch.reqs[0]
+                grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius)
+                images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
+                m = self._models[r.model]
+                C.smoe_bin(m, grid, bins.c, st.cuda_stream)
+                C.smoe_render(m, grid, bins.c, images.data_ptr(), None, None, None, st.cuda_stream)
+                slices = [(0, r.height * r.width, r.height, r.width)]
+            else:
+                n = len(batch.reqs)
+                host = (C.SmoeSegment * n).from_address(sl.table_host.data_ptr())
+                for sg, r in zip(host, batch.reqs):
+                    sg.width, sg.height, sg.scale = r.width, r.height, r.scale
+                    sg.origin_x, sg.origin_y = r.origin_x, r.origin_y
+                    sg.num_kernels, sg.param_offset = b.K[r.model], b.offset[r.model]
+                _, _, npx = C.smoe_segments_layout(host)
+                nb = n * ct.sizeof(C.SmoeSegment)
+                sl.table_dev[:nb].copy_(sl.table_host[:nb], non_blocking=True)
+                images = torch.empty((npx, b.C), dtype=torch.float32, device=dev)
+                cb = C.SmoeBatch(b.C, b.order, b.params.data_ptr(), b.params.shape[0], n,
+                                 sl.table_dev.data_ptr(), ct.addressof(host), b.radius)
+                C.smoe_bin_batched(cb, bins.c, st.cuda_stream)
+                C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
+                slices = [(sg.pixel_offset, sg.pixel_offset + sg.width * sg.height, sg.height,
+                           sg.width) for sg in host]
+            sl.status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
             batch.done = torch.cuda.Event(enable_timing=True)
             batch.done.record(st)
-        batch.keep = [segs, bins, images]
-        batch.status = status
+        batch.keep = [bins, images]
         if keep_outputs:
-            batch.slices = [images[a:e].view(h, w, b.C) for a, e, h, w in segs.pixel_slices()]
+            batch.slices = [images[a:e].view(h, w, b.C) for a, e, h, w in slices]
 
     def serve(self, requests, realtime: bool = True, keep_outputs: bool = False):
         """Serves every request; returns (results in request order, summary dict).  With
         realtime=False every request is taken as arrived at time 0 (saturation)."""
         reqs = _to_requests(requests)
-        order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
         if not realtime:
             reqs = [RenderRequest(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
+        order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
         results = [None] * len(reqs)
         index = {id(r): i for i, r in enumerate(reqs)}
         pending = deque()
-        inflight = []
-        free = list(range(len(self.streams)))
+        free = list(range(len(self.slots)))
+        inflight = 0
         in_use = peak = 0
-        nxt = nb = overflow = 0
+        nxt = nb = 0
         sizes = []
         clock = _Clock(self.streams[0])
+        footprint = lambda q: self.footprint(q)[0]  # noqa: E731
         while nxt < len(order) or pending or inflight:
             now = clock.now()
             while nxt < len(order) and reqs[order[nxt]].arrival <= now:
-                pending.append(reqs[order[nxt]])
+                r = reqs[order[nxt]]
+                self._info(r)
+                pending.append(r)
                 nxt += 1
-            for bt in list(inflight):
-                if bt.done.query():
+            if inflight:
+                for si, sl in enumerate(self.slots):
+                    bt = sl.batch
+                    if bt is None or not bt.done.query():
+                        continue
                     t = clock.at(bt.done)
-                    if int(bt.status[1]) != 0:
-                        overflow += 1
-                        raise RuntimeError("pair bound exceeded: batch overflowed its workspace")
+                    if int(sl.status[1]) != 0:
+                        raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
                     for j, r in enumerate(bt.reqs):
                         results[index[id(r)]] = RenderResult(
                             r, t, bt.bid, bt.slices[j] if keep_outputs else None)
                     in_use -= bt.nbytes
-                    free.append(bt.stream_index)
-                    inflight.remove(bt)
-            launched = False
+                    sl.batch = None
+                    free.append(si)
+                    inflight -= 1
             while free and pending:
-                got = admit(pending, in_use, self.budget, lambda q: self.footprint(q)[0],
-                            self.max_batch, self.max_batch_pixels)
+                got = admit(pending, in_use, self.budget, footprint, self.max_batch,
+                            self.max_batch_pixels)
                 if not got:
                     break
-                need = self.footprint(got)[0]
-                bt = _Batch(nb, free.pop(0), got, need)
+                need = footprint(got)
+                si = free.pop(0)
+                bt = _Batch(nb, si, got, need)
                 nb += 1
                 self._launch(bt, keep_outputs)
-                inflight.append(bt)
+                self.slots[si].batch = bt
+                inflight += 1
                 in_use += need
                 peak = max(peak, in_use)
                 sizes.append(len(got))
-                launched = True
-            if not launched and not inflight and not pending and nxt < len(order):
+            if not inflight and not pending and nxt < len(order):
                 _wait_until(clock, reqs[order[nxt]].arrival)
         torch.cuda.synchronize()
         return results, _summary(results, "batched", {
             "batches": nb, "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
-            "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.streams),
-            "peak_bytes": int(peak), "budget_bytes": self.budget, "overflows": overflow})
+            "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.slots),
+            "peak_bytes": int(peak), "budget_bytes": self.budget})
 
 
 class PlainServer:

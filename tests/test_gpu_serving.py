@@ -56,7 +56,6 @@ def test_batched_serving_results_equal_alone(bank_and_models, streams, budget_mb
     reqs = wl.serving_requests(sides, 48, rate=4000.0, max_side=700, seed=11)
     srv = Server(bank, budget_bytes=budget_mb << 20, streams=streams, max_batch=8)
     res, summ = srv.serve(reqs, keep_outputs=True)
-    assert summ["overflows"] == 0
     assert summ["peak_bytes"] <= summ["budget_bytes"]
     assert summ["batches"] < len(reqs) or budget_mb < 100
     for i, r in enumerate(res):
