@@ -44,9 +44,11 @@ WORKLOAD = "fit-2048x2048-rgb-K65536-linear-denoise"
 OPS_TESTED = 10
 OPS_ACTIVE_FWD = 12
 OPS_ACTIVE_BWD = 52
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 VALU lane-operations/s
-# (non-packed; packed FP32 is not used).
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X FP32 vector peak: 157.3 TFLOP/s counting an FMA as 2 flops = 256 CUs x 4 SIMDs x
+# 32 lanes x 2.4 GHz = 78.6e12 lane-operations/s (one FP32 instruction per lane).  The
+# counters agree: the fused kernel issues more than one wave64 VALU instruction per 4 cycles
+# per SIMD, so a wave64 FP32 instruction takes 2 cycles without packed math.
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK = 8.0e12
 
 STAGES = ["bin", "render_backward", "adam"]
@@ -454,8 +456,9 @@ STEP_KERNELS = {"k_fit_tile": KERNEL_SOURCES["render_backward"],
                            "paper_2510_05814_amd/csrc/device_common.h"],
                 "k_scatter": ["paper_2510_05814_amd/csrc/binning.hip",
                               "paper_2510_05814_amd/csrc/device_common.h"]}
-# CDNA issue model: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles, and a
-# binary32 transcendental (v_exp_f32, v_rcp_f32, ...) for 16 cycles (quarter rate).
+# Issue model: a wave64 FP32 VALU instruction occupies its SIMD for 2 cycles (32 lanes per
+# cycle, the 157.3 TFLOP/s vector peak), a binary32 transcendental (v_exp_f32, v_rcp_f32, ...)
+# for 8 cycles (quarter rate).
 N_SIMD = 256 * 4
 CLOCK_HZ = 2.4e9
 
@@ -534,9 +537,9 @@ def summarize_profile(prof_dir, cmd):
             nt = e["counters"].get("SQ_INSTS_VALU_TRANS_F32")
             slots = N_SIMD * CLOCK_HZ * dur
             if nv is not None:
-                e["valu_busy_frac"] = nv * 4 / slots
+                e["valu_busy_frac"] = nv * 2 / slots
             if nt is not None:
-                e["trans_busy_frac"] = nt * 16 / slots
+                e["trans_busy_frac"] = nt * 8 / slots
         if e["counters"]:
             out["kernels"][k] = e
 
@@ -552,8 +555,9 @@ def summarize_profile(prof_dir, cmd):
           f"Command (trace; each pmc_* run is the same program under `--pmc <counters>`): "
           f"`{cmd}`", "",
           "Bytes: FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB elementwise kernel of "
-          "known traffic.  VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x "
-          "duration); trans busy = SQ_INSTS_VALU_TRANS_F32 x 16 cycles / the same.", "",
+          "known traffic.  VALU busy = SQ_INSTS_VALU x 2 cycles / (1024 SIMDs x 2.4 GHz x "
+          "duration); trans busy = SQ_INSTS_VALU_TRANS_F32 x 8 cycles / the same.  Counters "
+          "are summed over all XCDs and shader engines.", "",
           *rows, "", "Counters collected: " + ", ".join(counters), ""]
     with open(os.path.join(ROOT, "profiles", "counters_fit2048.md"), "w") as fh:
         fh.write("\n".join(md))
