@@ -291,7 +291,8 @@ def run_serving(args):
     linear experts), a Poisson stream of render requests at 200 req/s, each at an upscale
     factor in {1, 2, 3, 4} with outputs up to 4096^2 RGB, admitted under an 8 GB budget.
     Reports p50/p99 latency and pixels/s of continuous batching against one launch
-    sequence per request, at the Poisson rate and at saturation (all requests at t = 0)."""
+    sequence per request, at the Poisson rate, at saturation (all requests at t = 0), and at
+    higher Poisson rates (2000, 5000, 10000 req/s) of the same request mix."""
     import numpy as np
     import torch
 
@@ -331,6 +332,15 @@ def run_serving(args):
     sat = reqs[:args.serve_saturation]
     _, out["batched_saturated"] = srv.serve(sat, realtime=False)
     _, out["plain_saturated"] = plain.serve(sat, realtime=False)
+    # higher offered loads (same request mix): where batching starts to pay
+    out["load_sweep"] = []
+    for rate in (2000.0, 5000.0, 10000.0):
+        rq = wl.serving_requests(sides, args.serve_sweep_requests, rate=rate, seed=11)
+        _, b = srv.serve(rq)
+        _, p = plain.serve(rq)
+        keys = ("p50_ms", "p99_ms", "pixels_per_s", "requests_per_s")
+        out["load_sweep"].append({"rate_hz": rate, "batched": {k: b[k] for k in keys + ("mean_batch",)},
+                                  "plain": {k: p[k] for k in keys}})
     return out
 
 
@@ -578,6 +588,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-saturation", type=int, default=300)
     ap.add_argument("--serve-fit-steps", type=int, default=50)
+    ap.add_argument("--serve-sweep-requests", type=int, default=600)
     ap.add_argument("--no-batched-fit", action="store_true")
     ap.add_argument("--bfit-steps", type=int, default=1000)
     ap.add_argument("--summarize-profile", metavar="DIR")

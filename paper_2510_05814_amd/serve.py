@@ -8,13 +8,14 @@ factor is a native super-resolution of the same model, not an interpolation of a
 Two servers share the request format and the report:
 
 * ``Server`` -- continuous batching.  Requests that have arrived wait in a FIFO queue.
-  Whenever one of its streams is free, the server takes the queue's head requests whose
-  memory (output image + their share of the binning workspace) fits the HBM budget
-  beside the batches still in flight, lays them out as segments of one raster table, and
-  issues one batched binning and ONE render launch over the concatenated (request,
-  block) list on that stream.  Batches on different streams overlap on the device;
-  finished batches release their memory and stream, and the queue is admitted again.
-  Nothing waits on the device except to learn which batches have finished.
+  Whenever one of its streams is free and the batches in flight leave part of the GPU idle
+  (fewer blocks than it renders at once), the server takes the queue's head requests whose
+  memory (output image + their share of the binning workspace) fits the HBM budget beside
+  the batches still in flight, lays them out as segments of one raster table, and issues
+  one batched binning and ONE render launch over the concatenated (request, block) list on
+  that stream.  Batches on different streams overlap on the device; finished batches
+  release their memory, stream and blocks, and the queue is admitted again.  Nothing waits
+  on the device except to learn which batches have finished.
 * ``PlainServer`` -- the baseline: one bin + render launch sequence per request, in
   arrival order on one stream, the host waiting for each request before the next.
 
@@ -57,6 +58,7 @@ class RenderResult:
     done: float               # device completion, seconds from the start of the run
     batch: int
     image: torch.Tensor | None = None
+    started: float = 0.0      # device start of its batch's first launch, same clock
 
     @property
     def latency(self) -> float:
@@ -163,8 +165,12 @@ def _summary(results, name: str, extra=None):
     px = sum(r.request.width * r.request.height for r in results)
     t0 = min(r.request.arrival for r in results)
     t1 = max(r.done for r in results)
+    wait = np.array([r.started - r.request.arrival for r in results]) * 1e3
+    gpu = np.array([r.done - r.started for r in results]) * 1e3
     out = {"server": name, "requests": len(results), "p50_ms": float(np.percentile(lat, 50)),
            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+           "wait_p50_ms": float(np.percentile(wait, 50)), "wait_p99_ms": float(np.percentile(wait, 99)),
+           "gpu_p50_ms": float(np.percentile(gpu, 50)), "gpu_p99_ms": float(np.percentile(gpu, 99)),
            "max_ms": float(lat.max()), "pixels": int(px), "makespan_s": float(t1 - t0),
            "pixels_per_s": float(px / max(t1 - t0, 1e-9)),
            "requests_per_s": float(len(results) / max(t1 - t0, 1e-9))}
@@ -205,21 +211,24 @@ class _Batch:
     slot: int
     reqs: list
     nbytes: int
+    blocks: int = 0
+    start: object = None
     done: object = None
+    status_ready: object = None
+    status: torch.Tensor | None = None
     keep: list = field(default_factory=list)   # tensors that must live until done
     slices: list = field(default_factory=list)
 
 
 class _Slot:
     """Per-stream resources reused by every batch the stream runs: a pinned staging area and
-    a device copy of the segment table, and a pinned copy of the binning status words."""
+    a device copy of the segment table."""
 
     def __init__(self, max_batch: int, device):
         self.stream = torch.cuda.Stream()
         nbytes = max_batch * ct.sizeof(C.SmoeSegment)
         self.table_host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         self.table_dev = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
         self.batch = None
 
 
@@ -227,9 +236,15 @@ class Server:
     """Continuous batching over `streams` streams under an HBM budget (bytes)."""
 
     def __init__(self, bank: ModelBank, budget_bytes: int = 8 << 30, streams: int = 2,
-                 max_batch: int = 32, max_batch_pixels: int = 1 << 26):
+                 max_batch: int = 32, max_batch_pixels: int = 1 << 26,
+                 fill_blocks: int = 8192):
+        """fill_blocks: a further batch is started beside those in flight only while they
+        hold fewer 16x16 blocks than this -- about what the GPU renders at once (256 CUs x
+        4 SIMDs x 7-8 one-wave blocks).  A batch that fills the GPU runs alone; requests that
+        arrive meanwhile queue and leave together in the next batch."""
         if streams < 1 or max_batch < 1:
             raise ValueError("at least one stream and one request per batch")
+        self.fill_blocks = int(fill_blocks)
         self.bank = bank
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
@@ -248,6 +263,11 @@ class Server:
             r._smoe_info = inf
         return inf
 
+    def _single_bytes(self, r) -> int:
+        k, t, p, n = self._info(r)
+        return (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
+                + n * self.nbytes_px + 64)
+
     def footprint(self, reqs) -> tuple[int, int, int, int]:
         """(bytes, kernels, blocks, pair bound) of one batch of requests."""
         K = T = P = px = 0
@@ -264,6 +284,8 @@ class Server:
         _, K, T, P = self.footprint(batch.reqs)
         dev = b.params.device
         with torch.cuda.stream(st):
+            batch.start = torch.cuda.Event(enable_timing=True)
+            batch.start.record(st)
             bins = Bins(K, b.C, b.order, T, P, device=dev, render_only=True, zero=False)
             if len(batch.reqs) == 1:
                 # one request: the single-raster calls, no segment table
@@ -291,9 +313,14 @@ class Server:
                 C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
                 slices = [(sg.pixel_offset, sg.pixel_offset + sg.width * sg.height, sg.height,
                            sg.width) for sg in host]
-            sl.status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
+            # the images are complete at `done`; the status words follow and are checked once
+            # their copy has landed (the batch's slot is released at `done`)
             batch.done = torch.cuda.Event(enable_timing=True)
             batch.done.record(st)
+            batch.status = torch.empty(4, dtype=torch.int32, pin_memory=True)
+            batch.status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
+            batch.status_ready = torch.cuda.Event()
+            batch.status_ready.record(st)
         batch.keep = [bins, images]
         if keep_outputs:
             batch.slices = [images[a:e].view(h, w, b.C) for a, e, h, w in slices]
@@ -310,9 +337,11 @@ class Server:
         pending = deque()
         free = list(range(len(self.slots)))
         inflight = 0
+        inflight_blocks = 0
         in_use = peak = 0
         nxt = nb = 0
         sizes = []
+        checks = []  # finished batches whose status words are still to be read
         clock = _Clock(self.streams[0])
         footprint = lambda q: self.footprint(q)[0]  # noqa: E731
         while nxt < len(order) or pending or inflight:
@@ -328,36 +357,43 @@ class Server:
                     if bt is None or not bt.done.query():
                         continue
                     t = clock.at(bt.done)
-                    if int(sl.status[1]) != 0:
-                        raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
+                    t_start = clock.at(bt.start)
+                    bt.keep = []  # later work on this stream may reuse the memory
+                    checks.append(bt)
                     for j, r in enumerate(bt.reqs):
                         results[index[id(r)]] = RenderResult(
-                            r, t, bt.bid, bt.slices[j] if keep_outputs else None)
+                            r, t, bt.bid, bt.slices[j] if keep_outputs else None, t_start)
                     in_use -= bt.nbytes
+                    inflight_blocks -= bt.blocks
                     sl.batch = None
                     free.append(si)
                     inflight -= 1
-            while free and pending:
+            while free and pending and inflight_blocks < self.fill_blocks:
                 got = admit(pending, in_use, self.budget, footprint, self.max_batch,
                             self.max_batch_pixels)
                 if not got:
                     break
-                need = footprint(got)
+                need = footprint(got) if len(got) > 1 else self._single_bytes(got[0])
                 si = free.pop(0)
-                bt = _Batch(nb, si, got, need)
+                bt = _Batch(nb, si, got, need, blocks=sum(self._info(r)[1] for r in got))
                 nb += 1
                 self._launch(bt, keep_outputs)
                 self.slots[si].batch = bt
                 inflight += 1
+                inflight_blocks += bt.blocks
                 in_use += need
                 peak = max(peak, in_use)
                 sizes.append(len(got))
             if not inflight and not pending and nxt < len(order):
                 _wait_until(clock, reqs[order[nxt]].arrival)
         torch.cuda.synchronize()
+        for bt in checks:
+            if int(bt.status[1]) != 0:
+                raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
         return results, _summary(results, "batched", {
             "batches": nb, "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
             "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.slots),
+            "fill_blocks": self.fill_blocks,
             "peak_bytes": int(peak), "budget_bytes": self.budget})
 
 
@@ -384,6 +420,8 @@ class PlainServer:
             rows = b.rows(r.model)
             m = model_struct(rows, b.C, b.order)
             with torch.cuda.stream(st):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(st)
                 bins = Bins(b.K[r.model], b.C, b.order, _tiles(r.width, r.height),
                             b.pair_bound(r.model, r.scale, r.width, r.height),
                             device=rows.device, render_only=True, zero=False)
@@ -396,7 +434,8 @@ class PlainServer:
             code, status = C.smoe_read_status(bins.c, st.cuda_stream)
             if code == C.SMOE_ERR_CAPACITY:
                 raise RuntimeError("pair bound exceeded: request overflowed its workspace")
-            results[i] = RenderResult(r, clock.at(ev), i, image if keep_outputs else None)
+            results[i] = RenderResult(r, clock.at(ev), i, image if keep_outputs else None,
+                                      clock.at(ev0))
         torch.cuda.synchronize()
         return results, _summary(results, "plain")
 
