@@ -329,6 +329,8 @@ def run_serving(args):
     plain.serve(warm, realtime=False)
     _, out["batched"] = srv.serve(reqs)
     _, out["plain"] = plain.serve(reqs)
+    if args.serve_one_stream:
+        _, out["batched_one_stream"] = Server(bank, budget_bytes=8 << 30, streams=1).serve(reqs)
     sat = reqs[:args.serve_saturation]
     _, out["batched_saturated"] = srv.serve(sat, realtime=False)
     _, out["plain_saturated"] = plain.serve(sat, realtime=False)
@@ -589,6 +591,8 @@ def main():
     ap.add_argument("--serve-saturation", type=int, default=300)
     ap.add_argument("--serve-fit-steps", type=int, default=50)
     ap.add_argument("--serve-sweep-requests", type=int, default=600)
+    ap.add_argument("--serve-one-stream", action="store_true",
+                    help="also serve the Poisson stream with a one-stream batched server")
     ap.add_argument("--no-batched-fit", action="store_true")
     ap.add_argument("--bfit-steps", type=int, default=1000)
     ap.add_argument("--summarize-profile", metavar="DIR")

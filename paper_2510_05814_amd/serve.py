@@ -8,8 +8,9 @@ factor is a native super-resolution of the same model, not an interpolation of a
 Two servers share the request format and the report:
 
 * ``Server`` -- continuous batching.  Requests that have arrived wait in a FIFO queue.
-  Whenever one of its streams is free and the batches in flight leave part of the GPU idle
-  (fewer blocks than it renders at once), the server takes the queue's head requests whose
+  Whenever one of its streams is free, the batches in flight leave part of the GPU idle
+  (fewer blocks than it renders at once) and, if a batch is in flight, a backlog has formed
+  (at least two requests wait), the server takes the queue's head requests whose
   memory (output image + their share of the binning workspace) fits the HBM budget beside
   the batches still in flight, lays them out as segments of one raster table, and issues
   one batched binning and ONE render launch over the concatenated (request, block) list on
@@ -27,7 +28,9 @@ sizes (Sec. IV-B), so no batch needs a host round-trip to learn its pair count.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as ct
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -196,6 +199,18 @@ class _Clock:
         return self.ref.elapsed_time(ev) * 1e-3
 
 
+@contextlib.contextmanager
+def _no_gc():
+    """The collector paused for a serving run (its pauses would land on request latencies)."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 def _wait_until(clock, t):
     while True:
         d = t - clock.now()
@@ -232,47 +247,56 @@ class _Slot:
         self.batch = None
 
 
+def _check(bt):
+    bt.status_ready.synchronize()
+    if int(bt.status[1]) != 0:
+        raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
+
+
 class Server:
     """Continuous batching over `streams` streams under an HBM budget (bytes)."""
 
     def __init__(self, bank: ModelBank, budget_bytes: int = 8 << 30, streams: int = 2,
                  max_batch: int = 32, max_batch_pixels: int = 1 << 26,
-                 fill_blocks: int = 8192):
+                 fill_blocks: int = 4096, overlap_backlog: int = 2):
         """fill_blocks: a further batch is started beside those in flight only while they
-        hold fewer 16x16 blocks than this -- about what the GPU renders at once (256 CUs x
-        4 SIMDs x 7-8 one-wave blocks).  A batch that fills the GPU runs alone; requests that
-        arrive meanwhile queue and leave together in the next batch."""
+        hold fewer 16x16 blocks than this -- about half of what the GPU renders at once
+        (256 CUs x 4 SIMDs x 7-8 one-wave blocks).  A batch that fills the GPU runs alone;
+        requests that arrive meanwhile queue and leave together in the next batch.
+        overlap_backlog: a batch is started beside one in flight only when at least this many
+        requests wait; a lone request waits for the batch in flight instead (measured: at
+        light load, overlapping a lone request lengthens the tail of the larger renders)."""
         if streams < 1 or max_batch < 1:
             raise ValueError("at least one stream and one request per batch")
         self.fill_blocks = int(fill_blocks)
+        self.overlap_backlog = max(1, int(overlap_backlog))
         self.bank = bank
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self.max_batch_pixels = int(max_batch_pixels)
         self.nbytes_px = 4 * bank.C
         self.slots = [_Slot(self.max_batch, bank.params.device) for _ in range(streams)]
+        # pinned status words of recent batches (a ring: a row is read before it is reused)
+        self._status = torch.zeros((256, 4), dtype=torch.int32, pin_memory=True)
         self.streams = [sl.stream for sl in self.slots]
         self._models = [model_struct(bank.rows(i), bank.C, bank.order) for i in range(len(bank))]
 
     def _info(self, r):
-        """(kernels, blocks, pair bound, pixels) of one request, computed once."""
+        """(kernels, blocks, pair bound, pixels, bytes alone) of one request, computed once."""
         inf = getattr(r, "_smoe_info", None)
         if inf is None:
-            inf = (self.bank.K[r.model], _tiles(r.width, r.height),
-                   self.bank.pair_bound(r.model, r.scale, r.width, r.height), r.width * r.height)
-            r._smoe_info = inf
+            k, t = self.bank.K[r.model], _tiles(r.width, r.height)
+            p, n = self.bank.pair_bound(r.model, r.scale, r.width, r.height), r.width * r.height
+            nbytes = (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
+                      + n * self.nbytes_px + 64)
+            inf = r._smoe_info = (k, t, p, n, nbytes)
         return inf
-
-    def _single_bytes(self, r) -> int:
-        k, t, p, n = self._info(r)
-        return (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
-                + n * self.nbytes_px + 64)
 
     def footprint(self, reqs) -> tuple[int, int, int, int]:
         """(bytes, kernels, blocks, pair bound) of one batch of requests."""
         K = T = P = px = 0
         for r in reqs:
-            k, t, p, n = self._info(r)
+            k, t, p, n, _ = self._info(r)
             K, T, P, px = K + k, T + t, P + p, px + n
         ws = C.smoe_render_workspace_bytes(K, self.bank.C, self.bank.order, T, P)
         return ws + px * self.nbytes_px + 64 * len(reqs), K, T, P
@@ -317,7 +341,7 @@ class Server:
             # their copy has landed (the batch's slot is released at `done`)
             batch.done = torch.cuda.Event(enable_timing=True)
             batch.done.record(st)
-            batch.status = torch.empty(4, dtype=torch.int32, pin_memory=True)
+            batch.status = self._status[batch.bid % len(self._status)]
             batch.status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
             batch.status_ready = torch.cuda.Event()
             batch.status_ready.record(st)
@@ -328,6 +352,10 @@ class Server:
     def serve(self, requests, realtime: bool = True, keep_outputs: bool = False):
         """Serves every request; returns (results in request order, summary dict).  With
         realtime=False every request is taken as arrived at time 0 (saturation)."""
+        with _no_gc():
+            return self._serve(requests, realtime, keep_outputs)
+
+    def _serve(self, requests, realtime, keep_outputs):
         reqs = _to_requests(requests)
         if not realtime:
             reqs = [RenderRequest(**{**r.__dict__, "arrival": 0.0}) for r in reqs]
@@ -368,13 +396,25 @@ class Server:
                     sl.batch = None
                     free.append(si)
                     inflight -= 1
-            while free and pending and inflight_blocks < self.fill_blocks:
-                got = admit(pending, in_use, self.budget, footprint, self.max_batch,
-                            self.max_batch_pixels)
-                if not got:
-                    break
-                need = footprint(got) if len(got) > 1 else self._single_bytes(got[0])
-                si = free.pop(0)
+            while (free and pending and inflight_blocks < self.fill_blocks
+                   and (not inflight or len(pending) >= self.overlap_backlog)):
+                if len(pending) == 1:  # the common case at low load
+                    need = pending[0]._smoe_info[4]
+                    if in_use + need > self.budget:
+                        if need > self.budget:
+                            raise ValueError(f"request needs {need} bytes, over the budget")
+                        break
+                    got = [pending.popleft()]
+                else:
+                    got = admit(pending, in_use, self.budget, footprint, self.max_batch,
+                                self.max_batch_pixels)
+                    if not got:
+                        break
+                    need = footprint(got)
+                while checks and checks[0].bid <= nb - len(self._status):
+                    _check(checks.pop(0))  # its status row is about to be reused
+                si = min(free)  # the lowest free stream: at low load always the same one
+                free.remove(si)
                 bt = _Batch(nb, si, got, need, blocks=sum(self._info(r)[1] for r in got))
                 nb += 1
                 self._launch(bt, keep_outputs)
@@ -388,12 +428,11 @@ class Server:
                 _wait_until(clock, reqs[order[nxt]].arrival)
         torch.cuda.synchronize()
         for bt in checks:
-            if int(bt.status[1]) != 0:
-                raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
+            _check(bt)
         return results, _summary(results, "batched", {
             "batches": nb, "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
             "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.slots),
-            "fill_blocks": self.fill_blocks,
+            "fill_blocks": self.fill_blocks, "overlap_backlog": self.overlap_backlog,
             "peak_bytes": int(peak), "budget_bytes": self.budget})
 
 
@@ -405,6 +444,10 @@ class PlainServer:
         self.stream = torch.cuda.Stream()
 
     def serve(self, requests, realtime: bool = True, keep_outputs: bool = False):
+        with _no_gc():
+            return self._serve(requests, realtime, keep_outputs)
+
+    def _serve(self, requests, realtime, keep_outputs):
         b = self.bank
         reqs = _to_requests(requests)
         if not realtime:
