@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
       }
     }
   }
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, false, sd,
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, false, 0ull, sd,
                                 a.pair_grads);
 }
 

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
 
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, D, N);
+  uint64_t live = 0;
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, D, N, live);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, true, sd, a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, true, live, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {

@@ -33,7 +33,8 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, D, N);
+  uint64_t live;
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, D, N, live);
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {

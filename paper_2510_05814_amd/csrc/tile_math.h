@@ -51,12 +51,14 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
 
 // Forward accumulation over a block's list [rg.x, rg.y) in list order:
 // D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers).
+// live: bit k set if any pixel of the block passed the truncation test for entry k of the
+// last staged chunk (the only chunk for lists of up to kChunk entries).
 template <int C, int ORDER>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
                                                    const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int2 rg,
                                                    float4* srec, float (&D)[kRows],
-                                                   float (&N)[kRows][C]) {
+                                                   float (&N)[kRows][C], uint64_t& live) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
 #pragma unroll
@@ -68,8 +70,10 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     stage_records<RS>(srec, records, vals, base, n);
+    live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
+      bool hit = false;
       // Truncation test: the binary32 sequence of the ABI contract (no contraction).
       const float dx = px.x - r[0];
       const float z1 = dx * r[2];
@@ -81,6 +85,7 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
         const float w = dy - tt;
         const float z2 = w * r[4];
         const float q = zz1 + z2 * z2;
+        hit |= q <= r2;
         if (q <= r2) {
           // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
@@ -96,6 +101,7 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
           }
         }
       }
+      if (__any(hit)) live |= 1ull << k;
     }
   }
 }
@@ -225,7 +231,9 @@ struct PixelSeed {
 // adjoints of its 6 + 3C raw parameters (recomputing pi K from the record, w = pi K / D),
 // sums them over the block's 256 pixels with the transposed reduction, and writes the
 // per-(block, kernel) partial row pair_grads[list position].  `staged`: the records of a
-// single-chunk list are already in srec (the fused fit kernel rendered from them).
+// single-chunk list are already in srec and `live` holds the forward's per-entry hits (the
+// fused fit kernel rendered from them): an entry no pixel passed gets a zero row without
+// repeating its tests -- the row it would reduce to, bit for bit.
 //   G = sum_c g_c (m_c - y_c),  H = w G                       (dL/drho)
 //   dL/da_c = g_c w,  dL/dwx_c = g_c w dx,  dL/dwy_c = g_c w dy
 //   bz2 = -H z2,  bz1 = -H z1 - bz2 l21/l22                  (through q = z1^2 + z2^2)
@@ -235,7 +243,7 @@ template <int C, int ORDER>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
                                                     const uint32_t* __restrict__ vals, int2 rg,
-                                                    float4* srec, bool staged,
+                                                    float4* srec, bool staged, uint64_t live,
                                                     const PixelSeed<C>& sd,
                                                     float* __restrict__ pair_grads) {
   constexpr int RS = record_stride(C, ORDER);
@@ -245,8 +253,15 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
   const int lane = threadIdx.x & 63;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    if (!staged || rg.y - rg.x > kChunk) stage_records<RS>(srec, records, vals, base, n);
+    const bool reuse = staged && rg.y - rg.x <= kChunk;
+    if (!reuse) stage_records<RS>(srec, records, vals, base, n);
     for (int k = 0; k < n; ++k) {
+      if (reuse && !((live >> k) & 1ull)) {
+        // no pixel of the block passed the forward's test: the partial row is zero
+        const int idx = lane >> 2;
+        if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = 0.0f;
+        continue;
+      }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
       float acc[16];
 #pragma unroll
