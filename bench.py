@@ -365,7 +365,7 @@ def run_batched_fit(args):
     tg = [torch.from_numpy(i).cuda() for i in imgs]
     rg = [torch.from_numpy(r).cuda() for r in raws]
     probe = smoe.FitState(tg, rg, 1, adam, max_steps=1)
-    cap = 4 * probe.bins.capacity        # graph replays cannot re-size the workspace
+    cap = 2 * probe.bins.capacity        # graph replays cannot re-size the workspace
     del probe
     st = smoe.FitState(tg, rg, 1, adam, max_steps=steps + 1, capacity=cap)
     st.step()                     # first step eagerly (prologue), then graphs

@@ -247,15 +247,17 @@ typedef struct smoe_fit_state {
 /* One fit iteration on `stream` with no host synchronisation: binning, forward render
  * with the fused squared-error loss, backward, then per kernel the deterministic
  * reduction of its block partials, the Adam update of the raw row and its
- * re-materialization.  The step runs as four kernels: the scan of the block counts into
- * list ranges; the scatter into block buckets; one kernel that per 16x16 block orders the
- * bucket, renders the block and runs its backward; and Adam, which also records the loss
- * and computes the next step's boxes, records and block counts (so the first step,
- * state->prepared == 0, computes those first and then sets state->prepared = 1).
- * loss_out (device float[1], may be NULL) and loss_history[step] receive the loss before
- * the update.  After a capacity overflow the step changes nothing (the step counter
- * included); smoe_read_status() reports it.  image, denom and grads hold the last step's
- * render, denominator and gradient. */
+ * re-materialization.  The step runs as three kernels: the scatter of the (block, kernel)
+ * pairs into block buckets; one kernel that per 16x16 block orders its bucket, renders the
+ * block and runs its backward; and Adam, which also records the loss and computes the next
+ * step's boxes and records (so the first step, state->prepared == 0, computes those first
+ * and then sets state->prepared = 1).  The workspace's pair storage is used as fixed-width
+ * buckets: each of the T blocks gets floor(bins.capacity / T) entries, so the capacity must
+ * cover T times the longest block list.  A fuller bucket is a capacity overflow: the step
+ * changes nothing (the step counter included) and smoe_read_status() reports it, with
+ * status[0] = T x the longest list and status[2] = the longest list.  loss_out (device
+ * float[1], may be NULL) and loss_history[step] receive the loss before the update.  image,
+ * denom and grads hold the last step's render, denominator and gradient. */
 smoe_status smoe_fit_step(smoe_fit_state* state, const float* target, float* loss_out,
                           void* stream);
 

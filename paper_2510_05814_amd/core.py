@@ -310,7 +310,8 @@ class FitState:
             else:
                 b = bin(self.model, C_, order, self.grid)
             _, st = b.read_status()
-            capacity = int(st[0] * 2) + 4096
+            # the fit step's buckets: room for twice the initial longest list (at least 64)
+            capacity = T * max(64, 2 * int(st[2]))
         self.bins = Bins(self.K, C_, order, T, capacity, dev)
         self._build_struct()
 
@@ -405,8 +406,9 @@ class FitState:
         """Host sync; after a pair-capacity overflow re-makes the workspace larger."""
         over, st = self.bins.read_status(stream)
         if over:
+            # status[0]: blocks x the longest list the step met
             self.bins = Bins(self.K, self.C, self.order, self.bins.max_tiles,
-                             int(st[0] * 1.5) + 4096, self.raw.device)
+                             max(int(st[0] * 1.5), self.bins.capacity + 1), self.raw.device)
             self._build_struct()
         return over
 

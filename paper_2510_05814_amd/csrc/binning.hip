@@ -9,14 +9,15 @@
 // is also the block ranges), a scatter into the buckets, and a per-bucket sort of the
 // kernel ids in LDS that restores the stable order the atomic scatter does not keep.
 // Every pass is integer work over a few MB, so the design minimises launches, not bytes.
-// The fit step fuses these passes into its other kernels (optim.hip, render.hip).
+// The fit step uses fixed-width buckets instead (k_scatter_fixed): no histogram and no scan,
+// the bucket of block t is entries [t W, t W + W) of the pair storage.
 #include "device_common.h"
 
 namespace smoe {
 namespace {
 
-// One thread per kernel row: block rectangle, count, render record, and one atomic
-// increment per covered block.
+// One thread per kernel row: block rectangle, count, render record, and (tile_counts not
+// null) one atomic increment per covered block.
 __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
                                                     const float* __restrict__ params, Segs S,
                                                     int4* __restrict__ tile_rects,
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
   tile_rects[j] = rc;
   counts[j] = rect_count(rc);
   write_record(records + (size_t)j * rs, p, ne, rs);
-  count_blocks(rc, sg, tile_counts);
+  if (tile_counts) count_blocks(rc, sg, tile_counts);
 }
 
 constexpr int kScanThreads = 1024;
@@ -68,6 +69,34 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
     const int pos = atomicAdd(&cursors[t], 1);
     const int2 rg = ranges[t];
     if (rg.x + pos < rg.y) vals[rg.x + pos] = (uint32_t)j;
+  }
+}
+
+// The fit step's scatter into fixed-width buckets: the kernel id goes to entry t W + c of
+// the pair storage, c the block's cursor; a bucket that fills up sets the step's overflow
+// flag (status word kStepFlags + parity of the step counter) and drops the entry -- the
+// step then changes nothing.  The cursors start at zero (the fused render resets them).
+// Thread 0 copies the step counter into the status words for the step's later kernels.
+__global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __restrict__ tile_rects,
+                                                       int32_t* __restrict__ cursors,
+                                                       uint32_t* __restrict__ vals, int width,
+                                                       int32_t* __restrict__ status,
+                                                       const int32_t* __restrict__ step) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t0 = step[0];
+  if (gid == 0) status[kStepShadow] = t0;
+  const int j = gid / kScatterLanes, q0 = gid % kScatterLanes;
+  if (j >= S.K) return;
+  const int4 rc = tile_rects[j];
+  const int n = rect_count(rc);
+  if (n == 0) return;
+  const SegGrid sg = seg_of_kernel(S, j);
+  const int w = rc.z - rc.x + 1;
+  for (int q = q0; q < n; q += kScatterLanes) {
+    const int t = sg.tile_offset + (rc.y + q / w) * sg.ntx + rc.x + q % w;
+    const int pos = atomicAdd(&cursors[t], 1);
+    if (pos < width) vals[(size_t)t * width + pos] = (uint32_t)j;
+    else status[kStepFlags + (t0 & 1)] = 1;
   }
 }
 
@@ -114,6 +143,25 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
 hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s, const int32_t* fit_step) {
   k_scan<<<1, kScanThreads, 0, s>>>(S.T, b.tile_counts, reinterpret_cast<int2*>(b.ranges),
                                     b.capacity, b.status, fit_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
+                              const smoe_bins& b, hipStream_t s) {
+  k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
+  if (S.K > 0) {
+    k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
+                                                 reinterpret_cast<int4*>(b.tile_rects), b.counts,
+                                                 b.records, b.record_stride, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width,
+                                const int32_t* step, hipStream_t s) {
+  k_scatter_fixed<<<max(1, cdiv((long long)S.K * kScatterLanes, 256)), 256, 0, s>>>(
+      S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, b.status,
+      step);
   return hipGetLastError();
 }
 

@@ -181,13 +181,14 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
   auto mark = [&](int i) -> hipError_t {
     return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
   };
+  // The pair storage as fixed-width block buckets: block t owns entries [t W, t W + W).
+  const int width = st->bins.capacity / S.T;
   hipError_t e = mark(0);
   if (e == hipSuccess && !st->prepared)
-    e = launch_count(st->C, st->order, st->model, S, st->bins, s);
-  if (e == hipSuccess) e = launch_scan(S, st->bins, s, st->step);
-  if (e == hipSuccess) e = launch_scatter(S, st->bins, s);
+    e = launch_prepare_fit(st->C, st->order, st->model, S, st->bins, s);
+  if (e == hipSuccess) e = launch_scatter_fixed(S, st->bins, width, st->step, s);
   if (e == hipSuccess) e = mark(1);
-  if (e == hipSuccess) e = launch_fit_tile(*st, S, target, s);
+  if (e == hipSuccess) e = launch_fit_tile(*st, S, width, target, s);
   if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = launch_adam_fit(*st, S, loss_out, s);
   if (e == hipSuccess) e = mark(3);

@@ -8,7 +8,8 @@
 namespace smoe {
 
 // Status word holding the fit step counter as the step began (written by the scan).
-constexpr int kStepShadow = 4;
+constexpr int kStepShadow = 4;  // status word: completed steps, copied by the step's first kernel
+constexpr int kStepFlags = 5;   // status words 5, 6: the fit step's overflow flag by step parity
 
 // Output-pixel index range whose centres lie in [lo, hi] (output units), clamped to
 // [0, n-1]; false when empty.  NaN inputs give an empty range.

@@ -1,19 +1,21 @@
 // Fit-step kernels on gfx950 (Sec. VI-B: gradient descent with Adam on all kernel
 // parameters, the centre learning rate decaying exponentially).
 //
-// A fit step runs four kernels after the first: the scan of the block counters into list
-// ranges and the scatter into block buckets (binning.hip), then
+// A fit step runs three kernels after the first: the scatter of the (block, kernel) pairs
+// into fixed-width block buckets (binning.hip), then
 //   k_fit_tile: one wave per 16x16 block orders the block's bucket, renders the block
 //     (image, D, squared error) and runs the backward over the same list while the
 //     pixels' y, D and dL/dy are still in its registers -- the backward of a block needs
 //     only that block's pixels, so nothing round-trips through HBM between the two;
 //   k_adam_fit: per kernel, the sum of its block partials, Adam, re-materialization, and
-//     the next step's box, render record and block counts.
+//     the next step's box and render record.
 // Cross-workgroup handoffs happen only at kernel boundaries: the 8 XCD L2 caches are not
 // coherent with each other, so a device-scope fence per workgroup would cost more than a
-// launch.  The step counter is read by every Adam workgroup and advanced by one: the scan
-// (the step's first kernel) copies it into a shadow status word that Adam reads, so the
-// single writer never races the readers.
+// launch.  The step counter is read by every Adam workgroup and advanced by one: the
+// scatter (the step's first kernel) copies it into a shadow status word that the later
+// kernels read, so the single writer never races the readers.  A bucket overflow sets the
+// step's flag (status word kStepFlags + parity of the step counter); Adam clears the next
+// step's flag, which no kernel of this step reads.
 #include "tile_math.h"
 
 namespace smoe {
@@ -22,10 +24,12 @@ namespace {
 struct FitTileArgs {
   Segs S;
   const float* __restrict__ records;
-  const int2* __restrict__ ranges;
+  int2* __restrict__ ranges;
   uint32_t* __restrict__ vals;
   uint32_t* __restrict__ vals_alt;
   int32_t* __restrict__ cursors;
+  int32_t* __restrict__ status;
+  int width;
   const float* __restrict__ target;
   float* __restrict__ image;
   float* __restrict__ denom;
@@ -38,14 +42,29 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
   __shared__ float4 srec[LDS_FLOATS / 4];
   const int tile = xcd_block(blockIdx.x, a.S.T);
-  const int2 rg = a.ranges[tile];
+  const int t0 = a.status[kStepShadow];
+  // The bucket's fill count; the cursor is then reset for the next step's scatter (the store
+  // depends on the loaded value, so it cannot overtake the load).
+  const int cnt = a.cursors[tile];
+  if (threadIdx.x == 0 && cnt >= 0) a.cursors[tile] = 0;
+  if (a.status[kStepFlags + (t0 & 1)] != 0) {
+    // Some bucket overflowed: nothing is rendered or updated this step.  The status words
+    // report the storage a step needs (blocks x longest bucket).
+    if (threadIdx.x == 0 && cnt > a.width) {
+      atomicMax(&a.status[2], cnt);
+      atomicMax(&a.status[0], (int)min((long long)cnt * a.S.T, (long long)INT32_MAX));
+      a.status[1] = 1;
+    }
+    return;
+  }
+  const int2 rg = make_int2(tile * a.width, tile * a.width + cnt);
+  if (threadIdx.x == 0) a.ranges[tile] = rg;  // the gradient gather reads the list back
   const SegGrid sg = seg_of_tile(a.S, tile);
   // MSE of this raster: dL/dy = 2 (y - t) / (W H C); its squared errors are stored already
   // divided by W H C, so that the sum over all blocks is the sum of the rasters' MSEs.
   const float inv_n2 = 2.0f / ((float)sg.W * (float)sg.H * (float)C);
   const float inv_n = 1.0f / ((float)sg.W * (float)sg.H * (float)C);
-  // Order the bucket (the scatter appended in arbitrary order) and reset its cursor.
-  if (threadIdx.x == 0) a.cursors[tile] = 0;
+  // Order the bucket (the scatter appended in arbitrary order).
   constexpr int run = LDS_FLOATS >= 1024 ? 1024 : (LDS_FLOATS >= 512 ? 512 : 256);
   sort_bucket(a.vals + rg.x, a.vals_alt + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec),
               run);
@@ -108,17 +127,16 @@ struct AdamFitArgs {
   float* __restrict__ records;
   int4* __restrict__ tile_rects_out;
   int32_t* __restrict__ counts;
-  int32_t* __restrict__ tile_counts;
 };
 
 
 // Fit-step Adam fused with the next step's binning front end.  16 lanes per kernel: lane i
 // owns raw parameter i -- its gradient (the sum of the kernel's block partials), Adam with
 // the group's learning rate, the re-materialized value -- and writes field i of the new
-// render record; lane 0 also writes the new block rectangle and count and increments the
-// covered blocks' counters, which the next step scans.  Block 0 also reduces the
-// per-block squared errors into the loss.  After an overflow the parameters stay as they
-// are, but the binning front end still runs so that the state stays consistent.
+// render record; lane 0 also writes the new block rectangle and count, which the next step
+// scatters.  Block 0 also reduces the per-block squared errors into the loss.  After an
+// overflow the parameters stay as they are, and the records and rectangles are rewritten
+// from them unchanged.
 constexpr int kAdamThreads = 256;
 template <int C, int ORDER>
 __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
@@ -128,10 +146,11 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   __shared__ int s_t0;
   __shared__ float s_sc[3];
   __shared__ float s_red[kAdamThreads / 64];
-  const bool skip = f.status[1] != 0;
   const smoe_adam_config& ad = f.step.adam;
+  const int t0_ = f.status[kStepShadow];  // completed steps, copied by this step's scatter
+  const bool skip = f.status[kStepFlags + (t0_ & 1)] != 0;
   if (threadIdx.x == 0) {
-    const int t0 = f.status[kStepShadow];  // completed steps, copied by this step's scan
+    const int t0 = t0_;
     float lr_mu = ad.lr_mu;
     if (ad.total_steps > 0 && ad.lr_mu > 0.0f && ad.lr_mu_final > 0.0f)
       lr_mu = ad.lr_mu * powf(ad.lr_mu_final / ad.lr_mu, (float)t0 / (float)ad.total_steps);
@@ -217,11 +236,14 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, sg, f.S.r);
       f.tile_rects_out[j] = rc;
       f.counts[j] = rect_count(rc);
-      count_blocks(rc, sg, f.tile_counts);
     }
   }
-  // The counter itself is written once; every workgroup read the shadow copy instead.
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !skip) f.step.step[0] = t0 + 1;
+  // The counter itself is written once; every workgroup read the shadow copy instead.  The
+  // next step's overflow flag is cleared here: no kernel of this step reads it.
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !skip) {
+    f.step.step[0] = t0 + 1;
+    f.status[kStepFlags + ((t0 + 1) & 1)] = 0;
+  }
 }
 
 // Reporting: the loss of each raster of the last fit step (one workgroup per segment sums
@@ -252,11 +274,11 @@ __global__ __launch_bounds__(128) void k_materialize(int n_rows, int NP,
 
 }  // namespace
 
-hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, const float* target,
-                           hipStream_t s) {
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
+                           const float* target, hipStream_t s) {
   const smoe_bins& b = st.bins;
-  FitTileArgs a{S,        b.records, reinterpret_cast<const int2*>(b.ranges),
-                b.vals,   b.vals_alt, b.tile_counts,
+  FitTileArgs a{S,        b.records, reinterpret_cast<int2*>(b.ranges),
+                b.vals,   b.vals_alt, b.tile_counts, b.status, width,
                 target,   st.image,  st.denom,
                 b.tile_loss, b.pair_grads};
   if (st.C == 1 && st.order == 0) k_fit_tile<1, 0><<<S.T, kWave, 0, s>>>(a);
@@ -284,8 +306,7 @@ hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_
                 st.grads,
                 b.records,
                 reinterpret_cast<int4*>(b.tile_rects),
-                b.counts,
-                b.tile_counts};
+                b.counts};
   // at least one workgroup, so that the loss and the step counter advance even for K = 0
   const int blocks = max(1, (int)(((long long)S.K * 16 + kAdamThreads - 1) / kAdamThreads));
   if (st.C == 1 && st.order == 0) k_adam_fit<1, 0><<<blocks, kAdamThreads, 0, s>>>(f);

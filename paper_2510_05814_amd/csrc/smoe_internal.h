@@ -146,7 +146,14 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
 hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s,
                        const int32_t* fit_step = nullptr);
 hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s);
-hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, const float* target,
+// Fit step: boxes and records of the current model with zeroed bucket cursors (the first
+// step), and the scatter into fixed-width buckets (every step).
+hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
+                              const smoe_bins& b, hipStream_t s);
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width,
+                                const int32_t* step, hipStream_t s);
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
+                           const float* target,
                            hipStream_t s);
 hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_out,
                            hipStream_t s);
