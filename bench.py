@@ -464,10 +464,8 @@ def _rocpd_counters(db_path):
 # Kernels of the fit step, with the sources whose digest tags their counters.
 STEP_KERNELS = {"k_fit_tile": KERNEL_SOURCES["render_backward"],
                 "k_adam_fit": KERNEL_SOURCES["render_backward"],
-                "k_scan": ["paper_2510_05814_amd/csrc/binning.hip",
-                           "paper_2510_05814_amd/csrc/device_common.h"],
-                "k_scatter": ["paper_2510_05814_amd/csrc/binning.hip",
-                              "paper_2510_05814_amd/csrc/device_common.h"]}
+                "k_scatter_fixed": ["paper_2510_05814_amd/csrc/binning.hip",
+                                    "paper_2510_05814_amd/csrc/device_common.h"]}
 # Issue model: a wave64 FP32 VALU instruction occupies its SIMD for 2 cycles (32 lanes per
 # cycle, the 157.3 TFLOP/s vector peak), a binary32 transcendental (v_exp_f32, v_rcp_f32, ...)
 # for 8 cycles (quarter rate).
