@@ -239,6 +239,8 @@ struct PixelSeed {
 //   bz2 = -H z2,  bz1 = -H z1 - bz2 l21/l22                  (through q = z1^2 + z2^2)
 //   dL/dmu_x = -(bz1/l11 + sum_c g_c w wx_c),  dL/dmu_y = -(bz2/l22 + sum_c g_c w wy_c)
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
+// The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
+// 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel.
 template <int C, int ORDER>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
@@ -263,13 +265,18 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         continue;
       }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      float acc[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
       const float dx = px.x - r[0];
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
       const float zz1 = z1 * z1;
+      // Per lane, over its four pixels: the sums that do not factor through the lane's
+      // column -- A_c = sum g_c w, Y_c = sum g_c w dy, B1 = sum bz1, B2 = sum bz2,
+      // S2 = sum -bz2 z2, R = sum H.  dx and z1 are the same for the lane's pixels, so
+      // sum g_c w dx = dx A_c, sum bz1 z1 = z1 B1 and sum g_c w wx_c = wx_c A_c.
+      float A[C], Y[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) A[c] = Y[c] = 0.0f;
+      float B1 = 0.0f, B2 = 0.0f, S2 = 0.0f, R = 0.0f;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
         const float dy = px.y[i] - r[1];
@@ -280,7 +287,6 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
           const float w = e * sd.invD[i];
           float Gs = -sd.gy[i];
-          float ex = 0.0f, ey = 0.0f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             float m = r[kRecExpert + c];
@@ -290,25 +296,38 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
             }
             Gs = __builtin_fmaf(sd.g[i][c], m, Gs);
             const float gw = sd.g[i][c] * w;
-            acc[6 + c] += gw;
-            if (ORDER == 1) {
-              acc[6 + C + c] = __builtin_fmaf(gw, dx, acc[6 + C + c]);
-              acc[6 + 2 * C + c] = __builtin_fmaf(gw, dy, acc[6 + 2 * C + c]);
-              ex = __builtin_fmaf(gw, r[kRecExpert + C + c], ex);
-              ey = __builtin_fmaf(gw, r[kRecExpert + 2 * C + c], ey);
-            }
+            A[c] += gw;
+            if (ORDER == 1) Y[c] = __builtin_fmaf(gw, dy, Y[c]);
           }
           const float Hh = w * Gs;
           const float bz2 = -Hh * z2;
           const float bz1 = __builtin_fmaf(-bz2, r[6], -Hh * z1);
-          acc[0] -= __builtin_fmaf(bz1, r[2], ex);
-          acc[1] -= __builtin_fmaf(bz2, r[4], ey);
-          acc[2] = __builtin_fmaf(-bz1, z1, acc[2]);
-          acc[3] = __builtin_fmaf(-bz2 * z1, r[4], acc[3]);
-          acc[4] = __builtin_fmaf(-bz2, z2, acc[4]);
-          acc[5] += Hh;
+          B1 += bz1;
+          B2 += bz2;
+          S2 = __builtin_fmaf(-bz2, z2, S2);
+          R += Hh;
         }
       }
+      float acc[16];
+      float ex = 0.0f, ey = 0.0f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[6 + c] = A[c];
+        if (ORDER == 1) {
+          acc[6 + C + c] = A[c] * dx;
+          acc[6 + 2 * C + c] = Y[c];
+          ex = __builtin_fmaf(A[c], r[kRecExpert + C + c], ex);
+          ey = __builtin_fmaf(A[c], r[kRecExpert + 2 * C + c], ey);
+        }
+      }
+      acc[0] = -__builtin_fmaf(B1, r[2], ex);
+      acc[1] = -__builtin_fmaf(B2, r[4], ey);
+      acc[2] = -B1 * z1;
+      acc[3] = -B2 * z1 * r[4];
+      acc[4] = S2;
+      acc[5] = R;
+#pragma unroll
+      for (int i = 6 + C * (1 + 2 * ORDER); i < 16; ++i) acc[i] = 0.0f;
       const float tot = wave_reduce16_transposed(acc);
       const int idx = lane >> 2;
       if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = tot;
