@@ -79,6 +79,12 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
       const float zz1 = z1 * z1;
+      // a_c + wx_c dx: the expert's value along the lane's column
+      float mx[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
+                           : r[kRecExpert + c];
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
         const float dy = px.y[i] - r[1];
@@ -92,11 +98,8 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
           D[i] += e;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            float m = r[kRecExpert + c];
-            if (ORDER == 1) {
-              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
-              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
-            }
+            float m = mx[c];
+            if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
             N[i][c] = __builtin_fmaf(e, m, N[i][c]);
           }
         }
@@ -269,6 +272,12 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
       const float zz1 = z1 * z1;
+      // a_c + wx_c dx: the expert's value along the lane's column
+      float mx[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
+                           : r[kRecExpert + c];
       // Per lane, over its four pixels: the sums that do not factor through the lane's
       // column -- A_c = sum g_c w, Y_c = sum g_c w dy, B1 = sum bz1, B2 = sum bz2,
       // S2 = sum -bz2 z2, R = sum H.  dx and z1 are the same for the lane's pixels, so
@@ -289,11 +298,8 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
           float Gs = -sd.gy[i];
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            float m = r[kRecExpert + c];
-            if (ORDER == 1) {
-              m = __builtin_fmaf(r[kRecExpert + C + c], dx, m);
-              m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
-            }
+            float m = mx[c];
+            if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
             Gs = __builtin_fmaf(sd.g[i][c], m, Gs);
             const float gw = sd.g[i][c] * w;
             A[c] += gw;
