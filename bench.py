@@ -119,21 +119,19 @@ def cpu_baseline(target, raw0, budget_s=20.0):
     H, W, C = target.shape
     threads = oracle.default_threads()
     model = oracle.materialize(raw0.astype(np.float64), C, 1)
+    # grow the band until one call takes about budget_s (at most three resizes)
     rows = 8
-    t_probe = None
-    while True:
+    for _ in range(4):
         t0 = time.perf_counter()
         oracle.loss_grad(model, C, 1, W, rows, target=target[:rows], threads=threads)
         dt = time.perf_counter() - t0
-        if t_probe is None and dt < 0.5 * budget_s / 8:
-            t_probe = dt
-            rows = int(min(H, max(rows + 8, rows * (budget_s / max(dt, 1e-3)) / 1.2)))
-            rows -= rows % 8
-            continue
-        break
+        if dt >= 0.6 * budget_s or rows >= H:
+            break
+        rows = int(min(H, max(rows + 8, rows * 0.9 * budget_s / max(dt, 1e-3))))
+        rows -= rows % 8
     full_s = dt * H / rows
     return {"value": 1.0 / full_s, "unit": "iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 loss+gradient over rows 0..{rows - 1} (2048x{rows} px) with all "
+            "sample": f"FP64 loss+gradient over rows 0..{rows - 1} ({W}x{rows} px) with all "
                       f"{raw0.shape[0]} kernels, {dt:.1f} s, scaled by {H}/{rows} rows",
             "seconds_per_iter": full_s}
 
