@@ -85,3 +85,36 @@ def test_plain_and_batched_servers_agree_with_oracle(bank_and_models, record_err
         worst = max(worst, float(np.max(np.abs(got - y_o))))
     record_error("serving render abs (sampled)", worst, 1e-5)
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("scale,ox,oy", [(2, 0, 0), (4, 1234, 2345)])
+def test_full_size_super_resolution_against_oracle(scale, ox, oy, record_error):
+    """A 4096^2 RGB output of the 2048^2, K = 65536 model (the serving workload's largest
+    request) through the batched server, at sampled pixels against the oracle."""
+    import torch
+
+    from paper_2510_05814_amd.serve import ModelBank, Server
+    say("serving full size", scale, ox, oy)
+    m = wl.serving_models(n=5)[4]
+    assert m["K"] == 65536 and m["side"] == 2048
+    _, model = wl.grid_init(m["image"], 256, 256, sigma=4.0, order=1)
+    rng = np.random.default_rng(21)
+    model = model.astype(np.float64)
+    model[:, 2] *= np.exp(rng.uniform(-0.3, 0.3, model.shape[0]))
+    model[:, 3] = rng.uniform(-0.4, 0.4, model.shape[0]) * model[:, 2]
+    model[:, 9:15] = rng.normal(0.0, 0.01, (model.shape[0], 6))
+    model = model.astype(np.float32)
+    bank = ModelBank([model], 3, 1)
+    req = dict(model=0, scale=scale, width=4096, height=4096, origin_x=ox, origin_y=oy)
+    res, summ = Server(bank, streams=1).serve([req, dict(req, origin_x=ox + 7)],
+                                               realtime=False, keep_outputs=True)
+    pix = np.stack([rng.integers(0, 4096, 1500), rng.integers(0, 4096, 1500)], 1)
+    worst = 0.0
+    for r in res:
+        q = r.request
+        y_o, _ = oracle.render(model.astype(np.float64), 3, 1, 4096, 4096, q.scale, q.origin_x,
+                               q.origin_y, pixels=pix)
+        got = r.image[torch.from_numpy(pix[:, 1]).cuda(), torch.from_numpy(pix[:, 0]).cuda()]
+        worst = max(worst, float(np.max(np.abs(got.cpu().numpy() - y_o))))
+    record_error(f"serving 4096^2 s={scale} abs (sampled)", worst, 1e-5)
+    assert worst <= 1e-5
