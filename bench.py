@@ -270,6 +270,8 @@ def run(args):
         out["serving"] = run_serving(args)
     if not args.no_batched_fit:
         out["batched_fit"] = run_batched_fit(args)
+    if not args.no_mm:
+        out["mm_denoise"] = run_mm_denoise(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -399,6 +401,38 @@ def run_batched_fit(args):
             "unbatched_iters_per_s": steps / t_unb,
             "psnr_mean_db": float(np.mean(psnr_b)), "psnr_min_db": float(np.min(psnr_b)),
             "psnr_max_abs_diff_vs_unbatched_db": float(d.max())}
+
+
+def run_mm_denoise(args):
+    """Multi-model fusion for denoising: the block-overlapping window models of a 512^2 RGB
+    image from the denoising workload's generator (clean + N(0, (25/255)^2)), fitted together for each
+    displacement d in {16, 8, 4, 2} (H = 1, 4, 16, 64 hypotheses per pixel); PSNR of the
+    fused estimate against the clean image, and fit iterations/s of the window batch."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.multimodel import MultiModelDenoiser
+    import workloads as wl
+
+    clean, noisy = wl.config3_images(H=args.mm_size, W=args.mm_size)
+    c = torch.from_numpy(clean).float().cuda()
+    out = {"size": args.mm_size, "steps": args.mm_steps,
+           "psnr_noisy_db": smoe.psnr(torch.from_numpy(noisy).float().cuda(), c), "runs": []}
+    for d in (16, 8, 4, 2):
+        mm = MultiModelDenoiser(noisy, d, adam=smoe.AdamConfig(total_steps=args.mm_steps),
+                                max_steps=args.mm_steps + 1)
+        mm.state.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mm.fit(args.mm_steps - 1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["runs"].append({"d": d, "hypotheses": mm.hypotheses, "windows": len(mm.windows),
+                            "kernels": int(mm.state.K), "iters_per_s": (args.mm_steps - 1) / el,
+                            "psnr_db": smoe.psnr(mm.image(), c)})
+        del mm
+        torch.cuda.empty_cache()
+    return out
 
 
 # ----------------------------------------------------------------------------- profiles
@@ -591,6 +625,9 @@ def main():
                     help="also serve the Poisson stream with a one-stream batched server")
     ap.add_argument("--no-batched-fit", action="store_true")
     ap.add_argument("--bfit-steps", type=int, default=1000)
+    ap.add_argument("--no-mm", action="store_true", help="skip the multi-model denoising run")
+    ap.add_argument("--mm-size", type=int, default=512)
+    ap.add_argument("--mm-steps", type=int, default=300)
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()

@@ -267,20 +267,22 @@ class FitState:
         if len(targets) != len(raws) or not targets:
             raise ValueError("one raw parameter array per target image")
         for t in targets:
-            if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 3):
-                raise ValueError("targets must be cuda float32 [H, W, C] tensors")
+            if not (t.dtype == torch.float32 and t.dim() == 3 and (batched or t.is_cuda)):
+                raise ValueError("targets must be float32 [H, W, C] tensors (cuda unless "
+                                 "several images are fitted together)")
         C_ = targets[0].shape[2]
-        dev = targets[0].device
+        # a batch may come from host memory: it is concatenated there and moved once
+        dev = targets[0].device if targets[0].is_cuda else torch.device("cuda")
         self.C, self.order, self.batched = C_, order, batched
         self.shapes = [tuple(t.shape[:2]) for t in targets]
-        self.raw = torch.cat([r.to(device=dev, dtype=torch.float32) for r in raws]).contiguous()
+        self.raw = torch.cat([r.to(dtype=torch.float32) for r in raws]).to(dev).contiguous()
         _check_params(self.raw, C_, order)
         self.K = self.raw.shape[0]
         self.segments = None
         if batched:
             self.segments = Segments([{"width": w, "height": h, "num_kernels": r.shape[0]}
                                       for (h, w), r in zip(self.shapes, raws)], device=dev)
-            self.target = torch.cat([t.reshape(-1, C_) for t in targets]).contiguous()
+            self.target = torch.cat([t.reshape(-1, C_) for t in targets]).to(dev).contiguous()
             npx = self.target.shape[0]
             self.image = torch.zeros((npx, C_), dtype=torch.float32, device=dev)
             self.denom = torch.zeros((npx,), dtype=torch.float32, device=dev)

@@ -1,0 +1,77 @@
+"""Multi-model fusion (block-overlapping window models, Sec. V-C): the fused image is the
+per-pixel mean of the window predictions, each window's fit is the fit of that window
+alone, and more hypotheses per pixel denoise better."""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _noisy_clean(size=96, seed=3):
+    clean, noisy = wl.config3_images(seed, H=size, W=size)
+    return noisy.astype(np.float32), clean.astype(np.float32)
+
+
+def test_fused_image_is_the_mean_of_window_predictions():
+    import torch
+
+    from paper_2510_05814_amd.multimodel import MultiModelDenoiser
+    say("mm mean of windows")
+    noisy, _ = _noisy_clean(40)
+    mm = MultiModelDenoiser(noisy, 8, max_steps=5).fit(5, graphed=False)
+    win = mm.window_images().cpu().numpy()
+    acc = np.zeros(noisy.shape, np.float64)
+    cnt = np.zeros(noisy.shape[:2], np.float64)
+    p = 0
+    for (y0, x0, h, w) in mm.windows:
+        acc[y0:y0 + h, x0:x0 + w] += win[p:p + h * w].reshape(h, w, 3)
+        cnt[y0:y0 + h, x0:x0 + w] += 1
+        p += h * w
+    assert np.all(cnt == mm.hypotheses)
+    got = mm.image().cpu().numpy()
+    assert np.max(np.abs(got - acc / cnt[..., None])) <= 1e-6
+    assert torch.isfinite(mm.image()).all()
+
+
+def test_each_window_fit_is_its_own_fit():
+    """Window fits in the batch equal fitting each window alone, bitwise."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.multimodel import MultiModelDenoiser, _grid_init
+    say("mm windows independent")
+    noisy, _ = _noisy_clean(48)
+    adam = smoe.AdamConfig(total_steps=6)
+    mm = MultiModelDenoiser(noisy, 16, adam=adam, max_steps=6).fit(6, graphed=False)
+    st = mm.state
+    for i in (0, 4, len(mm.windows) - 1):
+        y0, x0, h, w = mm.windows[i]
+        crop = np.ascontiguousarray(noisy[y0:y0 + h, x0:x0 + w])
+        raw = _grid_init(crop, 8, 4.0, 1)
+        one = smoe.FitState(torch.from_numpy(crop).cuda(), torch.from_numpy(raw).cuda(), 1,
+                            adam, max_steps=6)
+        for _ in range(6):
+            one.step()
+        sg = st.segments.host[i]
+        assert torch.equal(st.raw[sg.kernel_offset:sg.kernel_offset + sg.num_kernels], one.raw)
+
+
+def test_more_hypotheses_denoise_better(record_error):
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.multimodel import MultiModelDenoiser
+    say("mm psnr vs hypotheses")
+    noisy, clean = _noisy_clean(96)
+    import torch
+    c = torch.from_numpy(clean).cuda()
+    ps = {}
+    for d in (16, 4):
+        mm = MultiModelDenoiser(noisy, d, adam=smoe.AdamConfig(total_steps=200)).fit(200)
+        ps[d] = smoe.psnr(mm.image(), c)
+    print("[mm] psnr", ps, flush=True)
+    assert ps[4] > ps[16] + 0.3

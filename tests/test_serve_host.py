@@ -73,3 +73,19 @@ def test_admit_fifo_budget_and_limits():
     q = deque([_req(100, 100)])
     with pytest.raises(ValueError):
         admit(q, 0, 1000, fp, 8, 10 ** 9)
+
+
+def test_window_layout_covers_every_pixel_h_times():
+    """Block-overlapping windows (multi-model fusion): with displacement d every pixel lies
+    in (16 / d)^2 windows, the windows stay inside the image and none is empty."""
+    from paper_2510_05814_amd.multimodel import window_layout
+    for (H, W) in [(16, 16), (37, 50), (64, 33)]:
+        for d in (16, 8, 4, 2):
+            cover = np.zeros((H, W), np.int64)
+            for (y0, x0, h, w) in window_layout(H, W, d):
+                assert 0 <= y0 and 0 <= x0 and h > 0 and w > 0 and y0 + h <= H and x0 + w <= W
+                assert h <= 16 and w <= 16
+                cover[y0:y0 + h, x0:x0 + w] += 1
+            assert np.all(cover == (16 // d) ** 2), (H, W, d)
+    with pytest.raises(ValueError):
+        window_layout(16, 16, 3)
