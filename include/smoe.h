@@ -83,6 +83,11 @@ typedef struct smoe_grid {
   int32_t scale;               /* integer upscale factor, 1 .. 64 */
   int32_t origin_x, origin_y;  /* raster origin in output pixels, |.| <= 2^22 */
   float radius;                /* Mahalanobis truncation radius r > 0 (3 = 98.9 % mass) */
+  float sharpen;               /* native sharpening (Sec. II-B, VII): every kernel is rendered
+                                  with its bandwidth divided by this factor, L -> L / f (the
+                                  box and the truncation test follow); f > 0, 0 or 1 = none.
+                                  Render and binning only: the backward and the fit step
+                                  reject f != 1 */
 } smoe_grid;
 
 /* One raster of a batched call: an image of a batched fit, or one render request (the
@@ -98,7 +103,7 @@ typedef struct smoe_segment {
   int32_t param_offset;        /* first row of the model in the params array */
   int32_t kernel_offset;       /* set by smoe_segments_layout */
   int32_t tile_offset;         /* set by smoe_segments_layout */
-  int32_t reserved;
+  float sharpen;               /* as smoe_grid.sharpen (0 or 1 = none) */
   int64_t pixel_offset;        /* set by smoe_segments_layout */
 } smoe_segment;
 

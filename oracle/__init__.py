@@ -167,6 +167,21 @@ def loss_grad(model, C, order, W, H, target=None, grad_y=None, kernels=None, s=1
     return float(loss), g
 
 
+def sharpen(model, f):
+    """Native sharpening by kernel editing (Sec. II-B; the sharpened super-resolution of
+    Sec. V-D): every kernel's bandwidth is reduced by the factor f, i.e. the Cholesky factor
+    L of its covariance becomes L / f (Sigma -> Sigma / f^2); centres, gating weights and
+    experts are unchanged.  The division is taken in binary32 (the precision the model rows
+    and the truncation rule are decided in), so the edited rows are exactly the rows a
+    binary32 renderer sees.  f = 1 (or 0) returns the model unchanged."""
+    model = _d(model).copy()
+    f = float(f)
+    if f not in (0.0, 1.0):
+        L = model[:, 2:5].astype(np.float32)
+        model[:, 2:5] = (L / np.float32(f)).astype(np.float64)
+    return model
+
+
 def materialize(raw, C, order):
     raw, K = _KC(raw, C, order)
     out = np.zeros_like(raw)

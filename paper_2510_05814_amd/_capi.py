@@ -34,13 +34,13 @@ class SmoeModel(ct.Structure):
 
 class SmoeGrid(ct.Structure):
     _fields_ = [("width", _i32), ("height", _i32), ("scale", _i32), ("origin_x", _i32),
-                ("origin_y", _i32), ("radius", _f32)]
+                ("origin_y", _i32), ("radius", _f32), ("sharpen", _f32)]
 
 
 class SmoeSegment(ct.Structure):
     _fields_ = [("width", _i32), ("height", _i32), ("scale", _i32), ("origin_x", _i32),
                 ("origin_y", _i32), ("num_kernels", _i32), ("param_offset", _i32),
-                ("kernel_offset", _i32), ("tile_offset", _i32), ("reserved", _i32),
+                ("kernel_offset", _i32), ("tile_offset", _i32), ("sharpen", _f32),
                 ("pixel_offset", ct.c_int64)]
 
 

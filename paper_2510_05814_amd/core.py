@@ -25,9 +25,12 @@ def tiles(width: int, height: int) -> int:
     return ((width + TILE - 1) // TILE) * ((height + TILE - 1) // TILE)
 
 
-def make_grid(width, height, scale=1, origin_x=0, origin_y=0, radius=3.0) -> C.SmoeGrid:
+def make_grid(width, height, scale=1, origin_x=0, origin_y=0, radius=3.0,
+              sharpen=1.0) -> C.SmoeGrid:
+    """Output raster; sharpen = f renders every kernel with its bandwidth divided by f
+    (native sharpening by kernel editing, Sec. II-B), 1 = none."""
     return C.SmoeGrid(int(width), int(height), int(scale), int(origin_x), int(origin_y),
-                      float(radius))
+                      float(radius), float(sharpen))
 
 
 def _stream(stream=None) -> int:
@@ -163,7 +166,8 @@ class Segments:
     """A laid-out segment table (host ctypes array + device copy) for batched calls.
 
     rasters: list of dicts with width, height and optionally scale, origin_x, origin_y,
-    num_kernels, param_offset (default: the running sum of num_kernels)."""
+    sharpen (1 = none), num_kernels, param_offset (default: the running sum of
+    num_kernels)."""
 
     def __init__(self, rasters, device="cuda", stream=None):
         n = len(rasters)
@@ -176,6 +180,7 @@ class Segments:
             sg.width, sg.height = int(r["width"]), int(r["height"])
             sg.scale = int(r.get("scale", 1))
             sg.origin_x, sg.origin_y = int(r.get("origin_x", 0)), int(r.get("origin_y", 0))
+            sg.sharpen = float(r.get("sharpen", 1.0))
             sg.num_kernels = int(r.get("num_kernels", 0))
             sg.param_offset = int(r.get("param_offset", k))
             k += sg.num_kernels

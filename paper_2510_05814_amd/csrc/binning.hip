@@ -29,10 +29,17 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
   const SegGrid sg = seg_of_kernel(S, j);
   const int ne = expert_floats(C, order);
   const float* p = params + (size_t)(sg.param_offset + (j - sg.kernel_offset)) * (6 + ne);
-  const int4 rc = kernel_block_rect(p[0], p[1], p[2], p[3], p[4], sg, S.r);
+  // native sharpening: the raster sees L / f (a correctly rounded binary32 division)
+  float l11 = p[2], l21 = p[3], l22 = p[4];
+  if (sg.sharpen != 1.0f) {
+    l11 = l11 / sg.sharpen;
+    l21 = l21 / sg.sharpen;
+    l22 = l22 / sg.sharpen;
+  }
+  const int4 rc = kernel_block_rect(p[0], p[1], l11, l21, l22, sg, S.r);
   tile_rects[j] = rc;
   counts[j] = rect_count(rc);
-  write_record(records + (size_t)j * rs, p, ne, rs);
+  write_record(records + (size_t)j * rs, p, ne, rs, l11, l21, l22);
   if (tile_counts) count_blocks(rc, sg, tile_counts);
 }
 

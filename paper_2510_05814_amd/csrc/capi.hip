@@ -30,6 +30,9 @@ bool valid_raster(int32_t W, int32_t H, int32_t scale, int32_t ox, int32_t oy) {
 }
 
 bool valid_radius(float r) { return r > 0.0f && std::isfinite(r); }
+// Sharpening factor: 0 (none) or a finite positive bandwidth divisor.
+bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f)); }
+bool no_sharpen(float f) { return f == 0.0f || f == 1.0f; }
 
 long long raster_tiles(int32_t W, int32_t H) {
   return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
@@ -39,7 +42,7 @@ long long raster_tiles(int32_t W, int32_t H) {
 bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   if (!valid_model(m) || !g ||
       !valid_raster(g->width, g->height, g->scale, g->origin_x, g->origin_y) ||
-      !valid_radius(g->radius))
+      !valid_radius(g->radius) || !valid_sharpen(g->sharpen))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -49,6 +52,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   o.scale = g->scale;
   o.origin_x = g->origin_x;
   o.origin_y = g->origin_y;
+  o.sharpen = g->sharpen;
   o.num_kernels = m->K;
   S.r = g->radius;
   S.r2 = g->radius * g->radius;
@@ -65,7 +69,9 @@ bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int*
   long long t = 0, k = 0, px = 0;
   for (int i = 0; i < n; ++i) {
     const smoe_segment& s = h[i];
-    if (!valid_raster(s.width, s.height, s.scale, s.origin_x, s.origin_y)) return false;
+    if (!valid_raster(s.width, s.height, s.scale, s.origin_x, s.origin_y) ||
+        !valid_sharpen(s.sharpen))
+      return false;
     if (s.num_kernels < 0 || s.param_offset < 0) return false;
     if ((long long)s.param_offset + s.num_kernels > rows) return false;
     if (s.kernel_offset != k || s.tile_offset != t || s.pixel_offset != px) return false;
@@ -150,7 +156,8 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
     if (!check_segments(st->segments_host, st->num_segments, st->K, &S->T, &S->K)) return false;
     for (int i = 0; i < st->num_segments; ++i) {
       const smoe_segment& s = st->segments_host[i];
-      if (s.scale != 1 || s.origin_x != 0 || s.origin_y != 0 || s.param_offset != s.kernel_offset)
+      if (s.scale != 1 || s.origin_x != 0 || s.origin_y != 0 ||
+          s.param_offset != s.kernel_offset || !no_sharpen(s.sharpen))
         return false;
     }
     if (S->K != st->K) return false;
@@ -162,7 +169,8 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
   }
   const smoe_model m{st->K, st->C, st->order, st->model};
   if (!single_segs(&m, &st->grid, S)) return false;
-  return st->grid.scale == 1 && st->grid.origin_x == 0 && st->grid.origin_y == 0;
+  return st->grid.scale == 1 && st->grid.origin_x == 0 && st->grid.origin_y == 0 &&
+         no_sharpen(st->grid.sharpen);
 }
 
 smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
@@ -269,12 +277,11 @@ smoe_status smoe_segments_layout(smoe_segment* segs, int32_t n, int32_t* total_k
   for (int i = 0; i < n; ++i) {
     smoe_segment& s = segs[i];
     if (!valid_raster(s.width, s.height, s.scale, s.origin_x, s.origin_y) || s.num_kernels < 0 ||
-        s.param_offset < 0)
+        s.param_offset < 0 || !valid_sharpen(s.sharpen))
       return SMOE_ERR_INVALID;
     s.kernel_offset = (int32_t)k;
     s.tile_offset = (int32_t)t;
     s.pixel_offset = px;
-    s.reserved = 0;
     k += s.num_kernels;
     t += raster_tiles(s.width, s.height);
     px += (long long)s.width * s.height;
@@ -325,7 +332,7 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
   Segs S;
   if (!single_segs(model, grid, &S) || !bins_match(bins, model->K, model->C, model->order) ||
       !image || !denom || !grads || (grad_image == nullptr) == (target == nullptr) ||
-      !bins->pair_grads)
+      !bins->pair_grads || !no_sharpen(grid->sharpen))
     return SMOE_ERR_INVALID;
   if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -59,9 +59,10 @@ __device__ __forceinline__ void count_blocks(int4 rc, const SegGrid& g,
 
 // Render record of kernel row j from its materialized parameter row p (layout in
 // smoe_internal.h).
+// (l11, l21, l22): the Cholesky factor the record is built for (the row's own, or divided by
+// a sharpening factor).
 __device__ __forceinline__ void write_record(float* __restrict__ rec, const float* __restrict__ p,
-                                             int ne, int rs) {
-  const float l11 = p[2], l21 = p[3], l22 = p[4];
+                                             int ne, int rs, float l11, float l21, float l22) {
   const float i11 = 1.0f / l11;
   const float i22 = 1.0f / l22;
   rec[0] = p[0];

@@ -47,6 +47,7 @@ struct SegGrid {
   float inv_s;                 // 1/scale, binary32
   int tile_offset, kernel_offset, param_offset, K;
   long long pixel_offset;
+  float sharpen;               // bandwidth divisor, 1 = none
 };
 
 __host__ __device__ inline SegGrid seg_grid_of(const smoe_segment& s) {
@@ -63,6 +64,7 @@ __host__ __device__ inline SegGrid seg_grid_of(const smoe_segment& s) {
   g.param_offset = s.param_offset;
   g.K = s.num_kernels;
   g.pixel_offset = s.pixel_offset;
+  g.sharpen = s.sharpen > 0.0f ? s.sharpen : 1.0f;
   return g;
 }
 

@@ -4,6 +4,8 @@ A request names a resident model, an integer upscale factor s and an output wind
 (width, height, origin) in the upscaled raster.  Output pixel (u, v) samples the
 continuous regression (Eq. 3-5) at native coordinate ((origin + u) + 0.5) / s, so every
 factor is a native super-resolution of the same model, not an interpolation of a render.
+A request may also ask for native sharpening by a factor f: every kernel is rendered with
+its bandwidth divided by f (kernel editing, Sec. II-B), the resident model unchanged.
 
 Two servers share the request format and the report:
 
@@ -53,6 +55,7 @@ class RenderRequest:
     origin_x: int = 0
     origin_y: int = 0
     arrival: float = 0.0      # seconds from the start of the run
+    sharpen: float = 1.0      # bandwidth divisor f (1 = none)
 
 
 @dataclass
@@ -85,21 +88,24 @@ class BoxSpans:
             self._R.append(self.radius * np.sqrt(lam))
         self._spans = {}
 
-    def _span_table(self, i: int, scale: int):
+    def _span_table(self, i: int, scale: int, sharpen: float = 1.0):
         """Sorted per-kernel bound on the blocks its box spans per axis, with prefix sums."""
-        key = (i, scale)
+        f = 1.0 if sharpen in (0.0, 1.0) else float(sharpen)
+        key = (i, scale, f)
         if key not in self._spans:
-            # pixels spanned <= floor(2 R s) + 1; 2 more absorb the binary32 rounding of the
-            # box edges; n pixels at any alignment touch <= ceil((n - 1) / 16) + 1 blocks.
-            n = np.floor(2.0 * self._R[i] * scale * (1.0 + 1e-5)).astype(np.int64) + 3
+            # pixels spanned <= floor(2 R s / f) + 1 (sharpening divides L, hence R, by f);
+            # 2 more absorb the binary32 rounding of the box edges; n pixels at any
+            # alignment touch <= ceil((n - 1) / 16) + 1 blocks.
+            n = np.floor(2.0 * self._R[i] * scale / f * (1.0 + 1e-5)).astype(np.int64) + 3
             b = np.sort((n + TILE - 2) // TILE + 1)
             self._spans[key] = (b, np.concatenate([[0], np.cumsum(b)]),
                                 np.concatenate([[0], np.cumsum(b * b)]))
         return self._spans[key]
 
-    def pair_bound(self, i: int, scale: int, width: int, height: int) -> int:
+    def pair_bound(self, i: int, scale: int, width: int, height: int,
+                   sharpen: float = 1.0) -> int:
         """Sum over model i's kernels of min(span, blocks across) * min(span, blocks down)."""
-        b, s1, s2 = self._span_table(i, scale)
+        b, s1, s2 = self._span_table(i, scale, sharpen)
         a = (width + TILE - 1) // TILE
         c = (height + TILE - 1) // TILE
         a, c = min(a, c), max(a, c)
@@ -129,8 +135,9 @@ class ModelBank:
     def rows(self, i: int) -> torch.Tensor:
         return self.params[self.offset[i]:self.offset[i] + self.K[i]]
 
-    def pair_bound(self, i: int, scale: int, width: int, height: int) -> int:
-        return self.spans.pair_bound(i, scale, width, height)
+    def pair_bound(self, i: int, scale: int, width: int, height: int,
+                   sharpen: float = 1.0) -> int:
+        return self.spans.pair_bound(i, scale, width, height, sharpen)
 
 
 def admit(pending, in_use: int, budget: int, footprint, max_batch: int, max_pixels: int):
@@ -286,7 +293,8 @@ class Server:
         inf = getattr(r, "_smoe_info", None)
         if inf is None:
             k, t = self.bank.K[r.model], _tiles(r.width, r.height)
-            p, n = self.bank.pair_bound(r.model, r.scale, r.width, r.height), r.width * r.height
+            p = self.bank.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen)
+            n = r.width * r.height
             nbytes = (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
                       + n * self.nbytes_px + 64)
             inf = r._smoe_info = (k, t, p, n, nbytes)
@@ -314,7 +322,8 @@ class Server:
             if len(batch.reqs) == 1:
                 # one request: the single-raster calls, no segment table
                 r = batch.reqs[0]
-                grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius)
+                grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius,
+                                 r.sharpen)
                 images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
                 m = self._models[r.model]
                 C.smoe_bin(m, grid, bins.c, st.cuda_stream)
@@ -326,6 +335,7 @@ class Server:
                 for sg, r in zip(host, batch.reqs):
                     sg.width, sg.height, sg.scale = r.width, r.height, r.scale
                     sg.origin_x, sg.origin_y = r.origin_x, r.origin_y
+                    sg.sharpen = r.sharpen
                     sg.num_kernels, sg.param_offset = b.K[r.model], b.offset[r.model]
                 _, _, npx = C.smoe_segments_layout(host)
                 nb = n * ct.sizeof(C.SmoeSegment)
@@ -459,14 +469,15 @@ class PlainServer:
         for i in order:
             r = reqs[i]
             _wait_until(clock, r.arrival)
-            grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius)
+            grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius,
+                             r.sharpen)
             rows = b.rows(r.model)
             m = model_struct(rows, b.C, b.order)
             with torch.cuda.stream(st):
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev0.record(st)
                 bins = Bins(b.K[r.model], b.C, b.order, _tiles(r.width, r.height),
-                            b.pair_bound(r.model, r.scale, r.width, r.height),
+                            b.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen),
                             device=rows.device, render_only=True, zero=False)
                 image = torch.empty((r.height, r.width, b.C), dtype=torch.float32,
                                     device=rows.device)

@@ -1,0 +1,143 @@
+"""Native sharpening on the GPU (kernel editing, Sec. II-B): a raster whose sharpening factor is
+f renders every kernel with L / f.  Bars as for the other parity tests: block lists bit-exact
+against the oracle's on the edited model (oracle.sharpen), images within 1e-5 absolute; f = 1
+and f = 0 are bitwise the unsharpened render; a sharpened raster in a batch or a serving
+request is bitwise the same raster rendered alone."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+Y_TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smoe():
+    import torch  # noqa: F401
+
+    import paper_2510_05814_amd as smoe
+    return smoe
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [
+    # (f, scale, origin_x, origin_y)
+    (2.0, 1, 0, 0),
+    (3.0, 4, 5, 3),
+    (0.75, 2, 0, 0),
+    (1.7, 3, 1, 2),
+    (8.0, 1, 0, 0),
+]
+
+
+@pytest.mark.parametrize("f,s,ox,oy", CASES)
+def test_sharpened_bins_and_render_against_oracle(smoe, f, s, ox, oy, record_error):
+    say("sharpen", f, s, ox, oy)
+    W, H = 44, 35
+    m_np = wl.random_model(90, 3, 1, W, H, seed=400 + int(10 * f), sig_lo=0.6, sig_hi=9.0)
+    OW, OH = s * W - ox, s * H - oy
+    grid = smoe.make_grid(OW, OH, s, ox, oy, sharpen=f)
+    m = dev(m_np)
+    b = smoe.bin(m, 3, 1, grid)
+    over, st = b.read_status()
+    assert not over
+    ms = oracle.sharpen(m_np, f)
+    ob = oracle.bin(ms, 3, 1, OW, OH, s, ox, oy)
+    T = smoe.tiles(OW, OH)
+    P = st[0]
+    assert P == ob["P"]
+    assert np.array_equal(host(b.tile_rects()), ob["tile_rects"])
+    assert np.array_equal(host(b.counts()), ob["counts"])
+    assert np.array_equal(host(b.vals(P)).view(np.uint32), ob["vals"])
+    assert np.array_equal(host(b.ranges(T)), ob["ranges"])
+    img, D, _, _ = smoe.render(m, 3, 1, grid, bins=b)
+    y_o, D_o = oracle.render(ms, 3, 1, OW, OH, s, ox, oy)
+    ey = float(np.max(np.abs(host(img) - y_o)))
+    record_error("sharpened image abs", ey, Y_TOL)
+    assert ey <= Y_TOL
+    assert np.array_equal(host(D) > 0, D_o > 0)
+
+
+def test_factor_one_and_zero_are_the_plain_render_bitwise(smoe):
+    import torch
+    say("sharpen identity")
+    W, H = 50, 41
+    m = dev(wl.random_model(120, 3, 1, W, H, seed=410, sig_lo=0.6, sig_hi=9.0))
+    ref, Dref, _, _ = smoe.render(m, 3, 1, smoe.make_grid(W, H, 2, 3, 1, sharpen=1.0))
+    for f in (0.0, 1.0):
+        img, D, _, _ = smoe.render(m, 3, 1, smoe.make_grid(W, H, 2, 3, 1, sharpen=f))
+        assert torch.equal(img, ref) and torch.equal(D, Dref)
+    img, _, _, _ = smoe.render(m, 3, 1, smoe.make_grid(W, H, 2, 3, 1, sharpen=2.0))
+    assert not torch.equal(img, ref)
+
+
+def test_batched_mixed_factors_equal_alone(smoe):
+    import torch
+    say("sharpen batched")
+    models = [wl.random_model(K, 3, 1, 36, 30, seed=420 + K, sig_lo=0.6, sig_hi=8.0)
+              for K in (40, 70, 55)]
+    params = dev(np.concatenate(models))
+    rasters, k = [], 0
+    specs = [(0, 2.0, 2, 0, 0), (1, 1.0, 1, 0, 0), (2, 0.8, 3, 4, 5), (0, 5.0, 1, 0, 0),
+             (1, 1.5, 2, 7, 2)]
+    offs = np.concatenate([[0], np.cumsum([m.shape[0] for m in models])])
+    for i, f, s, ox, oy in specs:
+        rasters.append(dict(width=36 * s - ox, height=30 * s - oy, scale=s, origin_x=ox,
+                            origin_y=oy, sharpen=f, num_kernels=models[i].shape[0],
+                            param_offset=int(offs[i])))
+    segs = smoe.Segments(rasters)
+    bins = smoe.bin_batched(params, 3, 1, segs)
+    out = torch.empty((segs.pixels, 3), dtype=torch.float32, device="cuda")
+    smoe.render_batched(params, 3, 1, segs, bins, out)
+    for (a, e, h, w), (i, f, s, ox, oy) in zip(segs.pixel_slices(), specs):
+        grid = smoe.make_grid(w, h, s, ox, oy, sharpen=f)
+        alone, _, _, _ = smoe.render(dev(models[i]), 3, 1, grid)
+        assert torch.equal(out[a:e].view(h, w, 3), alone), (i, f, s)
+
+
+def test_serving_sharpened_requests_equal_alone(smoe):
+    import torch
+
+    from paper_2510_05814_amd.serve import ModelBank, PlainServer, RenderRequest, Server
+    say("sharpen serving")
+    models = [wl.random_model(K, 3, 1, 48, 40, seed=430 + K, sig_lo=0.6, sig_hi=10.0)
+              .astype(np.float32) for K in (80, 150)]
+    bank = ModelBank(models, 3, 1)
+    reqs = [RenderRequest(i % 2, 1 + i % 3, 40 + 7 * i, 33 + 5 * i, i, 2 * i,
+                          arrival=0.0, sharpen=[1.0, 2.0, 0.7, 3.0][i % 4]) for i in range(8)]
+    res, _ = Server(bank, streams=2).serve(reqs, realtime=False, keep_outputs=True)
+    res_p, _ = PlainServer(bank).serve(reqs, realtime=False, keep_outputs=True)
+    for r, rp in zip(res, res_p):
+        q = r.request
+        grid = smoe.make_grid(q.width, q.height, q.scale, q.origin_x, q.origin_y,
+                              sharpen=q.sharpen)
+        alone, _, _, _ = smoe.render(bank.rows(q.model), 3, 1, grid)
+        assert torch.equal(r.image, alone) and torch.equal(rp.image, alone), q
+
+
+def test_backward_rejects_sharpening(smoe):
+    import torch
+    from paper_2510_05814_amd._capi import SmoeError
+    say("sharpen backward rejected")
+    W, H = 32, 32
+    m = dev(wl.random_model(20, 3, 1, W, H, seed=440))
+    grid = smoe.make_grid(W, H, sharpen=2.0)
+    b = smoe.Bins(20, 3, 1, smoe.tiles(W, H), 4096)
+    img, D, _, b = smoe.render(m, 3, 1, grid, bins=b)
+    with pytest.raises(SmoeError):
+        smoe.render_backward(m, 3, 1, grid, b, img, D, grad_image=torch.zeros_like(img))

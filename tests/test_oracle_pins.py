@@ -199,6 +199,62 @@ def test_two_kernel_logistic_edge():
     assert np.all(y[:, 13, 0] == 0.5)  # centre x = 13.5 is the bisector
 
 
+# --------------------------------------------------------------------------- sharpening
+
+
+def test_sharpen_steepens_the_logistic_edge_by_f_squared():
+    """Native sharpening (Sec. II-B, Fig. 2b): with the bandwidth divided by f, q scales by
+    f^2, so the two-kernel edge is logistic(f^2 (q2 - q1) / 2) in the unsharpened q; the
+    bisector stays at exactly 1/2 and the flat sides move towards their expert values."""
+    s = 3.0
+    m = np.array([[10.5, 8.0, s, 0.0, s, 0.2, 1.0], [16.5, 8.0, s, 0.0, s, 0.2, 0.0]])
+    W, H = 27, 16
+    u, v, x, yy = centres(W, H)
+    q1 = ((x - 10.5) ** 2 + (yy - 8.0) ** 2) / s ** 2
+    q2 = ((x - 16.5) ** 2 + (yy - 8.0) ** 2) / s ** 2
+    prev = None
+    for f in (1.0, 1.5, 2.0, 3.0):  # s / f exact in binary32
+        ms = oracle.sharpen(m, f)
+        assert np.array_equal(ms[:, [0, 1, 5, 6]], m[:, [0, 1, 5, 6]])
+        y, _ = oracle.render(ms, 1, 0, W, H, truncated=False)
+        ref = 1.0 / (1.0 + np.exp(-f * f * (q2 - q1) / 2.0))
+        np.testing.assert_allclose(y[..., 0].ravel(), ref, rtol=1e-12)
+        assert np.all(y[:, 13, 0] == 0.5)
+        row = y[8, :, 0]
+        assert np.all(np.diff(row) <= 0)  # monotone across the edge
+        if prev is not None:
+            assert row[14] - row[12] < prev[14] - prev[12]  # steeper
+            assert np.all(row[:13] >= prev[:13]) and np.all(row[14:] <= prev[14:])
+        prev = row
+
+
+def test_sharpen_by_two_equals_coordinate_scaling_bitwise():
+    """Sigma / f^2 at x is Sigma at f x with centres f mu and slopes W / f: the model sharpened
+    by 2 rendered at scale 2 equals, bit for bit, the model with doubled centres and halved
+    slopes at scale 1 (powers of two scale every binary32 and fp64 step exactly), block lists
+    and truncation decisions included."""
+    W, H = 30, 22
+    m = wl.random_model(40, 3, 1, W, H, seed=31, sig_lo=0.7, sig_hi=6.0).astype(np.float64)
+    m2 = m.copy()
+    m2[:, 0:2] *= 2.0
+    m2[:, 9:15] *= 0.5
+    ms = oracle.sharpen(m, 2.0)
+    np.testing.assert_array_equal(ms[:, 2:5] * 2.0, m[:, 2:5])
+    ya, Da = oracle.render(ms, 3, 1, 2 * W, 2 * H, s=2)
+    yb, Db = oracle.render(m2, 3, 1, 2 * W, 2 * H, s=1)
+    np.testing.assert_array_equal(ya, yb)
+    np.testing.assert_array_equal(Da, Db)
+    ba, bb = oracle.bin(ms, 3, 1, 2 * W, 2 * H, s=2), oracle.bin(m2, 3, 1, 2 * W, 2 * H, s=1)
+    for k in ("tile_rects", "counts", "vals", "ranges"):
+        np.testing.assert_array_equal(ba[k], bb[k])
+
+
+def test_sharpen_one_or_zero_is_identity():
+    m = wl.random_model(10, 3, 1, 20, 20, seed=32).astype(np.float64)
+    for f in (0.0, 1.0):
+        np.testing.assert_array_equal(oracle.sharpen(m, f), m)
+
+
 # --------------------------------------------------------------------------- invariants
 
 

@@ -48,6 +48,26 @@ def test_pair_bound_single_kernel_closed_form():
         assert P <= 4
 
 
+def test_pair_bound_with_sharpening_covers_oracle_pairs():
+    """The box of a kernel sharpened by f has half-side R / f; the bound keyed by f covers
+    the pairs of the sharpened model (L / f in binary32) at every factor, below and above 1."""
+    rng = np.random.default_rng(6)
+    models = [wl.random_model(120, 3, 1, 40, 36, seed=310 + i, sig_lo=0.5, sig_hi=12.0)
+              for i in range(2)]
+    spans = BoxSpans(models, 3.0)
+    for _ in range(30):
+        i = int(rng.integers(2))
+        s = int(rng.integers(1, 4))
+        f = float(rng.choice([0.6, 1.0, 1.3, 2.0, 3.7]))
+        W, H = int(rng.integers(1, 40 * s + 1)), int(rng.integers(1, 36 * s + 1))
+        ox, oy = int(rng.integers(-10, 11)), int(rng.integers(-10, 11))
+        P = oracle.bin(oracle.sharpen(models[i], f), 3, 1, W, H, s, ox, oy)["P"]
+        assert spans.pair_bound(i, s, W, H, f) >= P, (i, s, f, W, H, ox, oy)
+    # sharpening shrinks the boxes: the bound does not grow with f
+    assert spans.pair_bound(0, 2, 80, 72, 2.0) <= spans.pair_bound(0, 2, 80, 72)
+    assert spans.pair_bound(0, 2, 80, 72, 0.0) == spans.pair_bound(0, 2, 80, 72, 1.0)
+
+
 def _req(w, h):
     return SimpleNamespace(width=w, height=h)
 
