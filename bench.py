@@ -272,6 +272,8 @@ def run(args):
         out["batched_fit"] = run_batched_fit(args)
     if not args.no_mm:
         out["mm_denoise"] = run_mm_denoise(args)
+    if not args.no_tight:
+        out["tight_box"] = run_tight_box(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -401,6 +403,77 @@ def run_batched_fit(args):
             "unbatched_iters_per_s": steps / t_unb,
             "psnr_mean_db": float(np.mean(psnr_b)), "psnr_min_db": float(np.min(psnr_b)),
             "psnr_max_abs_diff_vs_unbatched_db": float(d.max())}
+
+
+def run_tight_box(args):
+    """Square vs tight axis-aligned kernel boxes on fitted models: the headline workload is
+    fitted for --tight-fit-steps iterations (square boxes; the paper's 10000 by default),
+    then, from that model, for each box: its (block, kernel) pairs, the time of one binning +
+    render of the 2048^2 image, and fit iterations/s over --tight-steps graphed steps from
+    the same state.  Images are the same with either box (bit for bit)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    w = wl.workload(3)
+    H, W, C = w.target.shape
+    target = torch.from_numpy(w.target).cuda()
+    raw0 = torch.from_numpy(w.raw0).cuda()
+    n_fit, n_time = args.tight_fit_steps, args.tight_steps
+    adam = smoe.AdamConfig(total_steps=10000)
+    st = smoe.FitState(target, raw0, 1, adam, max_steps=1, capacity=W * H)
+    st.run_graphed(n_fit)
+    if st.bins.read_status()[0]:
+        raise RuntimeError("pair capacity overflow in the tight-box fit")
+    raw = st.raw.clone()
+    model = st.model.clone()
+    del st
+    out = {"workload": WORKLOAD, "fit_steps_before": n_fit, "timed_fit_steps": n_time}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    imgs = {}
+    for box in ("square", "tight"):
+        grid = smoe.make_grid(W, H, box=box)
+        bins = smoe.bin(model, C, 1, grid)
+        _, stt = bins.read_status()
+        out[f"pairs_{box}"] = int(stt[0])
+        out[f"longest_list_{box}"] = int(stt[2])
+        img = torch.empty((H, W, C), dtype=torch.float32, device="cuda")
+        den = torch.empty((H, W), dtype=torch.float32, device="cuda")
+        m = smoe.core.model_struct(model, C, 1)
+        sh = torch.cuda.current_stream().cuda_stream
+        reps = 50
+        for i in range(reps + 5):
+            if i == 5:
+                ev[0].record()
+            smoe._capi.smoe_bin(m, grid, bins.c, sh)
+            smoe._capi.smoe_render(m, grid, bins.c, img.data_ptr(), den.data_ptr(), None, None,
+                                   sh)
+        ev[1].record()
+        torch.cuda.synchronize()
+        out[f"render_ms_{box}"] = ev[0].elapsed_time(ev[1]) / reps
+        imgs[box] = img
+        # fit steps from the same fitted state
+        f = smoe.FitState(target, raw, 1, adam, max_steps=1, capacity=2 * W * H, box=box)
+        f.step()
+        g = f.capture(50)
+        f.replay(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_time // 50):
+            f.replay(g)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if f.bins.read_status()[0]:
+            raise RuntimeError("pair capacity overflow in the tight-box fit")
+        out[f"fit_iters_per_s_{box}"] = 50 * (n_time // 50) / dt
+        del f, g, bins
+    out["images_equal"] = bool(torch.equal(imgs["square"], imgs["tight"]))
+    out["pair_ratio"] = out["pairs_tight"] / max(1, out["pairs_square"])
+    out["render_speedup"] = out["render_ms_square"] / out["render_ms_tight"]
+    out["fit_speedup"] = out["fit_iters_per_s_tight"] / out["fit_iters_per_s_square"]
+    return out
 
 
 def run_mm_denoise(args):
@@ -628,6 +701,9 @@ def main():
     ap.add_argument("--no-mm", action="store_true", help="skip the multi-model denoising run")
     ap.add_argument("--mm-size", type=int, default=512)
     ap.add_argument("--mm-steps", type=int, default=300)
+    ap.add_argument("--no-tight", action="store_true", help="skip the square/tight box run")
+    ap.add_argument("--tight-fit-steps", type=int, default=10000)
+    ap.add_argument("--tight-steps", type=int, default=1000)
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()

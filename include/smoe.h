@@ -88,7 +88,21 @@ typedef struct smoe_grid {
                                   box and the truncation test follow); f > 0, 0 or 1 = none.
                                   Render and binning only: the backward and the fit step
                                   reject f != 1 */
+  int32_t box;                 /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT (below) */
 } smoe_grid;
+
+/* Kernel boxes (Sec. IV-B).  SMOE_BOX_SQUARE: the paper's square box of half-side
+ * R = r sqrt(lambda_max).  SMOE_BOX_TIGHT: the axis-aligned box of half-widths
+ * Rx = min(R, r |l11| (1 + 2^-10) + m), Ry = min(R, r sqrt(syy) (1 + 2^-10) + m) with
+ * syy = l21 l21 + l22 l22 and m = (|mu_x| + |mu_y| + R) 2^-18, in binary32 in that order:
+ * the extents of the r-ellipse along x and y, widened by a margin that covers the rounding
+ * of the binary32 ellipse test and of the pixel coordinates.  Every pixel the ellipse test
+ * accepts inside the square box lies in the tight box, so images and losses are those of
+ * the square box, bit for bit; only blocks the ellipse cannot reach leave the block lists.
+ * Gradients are the same sums of fewer (zero-free) per-block partials, grouped differently,
+ * so they agree up to that rounding.  Any other value is rejected. */
+#define SMOE_BOX_SQUARE 0
+#define SMOE_BOX_TIGHT 1
 
 /* One raster of a batched call: an image of a batched fit, or one render request (the
  * model rows params[param_offset, param_offset + num_kernels) rendered on this raster).
@@ -123,6 +137,7 @@ typedef struct smoe_batch {
   const smoe_segment* segments;       /* device copy of the laid-out table */
   const smoe_segment* segments_host;  /* host copy of the same table */
   float radius;                       /* Mahalanobis truncation radius */
+  int32_t box;                        /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT */
 } smoe_batch;
 
 /* Binning workspace: the block lists of Sec. IV-C and the scratch of the backward.
@@ -242,7 +257,8 @@ typedef struct smoe_fit_state {
    * kernels, as independent fits stepped in lock-step (the loss is the sum of the images'
    * MSEs, so every image's gradient is its own).  Segments laid out by
    * smoe_segments_layout with scale 1, origin 0 and param_offset == kernel_offset; target,
-   * image and denom are the concatenated images; K = total kernels; `grid` is unused. */
+   * image and denom are the concatenated images; K = total kernels; of `grid` only the radius
+   * and the box mode are used. */
   int32_t num_segments;
   const smoe_segment* segments;       /* device copy, or NULL for one image */
   const smoe_segment* segments_host;  /* host copy, or NULL */

@@ -20,6 +20,12 @@
 //     in exactly specified IEEE binary32 arithmetic (this file is built with
 //     -ffp-contract=off), the same precision as the GPU kernels, so that both take the
 //     same decisions.  Every continuous quantity (exp, sums, y, gradients) is FP64.
+//   * Optionally (box = 1) a tight axis-aligned box instead of the square one: half-widths
+//     r sqrt(Sigma_xx) and r sqrt(Sigma_yy), the extents of the r-ellipse along x and y,
+//     each widened by a small margin that covers the rounding of the binary32 ellipse test
+//     and capped at the square box.  Every pixel the ellipse test accepts inside the square
+//     box lies inside the widened tight box, so the model's values are unchanged; only
+//     blocks that the ellipse cannot reach leave the lists.
 //   * The untruncated ("global") model of Sec. III-B: every kernel at every pixel.
 //   * Block lists of Sec. IV-C: per 16x16 block, the kernels whose box covers it, in
 //     increasing kernel id.
@@ -58,6 +64,7 @@ struct Grid {
   int s;        // integer upscale factor (1 = native resolution)
   int ox, oy;   // raster origin in output pixels
   float r;      // Mahalanobis truncation radius
+  int box;      // 0: square box of Sec. IV-B; 1: tight axis-aligned box
   int ntx() const { return (W + 15) / 16; }
   int nty() const { return (H + 15) / 16; }
 };
@@ -103,11 +110,21 @@ Rect32 kernel_rect32(float mux, float muy, float l11, float l21, float l22, cons
   const float d = 0.5f * (sxx - syy);
   const float lam = h + std::sqrt(d * d + sxy * sxy);
   const float R = g.r * std::sqrt(lam);
+  float Rx = R, Ry = R;
+  if (g.box == 1) {
+    // The ellipse's x extent is r |l11| (z1 = dx / l11 and q >= z1^2); its y extent is
+    // r sqrt(syy) (dy = l21 z1 + l22 z2, Cauchy-Schwarz).  The margin: 2^-10 relative,
+    // plus 2^-18 of the coordinates' magnitude for the roundings of the pixel centre and
+    // of the box edges.
+    const float m = (std::fabs(mux) + std::fabs(muy) + R) * 0x1p-18f;
+    Rx = std::fmin(R, g.r * std::fabs(l11) * 1.0009765625f + m);
+    Ry = std::fmin(R, g.r * std::sqrt(syy) * 1.0009765625f + m);
+  }
   const float fs = (float)g.s;
-  const float X0 = (mux - R) * fs - (float)g.ox;
-  const float X1 = (mux + R) * fs - (float)g.ox;
-  const float Y0 = (muy - R) * fs - (float)g.oy;
-  const float Y1 = (muy + R) * fs - (float)g.oy;
+  const float X0 = (mux - Rx) * fs - (float)g.ox;
+  const float X1 = (mux + Rx) * fs - (float)g.ox;
+  const float Y0 = (muy - Ry) * fs - (float)g.oy;
+  const float Y1 = (muy + Ry) * fs - (float)g.oy;
   Rect32 rc{};
   rc.empty = !(axis_range(X0, X1, g.W, &rc.u0, &rc.u1) && axis_range(Y0, Y1, g.H, &rc.v0, &rc.v1));
   if (rc.empty) {
@@ -293,9 +310,10 @@ int oracle_num_params(int C, int order) { return num_params(C, order); }
 //   ranges     [T][2] = [begin, end) of each block's list in keys/vals
 // Returns the total number of pairs P (written only up to capacity).
 int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                   int oy, float r, int32_t* tile_rects, int32_t* pix_rects, int32_t* counts,
+                   int oy, float r, int box, int32_t* tile_rects, int32_t* pix_rects,
+                   int32_t* counts,
                    int64_t capacity, uint32_t* keys, uint32_t* vals, int32_t* ranges) {
-  const Grid g{W, H, s, ox, oy, r};
+  const Grid g{W, H, s, ox, oy, r, box};
   const Model M(K, C, order, model, g);
   const int ntx = g.ntx(), T = g.ntx() * g.nty();
   std::vector<std::vector<uint32_t>> lists(T);
@@ -328,9 +346,10 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
 // Renders y [npix][C] and D [npix] at the listed output pixels (pix [npix][2] = (u, v));
 // pix == NULL renders the whole raster in row-major order (npix ignored).
 void oracle_render(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                   int oy, float r, int truncated, int64_t npix, const int32_t* pix, double* y,
+                   int oy, float r, int box, int truncated, int64_t npix, const int32_t* pix,
+                   double* y,
                    double* D, int threads) {
-  const Grid g{W, H, s, ox, oy, r};
+  const Grid g{W, H, s, ox, oy, r, box};
   const Model M(K, C, order, model, g);
   const int64_t n = pix ? npix : (int64_t)W * H;
   parallel_for(n, threads, [&](int64_t i, int) {
@@ -349,9 +368,10 @@ void oracle_render(int K, int C, int order, const double* model, int W, int H, i
 //   grads [nsel or K][NP] raw-parameter order, overwritten.
 // Returns the loss (NaN in grad_y mode or with a kernel subset).
 double oracle_loss_grad(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                        int oy, float r, const double* target, const double* grad_y, int nsel,
+                        int oy, float r, int box, const double* target, const double* grad_y,
+                        int nsel,
                         const int32_t* sel, double* grads, int threads) {
-  const Grid g{W, H, s, ox, oy, r};
+  const Grid g{W, H, s, ox, oy, r, box};
   const Model M(K, C, order, model, g);
   const int NP = M.NP;
   const int nout = sel ? nsel : K;
@@ -454,7 +474,7 @@ void oracle_adam(int K, int C, int order, double* p, const double* g, double* m,
 
 // Full fit: `steps` iterations of materialize -> loss/gradient -> Adam, from raw0.
 // Writes the loss before each update into loss_hist [steps] and the final raw params.
-void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float r,
+void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float r, int box,
                 const double* target, int steps, int total_steps, double lr_mu,
                 double lr_mu_final, double lr_chol, double lr_rho, double lr_expert,
                 double beta1, double beta2, double eps, double* loss_hist, double* raw_out,
@@ -465,7 +485,8 @@ void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float
   double lrs[4];
   for (int it = 0; it < steps; ++it) {
     oracle_materialize(K, C, order, raw.data(), model.data());
-    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, target, nullptr,
+    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, box, target,
+                                     nullptr,
                                      0, nullptr, g.data(), threads);
     oracle_step_lrs(it, total_steps, lr_mu, lr_mu_final, lr_chol, lr_rho, lr_expert, lrs);
     oracle_adam(K, C, order, raw.data(), g.data(), m.data(), v.data(), it + 1, lrs, beta1, beta2,

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
     l21 = l21 / sg.sharpen;
     l22 = l22 / sg.sharpen;
   }
-  const int4 rc = kernel_block_rect(p[0], p[1], l11, l21, l22, sg, S.r);
+  const int4 rc = kernel_block_rect(p[0], p[1], l11, l21, l22, sg, S.r, S.box);
   tile_rects[j] = rc;
   counts[j] = rect_count(rc);
   write_record(records + (size_t)j * rs, p, ne, rs, l11, l21, l22);

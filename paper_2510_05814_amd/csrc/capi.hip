@@ -33,6 +33,7 @@ bool valid_radius(float r) { return r > 0.0f && std::isfinite(r); }
 // Sharpening factor: 0 (none) or a finite positive bandwidth divisor.
 bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f)); }
 bool no_sharpen(float f) { return f == 0.0f || f == 1.0f; }
+bool valid_box(int32_t b) { return b == SMOE_BOX_SQUARE || b == SMOE_BOX_TIGHT; }
 
 long long raster_tiles(int32_t W, int32_t H) {
   return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
@@ -42,7 +43,7 @@ long long raster_tiles(int32_t W, int32_t H) {
 bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   if (!valid_model(m) || !g ||
       !valid_raster(g->width, g->height, g->scale, g->origin_x, g->origin_y) ||
-      !valid_radius(g->radius) || !valid_sharpen(g->sharpen))
+      !valid_radius(g->radius) || !valid_sharpen(g->sharpen) || !valid_box(g->box))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -56,6 +57,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   o.num_kernels = m->K;
   S.r = g->radius;
   S.r2 = g->radius * g->radius;
+  S.box = g->box;
   S.T = (int)raster_tiles(g->width, g->height);
   S.K = m->K;
   *out = S;
@@ -87,7 +89,7 @@ bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int*
 
 bool batch_segs(const smoe_batch* b, Segs* out) {
   if (!b || !valid_shape(0, b->C, b->order) || !b->params || !b->segments ||
-      b->num_params_rows < 0 || !valid_radius(b->radius))
+      b->num_params_rows < 0 || !valid_radius(b->radius) || !valid_box(b->box))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -97,6 +99,7 @@ bool batch_segs(const smoe_batch* b, Segs* out) {
   S.n = b->num_segments;
   S.r = b->radius;
   S.r2 = b->radius * b->radius;
+  S.box = b->box;
   *out = S;
   return true;
 }
@@ -151,7 +154,9 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 // The rasters of a fit state: its segment table (batched fit) or its single grid.
 bool fit_segs(const smoe_fit_state* st, Segs* S) {
   if (st->num_segments > 0) {
-    if (!st->segments || !st->segments_host || !valid_radius(st->grid.radius)) return false;
+    if (!st->segments || !st->segments_host || !valid_radius(st->grid.radius) ||
+        !valid_box(st->grid.box))
+      return false;
     std::memset(S, 0, sizeof(*S));
     if (!check_segments(st->segments_host, st->num_segments, st->K, &S->T, &S->K)) return false;
     for (int i = 0; i < st->num_segments; ++i) {
@@ -165,6 +170,7 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
     S->n = st->num_segments;
     S->r = st->grid.radius;
     S->r2 = st->grid.radius * st->grid.radius;
+    S->box = st->grid.box;
     return true;
   }
   const smoe_model m{st->K, st->C, st->order, st->model};

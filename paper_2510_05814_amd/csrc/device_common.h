@@ -24,10 +24,12 @@ __device__ __forceinline__ bool axis_range(float lo, float hi, int n, int& i0, i
 }
 
 // Block rectangle (tx0, ty0, tx1, ty1) of one kernel, (0, 0, -1, -1) when empty: the pixel
-// centres inside the square box of half-side R = r sqrt(lambda_max(L L^T)) around mu,
-// as the exact binary32 sequence of the ABI contract.
+// centres inside the square box of half-side R = r sqrt(lambda_max(L L^T)) around mu, or
+// inside the tight axis-aligned box of the ellipse's x and y extents (widened by a rounding
+// margin, capped at R), as the exact binary32 sequences of the ABI contract.
 __device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l11, float l21,
-                                                  float l22, const SegGrid& g, float r) {
+                                                  float l22, const SegGrid& g, float r,
+                                                  int box) {
   const float sxx = l11 * l11;
   const float sxy = l11 * l21;
   const float syy = l21 * l21 + l22 * l22;
@@ -35,11 +37,17 @@ __device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l1
   const float d = 0.5f * (sxx - syy);
   const float lam = h + sqrtf(d * d + sxy * sxy);
   const float R = r * sqrtf(lam);
+  float Rx = R, Ry = R;
+  if (box == SMOE_BOX_TIGHT) {
+    const float m = (fabsf(mux) + fabsf(muy) + R) * 0x1p-18f;
+    Rx = fminf(R, r * fabsf(l11) * 1.0009765625f + m);
+    Ry = fminf(R, r * sqrtf(syy) * 1.0009765625f + m);
+  }
   const float fs = (float)g.scale;
-  const float X0 = (mux - R) * fs - (float)g.ox;
-  const float X1 = (mux + R) * fs - (float)g.ox;
-  const float Y0 = (muy - R) * fs - (float)g.oy;
-  const float Y1 = (muy + R) * fs - (float)g.oy;
+  const float X0 = (mux - Rx) * fs - (float)g.ox;
+  const float X1 = (mux + Rx) * fs - (float)g.ox;
+  const float Y0 = (muy - Ry) * fs - (float)g.oy;
+  const float Y1 = (muy + Ry) * fs - (float)g.oy;
   int u0, u1, v0, v1;
   const bool ok = axis_range(X0, X1, g.W, u0, u1) && axis_range(Y0, Y1, g.H, v0, v1);
   return ok ? make_int4(u0 >> 4, v0 >> 4, u1 >> 4, v1 >> 4) : make_int4(0, 0, -1, -1);

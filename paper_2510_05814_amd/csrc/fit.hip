@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       f.records[(size_t)j * RS + i] = fld;
     }
     if (i == 0) {
-      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, sg, f.S.r);
+      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box);
       f.tile_rects_out[j] = rc;
       f.counts[j] = rect_count(rc);
     }

@@ -55,6 +55,16 @@ MUTANTS = [
      "f = std::pow(lr_mu_final / lr_mu, (double)step_index / (double)total_steps);",
      "f = std::pow(lr_mu / lr_mu_final, (double)step_index / (double)total_steps);",
      [pins.test_adam_matches_torch_optim_adam]),
+    ("tight box y extent from l22 alone",
+     "Ry = std::fmin(R, g.r * std::sqrt(syy) * 1.0009765625f + m);",
+     "Ry = std::fmin(R, g.r * std::fabs(l22) * 1.0009765625f + m);",
+     [pins.test_tight_box_keeps_every_value_and_shortens_lists,
+      pins.test_tight_box_is_the_ellipse_extent]),
+    ("tight box axes swapped",
+     "const float X0 = (mux - Rx) * fs - (float)g.ox;\n  const float X1 = (mux + Rx)",
+     "const float X0 = (mux - Ry) * fs - (float)g.ox;\n  const float X1 = (mux + Ry)",
+     [pins.test_tight_box_keeps_every_value_and_shortens_lists,
+      pins.test_tight_box_is_the_ellipse_extent]),
     ("block list not in kernel order",
      "for (int j = 0; j < K; ++j) {\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",
      "for (int jj = 0; jj < K; ++jj) {\n    const int j = K - 1 - jj;\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",

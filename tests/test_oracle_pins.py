@@ -255,6 +255,102 @@ def test_sharpen_one_or_zero_is_identity():
         np.testing.assert_array_equal(oracle.sharpen(m, f), m)
 
 
+# --------------------------------------------------------------------------- tight box
+
+
+def aniso_model(K, W, H, seed):
+    return wl.stretched_model(K, 3, 1, W, H, seed).astype(np.float64)
+
+
+def _pixel_block_range(lo, hi, n):
+    """Blocks of the output pixels whose centres u + 0.5 lie in [lo, hi], clipped to [0, n)."""
+    u0 = max(0, int(np.ceil(lo - 0.5)))
+    u1 = min(n - 1, int(np.floor(hi - 0.5)))
+    return (u0 >> 4, u1 >> 4) if u1 >= u0 else None
+
+
+def test_tight_box_is_the_ellipse_extent():
+    """Half-widths r sqrt(Sigma_xx), r sqrt(Sigma_yy) (Sigma from numpy's L L^T), capped at
+    the square box: the oracle's block rectangles equal those of the exact extents wherever
+    a block edge does not fall inside the rounding margin."""
+    W, H = 70, 54
+    compared = 0
+    for s, ox, oy in [(1, 0, 0), (2, 3, 5), (3, 1, 0)]:
+        m = aniso_model(80, W, H, seed=40 + s)
+        S = sigma_of(m)
+        lam = np.linalg.eigvalsh(S)[:, 1]
+        tr = oracle.bin(m, 3, 1, s * W - ox, s * H - oy, s, ox, oy, box=1)["tile_rects"]
+        for j in range(m.shape[0]):
+            rng = []
+            for k, (mu, o, n) in enumerate([(m[j, 0], ox, s * W - ox), (m[j, 1], oy, s * H - oy)]):
+                e = min(R * np.sqrt(S[j, k, k]), R * np.sqrt(lam[j]))
+                tight = _pixel_block_range((mu - e) * s - o, (mu + e) * s - o, n)
+                e2 = min(e * (1 + 2e-3) + 1e-3, R * np.sqrt(lam[j]))
+                loose = _pixel_block_range((mu - e2) * s - o, (mu + e2) * s - o, n)
+                rng.append(tight if tight == loose else "skip")
+            if "skip" in rng:
+                continue
+            compared += 1
+            if rng[0] is None or rng[1] is None:
+                assert tr[j, 2] < tr[j, 0], j
+            else:
+                assert tuple(tr[j]) == (rng[0][0], rng[1][0], rng[0][1], rng[1][1]), (s, j)
+    assert compared > 200
+
+
+def test_tight_box_keeps_every_value_and_shortens_lists():
+    """The tight box changes no value (the ellipse test never accepts a pixel outside it) and
+    every list is a subset of the square box's list; brute force: every block holding a pixel
+    strictly inside the FP64 ellipse is in the kernel's tight rectangle."""
+    W, H = 61, 47
+    for s, ox, oy, f in [(1, 0, 0, 1.0), (2, 5, 2, 1.0), (3, 0, 7, 1.0), (1, 0, 0, 1.8)]:
+        m = oracle.sharpen(aniso_model(90, W, H, seed=50 + s), f)
+        OW, OH = s * W - ox, s * H - oy
+        ya, Da = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=0)
+        yb, Db = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=1)
+        np.testing.assert_array_equal(ya, yb)
+        np.testing.assert_array_equal(Da, Db)
+        sq = oracle.bin(m, 3, 1, OW, OH, s, ox, oy, box=0)
+        ti = oracle.bin(m, 3, 1, OW, OH, s, ox, oy, box=1)
+        assert ti["P"] < 0.8 * sq["P"]
+        a, b = sq["tile_rects"], ti["tile_rects"]
+        ne = b[:, 2] >= b[:, 0]
+        assert np.all(a[ne, 0] <= b[ne, 0]) and np.all(a[ne, 1] <= b[ne, 1])
+        assert np.all(a[ne, 2] >= b[ne, 2]) and np.all(a[ne, 3] >= b[ne, 3])
+        v, u = np.mgrid[0:OH, 0:OW]
+        x, y = (ox + u.ravel() + 0.5) / s, (oy + v.ravel() + 0.5) / s
+        q = maha_np(m, x, y)
+        for j in range(m.shape[0]):
+            hit = q[j] <= R * R * (1 - 1e-6)
+            if not hit.any():
+                continue
+            bx, by = u.ravel()[hit] >> 4, v.ravel()[hit] >> 4
+            assert b[j, 0] <= bx.min() and bx.max() <= b[j, 2], (s, j)
+            assert b[j, 1] <= by.min() and by.max() <= b[j, 3], (s, j)
+
+
+def test_tight_box_keeps_loss_and_gradient():
+    """The oracle's loss and gradient sum over pixels and participating kernels only, so the
+    tight box gives them bit for bit (one thread: the row-to-thread split of a threaded run,
+    and with it the FP64 rounding, varies from run to run)."""
+    W, H = 40, 33
+    m = aniso_model(50, W, H, seed=58)
+    t = np.random.default_rng(2).uniform(0, 1, (H, W, 3))
+    la, ga = oracle.loss_grad(m, 3, 1, W, H, target=t, box=0, threads=1)
+    lb, gb = oracle.loss_grad(m, 3, 1, W, H, target=t, box=1, threads=1)
+    assert la == lb
+    np.testing.assert_array_equal(ga, gb)
+
+
+def test_tight_box_of_round_kernels_is_the_square_box():
+    m = wl.random_model(50, 3, 1, 40, 40, seed=60).astype(np.float64)
+    m[:, 3] = 0.0
+    m[:, 4] = m[:, 2]
+    a = oracle.bin(m, 3, 1, 40, 40, box=0)
+    b = oracle.bin(m, 3, 1, 40, 40, box=1)
+    np.testing.assert_array_equal(a["tile_rects"], b["tile_rects"])
+
+
 # --------------------------------------------------------------------------- invariants
 
 

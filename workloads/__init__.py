@@ -199,6 +199,26 @@ def random_model(K: int, C: int, order: int, W: int, H: int, seed: int,
     return m.astype(np.float32)
 
 
+def stretched_model(K: int, C: int, order: int, W: int, H: int, seed: int,
+                    size_lo: float = 0.5, size_hi: float = 9.0, max_aspect: float = 8.0):
+    """Random materialized model whose kernels are ellipses of major standard deviation a in
+    [size_lo, size_hi], aspect ratio up to max_aspect, at uniform angles (the shapes a long
+    fit produces).  L is the Cholesky factor of R diag(a^2, b^2) R^T.  Float32 [K, NP]."""
+    rng = _rng(seed + 7)
+    m = random_model(K, C, order, W, H, seed).astype(np.float64)
+    th = rng.uniform(0.0, np.pi, K)
+    a = rng.uniform(size_lo, size_hi, K)
+    b = a / rng.uniform(1.0, max_aspect, K)
+    c, sn = np.cos(th), np.sin(th)
+    sxx = (c * a) ** 2 + (sn * b) ** 2
+    sxy = c * sn * (a * a - b * b)
+    syy = (sn * a) ** 2 + (c * b) ** 2
+    l11 = np.sqrt(sxx)
+    l21 = sxy / l11
+    m[:, 2], m[:, 3], m[:, 4] = l11, l21, np.sqrt(syy - l21 ** 2)
+    return m.astype(np.float32)
+
+
 def fd_crop_case(seed: int = SEEDS[3], size: int = 32, g: int = 4, order: int = 1):
     """Small gradient-check case: a size^2 RGB crop of the denoising target,
     K = g*g linear kernels from the grid init, randomly perturbed so every
