@@ -89,7 +89,19 @@ typedef struct smoe_grid {
                                   Render and binning only: the backward and the fit step
                                   reject f != 1 */
   int32_t box;                 /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT (below) */
+  int32_t mode;                /* SMOE_MODE_SMOE or SMOE_MODE_RBF (below) */
 } smoe_grid;
+
+/* Regression modes.  SMOE_MODE_SMOE: the gated regression of Eq. (2)-(4),
+ * y_c = sum_j m_jc(x) pi_j K_j(x) / D with D = sum_i pi_i K_i(x) (y = 0 where D = 0).
+ * SMOE_MODE_RBF: the weighted sum of kernels of Eq. (1) (RBF networks, Gaussian
+ * splatting), y_c = sum_j pi_j m_jc(x) K_j(x): the kernel weight of Eq. (1) is pi_j m_jc(x)
+ * (a constant for order 0), with no normalisation, so a pixel no kernel reaches renders 0.
+ * Both modes share the boxes, block lists, truncation rule, parameter layout and records,
+ * and write D; the render, the backward and the fit step follow the mode.  Any other value
+ * is rejected. */
+#define SMOE_MODE_SMOE 0
+#define SMOE_MODE_RBF 1
 
 /* Kernel boxes (Sec. IV-B).  SMOE_BOX_SQUARE: the paper's square box of half-side
  * R = r sqrt(lambda_max).  SMOE_BOX_TIGHT: the axis-aligned box of half-widths
@@ -138,6 +150,7 @@ typedef struct smoe_batch {
   const smoe_segment* segments_host;  /* host copy of the same table */
   float radius;                       /* Mahalanobis truncation radius */
   int32_t box;                        /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT */
+  int32_t mode;                       /* SMOE_MODE_SMOE or SMOE_MODE_RBF */
 } smoe_batch;
 
 /* Binning workspace: the block lists of Sec. IV-C and the scratch of the backward.
@@ -257,8 +270,8 @@ typedef struct smoe_fit_state {
    * kernels, as independent fits stepped in lock-step (the loss is the sum of the images'
    * MSEs, so every image's gradient is its own).  Segments laid out by
    * smoe_segments_layout with scale 1, origin 0 and param_offset == kernel_offset; target,
-   * image and denom are the concatenated images; K = total kernels; of `grid` only the radius
-   * and the box mode are used. */
+   * image and denom are the concatenated images; K = total kernels; of `grid` only the radius,
+   * the box and the mode are used. */
   int32_t num_segments;
   const smoe_segment* segments;       /* device copy, or NULL for one image */
   const smoe_segment* segments_host;  /* host copy, or NULL */

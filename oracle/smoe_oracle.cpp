@@ -26,6 +26,9 @@
 //     and capped at the square box.  Every pixel the ellipse test accepts inside the square
 //     box lies inside the widened tight box, so the model's values are unchanged; only
 //     blocks that the ellipse cannot reach leave the lists.
+//   * Optionally (rbf = 1) the weighted sum of kernels of Eq. (1) (RBF networks, Gaussian
+//     splatting) instead of the gates: y(x) = sum_j pi_j m_j(x) K_j(x), the kernel weight of
+//     Eq. (1) being pi_j m_j(x); no normalisation.  Same kernels, truncation and parameters.
 //   * The untruncated ("global") model of Sec. III-B: every kernel at every pixel.
 //   * Block lists of Sec. IV-C: per 16x16 block, the kernels whose box covers it, in
 //     increasing kernel id.
@@ -65,6 +68,7 @@ struct Grid {
   int ox, oy;   // raster origin in output pixels
   float r;      // Mahalanobis truncation radius
   int box;      // 0: square box of Sec. IV-B; 1: tight axis-aligned box
+  int rbf;      // 0: gated SMoE regression, Eq. (2)-(4); 1: weighted sum of kernels, Eq. (1)
   int ntx() const { return (W + 15) / 16; }
   int nty() const { return (H + 15) / 16; }
 };
@@ -208,7 +212,8 @@ inline double expert(const double* r, int C, int order, int c, double dx, double
   return m;
 }
 
-// y(x) and D(x) = sum_j pi_j K_j(x) over the participating kernels (all K if !truncated).
+// y(x) and D(x) = sum_j pi_j K_j(x) over the participating kernels (all K if !truncated);
+// y = N / D (Eq. 2-4) or, in the RBF mode, y = N (Eq. 1), with N_c = sum_j pi_j K_j m_jc.
 void eval_pixel(const Model& M, const Grid& g, bool truncated, int u, int v, double* y, double* D) {
   const float x32 = coord32(u, g.ox, g.s);
   const float y32 = coord32(v, g.oy, g.s);
@@ -224,7 +229,7 @@ void eval_pixel(const Model& M, const Grid& g, bool truncated, int u, int v, dou
     for (int c = 0; c < M.C; ++c) N[c] += t.e * expert(r, M.C, M.order, c, t.dx, t.dy);
   }
   *D = Dsum;
-  for (int c = 0; c < M.C; ++c) y[c] = (Dsum > 0.0) ? N[c] / Dsum : 0.0;
+  for (int c = 0; c < M.C; ++c) y[c] = g.rbf ? N[c] : ((Dsum > 0.0) ? N[c] / Dsum : 0.0);
 }
 
 template <class F>
@@ -264,10 +269,13 @@ void grad_pixel(const Model& M, const Grid& g, int u, int v, const double* gy_in
     if (!M.participates(j, u, v, x32, y32, r2)) continue;
     const double* r = M.p + (size_t)j * NP;
     const Term t = term(r, x, yy);
-    const double w = t.e / D;  // gate w_j(x), Eq. (4)
-    // dL/de_j = sum_c g_c (m_jc - y_c) / D, so dL/drho_j = w_j * sum_c g_c (m_jc - y_c).
+    // w = dy_c/dm_jc: the gate w_j(x) of Eq. (4), or pi_j K_j(x) in the RBF sum of Eq. (1).
+    const double w = g.rbf ? t.e : t.e / D;
+    // Gs = dL/de_j / (w / e_j), with e_j = pi_j K_j: gated, dL/de_j = sum_c g_c (m_jc - y_c)/D;
+    // RBF, dL/de_j = sum_c g_c m_jc.  Either way dL/drho_j = e_j dL/de_j = w Gs.
     double Gs = 0.0;
-    for (int c = 0; c < C; ++c) Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - y[c]);
+    for (int c = 0; c < C; ++c)
+      Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - (g.rbf ? 0.0 : y[c]));
     const double Hh = w * Gs;
     double* out = G + (size_t)sj * NP;
     out[5] += Hh;
@@ -313,7 +321,7 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
                    int oy, float r, int box, int32_t* tile_rects, int32_t* pix_rects,
                    int32_t* counts,
                    int64_t capacity, uint32_t* keys, uint32_t* vals, int32_t* ranges) {
-  const Grid g{W, H, s, ox, oy, r, box};
+  const Grid g{W, H, s, ox, oy, r, box, 0};
   const Model M(K, C, order, model, g);
   const int ntx = g.ntx(), T = g.ntx() * g.nty();
   std::vector<std::vector<uint32_t>> lists(T);
@@ -346,10 +354,11 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
 // Renders y [npix][C] and D [npix] at the listed output pixels (pix [npix][2] = (u, v));
 // pix == NULL renders the whole raster in row-major order (npix ignored).
 void oracle_render(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                   int oy, float r, int box, int truncated, int64_t npix, const int32_t* pix,
+                   int oy, float r, int box, int rbf, int truncated, int64_t npix,
+                   const int32_t* pix,
                    double* y,
                    double* D, int threads) {
-  const Grid g{W, H, s, ox, oy, r, box};
+  const Grid g{W, H, s, ox, oy, r, box, rbf};
   const Model M(K, C, order, model, g);
   const int64_t n = pix ? npix : (int64_t)W * H;
   parallel_for(n, threads, [&](int64_t i, int) {
@@ -368,10 +377,11 @@ void oracle_render(int K, int C, int order, const double* model, int W, int H, i
 //   grads [nsel or K][NP] raw-parameter order, overwritten.
 // Returns the loss (NaN in grad_y mode or with a kernel subset).
 double oracle_loss_grad(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                        int oy, float r, int box, const double* target, const double* grad_y,
+                        int oy, float r, int box, int rbf, const double* target,
+                        const double* grad_y,
                         int nsel,
                         const int32_t* sel, double* grads, int threads) {
-  const Grid g{W, H, s, ox, oy, r, box};
+  const Grid g{W, H, s, ox, oy, r, box, rbf};
   const Model M(K, C, order, model, g);
   const int NP = M.NP;
   const int nout = sel ? nsel : K;
@@ -475,6 +485,7 @@ void oracle_adam(int K, int C, int order, double* p, const double* g, double* m,
 // Full fit: `steps` iterations of materialize -> loss/gradient -> Adam, from raw0.
 // Writes the loss before each update into loss_hist [steps] and the final raw params.
 void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float r, int box,
+                int rbf,
                 const double* target, int steps, int total_steps, double lr_mu,
                 double lr_mu_final, double lr_chol, double lr_rho, double lr_expert,
                 double beta1, double beta2, double eps, double* loss_hist, double* raw_out,
@@ -485,7 +496,7 @@ void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float
   double lrs[4];
   for (int it = 0; it < steps; ++it) {
     oracle_materialize(K, C, order, raw.data(), model.data());
-    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, box, target,
+    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, box, rbf, target,
                                      nullptr,
                                      0, nullptr, g.data(), threads);
     oracle_step_lrs(it, total_steps, lr_mu, lr_mu_final, lr_chol, lr_rho, lr_expert, lrs);

@@ -29,7 +29,7 @@ struct BackwardArgs {
   float* __restrict__ pair_grads;
 };
 
-template <int C, int ORDER>
+template <int C, int ORDER, bool RBF>
 __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
   const int tile = xcd_block(blockIdx.x, a.S.T);
@@ -51,12 +51,12 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
       const float D = a.denom[p];
       if (D > 0.0f) {
         sd.valid[i] = true;
-        sd.invD[i] = 1.0f / D;
+        sd.invD[i] = RBF ? 1.0f : 1.0f / D;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const float yc = a.image[p * C + c];
           sd.g[i][c] = a.target ? (yc - a.target[p * C + c]) * inv_n2 : a.grad_image[p * C + c];
-          sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
+          if (!RBF) sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
         }
       }
     }
@@ -94,10 +94,10 @@ hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
                            const float* target, hipStream_t s) {
   BackwardArgs a{S,     C,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals,
                  image, denom, grad_image, target, b.pair_grads};
-  if (C == 1 && order == 0) k_backward<1, 0><<<S.T, kWave, 0, s>>>(a);
-  else if (C == 1 && order == 1) k_backward<1, 1><<<S.T, kWave, 0, s>>>(a);
-  else if (C == 3 && order == 0) k_backward<3, 0><<<S.T, kWave, 0, s>>>(a);
-  else k_backward<3, 1><<<S.T, kWave, 0, s>>>(a);
+  with_shape(C, order, S.mode, [&](auto sh) {
+    using T = decltype(sh);
+    k_backward<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
+  });
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ bool valid_radius(float r) { return r > 0.0f && std::isfinite(r); }
 bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f)); }
 bool no_sharpen(float f) { return f == 0.0f || f == 1.0f; }
 bool valid_box(int32_t b) { return b == SMOE_BOX_SQUARE || b == SMOE_BOX_TIGHT; }
+bool valid_mode(int32_t m) { return m == SMOE_MODE_SMOE || m == SMOE_MODE_RBF; }
 
 long long raster_tiles(int32_t W, int32_t H) {
   return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
@@ -43,7 +44,8 @@ long long raster_tiles(int32_t W, int32_t H) {
 bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   if (!valid_model(m) || !g ||
       !valid_raster(g->width, g->height, g->scale, g->origin_x, g->origin_y) ||
-      !valid_radius(g->radius) || !valid_sharpen(g->sharpen) || !valid_box(g->box))
+      !valid_radius(g->radius) || !valid_sharpen(g->sharpen) || !valid_box(g->box) ||
+      !valid_mode(g->mode))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -58,6 +60,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   S.r = g->radius;
   S.r2 = g->radius * g->radius;
   S.box = g->box;
+  S.mode = g->mode;
   S.T = (int)raster_tiles(g->width, g->height);
   S.K = m->K;
   *out = S;
@@ -89,7 +92,8 @@ bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int*
 
 bool batch_segs(const smoe_batch* b, Segs* out) {
   if (!b || !valid_shape(0, b->C, b->order) || !b->params || !b->segments ||
-      b->num_params_rows < 0 || !valid_radius(b->radius) || !valid_box(b->box))
+      b->num_params_rows < 0 || !valid_radius(b->radius) || !valid_box(b->box) ||
+      !valid_mode(b->mode))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -100,6 +104,7 @@ bool batch_segs(const smoe_batch* b, Segs* out) {
   S.r = b->radius;
   S.r2 = b->radius * b->radius;
   S.box = b->box;
+  S.mode = b->mode;
   *out = S;
   return true;
 }
@@ -155,7 +160,7 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 bool fit_segs(const smoe_fit_state* st, Segs* S) {
   if (st->num_segments > 0) {
     if (!st->segments || !st->segments_host || !valid_radius(st->grid.radius) ||
-        !valid_box(st->grid.box))
+        !valid_box(st->grid.box) || !valid_mode(st->grid.mode))
       return false;
     std::memset(S, 0, sizeof(*S));
     if (!check_segments(st->segments_host, st->num_segments, st->K, &S->T, &S->K)) return false;
@@ -171,6 +176,7 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
     S->r = st->grid.radius;
     S->r2 = st->grid.radius * st->grid.radius;
     S->box = st->grid.box;
+    S->mode = st->grid.mode;
     return true;
   }
   const smoe_model m{st->K, st->C, st->order, st->model};

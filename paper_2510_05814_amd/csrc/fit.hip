@@ -37,7 +37,7 @@ struct FitTileArgs {
   float* __restrict__ pair_grads;
 };
 
-template <int C, int ORDER>
+template <int C, int ORDER, bool RBF>
 __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
   __shared__ float4 srec[LDS_FLOATS / 4];
@@ -87,16 +87,17 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
     if (px.u < sg.W && v < sg.H) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const bool cov = D[i] > 0.0f;
-      const float invD = cov ? 1.0f / D[i] : 0.0f;
+      const float invD = RBF ? 1.0f : (cov ? 1.0f / D[i] : 0.0f);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const float yc = cov ? N[i][c] / D[i] : 0.0f;
+        // Eq. (2)-(4): y = N / D; Eq. (1): y = N
+        const float yc = RBF ? N[i][c] : (cov ? N[i][c] / D[i] : 0.0f);
         a.image[p * C + c] = yc;
         const float d = yc - a.target[p * C + c];
         err = __builtin_fmaf(d, d, err);
         if (cov) {
           sd.g[i][c] = d * inv_n2;
-          sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
+          if (!RBF) sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
         }
       }
       a.denom[p] = D[i];
@@ -281,10 +282,10 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
                 b.vals,   b.vals_alt, b.tile_counts, b.status, width,
                 target,   st.image,  st.denom,
                 b.tile_loss, b.pair_grads};
-  if (st.C == 1 && st.order == 0) k_fit_tile<1, 0><<<S.T, kWave, 0, s>>>(a);
-  else if (st.C == 1 && st.order == 1) k_fit_tile<1, 1><<<S.T, kWave, 0, s>>>(a);
-  else if (st.C == 3 && st.order == 0) k_fit_tile<3, 0><<<S.T, kWave, 0, s>>>(a);
-  else k_fit_tile<3, 1><<<S.T, kWave, 0, s>>>(a);
+  with_shape(st.C, st.order, S.mode, [&](auto sh) {
+    using T = decltype(sh);
+    k_fit_tile<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
+  });
   return hipGetLastError();
 }
 

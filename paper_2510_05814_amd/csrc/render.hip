@@ -26,7 +26,7 @@ struct RenderArgs {
   float* __restrict__ tile_loss;
 };
 
-template <int C, int ORDER>
+template <int C, int ORDER, bool RBF>
 __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
   const int tile = xcd_block(blockIdx.x, a.S.T);
@@ -43,7 +43,8 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const float yc = (D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f;
+        // Eq. (2)-(4): y = N / D; Eq. (1): y = N
+        const float yc = RBF ? N[i][c] : ((D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f);
         a.image[p * C + c] = yc;
         if (a.target) {
           const float d = yc - a.target[p * C + c];
@@ -135,10 +136,10 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
                          float* denom, const float* target, hipStream_t s) {
   RenderArgs a{S,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
                target, target ? b.tile_loss : nullptr};
-  if (C == 1 && order == 0) k_render<1, 0><<<S.T, kWave, 0, s>>>(a);
-  else if (C == 1 && order == 1) k_render<1, 1><<<S.T, kWave, 0, s>>>(a);
-  else if (C == 3 && order == 0) k_render<3, 0><<<S.T, kWave, 0, s>>>(a);
-  else k_render<3, 1><<<S.T, kWave, 0, s>>>(a);
+  with_shape(C, order, S.mode, [&](auto sh) {
+    using T = decltype(sh);
+    k_render<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
+  });
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct Segs {
   smoe_segment one;                      // the single raster when tab is null
   float r, r2;                           // truncation radius and r*r (binary32)
   int box;                               // SMOE_BOX_SQUARE or SMOE_BOX_TIGHT
+  int mode;                              // SMOE_MODE_SMOE or SMOE_MODE_RBF
   int T;                                 // blocks of all segments
   int K;                                 // kernel rows of all segments
 };

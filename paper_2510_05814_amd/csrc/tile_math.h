@@ -12,6 +12,24 @@
 namespace smoe {
 
 constexpr int kWave = 64;
+
+// Compile-time shape of a launch: channels, expert order and regression mode (RBF: the
+// un-normalised sum of Eq. 1 instead of the gated SMoE of Eq. 2-4).
+template <int C_, int ORDER_, bool RBF_>
+struct Shape {
+  static constexpr int C = C_, ORDER = ORDER_;
+  static constexpr bool RBF = RBF_;
+};
+
+// Calls f(Shape<...>{}) for the run-time (C, order, mode); C is 1 or 3, order 0 or 1.
+template <class F>
+inline void with_shape(int C, int order, int mode, F&& f) {
+  const bool rbf = mode == SMOE_MODE_RBF;
+  if (C == 1 && order == 0) rbf ? f(Shape<1, 0, true>{}) : f(Shape<1, 0, false>{});
+  else if (C == 1 && order == 1) rbf ? f(Shape<1, 1, true>{}) : f(Shape<1, 1, false>{});
+  else if (C == 3 && order == 0) rbf ? f(Shape<3, 0, true>{}) : f(Shape<3, 0, false>{});
+  else rbf ? f(Shape<3, 1, true>{}) : f(Shape<3, 1, false>{});
+}
 constexpr int kChunk = 64;                     // records staged in LDS per chunk
 constexpr int kRows = kTilePixels / kWave;     // pixels per lane (4)
 
@@ -221,7 +239,9 @@ __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& s
 }
 
 // Adjoint seed of one pixel: dL/dy (g), 1/D, sum_c g_c y_c; `valid` false where D = 0 or the
-// pixel lies outside the raster (no gradient flows there).
+// pixel lies outside the raster (no gradient flows there).  With the seed 1/D -> 1 and
+// sum_c g_c y_c -> 0 the same backward is the adjoint of the un-normalised sum of Eq. (1):
+// then w = pi K is dy_c/dm_c and G = sum_c g_c m_c is dL/d(pi K).
 template <int C>
 struct PixelSeed {
   float g[kRows][C];

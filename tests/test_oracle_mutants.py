@@ -35,8 +35,8 @@ MUTANTS = [
      [pins.test_truncation_rule_matches_ellipse_and_stays_in_box]),
     ("block rect off by one", "rc.tx1 = rc.u1 >> 4;", "rc.tx1 = (rc.u1 + 1) >> 4;",
      [pins.test_box_half_side_is_r_sqrt_lambda_max]),
-    ("no normalisation of the gates", "y[c] = (Dsum > 0.0) ? N[c] / Dsum : 0.0;",
-     "y[c] = (Dsum > 0.0) ? N[c] : 0.0;", [pins.test_untruncated_gates_are_softmax]),
+    ("no normalisation of the gates", "((Dsum > 0.0) ? N[c] / Dsum : 0.0);",
+     "((Dsum > 0.0) ? N[c] : 0.0);", [pins.test_untruncated_gates_are_softmax]),
     ("z2 chain term sign in the gradient", "const double bz1 = -Hh * t.z1 - bz2 * r[3] / r[4];",
      "const double bz1 = -Hh * t.z1 + bz2 * r[3] / r[4];", [pins.test_gradient_central_differences]),
     ("expert slope dropped from d/dmu", "const double bdx = bz1 / r[2] + ex;",
@@ -44,8 +44,8 @@ MUTANTS = [
     ("l21 gradient missing 1/l22", "out[3] += -bz2 * t.z1 / r[4];", "out[3] += -bz2 * t.z1;",
      [pins.test_gradient_central_differences]),
     ("gradient of y_c uses y of another channel",
-     "Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - y[c]);",
-     "Gs += gy_in[c] * (expert(r, C, M.order, c, t.dx, t.dy) - y[0]);",
+     "(g.rbf ? 0.0 : y[c]));",
+     "(g.rbf ? 0.0 : y[0]));",
      [pins.test_gradient_central_differences]),
     ("loss mean over H*W only", "const double inv_n = 1.0 / ((double)W * H * C);",
      "const double inv_n = 1.0 / ((double)W * H);", [pins.test_upstream_gradient_mode_and_subsets]),
@@ -65,6 +65,11 @@ MUTANTS = [
      "const float X0 = (mux - Ry) * fs - (float)g.ox;\n  const float X1 = (mux + Ry)",
      [pins.test_tight_box_keeps_every_value_and_shortens_lists,
       pins.test_tight_box_is_the_ellipse_extent]),
+    ("RBF sum still normalised", "y[c] = g.rbf ? N[c] : ((Dsum",
+     "y[c] = g.rbf ? N[c] / Dsum : ((Dsum",
+     [pins.test_rbf_single_kernel_closed_form, pins.test_rbf_superposition_and_numerator]),
+    ("RBF gradient through the gate", "const double w = g.rbf ? t.e : t.e / D;",
+     "const double w = t.e / D;", [pins.test_rbf_gradient_central_differences]),
     ("block list not in kernel order",
      "for (int j = 0; j < K; ++j) {\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",
      "for (int jj = 0; jj < K; ++jj) {\n    const int j = K - 1 - jj;\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",

@@ -569,3 +569,77 @@ def test_fit_reduces_loss_workload1():
                            lr_rho=1e-2, lr_expert=1e-2)
     assert hist[-1] < 0.7 * hist[0]
     assert np.all(np.isfinite(out))
+
+
+# --------------------------------------------------------------------------- RBF sum (Eq. 1)
+
+
+def test_rbf_single_kernel_closed_form():
+    """Eq. (1) with one kernel, untruncated: y_c = pi K(x) m_c(x), K from numpy's Mahalanobis
+    form, m the linear expert; D = pi K as in the gated mode."""
+    W, H = 21, 17
+    m = wl.random_model(5, 3, 1, W, H, seed=70, margin=0.0).astype(np.float64)
+    u, v, x, y = centres(W, H)
+    q = maha_np(m, x, y)
+    for j in range(m.shape[0]):
+        yr, D = oracle.render(m[j:j + 1], 3, 1, W, H, truncated=False, rbf=True)
+        e = np.exp(m[j, 5] - 0.5 * q[j])
+        dx, dy = x - m[j, 0], y - m[j, 1]
+        for c in range(3):
+            ref = e * (m[j, 6 + c] + m[j, 9 + c] * dx + m[j, 12 + c] * dy)
+            np.testing.assert_allclose(yr[..., c].ravel(), ref, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(D.ravel(), e, rtol=1e-12)
+
+
+def test_rbf_superposition_and_numerator():
+    """Eq. (1) is additive over kernels (a model's render is the sum of its halves' renders,
+    truncated or not) and equals the gated mode's numerator y_smoe D."""
+    W, H = 45, 38
+    m = wl.random_model(80, 3, 1, W, H, seed=71, sig_lo=0.7, sig_hi=8.0).astype(np.float64)
+    for trunc in (True, False):
+        y, _ = oracle.render(m, 3, 1, W, H, truncated=trunc, rbf=True)
+        ya, _ = oracle.render(m[:37], 3, 1, W, H, truncated=trunc, rbf=True)
+        yb, _ = oracle.render(m[37:], 3, 1, W, H, truncated=trunc, rbf=True)
+        np.testing.assert_allclose(y, ya + yb, rtol=1e-12, atol=1e-14)
+        ys, Ds = oracle.render(m, 3, 1, W, H, truncated=trunc)
+        np.testing.assert_allclose(y, ys * Ds[..., None], rtol=1e-12, atol=1e-14)
+
+
+def test_rbf_gradient_central_differences():
+    """Analytic gradient of the MSE of the RBF sum against FP64 central differences (h = 1e-6)
+    on the 32x32 crop with K = 16 linear experts."""
+    tgt, raw = wl.fd_crop_case(seed=11)
+    H, W, C = tgt.shape
+    raw = raw.astype(np.float64)
+    model = oracle.materialize(raw, 3, 1)
+    _fd_guard(model, W, H)
+    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt, rbf=True)
+    h = 1e-6
+    fd = np.zeros_like(g)
+    for j in range(raw.shape[0]):
+        for k in range(raw.shape[1]):
+            rp = raw.copy(); rp[j, k] += h
+            rm = raw.copy(); rm[j, k] -= h
+            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt, rbf=True)
+            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt, rbf=True)
+            fd[j, k] = (lp - lm) / (2 * h)
+    groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
+              "wx": [9, 10, 11], "wy": [12, 13, 14]}
+    for name, cols in groups.items():
+        ref = fd[:, cols]
+        err = np.max(np.abs(g[:, cols] - ref)) / np.max(np.abs(ref))
+        assert err < 2e-5, (name, err)
+        assert np.max(np.abs(ref)) > 0
+
+
+def test_rbf_rho_gradient_closed_form():
+    """Constant experts in Eq. (1): y = sum_j pi_j a_j K_j, so dL/drho_j = sum_c a_jc dL/da_jc
+    (pi and a enter as a product); the gated mode has no such identity."""
+    W, H = 40, 36
+    m = wl.random_model(60, 3, 0, W, H, seed=72, sig_lo=1.0, sig_hi=6.0).astype(np.float64)
+    t = np.random.default_rng(4).uniform(0, 1, (H, W, 3))
+    _, g = oracle.loss_grad(m, 3, 0, W, H, target=t, rbf=True)
+    ref = (m[:, 6:9] * g[:, 6:9]).sum(axis=1)
+    np.testing.assert_allclose(g[:, 5], ref, rtol=1e-10, atol=1e-14 * np.abs(ref).max())
+    _, gs = oracle.loss_grad(m, 3, 0, W, H, target=t)
+    assert not np.allclose(gs[:, 5], (m[:, 6:9] * gs[:, 6:9]).sum(axis=1), rtol=1e-3)
