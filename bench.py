@@ -37,8 +37,8 @@ WORKLOAD = "fit-2048x2048-rgb-K65536-linear-denoise"
 # Algorithmic FP32 work per (pixel, kernel) pair, in VALU operations (one add, mul, fma,
 # compare or exp each), C = 3 linear experts:
 #   tested pair (the truncation test):  dx, dy, z1, l21*z1, w, z2, z1^2, z2^2, q, compare = 10
-#   forward, participating pair: exponent fma, exp, D add, 6 fma expert, 3 fma numerators = 12
-#   backward, participating pair: exponent fma, exp, w, 6 expert fma, 3 G fma, 3 g*w,
+#   forward, every tested pair: exponent fma, exp, D add, 6 fma expert, 3 fma numerators = 12
+#   backward, pair inside the ellipse: exponent fma, exp, w, 6 expert fma, 3 G fma, 3 g*w,
 #     H, bz2, 2 bz1, 2 chain fma, 6 slope-chain fma, 6 slope products, s1, 2 l21, s2,
 #     15 accumulations = 52
 OPS_TESTED = 10
@@ -229,8 +229,10 @@ def run(args):
     T = smoe.tiles(W, H)
 
     dom_avg_s = float(np.mean(dom_ms)) * 1e-3
-    # the fused kernel tests every pair twice (forward, then the recomputing backward)
-    ops = tested * 2 * OPS_TESTED + active * (OPS_ACTIVE_FWD + OPS_ACTIVE_BWD)
+    # the fused kernel tests every pair twice (forward, then the recomputing backward); the
+    # forward accumulates every tested pair (the block lists decide the render, Sec. IV-B),
+    # the backward only the pairs inside the ellipse
+    ops = tested * (2 * OPS_TESTED + OPS_ACTIVE_FWD) + active * OPS_ACTIVE_BWD
     achieved = ops / dom_avg_s
     roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dominant], "achieved": achieved / 1e12,
                 "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (FP32 VALU lane-ops)",
@@ -254,7 +256,8 @@ def run(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "image": f"{W}x{H}x{C}", "K": st.K, "experts": "linear",
-                   "tile": 16, "radius": 3.0, "fit_steps_before_timing": args.warmup},
+                   "tile": 16, "radius": 3.0, "fit_steps_before_timing": args.warmup,
+                   "truncation": "block lists in the render, ellipse in the gradient"},
         "roofline": roofline,
         "stages_ms": stage_avg,
         "pairs": {"P_init": P0, "P": P, "mean_list": P / T, "longest_list": status[2], "tested": tested,
@@ -274,6 +277,8 @@ def run(args):
         out["mm_denoise"] = run_mm_denoise(args)
     if not args.no_tight:
         out["tight_box"] = run_tight_box(args)
+    if not args.no_rbf:
+        out["rbf_vs_smoe"] = run_rbf_vs_smoe(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -410,7 +415,9 @@ def run_tight_box(args):
     fitted for --tight-fit-steps iterations (square boxes; the paper's 10000 by default),
     then, from that model, for each box: its (block, kernel) pairs, the time of one binning +
     render of the 2048^2 image, and fit iterations/s over --tight-steps graphed steps from
-    the same state.  Images are the same with either box (bit for bit)."""
+    the same state.  With the ellipse test in the render the images are the same with either
+    box, bit for bit (checked); with the block lists deciding the render (the default) the
+    tight box drops far tails, and the largest pixel difference is reported."""
     import numpy as np
     import torch
 
@@ -429,11 +436,16 @@ def run_tight_box(args):
         raise RuntimeError("pair capacity overflow in the tight-box fit")
     raw = st.raw.clone()
     model = st.model.clone()
+    psnr_fit = smoe.psnr(st.image, torch.from_numpy(w.clean).cuda())
     del st
-    out = {"workload": WORKLOAD, "fit_steps_before": n_fit, "timed_fit_steps": n_time}
+    out = {"workload": WORKLOAD, "fit_steps_before": n_fit, "timed_fit_steps": n_time,
+           "psnr_vs_clean_after_fit_db": psnr_fit}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     imgs = {}
     for box in ("square", "tight"):
+        # images with the ellipse test in the render, where the tight box is exact
+        img_r, _, _, _ = smoe.render(model, C, 1, smoe.make_grid(W, H, box=box, trunc="render"))
+        imgs[box + "_render"] = img_r
         grid = smoe.make_grid(W, H, box=box)
         bins = smoe.bin(model, C, 1, grid)
         _, stt = bins.read_status()
@@ -469,10 +481,55 @@ def run_tight_box(args):
             raise RuntimeError("pair capacity overflow in the tight-box fit")
         out[f"fit_iters_per_s_{box}"] = 50 * (n_time // 50) / dt
         del f, g, bins
-    out["images_equal"] = bool(torch.equal(imgs["square"], imgs["tight"]))
+    out["images_equal_ellipse_in_render"] = bool(torch.equal(imgs["square_render"],
+                                                             imgs["tight_render"]))
+    out["image_max_abs_diff_default_reading"] = float((imgs["square"] - imgs["tight"]).abs().max())
     out["pair_ratio"] = out["pairs_tight"] / max(1, out["pairs_square"])
     out["render_speedup"] = out["render_ms_square"] / out["render_ms_tight"]
     out["fit_speedup"] = out["fit_iters_per_s_tight"] / out["fit_iters_per_s_square"]
+    return out
+
+
+def run_rbf_vs_smoe(args):
+    """The RBF-vs-SMoE contrast of Fig. 2 and Table I, on synthetic step edges: a 512^2 RGB
+    piecewise-constant image (12 random lines), clean and with Gaussian noise of std 0.05.
+    Gated SMoE (Eq. 2-4) and RBF (Eq. 1) models with the same constant-expert kernels on a
+    regular grid (K = 256, 1024 and 4096, sigma = half the spacing; the RBF weights start at the
+    grid's kernel density so that both start from the same image scale), the same Adam
+    settings (the paper's training protocol, Sec. VI-B: 10 000 iterations by default),
+    --rbf-steps iterations each; PSNR of the fit against the clean image."""
+    import numpy as np
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    side, steps = 512, args.rbf_steps
+    clean = wl.step_edge_image(seed=31, H=side, W=side, C=3, n_lines=12)
+    noisy = wl.step_edge_image(seed=31, H=side, W=side, C=3, n_lines=12, noise_std=0.05)
+    c = torch.from_numpy(clean).cuda()
+    out = {"image": f"{side}x{side}x3 step edges", "steps": steps, "experts": "constant",
+           "runs": []}
+    for g in (16, 32, 64):
+        spacing = side / g
+        sigma = spacing / 2
+        for name, img in (("clean", clean), ("noisy", noisy)):
+            t = torch.from_numpy(img).cuda()
+            row = {"K": g * g, "target": name, "psnr_target_db": smoe.psnr(t, c)}
+            for mode in ("smoe", "rbf"):
+                raw, _ = wl.grid_init(img, g, g, sigma=sigma, order=0)
+                if mode == "rbf":
+                    raw[:, 5] = np.float32(math.log(spacing * spacing / (2 * math.pi * sigma ** 2)))
+                st = smoe.FitState(t, torch.from_numpy(raw).cuda(), 0,
+                                   smoe.AdamConfig(total_steps=steps), max_steps=1, mode=mode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st.run_graphed(steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                row[f"psnr_{mode}_db"] = smoe.psnr(st.image, c)
+                row[f"iters_per_s_{mode}"] = steps / dt
+            out["runs"].append(row)
     return out
 
 
@@ -704,6 +761,8 @@ def main():
     ap.add_argument("--no-tight", action="store_true", help="skip the square/tight box run")
     ap.add_argument("--tight-fit-steps", type=int, default=10000)
     ap.add_argument("--tight-steps", type=int, default=1000)
+    ap.add_argument("--no-rbf", action="store_true", help="skip the RBF vs SMoE run")
+    ap.add_argument("--rbf-steps", type=int, default=10000)
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()

@@ -90,7 +90,23 @@ typedef struct smoe_grid {
                                   reject f != 1 */
   int32_t box;                 /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT (below) */
   int32_t mode;                /* SMOE_MODE_SMOE or SMOE_MODE_RBF (below) */
+  int32_t trunc;               /* SMOE_TRUNC_GRADIENT (0) or SMOE_TRUNC_RENDER (below) */
 } smoe_grid;
+
+/* Where the ellipse test of the truncation rule applies (Sec. IV-B).
+ * SMOE_TRUNC_GRADIENT (the default): the render takes every kernel whose box covers the
+ * pixel's block (the block lists), up to q <= (2r)^2 (the same binary32 sequence as the
+ * ellipse test with twice the radius: terms beyond are below e^(-2 r^2) of the kernel's
+ * peak, and FP32 exp would lose them to underflow and rounding); pixels outside a kernel's
+ * ellipse q <= r^2 are dropped from the gradient only, which is then the sum of the
+ * in-ellipse (pixel, kernel) pairs' terms of the rendered loss's gradient, with the
+ * render's y and D.
+ * SMOE_TRUNC_RENDER: a kernel takes part at a pixel iff its box covers the pixel's block
+ * and q <= r^2, in the render and in the gradient (the gradient is that of the rendered
+ * loss).  Pixels that every ellipse has left render 0 and get no gradient, so a long fit
+ * can strand them.  Any other value is rejected. */
+#define SMOE_TRUNC_GRADIENT 0
+#define SMOE_TRUNC_RENDER 1
 
 /* Regression modes.  SMOE_MODE_SMOE: the gated regression of Eq. (2)-(4),
  * y_c = sum_j m_jc(x) pi_j K_j(x) / D with D = sum_i pi_i K_i(x) (y = 0 where D = 0).
@@ -151,6 +167,7 @@ typedef struct smoe_batch {
   float radius;                       /* Mahalanobis truncation radius */
   int32_t box;                        /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT */
   int32_t mode;                       /* SMOE_MODE_SMOE or SMOE_MODE_RBF */
+  int32_t trunc;                      /* SMOE_TRUNC_GRADIENT or SMOE_TRUNC_RENDER */
 } smoe_batch;
 
 /* Binning workspace: the block lists of Sec. IV-C and the scratch of the backward.
@@ -271,7 +288,7 @@ typedef struct smoe_fit_state {
    * MSEs, so every image's gradient is its own).  Segments laid out by
    * smoe_segments_layout with scale 1, origin 0 and param_offset == kernel_offset; target,
    * image and denom are the concatenated images; K = total kernels; of `grid` only the radius,
-   * the box and the mode are used. */
+   * the box, the mode and the truncation are used. */
   int32_t num_segments;
   const smoe_segment* segments;       /* device copy, or NULL for one image */
   const smoe_segment* segments_host;  /* host copy, or NULL */

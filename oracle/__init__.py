@@ -62,9 +62,9 @@ def lib():
         L.oracle_num_params.restype = I
         L.oracle_bin.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, i32p, i32p, i32p, I64, u32p, u32p, i32p]
         L.oracle_bin.restype = I64
-        L.oracle_render.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, I, I64, i32p, dp, dp, I]
+        L.oracle_render.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, I, I, I64, i32p, dp, dp, I]
         L.oracle_render.restype = None
-        L.oracle_loss_grad.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, dp, dp, I, i32p, dp, I]
+        L.oracle_loss_grad.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, I, dp, dp, I, i32p, dp, I]
         L.oracle_loss_grad.restype = D
         L.oracle_materialize.argtypes = [I, I, I, dp, dp]
         L.oracle_materialize.restype = None
@@ -72,7 +72,7 @@ def lib():
         L.oracle_step_lrs.restype = None
         L.oracle_adam.argtypes = [I, I, I, dp, dp, dp, dp, I, dp, D, D, D]
         L.oracle_adam.restype = None
-        L.oracle_fit.argtypes = [I, I, I, dp, I, I, F, I, I, dp, I, I, D, D, D, D, D, D, D, D, dp, dp, I]
+        L.oracle_fit.argtypes = [I, I, I, dp, I, I, F, I, I, I, dp, I, I, D, D, D, D, D, D, D, D, dp, dp, I]
         L.oracle_fit.restype = None
         _lib = L
     return _lib
@@ -91,6 +91,10 @@ def _d(a):
 
 def _ptr(a, t):
     return None if a is None else a.ctypes.data_as(ct.POINTER(t))
+
+
+def _trunc(trunc) -> int:
+    return {"render": 0, "gradient": 1}[trunc]
 
 
 def num_params(C: int, order: int) -> int:
@@ -130,29 +134,32 @@ def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0):
 
 
 def render(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, truncated=True, pixels=None,
-           threads=None, box=0, rbf=False):
+           threads=None, box=0, rbf=False, trunc="gradient"):
     """y [H, W, C] and D [H, W] (or [n, C], [n] at the listed (u, v) pixels).  rbf: the
-    weighted sum of kernels of Eq. (1) instead of the gated regression of Eq. (2)-(4)."""
+    weighted sum of kernels of Eq. (1) instead of the gated regression of Eq. (2)-(4).
+    trunc: "gradient" (the render takes every kernel of the block's list; the ellipse test
+    applies to gradients only -- Sec. IV-B) or "render" (the ellipse test applies to the
+    render as well)."""
     model, K = _KC(model, C, order)
     threads = threads or default_threads()
     if pixels is None:
         y = np.zeros((H, W, C), np.float64)
         D = np.zeros((H, W), np.float64)
         lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box, int(rbf),
-                            int(truncated), 0, None, _ptr(y, ct.c_double), _ptr(D, ct.c_double),
+                            _trunc(trunc), int(truncated), 0, None, _ptr(y, ct.c_double), _ptr(D, ct.c_double),
                             threads)
     else:
         pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
         y = np.zeros((pix.shape[0], C), np.float64)
         D = np.zeros(pix.shape[0], np.float64)
         lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box, int(rbf),
-                            int(truncated), pix.shape[0], _ptr(pix, ct.c_int32),
+                            _trunc(trunc), int(truncated), pix.shape[0], _ptr(pix, ct.c_int32),
                             _ptr(y, ct.c_double), _ptr(D, ct.c_double), threads)
     return y, D
 
 
 def loss_grad(model, C, order, W, H, target=None, grad_y=None, kernels=None, s=1, ox=0, oy=0,
-              r=3.0, threads=None, box=0, rbf=False):
+              r=3.0, threads=None, box=0, rbf=False, trunc="gradient"):
     """(loss, grads [K or len(kernels), NP]) in raw-parameter order."""
     model, K = _KC(model, C, order)
     NP = model.shape[1]
@@ -163,7 +170,7 @@ def loss_grad(model, C, order, W, H, target=None, grad_y=None, kernels=None, s=1
     nout = K if sel is None else sel.shape[0]
     g = np.zeros((nout, NP), np.float64)
     loss = lib().oracle_loss_grad(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box, int(rbf),
-                                  _ptr(t, ct.c_double), _ptr(gy, ct.c_double),
+                                  _trunc(trunc), _ptr(t, ct.c_double), _ptr(gy, ct.c_double),
                                   0 if sel is None else sel.shape[0], _ptr(sel, ct.c_int32),
                                   _ptr(g, ct.c_double), threads or default_threads())
     return float(loss), g
@@ -212,14 +219,15 @@ def adam(p, g, m, v, t, lrs4, C, order, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def fit(raw0, C, order, target, steps, total_steps=None, lr_mu=1e-2, lr_mu_final=None,
         lr_chol=1e-2, lr_rho=1e-2, lr_expert=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, r=3.0,
-        threads=None, box=0, rbf=False):
+        threads=None, box=0, rbf=False, trunc="gradient"):
     """FP64 fit.  Returns (loss history [steps], final raw params [K, NP])."""
     raw0, K = _KC(raw0, C, order)
     t = _d(target)
     H, W = t.shape[:2]
     hist = np.zeros(steps, np.float64)
     out = np.zeros_like(raw0)
-    lib().oracle_fit(K, C, order, _ptr(raw0, ct.c_double), W, H, r, box, int(rbf), _ptr(t, ct.c_double),
+    lib().oracle_fit(K, C, order, _ptr(raw0, ct.c_double), W, H, r, box, int(rbf), _trunc(trunc),
+                     _ptr(t, ct.c_double),
                      steps,
                      total_steps or steps, lr_mu, lr_mu if lr_mu_final is None else lr_mu_final,
                      lr_chol, lr_rho, lr_expert, beta1, beta2, eps, _ptr(hist, ct.c_double),

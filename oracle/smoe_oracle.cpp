@@ -13,19 +13,29 @@
 //   * Soft gates, Eq. (4): w_j = pi_j K_j / sum_i pi_i K_i, with pi_j = exp(rho_j).
 //   * SMoE regression, Eq. (3): y(x) = sum_j m_j(x) w_j(x); experts are constant
 //     m_j = a_j (Sec. II-A) or linear ("steered") m_j(x) = a_j + W_j (x - mu_j).
-//   * Rasterized truncation, Eq. (5) with the discard rule of Sec. IV-B: kernel j takes
-//     part at pixel x iff the 16x16 block holding x is covered by j's square bounding box
-//     (side = major axis of its confidence ellipse, Fig. 3b) AND x lies inside the
-//     ellipse q_j(x) <= r^2.  Both conjuncts are discrete decisions and are evaluated
-//     in exactly specified IEEE binary32 arithmetic (this file is built with
-//     -ffp-contract=off), the same precision as the GPU kernels, so that both take the
-//     same decisions.  Every continuous quantity (exp, sums, y, gradients) is FP64.
+//   * Rasterized truncation, Eq. (5) with the discard rule of Sec. IV-B.  A kernel's 16x16
+//     blocks are those its square bounding box covers (side = major axis of its confidence
+//     ellipse, Fig. 3b); pixels of those blocks outside the ellipse q_j(x) <= r^2 are
+//     discarded in the gradient.  Two readings (trunc): 1 = as the section states, the
+//     render takes every kernel of the block's list and the ellipse test only removes
+//     (pixel, kernel) pairs from the gradient, which is then the sum of the in-ellipse
+//     pairs' terms of the rendered loss's gradient (with the render's D and y) -- the
+//     render stops at q <= (2r)^2, binary32 like the ellipse test (terms beyond are below
+//     e^(-2 r^2) of the kernel's peak, where FP32 exp underflows or loses accuracy); 0 = the
+//     ellipse test applies to the render too (kernel j takes part at x iff its box covers
+//     x's block AND q_j(x) <= r^2), so the gradient is exactly the rendered loss's.  Both
+//     conjuncts are discrete decisions evaluated in exactly specified IEEE binary32
+//     arithmetic (this file is built with -ffp-contract=off), the same precision as the GPU
+//     kernels, so that both take the same decisions.  Every continuous quantity (exp, sums,
+//     y, gradients) is FP64.
 //   * Optionally (box = 1) a tight axis-aligned box instead of the square one: half-widths
 //     r sqrt(Sigma_xx) and r sqrt(Sigma_yy), the extents of the r-ellipse along x and y,
 //     each widened by a small margin that covers the rounding of the binary32 ellipse test
 //     and capped at the square box.  Every pixel the ellipse test accepts inside the square
-//     box lies inside the widened tight box, so the model's values are unchanged; only
-//     blocks that the ellipse cannot reach leave the lists.
+//     box lies inside the widened tight box, so with the ellipse test in the render the
+//     model's values are unchanged; only blocks that the ellipse cannot reach leave the
+//     lists.  (When the block lists alone decide the render, the tight box drops far tails
+//     from it.)
 //   * Optionally (rbf = 1) the weighted sum of kernels of Eq. (1) (RBF networks, Gaussian
 //     splatting) instead of the gates: y(x) = sum_j pi_j m_j(x) K_j(x), the kernel weight of
 //     Eq. (1) being pi_j m_j(x); no normalisation.  Same kernels, truncation and parameters.
@@ -69,6 +79,7 @@ struct Grid {
   float r;      // Mahalanobis truncation radius
   int box;      // 0: square box of Sec. IV-B; 1: tight axis-aligned box
   int rbf;      // 0: gated SMoE regression, Eq. (2)-(4); 1: weighted sum of kernels, Eq. (1)
+  int trunc;    // 1: the ellipse test applies to the gradient only; 0: render and gradient
   int ntx() const { return (W + 15) / 16; }
   int nty() const { return (H + 15) / 16; }
 };
@@ -218,11 +229,13 @@ void eval_pixel(const Model& M, const Grid& g, bool truncated, int u, int v, dou
   const float x32 = coord32(u, g.ox, g.s);
   const float y32 = coord32(v, g.oy, g.s);
   const float r2 = g.r * g.r;
+  const float r_twice = 2.0f * g.r;
+  const float r2_render = r_twice * r_twice;
   const double x = (double)x32, yy = (double)y32;
   double Dsum = 0.0;
   std::vector<double> N(M.C, 0.0);
   for (int j = 0; j < M.K; ++j) {
-    if (truncated && !M.participates(j, u, v, x32, y32, r2)) continue;
+    if (truncated && !M.participates(j, u, v, x32, y32, g.trunc == 1 ? r2_render : r2)) continue;
     const double* r = M.p + (size_t)j * M.NP;
     const Term t = term(r, x, yy);
     Dsum += t.e;
@@ -354,11 +367,11 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
 // Renders y [npix][C] and D [npix] at the listed output pixels (pix [npix][2] = (u, v));
 // pix == NULL renders the whole raster in row-major order (npix ignored).
 void oracle_render(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                   int oy, float r, int box, int rbf, int truncated, int64_t npix,
+                   int oy, float r, int box, int rbf, int trunc, int truncated, int64_t npix,
                    const int32_t* pix,
                    double* y,
                    double* D, int threads) {
-  const Grid g{W, H, s, ox, oy, r, box, rbf};
+  const Grid g{W, H, s, ox, oy, r, box, rbf, trunc};
   const Model M(K, C, order, model, g);
   const int64_t n = pix ? npix : (int64_t)W * H;
   parallel_for(n, threads, [&](int64_t i, int) {
@@ -377,11 +390,11 @@ void oracle_render(int K, int C, int order, const double* model, int W, int H, i
 //   grads [nsel or K][NP] raw-parameter order, overwritten.
 // Returns the loss (NaN in grad_y mode or with a kernel subset).
 double oracle_loss_grad(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                        int oy, float r, int box, int rbf, const double* target,
+                        int oy, float r, int box, int rbf, int trunc, const double* target,
                         const double* grad_y,
                         int nsel,
                         const int32_t* sel, double* grads, int threads) {
-  const Grid g{W, H, s, ox, oy, r, box, rbf};
+  const Grid g{W, H, s, ox, oy, r, box, rbf, trunc};
   const Model M(K, C, order, model, g);
   const int NP = M.NP;
   const int nout = sel ? nsel : K;
@@ -485,7 +498,7 @@ void oracle_adam(int K, int C, int order, double* p, const double* g, double* m,
 // Full fit: `steps` iterations of materialize -> loss/gradient -> Adam, from raw0.
 // Writes the loss before each update into loss_hist [steps] and the final raw params.
 void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float r, int box,
-                int rbf,
+                int rbf, int trunc,
                 const double* target, int steps, int total_steps, double lr_mu,
                 double lr_mu_final, double lr_chol, double lr_rho, double lr_expert,
                 double beta1, double beta2, double eps, double* loss_hist, double* raw_out,
@@ -496,7 +509,7 @@ void oracle_fit(int K, int C, int order, const double* raw0, int W, int H, float
   double lrs[4];
   for (int it = 0; it < steps; ++it) {
     oracle_materialize(K, C, order, raw.data(), model.data());
-    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, box, rbf, target,
+    loss_hist[it] = oracle_loss_grad(K, C, order, model.data(), W, H, 1, 0, 0, r, box, rbf, trunc, target,
                                      nullptr,
                                      0, nullptr, g.data(), threads);
     oracle_step_lrs(it, total_steps, lr_mu, lr_mu_final, lr_chol, lr_rho, lr_expert, lrs);

@@ -28,6 +28,8 @@ SMOE_BOX_SQUARE = 0
 SMOE_BOX_TIGHT = 1
 SMOE_MODE_SMOE = 0
 SMOE_MODE_RBF = 1
+SMOE_TRUNC_GRADIENT = 0
+SMOE_TRUNC_RENDER = 1
 TILE = 16
 
 _i32, _f32, _vp, _sz = ct.c_int32, ct.c_float, ct.c_void_p, ct.c_size_t
@@ -40,7 +42,7 @@ class SmoeModel(ct.Structure):
 class SmoeGrid(ct.Structure):
     _fields_ = [("width", _i32), ("height", _i32), ("scale", _i32), ("origin_x", _i32),
                 ("origin_y", _i32), ("radius", _f32), ("sharpen", _f32),
-                ("box", _i32), ("mode", _i32)]
+                ("box", _i32), ("mode", _i32), ("trunc", _i32)]
 
 
 class SmoeSegment(ct.Structure):
@@ -53,7 +55,7 @@ class SmoeSegment(ct.Structure):
 class SmoeBatch(ct.Structure):
     _fields_ = [("C", _i32), ("order", _i32), ("params", _vp), ("num_params_rows", _i32),
                 ("num_segments", _i32), ("segments", _vp), ("segments_host", _vp),
-                ("radius", _f32), ("box", _i32), ("mode", _i32)]
+                ("radius", _f32), ("box", _i32), ("mode", _i32), ("trunc", _i32)]
 
 
 class SmoeBins(ct.Structure):

@@ -45,15 +45,28 @@ def _mode(mode) -> int:
     return m
 
 
+TRUNCS = {"render": C.SMOE_TRUNC_RENDER, "gradient": C.SMOE_TRUNC_GRADIENT}
+
+
+def _trunc(trunc) -> int:
+    t = TRUNCS.get(trunc, trunc)
+    if t not in TRUNCS.values():
+        raise ValueError(f"trunc must be one of {sorted(TRUNCS)}")
+    return t
+
+
 def make_grid(width, height, scale=1, origin_x=0, origin_y=0, radius=3.0,
-              sharpen=1.0, box="square", mode="smoe") -> C.SmoeGrid:
+              sharpen=1.0, box="square", mode="smoe", trunc="gradient") -> C.SmoeGrid:
     """Output raster; sharpen = f renders every kernel with its bandwidth divided by f
     (native sharpening by kernel editing, Sec. II-B), 1 = none.  box: "square" (the
     square box of Sec. IV-B) or "tight" (the ellipse's axis-aligned extents: the same
     image from shorter block lists).  mode: "smoe" (the gated regression, Eq. 2-4) or
-    "rbf" (the un-normalised weighted sum of kernels, Eq. 1)."""
+    "rbf" (the un-normalised weighted sum of kernels, Eq. 1).  trunc: where the ellipse test
+    applies -- "gradient" (the render takes every kernel of the block list; out-of-ellipse
+    pixels are discarded in the gradient only, Sec. IV-B) or "render" (render and
+    gradient)."""
     return C.SmoeGrid(int(width), int(height), int(scale), int(origin_x), int(origin_y),
-                      float(radius), float(sharpen), _box(box), _mode(mode))
+                      float(radius), float(sharpen), _box(box), _mode(mode), _trunc(trunc))
 
 
 def _stream(stream=None) -> int:
@@ -227,12 +240,13 @@ class Segments:
 
 def bin_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, radius: float = 3.0,
                 bins: Bins | None = None, capacity: int | None = None, stream=None,
-                grow: bool = True, box="square", mode="smoe") -> Bins:
+                grow: bool = True, box="square", mode="smoe", trunc="gradient") -> Bins:
     """smoe_bin_batched over every segment; with grow=True the workspace is re-made until the
     pairs fit (host sync)."""
     _check_params(params, C_, order)
     batch = C.SmoeBatch(C_, order, params.data_ptr(), params.shape[0], segs.n, segs.dev.data_ptr(),
-                        ct.addressof(segs.host), float(radius), _box(box), _mode(mode))
+                        ct.addressof(segs.host), float(radius), _box(box), _mode(mode),
+                        _trunc(trunc))
     if bins is None:
         bins = Bins(segs.K, C_, order, segs.T, capacity or initial_capacity(segs.K, segs.T),
                     params.device)
@@ -248,11 +262,12 @@ def bin_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, radiu
 
 def render_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, bins: Bins,
                    images: torch.Tensor, denoms: torch.Tensor | None = None, radius: float = 3.0,
-                   stream=None, box="square", mode="smoe"):
+                   stream=None, box="square", mode="smoe", trunc="gradient"):
     """smoe_render_batched into the concatenated images [total pixels, C]."""
     _check_params(params, C_, order)
     batch = C.SmoeBatch(C_, order, params.data_ptr(), params.shape[0], segs.n, segs.dev.data_ptr(),
-                        ct.addressof(segs.host), float(radius), _box(box), _mode(mode))
+                        ct.addressof(segs.host), float(radius), _box(box), _mode(mode),
+                        _trunc(trunc))
     C.smoe_render_batched(batch, bins.c, images.data_ptr(), _ptr(denoms), _stream(stream))
     return images
 
@@ -289,7 +304,7 @@ class FitState:
 
     def __init__(self, target, raw0, order: int, adam: AdamConfig, max_steps: int = 0,
                  capacity: int | None = None, radius: float = 3.0, box="square",
-                 mode="smoe"):
+                 mode="smoe", trunc="gradient"):
         batched = isinstance(target, (list, tuple))
         targets = list(target) if batched else [target]
         raws = list(raw0) if batched else [raw0]
@@ -333,8 +348,8 @@ class FitState:
         self.step_counter = torch.zeros(1, dtype=torch.int32, device=dev)
         self.scalars = torch.zeros(4, dtype=torch.float32, device=dev)
         H0, W0 = self.shapes[0]
-        self.grid = make_grid(W0, H0, 1, 0, 0, radius, box=box, mode=mode)
-        self.box, self.mode = box, mode
+        self.grid = make_grid(W0, H0, 1, 0, 0, radius, box=box, mode=mode, trunc=trunc)
+        self.box, self.mode, self.trunc = box, mode, trunc
         self.adam = adam
         if capacity is None:
             if batched:

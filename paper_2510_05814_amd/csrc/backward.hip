@@ -94,7 +94,7 @@ hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
                            const float* target, hipStream_t s) {
   BackwardArgs a{S,     C,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals,
                  image, denom, grad_image, target, b.pair_grads};
-  with_shape(C, order, S.mode, [&](auto sh) {
+  with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_backward<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
   });

@@ -35,6 +35,14 @@ bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f))
 bool no_sharpen(float f) { return f == 0.0f || f == 1.0f; }
 bool valid_box(int32_t b) { return b == SMOE_BOX_SQUARE || b == SMOE_BOX_TIGHT; }
 bool valid_mode(int32_t m) { return m == SMOE_MODE_SMOE || m == SMOE_MODE_RBF; }
+bool valid_trunc(int32_t t) { return t == SMOE_TRUNC_RENDER || t == SMOE_TRUNC_GRADIENT; }
+
+// The render's bound on q (binary32): the ellipse r^2 when the ellipse test applies to the
+// render; (2r)^2 when the block lists decide it.
+float render_bound(float r, int32_t trunc) {
+  const float r2r = 2.0f * r;
+  return trunc == SMOE_TRUNC_RENDER ? r * r : r2r * r2r;
+}
 
 long long raster_tiles(int32_t W, int32_t H) {
   return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
@@ -45,7 +53,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   if (!valid_model(m) || !g ||
       !valid_raster(g->width, g->height, g->scale, g->origin_x, g->origin_y) ||
       !valid_radius(g->radius) || !valid_sharpen(g->sharpen) || !valid_box(g->box) ||
-      !valid_mode(g->mode))
+      !valid_mode(g->mode) || !valid_trunc(g->trunc))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -61,6 +69,8 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   S.r2 = g->radius * g->radius;
   S.box = g->box;
   S.mode = g->mode;
+  S.trunc = g->trunc;
+  S.r2_render = render_bound(S.r, S.trunc);
   S.T = (int)raster_tiles(g->width, g->height);
   S.K = m->K;
   *out = S;
@@ -93,7 +103,7 @@ bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int*
 bool batch_segs(const smoe_batch* b, Segs* out) {
   if (!b || !valid_shape(0, b->C, b->order) || !b->params || !b->segments ||
       b->num_params_rows < 0 || !valid_radius(b->radius) || !valid_box(b->box) ||
-      !valid_mode(b->mode))
+      !valid_mode(b->mode) || !valid_trunc(b->trunc))
     return false;
   Segs S;
   std::memset(&S, 0, sizeof(S));
@@ -105,6 +115,8 @@ bool batch_segs(const smoe_batch* b, Segs* out) {
   S.r2 = b->radius * b->radius;
   S.box = b->box;
   S.mode = b->mode;
+  S.trunc = b->trunc;
+  S.r2_render = render_bound(S.r, S.trunc);
   *out = S;
   return true;
 }
@@ -160,7 +172,7 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 bool fit_segs(const smoe_fit_state* st, Segs* S) {
   if (st->num_segments > 0) {
     if (!st->segments || !st->segments_host || !valid_radius(st->grid.radius) ||
-        !valid_box(st->grid.box) || !valid_mode(st->grid.mode))
+        !valid_box(st->grid.box) || !valid_mode(st->grid.mode) || !valid_trunc(st->grid.trunc))
       return false;
     std::memset(S, 0, sizeof(*S));
     if (!check_segments(st->segments_host, st->num_segments, st->K, &S->T, &S->K)) return false;
@@ -177,6 +189,8 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
     S->r2 = st->grid.radius * st->grid.radius;
     S->box = st->grid.box;
     S->mode = st->grid.mode;
+    S->trunc = st->grid.trunc;
+    S->r2_render = render_bound(S->r, S->trunc);
     return true;
   }
   const smoe_model m{st->K, st->C, st->order, st->model};

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live = 0;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, D, N, live);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, rg, srec, D, N, live);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -282,7 +282,7 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
                 b.vals,   b.vals_alt, b.tile_counts, b.status, width,
                 target,   st.image,  st.denom,
                 b.tile_loss, b.pair_grads};
-  with_shape(st.C, st.order, S.mode, [&](auto sh) {
+  with_shape(st.C, st.order, S, [&](auto sh) {
     using T = decltype(sh);
     k_fit_tile<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
   });

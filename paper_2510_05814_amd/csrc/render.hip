@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, D, N, live);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, a.ranges[tile], srec, D, N, live);
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
@@ -136,7 +136,7 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
                          float* denom, const float* target, hipStream_t s) {
   RenderArgs a{S,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals, image, denom,
                target, target ? b.tile_loss : nullptr};
-  with_shape(C, order, S.mode, [&](auto sh) {
+  with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_render<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
   });

@@ -37,8 +37,10 @@ struct Segs {
   int n;
   smoe_segment one;                      // the single raster when tab is null
   float r, r2;                           // truncation radius and r*r (binary32)
+  float r2_render;                       // the render's bound on q: r2, or (2r)^2
   int box;                               // SMOE_BOX_SQUARE or SMOE_BOX_TIGHT
   int mode;                              // SMOE_MODE_SMOE or SMOE_MODE_RBF
+  int trunc;                             // SMOE_TRUNC_RENDER or SMOE_TRUNC_GRADIENT
   int T;                                 // blocks of all segments
   int K;                                 // kernel rows of all segments
 };

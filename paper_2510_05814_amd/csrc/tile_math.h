@@ -23,8 +23,8 @@ struct Shape {
 
 // Calls f(Shape<...>{}) for the run-time (C, order, mode); C is 1 or 3, order 0 or 1.
 template <class F>
-inline void with_shape(int C, int order, int mode, F&& f) {
-  const bool rbf = mode == SMOE_MODE_RBF;
+inline void with_shape(int C, int order, const Segs& S, F&& f) {
+  const bool rbf = S.mode == SMOE_MODE_RBF;
   if (C == 1 && order == 0) rbf ? f(Shape<1, 0, true>{}) : f(Shape<1, 0, false>{});
   else if (C == 1 && order == 1) rbf ? f(Shape<1, 1, true>{}) : f(Shape<1, 1, false>{});
   else if (C == 3 && order == 0) rbf ? f(Shape<3, 0, true>{}) : f(Shape<3, 0, false>{});
@@ -68,11 +68,14 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
 }
 
 // Forward accumulation over a block's list [rg.x, rg.y) in list order:
-// D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers).
-// live: bit k set if any pixel of the block passed the truncation test for entry k of the
-// last staged chunk (the only chunk for lists of up to kChunk entries).
+// D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers), over the
+// pairs with q <= r2_render: r^2 (the ellipse test in the render) or (2r)^2 (the block lists
+// decide the render; the cut keeps every term inside FP32's accurate range).
+// live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
+// the last staged chunk (the only chunk for lists of up to kChunk entries).
 template <int C, int ORDER>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
+                                                   float r2_render,
                                                    const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int2 rg,
                                                    float4* srec, float (&D)[kRows],
@@ -110,7 +113,7 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
         const float z2 = w * r[4];
         const float q = zz1 + z2 * z2;
         hit |= q <= r2;
-        if (q <= r2) {
+        if (q <= r2_render) {
           // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
           D[i] += e;

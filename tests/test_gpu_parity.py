@@ -212,12 +212,15 @@ def test_translation_equivariance_bitwise(smoe):
     W, H = 64, 48
     m_np = wl.random_model(40, 3, 1, W, H, seed=43, margin=-8.0)
     m_np[:, :2] = np.round(m_np[:, :2] * 256) / 256
-    img0, _, _, _ = smoe.render(dev(m_np), 3, 1, smoe.make_grid(W, H))
-    m2 = m_np.copy()
-    m2[:, 0] += 5
-    m2[:, 1] += 3
-    img1, _, _, _ = smoe.render(dev(m2), 3, 1, smoe.make_grid(W + 5, H + 3))
-    assert np.array_equal(host(img1)[3:, 5:], host(img0))
+    # any integer shift with the ellipse test in the render; whole blocks when the block
+    # lists alone decide the render
+    for trunc, (tx, ty) in (("render", (5, 3)), ("gradient", (16, 32))):
+        img0, _, _, _ = smoe.render(dev(m_np), 3, 1, smoe.make_grid(W, H, trunc=trunc))
+        m2 = m_np.copy()
+        m2[:, 0] += tx
+        m2[:, 1] += ty
+        img1, _, _, _ = smoe.render(dev(m2), 3, 1, smoe.make_grid(W + tx, H + ty, trunc=trunc))
+        assert np.array_equal(host(img1)[ty:, tx:], host(img0)), trunc
 
 
 def test_render_and_backward_deterministic(smoe):

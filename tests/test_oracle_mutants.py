@@ -70,6 +70,12 @@ MUTANTS = [
      [pins.test_rbf_single_kernel_closed_form, pins.test_rbf_superposition_and_numerator]),
     ("RBF gradient through the gate", "const double w = g.rbf ? t.e : t.e / D;",
      "const double w = t.e / D;", [pins.test_rbf_gradient_central_differences]),
+    ("render drops out-of-ellipse pairs under the block-list reading",
+     "g.trunc == 1 ? r2_render : r2", "r2",
+     [pins.test_blocklist_render_bruteforce]),
+    ("gradient keeps out-of-ellipse pairs", "if (!M.participates(j, u, v, x32, y32, r2)) continue;",
+     "if (!M.participates(j, u, v, x32, y32, 4.0f * r2)) continue;",
+     [pins.test_gradient_only_ellipse_per_pair_differences]),
     ("block list not in kernel order",
      "for (int j = 0; j < K; ++j) {\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",
      "for (int jj = 0; jj < K; ++jj) {\n    const int j = K - 1 - jj;\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",

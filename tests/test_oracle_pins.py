@@ -69,8 +69,12 @@ def test_hand_computed_single_kernel():
     # pixel (0, 0):  q = (56.25 + 56.25)/16 = 7.03125 -> inside;  r = 2.5 excludes it
     _, D2 = oracle.render(m, 1, 0, 16, 16, pixels=[(14, 8), (8, 0), (0, 0)])
     np.testing.assert_allclose(D2, np.exp(-0.5 * np.array([2.65625, 3.53125, 7.03125])), rtol=1e-15)
-    _, D3 = oracle.render(m, 1, 0, 16, 16, pixels=[(0, 0)], r=2.5)
+    _, D3 = oracle.render(m, 1, 0, 16, 16, pixels=[(0, 0)], r=2.5, trunc="render")
     assert D3[0] == 0.0
+    # with the ellipse in the gradient only, the kernel's box (half-side 10) still covers
+    # block 0, so pixel (0, 0) keeps its term
+    _, D4 = oracle.render(m, 1, 0, 16, 16, pixels=[(0, 0)], r=2.5)
+    assert D4[0] == pytest.approx(math.exp(-0.5 * 7.03125), rel=1e-15)
 
 
 def test_box_half_side_is_r_sqrt_lambda_max():
@@ -130,7 +134,7 @@ def test_truncation_rule_matches_ellipse_and_stays_in_box():
     q = maha_np(m, x, y)
     b = oracle.bin(m, 1, 0, W, H)
     for j in range(m.shape[0]):
-        _, D = oracle.render(m[j:j + 1], 1, 0, W, H)
+        _, D = oracle.render(m[j:j + 1], 1, 0, W, H, trunc="render")
         on = D.ravel() > 0
         band = np.abs(q[j] - R * R) < 1e-5
         assert np.array_equal(on[~band], (q[j] <= R * R)[~band]), j
@@ -299,15 +303,16 @@ def test_tight_box_is_the_ellipse_extent():
 
 
 def test_tight_box_keeps_every_value_and_shortens_lists():
-    """The tight box changes no value (the ellipse test never accepts a pixel outside it) and
+    """With the ellipse test in the render, the tight box changes no value (the test never
+    accepts a pixel outside it) and
     every list is a subset of the square box's list; brute force: every block holding a pixel
     strictly inside the FP64 ellipse is in the kernel's tight rectangle."""
     W, H = 61, 47
     for s, ox, oy, f in [(1, 0, 0, 1.0), (2, 5, 2, 1.0), (3, 0, 7, 1.0), (1, 0, 0, 1.8)]:
         m = oracle.sharpen(aniso_model(90, W, H, seed=50 + s), f)
         OW, OH = s * W - ox, s * H - oy
-        ya, Da = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=0)
-        yb, Db = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=1)
+        ya, Da = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=0, trunc="render")
+        yb, Db = oracle.render(m, 3, 1, OW, OH, s, ox, oy, box=1, trunc="render")
         np.testing.assert_array_equal(ya, yb)
         np.testing.assert_array_equal(Da, Db)
         sq = oracle.bin(m, 3, 1, OW, OH, s, ox, oy, box=0)
@@ -330,14 +335,14 @@ def test_tight_box_keeps_every_value_and_shortens_lists():
 
 
 def test_tight_box_keeps_loss_and_gradient():
-    """The oracle's loss and gradient sum over pixels and participating kernels only, so the
-    tight box gives them bit for bit (one thread: the row-to-thread split of a threaded run,
+    """With the ellipse test in the render, the oracle's loss and gradient sum over pixels and
+    participating kernels only, so the tight box gives them bit for bit (one thread: the row-to-thread split of a threaded run,
     and with it the FP64 rounding, varies from run to run)."""
     W, H = 40, 33
     m = aniso_model(50, W, H, seed=58)
     t = np.random.default_rng(2).uniform(0, 1, (H, W, 3))
-    la, ga = oracle.loss_grad(m, 3, 1, W, H, target=t, box=0, threads=1)
-    lb, gb = oracle.loss_grad(m, 3, 1, W, H, target=t, box=1, threads=1)
+    la, ga = oracle.loss_grad(m, 3, 1, W, H, target=t, box=0, threads=1, trunc="render")
+    lb, gb = oracle.loss_grad(m, 3, 1, W, H, target=t, box=1, threads=1, trunc="render")
     assert la == lb
     np.testing.assert_array_equal(ga, gb)
 
@@ -359,11 +364,12 @@ def test_gates_sum_to_one_all_ones_experts():
     m = wl.random_model(50, 3, 1, W, H, seed=41)
     m[:, 6:9] = 1.0
     m[:, 9:] = 0.0
-    y, D = oracle.render(m, 3, 1, W, H)
-    cov = D > 0
-    assert cov.any() and (~cov).any()
-    np.testing.assert_allclose(y[cov], 1.0, rtol=1e-14)
-    assert np.all(y[~cov] == 0.0)
+    for trunc in ("render", "gradient"):
+        y, D = oracle.render(m, 3, 1, W, H, trunc=trunc)
+        cov = D > 0
+        assert cov.any() and (trunc == "gradient" or (~cov).any())
+        np.testing.assert_allclose(y[cov], 1.0, rtol=1e-14)
+        assert np.all(y[~cov] == 0.0)
 
 
 def test_single_kernel_reproduces_linear_expert():
@@ -389,18 +395,20 @@ def test_equal_constant_experts_render_the_constant():
 
 
 def test_integer_translation_equivariance():
-    """mu on a 2^-8 grid, integer shift t: render(mu + t)[p + t] = render(mu)[p]."""
+    """mu on a 2^-8 grid, integer shift t: render(mu + t)[p + t] = render(mu)[p] -- any shift
+    with the ellipse test in the render; shifts by whole blocks with the block lists alone
+    deciding the render (the rule then depends on the 16 x 16 grid)."""
     W, H = 64, 48
     m = wl.random_model(30, 3, 1, W, H, seed=43, margin=-8.0).astype(np.float64)
     m[:, :2] = np.round(m[:, :2] * 256) / 256
-    y0, D0 = oracle.render(m, 3, 1, W, H)
-    tx, ty = 5, 3
-    m2 = m.copy()
-    m2[:, 0] += tx
-    m2[:, 1] += ty
-    y1, D1 = oracle.render(m2, 3, 1, W + tx, H + ty)
-    np.testing.assert_allclose(y1[ty:, tx:], y0, rtol=1e-12, atol=1e-14)
-    np.testing.assert_allclose(D1[ty:, tx:], D0, rtol=1e-12, atol=1e-300)
+    for trunc, (tx, ty) in (("render", (5, 3)), ("gradient", (16, 32))):
+        y0, D0 = oracle.render(m, 3, 1, W, H, trunc=trunc)
+        m2 = m.copy()
+        m2[:, 0] += tx
+        m2[:, 1] += ty
+        y1, D1 = oracle.render(m2, 3, 1, W + tx, H + ty, trunc=trunc)
+        np.testing.assert_allclose(y1[ty:, tx:], y0, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(D1[ty:, tx:], D0, rtol=1e-12, atol=1e-300)
 
 
 def test_subpixel_sampling_scale3():
@@ -408,12 +416,16 @@ def test_subpixel_sampling_scale3():
     same point as native pixel i; scale 1 with origin 0 is the native raster."""
     W, H = 30, 26
     m = wl.random_model(25, 3, 1, W, H, seed=44)
-    y1, _ = oracle.render(m, 3, 1, W, H)
-    y3, _ = oracle.render(m, 3, 1, 3 * W, 3 * H, s=3)
+    y1, _ = oracle.render(m, 3, 1, W, H, trunc="render")
+    y3, _ = oracle.render(m, 3, 1, 3 * W, 3 * H, s=3, trunc="render")
     np.testing.assert_allclose(y3[1::3, 1::3], y1, atol=1e-5)
-    # an origin shift by whole output pixels is a crop
-    yc, _ = oracle.render(m, 3, 1, 40, 35, s=3, ox=11, oy=7)
+    # an origin shift by whole output pixels is a crop (by whole blocks when the block lists
+    # alone decide the render)
+    yc, _ = oracle.render(m, 3, 1, 40, 35, s=3, ox=11, oy=7, trunc="render")
     np.testing.assert_array_equal(yc, y3[7:42, 11:51])
+    y3g, _ = oracle.render(m, 3, 1, 3 * W, 3 * H, s=3)
+    ycg, _ = oracle.render(m, 3, 1, 40, 35, s=3, ox=16, oy=32)
+    np.testing.assert_array_equal(ycg, y3g[32:67, 16:56])
 
 
 def test_common_pi_scale_invariance():
@@ -446,21 +458,24 @@ def _fd_guard(model, W, H, margin=1e-4):
 
 def test_gradient_central_differences():
     """Analytic gradient of the MSE (raw parameters, Cholesky log-diagonal) against FP64
-    central differences, h = 1e-6, on a 32x32 crop with K = 16 linear experts."""
+    central differences, h = 1e-6, on a 32x32 crop with K = 16 linear experts -- with the
+    ellipse test in the render, where the gradient is the rendered loss's."""
     tgt, raw = wl.fd_crop_case()
     H, W, C = tgt.shape
     raw = raw.astype(np.float64)
     model = oracle.materialize(raw, 3, 1)
     _fd_guard(model, W, H)
-    loss, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt)
+    loss, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt, trunc="render")
     h = 1e-6
     fd = np.zeros_like(g)
     for j in range(raw.shape[0]):
         for k in range(raw.shape[1]):
             rp = raw.copy(); rp[j, k] += h
             rm = raw.copy(); rm[j, k] -= h
-            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt)
-            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt)
+            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt,
+                                    trunc="render")
+            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt,
+                                    trunc="render")
             fd[j, k] = (lp - lm) / (2 * h)
     groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
               "wx": [9, 10, 11], "wy": [12, 13, 14]}
@@ -477,7 +492,7 @@ def test_gradient_rho_sums_to_zero():
     tgt, raw = wl.fd_crop_case(seed=7)
     H, W, _ = tgt.shape
     model = oracle.materialize(raw.astype(np.float64), 3, 1)
-    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt)
+    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt, trunc="render")
     assert abs(g[:, 5].sum()) < 1e-12 * np.abs(g[:, 5]).sum()
     assert np.abs(g[:, 5]).max() > 1e-6
 
@@ -491,8 +506,8 @@ def test_gradient_constant_expert_sum_closed_form():
     model[:, :2] += rng.uniform(-2, 2, size=(64, 2))
     model[:, 6] += rng.uniform(-0.1, 0.1, size=64)
     H, W, _ = img.shape
-    y, D = oracle.render(model, 1, 0, W, H)
-    loss, g = oracle.loss_grad(model, 1, 0, W, H, target=img)
+    y, D = oracle.render(model, 1, 0, W, H, trunc="render")
+    loss, g = oracle.loss_grad(model, 1, 0, W, H, target=img, trunc="render")
     gy = 2 * (y - img) / (H * W)
     assert g[:, 6].sum() == pytest.approx(gy[D > 0].sum(), rel=1e-11)
     assert loss == pytest.approx(np.mean((y - img) ** 2), rel=1e-13)
@@ -613,15 +628,17 @@ def test_rbf_gradient_central_differences():
     raw = raw.astype(np.float64)
     model = oracle.materialize(raw, 3, 1)
     _fd_guard(model, W, H)
-    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt, rbf=True)
+    _, g = oracle.loss_grad(model, 3, 1, W, H, target=tgt, rbf=True, trunc="render")
     h = 1e-6
     fd = np.zeros_like(g)
     for j in range(raw.shape[0]):
         for k in range(raw.shape[1]):
             rp = raw.copy(); rp[j, k] += h
             rm = raw.copy(); rm[j, k] -= h
-            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt, rbf=True)
-            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt, rbf=True)
+            lp, _ = oracle.loss_grad(oracle.materialize(rp, 3, 1), 3, 1, W, H, target=tgt, rbf=True,
+                                    trunc="render")
+            lm, _ = oracle.loss_grad(oracle.materialize(rm, 3, 1), 3, 1, W, H, target=tgt, rbf=True,
+                                    trunc="render")
             fd[j, k] = (lp - lm) / (2 * h)
     groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
               "wx": [9, 10, 11], "wy": [12, 13, 14]}
@@ -643,3 +660,117 @@ def test_rbf_rho_gradient_closed_form():
     np.testing.assert_allclose(g[:, 5], ref, rtol=1e-10, atol=1e-14 * np.abs(ref).max())
     _, gs = oracle.loss_grad(m, 3, 0, W, H, target=t)
     assert not np.allclose(gs[:, 5], (m[:, 6:9] * gs[:, 6:9]).sum(axis=1), rtol=1e-3)
+
+
+# --------------------------------------------------------------- ellipse in the gradient only
+
+
+def _np_block_rects(m, W, H, s=1, ox=0, oy=0):
+    """Square-box block rectangles in FP64 numpy: half-side r sqrt(lambda_max) from eigvalsh
+    of L L^T, the output pixels whose centres lie in the box, and their blocks."""
+    lam = np.linalg.eigvalsh(sigma_of(m))[:, 1]
+    Rj = R * np.sqrt(lam)
+    out = []
+    for j in range(m.shape[0]):
+        bx = _pixel_block_range((m[j, 0] - Rj[j]) * s - ox, (m[j, 0] + Rj[j]) * s - ox, W)
+        by = _pixel_block_range((m[j, 1] - Rj[j]) * s - oy, (m[j, 1] + Rj[j]) * s - oy, H)
+        out.append(None if bx is None or by is None else (bx[0], by[0], bx[1], by[1]))
+    return out
+
+
+def _np_blocklist_terms(m, C, order, W, H, rects):
+    """Per (kernel, pixel): whether the kernel takes part in the render (its block list holds
+    the pixel's block and q <= (2r)^2), pi K, q, and the experts' values [K, n, C] (numpy
+    FP64, native raster)."""
+    u, v, x, y = centres(W, H)
+    q = maha_np(m, x, y)
+    cover = np.zeros(q.shape, dtype=bool)
+    for j, rc in enumerate(rects):
+        if rc is not None:
+            cover[j] = ((u >> 4) >= rc[0]) & ((u >> 4) <= rc[2]) & ((v >> 4) >= rc[1]) & \
+                       ((v >> 4) <= rc[3]) & (q[j] <= 4 * R * R)
+    e = np.where(cover, np.exp(m[:, 5:6] - 0.5 * q), 0.0)
+    dx, dy = x[None, :] - m[:, 0:1], y[None, :] - m[:, 1:2]
+    ex = np.stack([m[:, 6 + c:7 + c] + (m[:, 6 + C + c:7 + C + c] * dx +
+                                        m[:, 6 + 2 * C + c:7 + 2 * C + c] * dy if order else 0.0)
+                   for c in range(C)], axis=-1)
+    return cover, e, q, ex
+
+
+def _np_blocklist_render(m, C, order, W, H, rects):
+    _, e, _, ex = _np_blocklist_terms(m, C, order, W, H, rects)
+    D = e.sum(axis=0)
+    N = (e[..., None] * ex).sum(axis=0)
+    y = np.where(D[:, None] > 0, N / np.where(D > 0, D, 1.0)[:, None], 0.0)
+    return y.reshape(H, W, C), D.reshape(H, W)
+
+
+def test_blocklist_render_bruteforce():
+    """Sec. IV-B with the discard in the gradient only: every kernel of a block's list takes
+    part at every pixel of the block up to q <= (2r)^2.  numpy FP64 brute force (boxes from
+    eigvalsh, Gaussians from numpy.linalg.solve) against the oracle's render."""
+    for (W, H, K, seed) in [(45, 38, 40, 81), (32, 32, 8, 82), (70, 20, 60, 83)]:
+        m = wl.random_model(K, 3, 1, W, H, seed=seed, sig_lo=0.7, sig_hi=9.0).astype(np.float64)
+        rects = _np_block_rects(m, W, H)
+        tr = oracle.bin(m, 3, 1, W, H)["tile_rects"]
+        for j, rc in enumerate(rects):
+            assert (tuple(tr[j]) == rc) if rc is not None else tr[j, 2] < tr[j, 0], j
+        cover, _, q, _ = _np_blocklist_terms(m, 3, 1, W, H, rects)
+        # no pair near the render's edge (binary32 q is within ~1e-5 of FP64 there)
+        near = np.abs(q - 4 * R * R) < 3e-5
+        assert not near.any(), np.argwhere(near)
+        y_np, D_np = _np_blocklist_render(m, 3, 1, W, H, rects)
+        y, D = oracle.render(m, 3, 1, W, H)
+        np.testing.assert_allclose(D, D_np, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(y, y_np, rtol=1e-11, atol=1e-13)
+        # some pixels take kernels beyond their ellipse, which the other reading drops
+        y_r, _ = oracle.render(m, 3, 1, W, H, trunc="render")
+        assert np.max(np.abs(y - y_r)) > 1e-6
+
+
+def test_gradient_only_ellipse_per_pair_differences():
+    """The gradient with out-of-ellipse pixels discarded (Sec. IV-B): kernel j's gradient is
+    the sum, over the pixels inside its ellipse, of the derivative of that pixel's squared
+    error with respect to j's raw parameters (render over the block lists, rule held fixed).
+    Brute force: FP64 central differences of every pixel's error, h = 1e-6, masked by numpy's
+    q <= r^2, on a 32x32 RGB case with 6 linear experts."""
+    W = H = 32
+    C, order = 3, 1
+    m0 = wl.random_model(6, C, order, W, H, seed=84, sig_lo=2.0, sig_hi=7.0, margin=0.0)
+    m0 = m0.astype(np.float64)
+    raw = m0.copy()
+    raw[:, 2], raw[:, 4] = np.log(m0[:, 2]), np.log(m0[:, 4])
+    tgt = np.random.default_rng(85).uniform(0, 1, (H, W, C))
+    rects = _np_block_rects(m0, W, H)
+    cover, _, q, _ = _np_blocklist_terms(m0, C, order, W, H, rects)
+    assert np.min(np.abs(q - R * R)) > 1e-4 and np.min(np.abs(q - 4 * R * R)) > 1e-4
+    inside = cover & (q <= R * R)
+    assert (cover & ~inside).any()
+
+    def pixel_errors(r):
+        mm = r.copy()
+        mm[:, 2], mm[:, 4] = np.exp(r[:, 2]), np.exp(r[:, 4])
+        y, _ = _np_blocklist_render(mm, C, order, W, H, rects)
+        return ((y - tgt) ** 2).sum(axis=-1).ravel() / (W * H * C)
+
+    h = 1e-6
+    fd = np.zeros_like(raw)
+    for j in range(raw.shape[0]):
+        for k in range(raw.shape[1]):
+            rp = raw.copy(); rp[j, k] += h
+            rm = raw.copy(); rm[j, k] -= h
+            fd[j, k] = ((pixel_errors(rp) - pixel_errors(rm)) / (2 * h))[inside[j]].sum()
+    _, g = oracle.loss_grad(m0, C, order, W, H, target=tgt)
+    groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
+              "wx": [9, 10, 11], "wy": [12, 13, 14]}
+    for name, cols in groups.items():
+        ref = fd[:, cols]
+        err = np.max(np.abs(g[:, cols] - ref)) / np.max(np.abs(ref))
+        assert err < 2e-5, (name, err)
+    # and it is not the rendered loss's full gradient
+    full = np.zeros_like(raw)
+    for j in range(raw.shape[0]):
+        rp = raw.copy(); rp[j, 6] += h
+        rm = raw.copy(); rm[j, 6] -= h
+        full[j, 6] = ((pixel_errors(rp) - pixel_errors(rm)) / (2 * h))[cover[j]].sum()
+    assert np.max(np.abs(full[:, 6] - g[:, 6])) > 1e-3 * np.max(np.abs(g[:, 6]))

@@ -119,6 +119,28 @@ def config2_image(seed: int = SEEDS[2], H: int = 512, W: int = 512, n_edges: int
     return np.clip(img, 0.0, 1.0).astype(np.float32)
 
 
+def step_edge_image(seed: int = 21, H: int = 256, W: int = 256, C: int = 1, n_lines: int = 6,
+                    noise_std: float = 0.0) -> np.ndarray:
+    """Piecewise-constant image with sharp edges (the 2D counterpart of the 1D step signal of
+    Fig. 2): n_lines random straight lines cut the image into cells, each cell a constant
+    colour in [0.1, 0.9]; the edges are exact pixel-centre steps.  Optional Gaussian noise."""
+    rng = _rng(seed)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    xs += 0.5
+    ys += 0.5
+    code = np.zeros((H, W), dtype=np.int64)
+    for k in range(n_lines):
+        px, py = rng.uniform(0, W), rng.uniform(0, H)
+        th = rng.uniform(0, math.pi)
+        side = (xs - px) * math.cos(th) + (ys - py) * math.sin(th) > 0
+        code |= side.astype(np.int64) << k
+    levels = rng.uniform(0.1, 0.9, size=(1 << n_lines, C))
+    img = levels[code]
+    if noise_std > 0:
+        img = img + rng.normal(0.0, noise_std, size=img.shape)
+    return img.astype(np.float32)
+
+
 def config3_images(seed: int = SEEDS[3], H: int = 2048, W: int = 2048,
                    noise_std: float = 25.0 / 255.0):
     """Denoising workload: (clean, noisy target), float32 [H, W, 3].
