@@ -279,6 +279,8 @@ def run(args):
         out["tight_box"] = run_tight_box(args)
     if not args.no_rbf:
         out["rbf_vs_smoe"] = run_rbf_vs_smoe(args)
+    if not args.no_long:
+        out["long_lists"] = run_long_lists(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -533,6 +535,38 @@ def run_rbf_vs_smoe(args):
     return out
 
 
+def run_long_lists(args):
+    """Renders of models with very wide kernels (standard deviations 20-40 px), whose block
+    lists run to hundreds or thousands of entries: such blocks are split over four waves.
+    Reports pairs, the longest list, the blocks with lists over the split threshold and the
+    time of one render (binning excluded), averaged over 20 renders."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    out = []
+    for side, K in ((256, 2000), (512, 4000)):
+        m = torch.from_numpy(wl.random_model(K, 3, 1, side, side, 5, sig_lo=20.0,
+                                             sig_hi=40.0)).cuda()
+        grid = smoe.make_grid(side, side)
+        _, _, _, b = smoe.render(m, 3, 1, grid)
+        _, st = b.read_status()
+        rg = b.ranges(smoe.tiles(side, side))
+        long_blocks = int(((rg[:, 1] - rg[:, 0]) > 128).sum().item())
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for i in range(25):
+            if i == 5:
+                ev[0].record()
+            smoe.render(m, 3, 1, grid, bins=b)
+        ev[1].record()
+        torch.cuda.synchronize()
+        out.append({"side": side, "K": K, "pairs": int(st[0]), "longest_list": int(st[2]),
+                    "blocks": smoe.tiles(side, side), "blocks_split": long_blocks,
+                    "render_ms": ev[0].elapsed_time(ev[1]) / 20})
+    return out
+
+
 def run_mm_denoise(args):
     """Multi-model fusion for denoising: the block-overlapping window models of a 512^2 RGB
     image from the denoising workload's generator (clean + N(0, (25/255)^2)), fitted together for each
@@ -763,6 +797,7 @@ def main():
     ap.add_argument("--tight-steps", type=int, default=1000)
     ap.add_argument("--no-rbf", action="store_true", help="skip the RBF vs SMoE run")
     ap.add_argument("--rbf-steps", type=int, default=10000)
+    ap.add_argument("--no-long", action="store_true", help="skip the long-list render run")
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()

@@ -8,6 +8,12 @@
 // y_c = N_c / D.  No MFMA: there is no dense contraction here, the work is FP32 VALU plus
 // one v_exp_f32 per participating pair.
 //
+// Long lists (more than kSplitMin entries, which only very wide kernels produce) are split
+// over the four waves of a workgroup instead (k_render_wide): wave w accumulates the w-th
+// contiguous quarter of the list, and wave 0 adds the four partial sums in wave order -- a
+// fixed order, so the render stays deterministic.  Every block is rendered by exactly one of
+// the two kernels.
+//
 // Optional fused squared error against a target: each block writes its sum of squared
 // errors to tile_loss[block]; launch_loss_reduce() then reduces those in a fixed order.
 #include "tile_math.h"
@@ -26,15 +32,16 @@ struct RenderArgs {
   float* __restrict__ tile_loss;
 };
 
-template <int C, int ORDER, bool RBF>
-__global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
-  __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  const int tile = xcd_block(blockIdx.x, a.S.T);
-  const SegGrid sg = seg_of_tile(a.S, tile);
-  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
-  float D[kRows], N[kRows][C];
-  uint64_t live;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, a.ranges[tile], srec, D, N, live);
+// Blocks whose list is longer than this go to k_render_wide.
+constexpr int kSplitMin = 2 * kChunk;
+constexpr int kSplitWaves = 4;
+
+// Writes the block's pixels (y from N and D, Eq. 2-4 or Eq. 1) and its squared error.
+template <int C, bool RBF>
+__device__ __forceinline__ void render_epilogue(const RenderArgs& a, const SegGrid& sg,
+                                                const PixelCoords& px, int tile,
+                                                const float (&D)[kRows],
+                                                const float (&N)[kRows][C]) {
   float err = 0.0f;
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
@@ -56,8 +63,82 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   }
   if (a.tile_loss) {
     for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
-    if (threadIdx.x == 0) a.tile_loss[tile] = err;
+    if ((threadIdx.x & 63) == 0) a.tile_loss[tile] = err;
   }
+}
+
+template <int C, int ORDER, bool RBF>
+__global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
+  __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
+  const int tile = xcd_block(blockIdx.x, a.S.T);
+  const int2 rg = a.ranges[tile];
+  if (rg.y - rg.x > kSplitMin) return;  // a long list: k_render_wide renders this block
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
+  float D[kRows], N[kRows][C];
+  uint64_t live;
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, rg, srec, D, N,
+                               live);
+  render_epilogue<C, RBF>(a, sg, px, tile, D, N);
+}
+
+// Four waves per block for lists longer than kSplitMin.  Each wave stages its own records
+// in its own LDS region; within a wave, LDS stores and loads execute in program order, so
+// the staging needs no workgroup barrier (the waves' chunk counts differ).  The one barrier
+// is reached once by every wave of the workgroup.
+template <int C, int ORDER, bool RBF>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs a) {
+  constexpr int RS = record_stride(C, ORDER);
+  constexpr int Q = RS / 4;
+  constexpr int NV = kRows * (1 + C);  // per lane: D and N_c of four pixels
+  __shared__ float4 srec[kSplitWaves][kChunk * Q];
+  __shared__ float part[kSplitWaves - 1][NV][kWave];
+  const int tile = xcd_block(blockIdx.x, a.S.T);
+  const int2 rg = a.ranges[tile];
+  const int len = rg.y - rg.x;
+  if (len <= kSplitMin) return;  // the same for every wave: k_render renders this block
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
+  const int per = (len + kSplitWaves - 1) / kSplitWaves;
+  const int b = rg.x + min(len, wv * per), e = rg.x + min(len, (wv + 1) * per);
+  float D[kRows], N[kRows][C];
+  zero_sums<C>(D, N);
+  float4* my = srec[wv];
+  for (int base = b; base < e; base += kChunk) {
+    const int n = min(kChunk, e - base);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < n * Q; i += kWave) {
+      const int k = i / Q, c = i - k * Q;
+      my[i] = reinterpret_cast<const float4*>(a.records + (size_t)a.vals[base + k] * RS)[c];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < n; ++k)
+      forward_entry<C, ORDER>(px, a.S.r2, a.S.r2_render,
+                              reinterpret_cast<const float*>(&my[k * Q]), D, N);
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      part[wv - 1][i * (1 + C)][lane] = D[i];
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[wv - 1][i * (1 + C) + 1 + c][lane] = N[i][c];
+    }
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int w = 0; w < kSplitWaves - 1; ++w) {
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      D[i] += part[w][i * (1 + C)][lane];
+#pragma unroll
+      for (int c = 0; c < C; ++c) N[i][c] += part[w][i * (1 + C) + 1 + c][lane];
+    }
+  }
+  render_epilogue<C, RBF>(a, sg, px, tile, D, N);
 }
 
 // One workgroup: loss = inv_n * sum of the per-block partials, in a fixed order.
@@ -139,6 +220,7 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
   with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_render<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
+    k_render_wide<T::C, T::ORDER, T::RBF><<<S.T, kSplitWaves * kWave, 0, s>>>(a);
   });
   return hipGetLastError();
 }

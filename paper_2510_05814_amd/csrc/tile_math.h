@@ -67,10 +67,62 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
   __syncthreads();
 }
 
-// Forward accumulation over a block's list [rg.x, rg.y) in list order:
-// D = sum pi K and N_c = sum pi K m_c for the lane's four pixels (FP32 registers), over the
-// pairs with q <= r2_render: r^2 (the ellipse test in the render) or (2r)^2 (the block lists
-// decide the render; the cut keeps every term inside FP32's accurate range).
+// One list entry of the forward: adds its terms to D = sum pi K and N_c = sum pi K m_c of
+// the lane's four pixels, for the pixels with q <= r2_render: r^2 (the ellipse test in the
+// render) or (2r)^2 (the block lists decide the render; the cut keeps every term inside
+// FP32's accurate range).  Returns whether any of the lane's pixels passed the ellipse test
+// q <= r2.  r: the entry's render record.
+template <int C, int ORDER>
+__device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, float r2_render,
+                                              const float* r, float (&D)[kRows],
+                                              float (&N)[kRows][C]) {
+  bool hit = false;
+  // Truncation test: the binary32 sequence of the ABI contract (no contraction).
+  const float dx = px.x - r[0];
+  const float z1 = dx * r[2];
+  const float tt = r[3] * z1;
+  const float zz1 = z1 * z1;
+  // a_c + wx_c dx: the expert's value along the lane's column
+  float mx[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
+                       : r[kRecExpert + c];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    const float dy = px.y[i] - r[1];
+    const float w = dy - tt;
+    const float z2 = w * r[4];
+    const float q = zz1 + z2 * z2;
+    hit |= q <= r2;
+    // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2); a pair beyond the render's
+    // bound adds exactly zero (no branch: nearly every tested pair is inside it when the
+    // block lists decide the render, and the four rows then interleave freely)
+    const float ex = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+    const float e = q <= r2_render ? ex : 0.0f;
+    D[i] += e;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      float m = mx[c];
+      if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+      N[i][c] = __builtin_fmaf(e, m, N[i][c]);
+    }
+  }
+  return hit;
+}
+
+template <int C>
+__device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C]) {
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    D[i] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) N[i][c] = 0.0f;
+  }
+}
+
+// Forward accumulation over a block's list [rg.x, rg.y) in list order (forward_entry per
+// entry, records staged through LDS in chunks).
 // live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
 template <int C, int ORDER>
@@ -82,50 +134,14 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
                                                    float (&N)[kRows][C], uint64_t& live) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
-#pragma unroll
-  for (int i = 0; i < kRows; ++i) {
-    D[i] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < C; ++c) N[i][c] = 0.0f;
-  }
+  zero_sums<C>(D, N);
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     stage_records<RS>(srec, records, vals, base, n);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      bool hit = false;
-      // Truncation test: the binary32 sequence of the ABI contract (no contraction).
-      const float dx = px.x - r[0];
-      const float z1 = dx * r[2];
-      const float tt = r[3] * z1;
-      const float zz1 = z1 * z1;
-      // a_c + wx_c dx: the expert's value along the lane's column
-      float mx[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c)
-        mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
-                           : r[kRecExpert + c];
-#pragma unroll
-      for (int i = 0; i < kRows; ++i) {
-        const float dy = px.y[i] - r[1];
-        const float w = dy - tt;
-        const float z2 = w * r[4];
-        const float q = zz1 + z2 * z2;
-        hit |= q <= r2;
-        if (q <= r2_render) {
-          // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
-          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
-          D[i] += e;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            float m = mx[c];
-            if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
-            N[i][c] = __builtin_fmaf(e, m, N[i][c]);
-          }
-        }
-      }
-      if (__any(hit)) live |= 1ull << k;
+      if (__any(forward_entry<C, ORDER>(px, r2, r2_render, r, D, N))) live |= 1ull << k;
     }
   }
 }

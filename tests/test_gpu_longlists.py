@@ -1,0 +1,137 @@
+"""Long block lists (very wide kernels): lists longer than 128 entries are rendered by four
+waves per block, each over a contiguous quarter of the list, with the partial sums added in
+wave order.  Against the oracle (images within 1e-5, D within 1e-5 relative, losses within
+1e-5 relative), deterministic run to run, blocks with short lists in the same raster
+rendered as before (bitwise equal to the fit step's render), and the gradient of such
+models against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smoe():
+    import torch  # noqa: F401
+
+    import paper_2510_05814_amd as smoe
+    return smoe
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def wide_model(K, C, order, W, H, seed, lo, hi):
+    return wl.random_model(K, C, order, W, H, seed, sig_lo=lo, sig_hi=hi, rho_std=0.3)
+
+
+CASES = [
+    # (W, H, K, C, order, sig_lo, sig_hi, scale, mode, seed)
+    (64, 64, 400, 3, 1, 15.0, 30.0, 1, "smoe", 701),
+    (96, 80, 700, 1, 0, 10.0, 40.0, 1, "smoe", 702),
+    (40, 36, 300, 3, 0, 12.0, 25.0, 3, "smoe", 703),
+    (64, 48, 350, 3, 1, 15.0, 30.0, 1, "rbf", 704),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}K{c[2]}s{c[7]}{c[8]}" for c in CASES])
+def test_long_lists_against_oracle(smoe, case, record_error):
+    W, H, K, C, order, lo, hi, s, mode, seed = case
+    say("long lists", case)
+    m_np = wide_model(K, C, order, W, H, seed, lo, hi)
+    if mode == "rbf":
+        m_np[:, 5] -= 4.0
+    OW, OH = s * W, s * H
+    m = dev(m_np)
+    grid = smoe.make_grid(OW, OH, s, mode=mode)
+    img, D, _, b = smoe.render(m, C, order, grid)
+    _, st = b.read_status()
+    assert st[2] > 128, "the case must produce lists longer than the split threshold"
+    y_o, D_o = oracle.render(m_np, C, order, OW, OH, s, rbf=(mode == "rbf"))
+    peak = max(1.0, float(np.max(np.abs(y_o))))
+    ey = float(np.max(np.abs(host(img) - y_o))) / peak
+    eD = float(np.max(np.abs(host(D) - D_o) / np.maximum(D_o, 1e-30)))
+    record_error("long-list image abs", ey, 1e-5)
+    record_error("long-list D rel", eD, 1e-5)
+    assert ey <= 1e-5 and eD <= 1e-5
+    img2, D2, _, _ = smoe.render(m, C, order, grid, bins=b)
+    assert np.array_equal(host(img2), host(img)) and np.array_equal(host(D2), host(D))
+
+
+def test_mixed_lists_and_loss(smoe, record_error):
+    """A raster with both long and short lists, with the fused loss; the short-list blocks
+    equal the fit step's render bit for bit, every block matches the oracle."""
+    import torch
+    say("mixed lists")
+    W, H = 256, 96
+    # long lists on the left (wide kernels, boxes reach x < 130), short lists from x = 176
+    wide = wide_model(300, 3, 1, 40, 40, 710, 12.0, 20.0)
+    narrow = wl.random_model(400, 3, 1, 76, H, 711, sig_lo=0.8, sig_hi=3.0, margin=0.0)
+    narrow[:, 0] += 180.0
+    m_np = np.concatenate([wide, narrow]).astype(np.float32)
+    t_np = np.random.default_rng(3).uniform(0, 1, (H, W, 3)).astype(np.float32)
+    m, t = dev(m_np), dev(t_np)
+    grid = smoe.make_grid(W, H)
+    img, D, loss, b = smoe.render(m, 3, 1, grid, target=t)
+    ranges = host(b.ranges(smoe.tiles(W, H)))
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert (lens > 128).any() and (lens <= 128).any()
+    y_o, _ = oracle.render(m_np, 3, 1, W, H)
+    ey = float(np.max(np.abs(host(img) - y_o)))
+    record_error("mixed-list image abs", ey, 1e-5)
+    assert ey <= 1e-5
+    l_o = float(np.mean((y_o - t_np) ** 2))
+    el = abs(loss.item() - l_o) / l_o
+    record_error("mixed-list loss rel", el, 1e-5)
+    assert el <= 1e-5
+    # the fused fit step renders every block with one wave: equal on the short-list blocks
+    raw = m_np.astype(np.float64).copy()
+    raw[:, 2], raw[:, 4] = np.log(m_np[:, 2]), np.log(m_np[:, 4])
+    st = smoe.FitState(t, dev(raw), 1, smoe.AdamConfig(total_steps=1), max_steps=1,
+                       capacity=smoe.tiles(W, H) * int(lens.max() * 2))
+    m_fit = st.model.clone()          # the rows the first step renders
+    st.step()
+    torch.cuda.synchronize()
+    img_f, _, _, bf = smoe.render(m_fit, 3, 1, grid)
+    lens_f = host(bf.ranges(smoe.tiles(W, H)))
+    lens_f = lens_f[:, 1] - lens_f[:, 0]
+    fi, gi = host(st.image), host(img_f)
+    ntx = (W + 15) // 16
+    short = np.flatnonzero(lens_f <= 128)
+    assert short.size and (lens_f > 128).any()
+    for tile in short:
+        ty, tx = divmod(int(tile), ntx)
+        sl = (slice(16 * ty, 16 * ty + 16), slice(16 * tx, 16 * tx + 16))
+        assert np.array_equal(fi[sl], gi[sl]), tile
+
+
+def test_long_lists_gradient(smoe, record_error):
+    say("long-list gradient")
+    W, H = 48, 48
+    m_np = wide_model(200, 3, 1, W, H, 720, 12.0, 22.0)
+    t_np = np.random.default_rng(8).uniform(0, 1, (H, W, 3)).astype(np.float32)
+    m, t = dev(m_np), dev(t_np)
+    grid = smoe.make_grid(W, H)
+    img, D, loss, b = smoe.render(m, 3, 1, grid, target=t)
+    g = host(smoe.render_backward(m, 3, 1, grid, b, img, D, target=t))
+    _, g_o = oracle.loss_grad(m_np, 3, 1, W, H, target=t_np)
+    groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
+              "wx": [9, 10, 11], "wy": [12, 13, 14]}
+    for name, cols in groups.items():
+        scale = float(np.max(np.abs(g_o[:, cols])))
+        e = float(np.max(np.abs(g[:, cols] - g_o[:, cols]))) / scale
+        record_error(f"long-list grad {name} rel", e, 1e-3)
+        assert e <= 1e-3, name
