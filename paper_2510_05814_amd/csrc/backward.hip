@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
       const float D = a.denom[p];
       if (D > 0.0f) {
         sd.valid[i] = true;
-        sd.invD[i] = RBF ? 1.0f : 1.0f / D;
+        sd.invD[i] = RBF ? 1.0f : __builtin_amdgcn_rcpf(D);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const float yc = a.image[p * C + c];

@@ -87,11 +87,12 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
     if (px.u < sg.W && v < sg.H) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const bool cov = D[i] > 0.0f;
-      const float invD = RBF ? 1.0f : (cov ? 1.0f / D[i] : 0.0f);
+      // 1/D by v_rcp_f32 (1 ulp); y = N / D refined from it, as in the render
+      const float invD = RBF ? 1.0f : (cov ? __builtin_amdgcn_rcpf(D[i]) : 0.0f);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         // Eq. (2)-(4): y = N / D; Eq. (1): y = N
-        const float yc = RBF ? N[i][c] : (cov ? N[i][c] / D[i] : 0.0f);
+        const float yc = RBF ? N[i][c] : (cov ? div_refined(N[i][c], D[i], invD) : 0.0f);
         a.image[p * C + c] = yc;
         const float d = yc - a.target[p * C + c];
         err = __builtin_fmaf(d, d, err);

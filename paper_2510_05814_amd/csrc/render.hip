@@ -50,8 +50,11 @@ __device__ __forceinline__ void render_epilogue(const RenderArgs& a, const SegGr
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        // Eq. (2)-(4): y = N / D; Eq. (1): y = N
-        const float yc = RBF ? N[i][c] : ((D[i] > 0.0f) ? N[i][c] / D[i] : 0.0f);
+        // Eq. (2)-(4): y = N / D, refined from v_rcp_f32(D) exactly as the fit step's render;
+        // Eq. (1): y = N
+        const float yc =
+            RBF ? N[i][c]
+                : ((D[i] > 0.0f) ? div_refined(N[i][c], D[i], __builtin_amdgcn_rcpf(D[i])) : 0.0f);
         a.image[p * C + c] = yc;
         if (a.target) {
           const float d = yc - a.target[p * C + c];
