@@ -15,10 +15,12 @@ from . import core
 
 class SMoERender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, raw, C, order, width, height, scale=1, origin_x=0, origin_y=0, radius=3.0):
+    def forward(ctx, raw, C, order, width, height, scale=1, origin_x=0, origin_y=0, radius=3.0,
+                mode="smoe", trunc="gradient"):
         if not (raw.is_cuda and raw.dtype == torch.float32):
             raise ValueError("raw must be a cuda float32 [K, NP] tensor")
-        grid = core.make_grid(width, height, scale, origin_x, origin_y, radius)
+        grid = core.make_grid(width, height, scale, origin_x, origin_y, radius, mode=mode,
+                              trunc=trunc)
         model = core.materialize(raw.detach().contiguous(), C, order)
         bins = core.bin(model, C, order, grid)
         image, denom, _, _ = core.render(model, C, order, grid, bins=bins)
@@ -31,10 +33,13 @@ class SMoERender(torch.autograd.Function):
         model, image, denom = ctx.saved_tensors
         g = core.render_backward(model, ctx.C, ctx.order, ctx.grid, ctx.bins, image, denom,
                                  grad_image=grad_image.contiguous())
-        return g, None, None, None, None, None, None, None, None
+        return g, None, None, None, None, None, None, None, None, None, None
 
 
 def smoe_render(raw: torch.Tensor, C: int, order: int, width: int, height: int, scale: int = 1,
-                origin_x: int = 0, origin_y: int = 0, radius: float = 3.0) -> torch.Tensor:
-    """Differentiable render of raw kernel rows [K, 6 + C(1 + 2 order)] into [H, W, C]."""
-    return SMoERender.apply(raw, C, order, width, height, scale, origin_x, origin_y, radius)
+                origin_x: int = 0, origin_y: int = 0, radius: float = 3.0, mode: str = "smoe",
+                trunc: str = "gradient") -> torch.Tensor:
+    """Differentiable render of raw kernel rows [K, 6 + C(1 + 2 order)] into [H, W, C];
+    mode "rbf" renders the weighted sum of kernels of Eq. (1) instead of the gates."""
+    return SMoERender.apply(raw, C, order, width, height, scale, origin_x, origin_y, radius,
+                            mode, trunc)

@@ -87,19 +87,19 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
 
 // Four waves per block for lists longer than kSplitMin.  Each wave stages its own records
 // in its own LDS region; within a wave, LDS stores and loads execute in program order, so
-// the staging needs no workgroup barrier (the waves' chunk counts differ).  The one barrier
-// is reached once by every wave of the workgroup.
+// the staging needs no workgroup barrier (the waves' chunk counts differ).  A workgroup
+// walks the blocks with a grid stride (at most kWideGroups workgroups, so that a raster
+// without long lists costs only a scan of its ranges); every decision in the walk is the
+// same for the four waves, so each barrier is reached by all of them.
+constexpr int kWideGroups = 1024;
+
 template <int C, int ORDER, bool RBF>
-__global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs a) {
+__device__ __forceinline__ void render_wide_block(const RenderArgs& a, int tile, int2 rg,
+                                                  float4 (*srec)[kChunk * record_stride(C, ORDER) / 4],
+                                                  float (*part)[kRows * (1 + C)][kWave]) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
-  constexpr int NV = kRows * (1 + C);  // per lane: D and N_c of four pixels
-  __shared__ float4 srec[kSplitWaves][kChunk * Q];
-  __shared__ float part[kSplitWaves - 1][NV][kWave];
-  const int tile = xcd_block(blockIdx.x, a.S.T);
-  const int2 rg = a.ranges[tile];
   const int len = rg.y - rg.x;
-  if (len <= kSplitMin) return;  // the same for every wave: k_render renders this block
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
@@ -131,17 +131,30 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs 
     }
   }
   __syncthreads();
-  if (wv != 0) return;
+  if (wv == 0) {
 #pragma unroll
-  for (int w = 0; w < kSplitWaves - 1; ++w) {
+    for (int w = 0; w < kSplitWaves - 1; ++w) {
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-      D[i] += part[w][i * (1 + C)][lane];
+      for (int i = 0; i < kRows; ++i) {
+        D[i] += part[w][i * (1 + C)][lane];
 #pragma unroll
-      for (int c = 0; c < C; ++c) N[i][c] += part[w][i * (1 + C) + 1 + c][lane];
+        for (int c = 0; c < C; ++c) N[i][c] += part[w][i * (1 + C) + 1 + c][lane];
+      }
     }
+    render_epilogue<C, RBF>(a, sg, px, tile, D, N);
   }
-  render_epilogue<C, RBF>(a, sg, px, tile, D, N);
+  __syncthreads();  // part is reused by the next block of the walk
+}
+
+template <int C, int ORDER, bool RBF>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs a) {
+  __shared__ float4 srec[kSplitWaves][kChunk * record_stride(C, ORDER) / 4];
+  __shared__ float part[kSplitWaves - 1][kRows * (1 + C)][kWave];
+  for (int tile = blockIdx.x; tile < a.S.T; tile += gridDim.x) {
+    const int2 rg = a.ranges[tile];
+    if (rg.y - rg.x <= kSplitMin) continue;  // k_render renders this block
+    render_wide_block<C, ORDER, RBF>(a, tile, rg, srec, part);
+  }
 }
 
 // One workgroup: loss = inv_n * sum of the per-block partials, in a fixed order.
@@ -223,7 +236,7 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
   with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_render<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
-    k_render_wide<T::C, T::ORDER, T::RBF><<<S.T, kSplitWaves * kWave, 0, s>>>(a);
+    k_render_wide<T::C, T::ORDER, T::RBF><<<min(S.T, kWideGroups), kSplitWaves * kWave, 0, s>>>(a);
   });
   return hipGetLastError();
 }

@@ -93,3 +93,30 @@ def test_autograd_with_torch_adam_reduces_loss():
         opt.step()
         losses.append(loss.item())
     assert losses[-1] < 0.8 * losses[0]
+
+
+@pytest.mark.parametrize("mode,trunc", [("rbf", "gradient"), ("smoe", "render"), ("rbf", "render")])
+def test_autograd_modes_against_oracle(mode, trunc, record_error):
+    """The autograd path with the RBF sum of Eq. (1) and/or the ellipse test in the render."""
+    import torch
+
+    from paper_2510_05814_amd.autograd import smoe_render
+    print("[case] autograd", mode, trunc, flush=True)
+    W, H = 44, 37
+    m = wl.random_model(70, 3, 1, W, H, seed=93, rho_std=0.3)
+    m[:, 5] -= 1.0
+    raw = m.astype(np.float64).copy()
+    raw[:, 2] = np.log(raw[:, 2])
+    raw[:, 4] = np.log(raw[:, 4])
+    wts = np.random.default_rng(4).normal(size=(H, W, 3))
+    r = _dev(raw).requires_grad_(True)
+    img = smoe_render(r, 3, 1, W, H, mode=mode, trunc=trunc)
+    (img * _dev(wts)).sum().backward()
+    model = oracle.materialize(raw, 3, 1)
+    y_o, _ = oracle.render(model, 3, 1, W, H, rbf=(mode == "rbf"), trunc=trunc)
+    ey = float(np.max(np.abs(img.detach().cpu().numpy() - y_o))) / max(1.0, float(np.abs(y_o).max()))
+    _, g_o = oracle.loss_grad(model, 3, 1, W, H, grad_y=wts, rbf=(mode == "rbf"), trunc=trunc)
+    err = np.max(np.abs(r.grad.cpu().numpy() - g_o)) / np.max(np.abs(g_o))
+    record_error(f"autograd {mode}/{trunc} image", ey, 1e-5)
+    record_error(f"autograd {mode}/{trunc} grad rel", err, 1e-3)
+    assert ey <= 1e-5 and err <= 1e-3

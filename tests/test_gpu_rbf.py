@@ -158,3 +158,28 @@ def test_rbf_batched_equals_single(smoe):
         alone, _, _, _ = smoe.render(dev(models[i]), 3, 1,
                                      smoe.make_grid(w, h, s, ox, oy, mode="rbf"))
         assert torch.equal(out[a:e].view(h, w, 3), alone), (i, s)
+
+
+def test_rbf_batched_fit_equals_individual_fits(smoe):
+    """Two images fitted together in the RBF mode, bit for bit the images fitted alone."""
+    import torch
+    say("rbf batched fit")
+    imgs = [wl.step_edge_image(seed=s, H=h, W=w, C=3) for s, h, w in ((41, 48, 64), (42, 40, 40))]
+    raws = []
+    for im in imgs:
+        raw, _ = wl.grid_init(im, 6, 5, 4.0, order=1)
+        raw[:, 5] = -0.5
+        raws.append(raw)
+    adam = smoe.AdamConfig(total_steps=20)
+    tg = [torch.from_numpy(i) for i in imgs]
+    rw = [torch.from_numpy(r) for r in raws]
+    both = smoe.FitState(tg, rw, 1, adam, max_steps=21, mode="rbf")
+    both.run(20)
+    alone = []
+    for t, r in zip(tg, rw):
+        st = smoe.FitState(t.cuda(), r.cuda(), 1, adam, max_steps=21, mode="rbf")
+        st.run(20)
+        alone.append(st)
+    torch.cuda.synchronize()
+    for (a, e, h, w), st in zip(both.segments.pixel_slices(), alone):
+        assert torch.equal(both.image[a:e].view(h, w, 3), st.image)
