@@ -99,6 +99,26 @@ def test_invalid_arguments_rejected_before_launch():
               C.SmoeGrid(64, 64, 1, 0, 0, 0.0), C.SmoeGrid(64, 64, 1, 0, 0, float("nan")),
               C.SmoeGrid(64, 64, 1, 1 << 23, 0, 3.0), C.SmoeGrid(70000, 64, 1, 0, 0, 3.0)]:
         assert lib.smoe_bin(ct.byref(m), ct.byref(g), ct.byref(b), None) == C.SMOE_ERR_INVALID
+    # the rule's variants: sharpening factor, box, regression mode, truncation reading
+    for fields in [dict(sharpen=-1.0), dict(sharpen=float("nan")), dict(sharpen=float("inf")),
+                   dict(box=2), dict(box=-1), dict(mode=2), dict(trunc=2), dict(trunc=-1)]:
+        g = C.SmoeGrid(64, 64, 1, 0, 0, 3.0)
+        for k, v in fields.items():
+            setattr(g, k, v)
+        assert lib.smoe_bin(ct.byref(m), ct.byref(g), ct.byref(b), None) == C.SMOE_ERR_INVALID, fields
+    for ok in [dict(sharpen=2.5), dict(box=1), dict(mode=1), dict(trunc=1)]:
+        g = C.SmoeGrid(80, 80, 1, 0, 0, 3.0)
+        for k, v in ok.items():
+            setattr(g, k, v)
+        # valid fields: the call gets as far as the size check (80x80 needs 25 blocks, the
+        # workspace holds 16), still before any launch
+        assert lib.smoe_bin(ct.byref(m), ct.byref(g), ct.byref(b), None) == C.SMOE_ERR_TOO_LARGE, ok
+    # the backward (and the fit step) take no sharpening
+    sharp = C.SmoeGrid(64, 64, 1, 0, 0, 3.0)
+    sharp.sharpen = 2.0
+    q = 1 << 20
+    assert lib.smoe_render_backward(ct.byref(m), ct.byref(sharp), ct.byref(b), q, q, q, None, q,
+                                    None) == C.SMOE_ERR_INVALID
     # more blocks than the workspace holds (16): 80x80 needs 25
     big = C.SmoeGrid(80, 80, 1, 0, 0, 3.0)
     assert lib.smoe_bin(ct.byref(m), ct.byref(big), ct.byref(b), None) == C.SMOE_ERR_TOO_LARGE
