@@ -34,8 +34,8 @@ def pytest_collection_modifyitems(config, items):
 
 @pytest.fixture
 def record_error(request):
-    """Records the error of a GPU result against the FP64 oracle (printed and, when a
-    gpurun_out/ folder exists, written to gpurun_out/parity_errors.json)."""
+    """Records the error of a GPU result against the FP64 oracle (printed, and written as
+    JSON to the file named by the SMOE_PARITY_ERRORS environment variable, if set)."""
 
     def rec(what: str, value: float, bound: float):
         entry = {"test": request.node.name, "what": what, "error": float(value),
@@ -48,7 +48,7 @@ def record_error(request):
 
 
 def pytest_sessionfinish(session, exitstatus):
-    out = os.path.join(ROOT, "gpurun_out")
-    if _ERRORS and os.path.isdir(out):
-        with open(os.path.join(out, "parity_errors.json"), "w") as f:
+    path = os.environ.get("SMOE_PARITY_ERRORS")
+    if _ERRORS and path:
+        with open(path, "w") as f:
             json.dump(_ERRORS, f, indent=1)
