@@ -199,17 +199,21 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const SegGrid sg = seg_of_kernel(f.S, live ? j : 0);
   float pm = 0.0f;  // materialized value of parameter i after the step
   if (live && skip && i < NP) pm = f.model[(size_t)j * NP + i];
+  // Adam's state is loaded before the gather, so that these loads overlap its chain of
+  // dependent loads instead of following it.
+  const size_t e = (size_t)j * NP + i;
+  const bool upd = live && !skip && i < NP;
+  const float m0 = upd ? f.m[e] : 0.0f, v0 = upd ? f.v[e] : 0.0f, raw0 = upd ? f.raw[e] : 0.0f;
   // every lane takes part in the gather's row reduction
   const float gi = gather_param<NP>(j, live && !skip, sg, f.tile_rects_in, f.ranges, f.vals,
                                     f.pair_grads);
-  if (live && !skip && i < NP) {
+  if (upd) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
-    const size_t e = (size_t)j * NP + i;
-    const float mi = ad.beta1 * f.m[e] + (1.0f - ad.beta1) * gi;
-    const float vi = ad.beta2 * f.v[e] + (1.0f - ad.beta2) * gi * gi;
+    const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;
+    const float vi = ad.beta2 * v0 + (1.0f - ad.beta2) * gi * gi;
     f.m[e] = mi;
     f.v[e] = vi;
-    const float p = f.raw[e] - lr * (mi / s_sc[1]) / (sqrtf(vi / s_sc[2]) + ad.eps);
+    const float p = raw0 - lr * (mi / s_sc[1]) / (sqrtf(vi / s_sc[2]) + ad.eps);
     f.raw[e] = p;
     pm = (i == 2 || i == 4) ? expf(p) : p;
     f.model[e] = pm;
