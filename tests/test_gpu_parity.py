@@ -322,6 +322,37 @@ def test_backward_full_size_sampled_kernels(smoe, record_error):
     check_grads(g[sel], g_o, C, 1, record_error, "2048 sampled")
 
 
+def test_fit_step_full_size_after_graphed_steps(smoe, record_error):
+    """The fused fit step in the configuration the benchmark times (2048^2 RGB, K = 65536,
+    pair capacity 8 P0 + 65536, steps replayed from HIP graphs): after 40 steps, one more
+    step's render (of the model it starts from) on 3000 sampled pixels and its gradient of 24
+    sampled kernels against the oracle on that model."""
+    import torch
+    say("full-size fit step")
+    w = wl.workload(3)
+    H, W, C = w.target.shape
+    target = dev(w.target)
+    raw0 = dev(w.raw0)
+    b0 = smoe.bin(smoe.materialize(raw0, C, 1), C, 1, smoe.make_grid(W, H))
+    P0 = b0.read_status()[1][0]
+    st = smoe.FitState(target, raw0, 1, smoe.AdamConfig(total_steps=10000), max_steps=64,
+                       capacity=8 * P0 + 65536)
+    st.run_graphed(40)
+    model_np = host(st.model).copy()
+    st.step()
+    torch.cuda.synchronize()
+    assert not st.bins.read_status()[0]
+    rng = np.random.default_rng(31)
+    pix = np.stack([rng.integers(0, W, 3000), rng.integers(0, H, 3000)], 1)
+    y_o, _ = oracle.render(model_np, C, 1, W, H, pixels=pix)
+    ey = float(np.max(np.abs(host(st.image)[pix[:, 1], pix[:, 0]] - y_o)))
+    record_error("full-size fit step image abs (sampled)", ey, Y_TOL)
+    assert ey <= Y_TOL
+    sel = np.concatenate([[0, w.K - 1], rng.choice(w.K, 22, replace=False)])
+    _, g_o = oracle.loss_grad(model_np, C, 1, W, H, target=w.target, kernels=sel)
+    check_grads(host(st.grads)[sel], g_o, C, 1, record_error, "full-size fit step sampled")
+
+
 def test_fit_step_one_step_against_oracle_adam(smoe, record_error):
     """One smoe_fit_step from the same raw state: the loss, the gradient and the Adam update
     (within the propagated gradient tolerance) against the oracle's FP64 pieces."""
