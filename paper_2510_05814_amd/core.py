@@ -300,7 +300,9 @@ class FitState:
 
     target: one cuda float32 [H, W, C] image with raw0 [K, NP] -- or, for a batched fit, a
     list of images with a list of raw0 arrays (one per image): the images are fitted together
-    in lock-step, each by its own kernels, with one launch per stage for all of them."""
+    in lock-step, each by its own kernels, with one launch per stage for all of them.
+    radius, box, mode, trunc: the rule's settings, as in make_grid (mode "rbf" fits the
+    weighted sum of kernels of Eq. 1)."""
 
     def __init__(self, target, raw0, order: int, adam: AdamConfig, max_steps: int = 0,
                  capacity: int | None = None, radius: float = 3.0, box="square",
