@@ -41,7 +41,7 @@ import numpy as np
 import torch
 
 from . import _capi as C
-from .core import Bins, _box, _check_params, _trunc, make_grid, model_struct
+from .core import Bins, _box, _check_params, _mode, _trunc, make_grid, model_struct
 
 TILE = 16
 
@@ -119,15 +119,17 @@ class ModelBank:
     host-side pair bounds of their renders.  models: float32 [K_i, NP] materialized rows
     (numpy arrays or tensors).  box: the kernel boxes the renders bin with ("square", the
     boxes the models were fitted with, or "tight"); the pair bound (square boxes) holds for
-    both.  trunc: the truncation reading of the renders (as in make_grid)."""
+    both.  mode, trunc: the regression (gated SMoE or the RBF sum of Eq. 1) and the
+    truncation reading of the renders (as in make_grid)."""
 
     def __init__(self, models, C_: int, order: int, radius: float = 3.0, device="cuda",
-                 box="square", trunc="gradient"):
+                 box="square", trunc="gradient", mode="smoe"):
         rows = [m.detach().float().cpu() if torch.is_tensor(m) else
                 torch.as_tensor(np.asarray(m, dtype=np.float32)) for m in models]
         self.C, self.order, self.radius = C_, order, float(radius)
         self.box = _box(box)
         self.trunc = _trunc(trunc)
+        self.mode = _mode(mode)
         self.K = [int(r.shape[0]) for r in rows]
         self.offset = [int(x) for x in np.concatenate([[0], np.cumsum(self.K)[:-1]])]
         self.params = torch.cat(rows).to(device).contiguous()
@@ -328,7 +330,7 @@ class Server:
                 # one request: the single-raster calls, no segment table
                 r = batch.reqs[0]
                 grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius,
-                                 r.sharpen, b.box, trunc=b.trunc)
+                                 r.sharpen, b.box, mode=b.mode, trunc=b.trunc)
                 images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
                 m = self._models[r.model]
                 C.smoe_bin(m, grid, bins.c, st.cuda_stream)
@@ -348,7 +350,7 @@ class Server:
                 images = torch.empty((npx, b.C), dtype=torch.float32, device=dev)
                 cb = C.SmoeBatch(b.C, b.order, b.params.data_ptr(), b.params.shape[0], n,
                                  sl.table_dev.data_ptr(), ct.addressof(host), b.radius, b.box,
-                                 C.SMOE_MODE_SMOE, b.trunc)
+                                 b.mode, b.trunc)
                 C.smoe_bin_batched(cb, bins.c, st.cuda_stream)
                 C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
                 slices = [(sg.pixel_offset, sg.pixel_offset + sg.width * sg.height, sg.height,
@@ -476,7 +478,7 @@ class PlainServer:
             r = reqs[i]
             _wait_until(clock, r.arrival)
             grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius,
-                             r.sharpen, b.box, trunc=b.trunc)
+                             r.sharpen, b.box, mode=b.mode, trunc=b.trunc)
             rows = b.rows(r.model)
             m = model_struct(rows, b.C, b.order)
             with torch.cuda.stream(st):

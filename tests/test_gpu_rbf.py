@@ -183,3 +183,23 @@ def test_rbf_batched_fit_equals_individual_fits(smoe):
     torch.cuda.synchronize()
     for (a, e, h, w), st in zip(both.segments.pixel_slices(), alone):
         assert torch.equal(both.image[a:e].view(h, w, 3), st.image)
+
+
+def test_rbf_serving_equals_alone(smoe):
+    """A model bank in the RBF mode: batched and plain servers give each request the image of
+    rendering it alone."""
+    import torch
+
+    from paper_2510_05814_amd.serve import ModelBank, PlainServer, RenderRequest, Server
+    say("rbf serving")
+    models = [rbf_model(K, 3, 1, 48, 40, 630 + K).astype(np.float32) for K in (70, 130)]
+    bank = ModelBank(models, 3, 1, mode="rbf")
+    reqs = [RenderRequest(i % 2, 1 + i % 3, 40 + 7 * i, 33 + 5 * i, i, 2 * i, arrival=0.0)
+            for i in range(6)]
+    res, _ = Server(bank, streams=2).serve(reqs, realtime=False, keep_outputs=True)
+    res_p, _ = PlainServer(bank).serve(reqs, realtime=False, keep_outputs=True)
+    for r, rp in zip(res, res_p):
+        q = r.request
+        grid = smoe.make_grid(q.width, q.height, q.scale, q.origin_x, q.origin_y, mode="rbf")
+        alone, _, _, _ = smoe.render(bank.rows(q.model), 3, 1, grid)
+        assert torch.equal(r.image, alone) and torch.equal(rp.image, alone), q
