@@ -30,11 +30,15 @@
  *    s1 = ln l11, s2 = ln l22, rho = ln pi (Eq. 4), and the expert is
  *    m(x) = a + wx (x - mu_x) + wy (y - mu_y) (order 1) or m = a (order 0).
  *    Gradients are reported in the raw order (d/ds1 = l11 d/dl11, d/ds2 = l22 d/dl22).
- *  - Truncation rule (Eq. 5 with the ellipse discard of Sec. IV-B): kernel j takes part
- *    at output pixel p iff p's block lies in j's block rectangle AND
- *    q_j(p) = |L_j^-1 (p - mu_j)|^2 <= r^2.  The block rectangle comes from the square
- *    box of half-side r * sqrt(lambda_max(Sigma_j)) (side = major axis of the ellipse,
- *    Fig. 3b).  Both decisions are exactly specified binary32 computations:
+ *  - Truncation rule (Eq. 5 with the ellipse discard of Sec. IV-B): kernel j is in the
+ *    list of every block its box covers; with the default reading (SMOE_TRUNC_GRADIENT,
+ *    below) it takes part in the render at output pixel p iff p's block lies in j's block
+ *    rectangle AND q_j(p) = |L_j^-1 (p - mu_j)|^2 <= (2r)^2, and in the gradient iff
+ *    moreover q_j(p) <= r^2 (with SMOE_TRUNC_RENDER, q_j(p) <= r^2 for both).  The block
+ *    rectangle comes from the square box of half-side r * sqrt(lambda_max(Sigma_j)) (side
+ *    = major axis of the ellipse, Fig. 3b), or the tight box (SMOE_BOX_TIGHT).  Every
+ *    decision is an exactly specified binary32 computation (q bounds compared the same way
+ *    with (2r)*(2r)):
  *      i11 = 1/l11, i22 = 1/l22; dx = x - mu_x, dy = y - mu_y; z1 = dx*i11;
  *      z2 = (dy - l21*z1)*i22; q = z1*z1 + z2*z2 (each op rounded, no fma); q <= r*r;
  *      sxx = l11*l11, sxy = l11*l21, syy = l21*l21 + l22*l22;
@@ -125,10 +129,12 @@ typedef struct smoe_grid {
  * syy = l21 l21 + l22 l22 and m = (|mu_x| + |mu_y| + R) 2^-18, in binary32 in that order:
  * the extents of the r-ellipse along x and y, widened by a margin that covers the rounding
  * of the binary32 ellipse test and of the pixel coordinates.  Every pixel the ellipse test
- * accepts inside the square box lies in the tight box, so images and losses are those of
- * the square box, bit for bit; only blocks the ellipse cannot reach leave the block lists.
- * Gradients are the same sums of fewer (zero-free) per-block partials, grouped differently,
- * so they agree up to that rounding.  Any other value is rejected. */
+ * accepts inside the square box lies in the tight box, so with SMOE_TRUNC_RENDER images and
+ * losses are those of the square box, bit for bit; only blocks the ellipse cannot reach
+ * leave the block lists, and gradients are the same sums of fewer (zero-free) per-block
+ * partials, grouped differently, so they agree up to that rounding.  With
+ * SMOE_TRUNC_GRADIENT the render of the dropped blocks loses the kernel's far tail, so the
+ * tight box is then a different (cheaper) rule.  Any other value is rejected. */
 #define SMOE_BOX_SQUARE 0
 #define SMOE_BOX_TIGHT 1
 
@@ -210,7 +216,7 @@ smoe_status smoe_render_workspace_layout(smoe_bins* out, void* workspace, size_t
                                          int32_t C, int32_t order, int32_t max_tiles,
                                          int32_t capacity);
 
-/* Binning (Sec. IV-B, IV-C): per-kernel square box -> block rectangle and count, the
+/* Binning (Sec. IV-B, IV-C): per-kernel box (smoe_grid.box) -> block rectangle and count, the
  * per-kernel render record, then the (block, kernel) pairs ordered by block and, within a
  * block, by kernel id, and each block's [begin, end) range.  The order is the one a
  * stable radix sort by block id of the kernel-major pair list gives.  If P exceeds
