@@ -160,3 +160,20 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
                          check=True).stdout
     assert out.startswith("1 "), out
+
+
+def test_python_rule_settings_validated():
+    """make_grid takes the rule's settings by name and refuses unknown ones (host only)."""
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd import _capi as C
+
+    g = smoe.make_grid(32, 16, 2, 1, 3, 3.0, sharpen=1.5, box="tight", mode="rbf",
+                       trunc="render")
+    assert (g.box, g.mode, g.trunc) == (C.SMOE_BOX_TIGHT, C.SMOE_MODE_RBF, C.SMOE_TRUNC_RENDER)
+    assert abs(g.sharpen - 1.5) < 1e-7 and g.scale == 2 and g.origin_y == 3
+    d = smoe.make_grid(8, 8)
+    assert (d.sharpen, d.box, d.mode, d.trunc) == (1.0, C.SMOE_BOX_SQUARE, C.SMOE_MODE_SMOE,
+                                                   C.SMOE_TRUNC_GRADIENT)
+    for bad in (dict(box="round"), dict(mode="gauss"), dict(trunc="both")):
+        with pytest.raises(ValueError):
+            smoe.make_grid(8, 8, **bad)
