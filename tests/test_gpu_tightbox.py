@@ -184,3 +184,28 @@ def test_tight_batched_and_serving_equal_square(smoe):
         res.append(r)
     for a, b in zip(*res):
         assert torch.equal(a.image, b.image)
+
+
+@pytest.mark.parametrize("trunc", ["gradient", "render"])
+@pytest.mark.parametrize("mode", ["smoe", "rbf"])
+def test_all_rule_settings_combined(smoe, mode, trunc, record_error):
+    """Sharpening, the tight box, the regression mode and the truncation reading together:
+    block lists bit-exact and images within 1e-5 (of the peak magnitude) of the oracle."""
+    say("combined", mode, trunc)
+    W, H, s, ox, oy, f = 52, 44, 2, 3, 5, 1.4
+    m_np = wl.stretched_model(160, 3, 1, W, H, 530)
+    m_np[:, 5] -= 1.0
+    OW, OH = s * W - ox, s * H - oy
+    m = dev(m_np)
+    grid = smoe.make_grid(OW, OH, s, ox, oy, sharpen=f, box="tight", mode=mode, trunc=trunc)
+    b, got = _bins(smoe, m, grid, smoe.tiles(OW, OH))
+    ms = oracle.sharpen(m_np, f)
+    ob = oracle.bin(ms, 3, 1, OW, OH, s, ox, oy, box=1)
+    assert got["P"] == ob["P"]
+    for k in ("tile_rects", "counts", "vals", "ranges"):
+        assert np.array_equal(got[k], ob[k]), k
+    img, _, _, _ = smoe.render(m, 3, 1, grid, bins=b)
+    y_o, _ = oracle.render(ms, 3, 1, OW, OH, s, ox, oy, box=1, rbf=(mode == "rbf"), trunc=trunc)
+    e = float(np.max(np.abs(host(img) - y_o))) / max(1.0, float(np.abs(y_o).max()))
+    record_error(f"combined {mode}/{trunc} image", e, Y_TOL)
+    assert e <= Y_TOL
