@@ -281,6 +281,8 @@ def run(args):
         out["rbf_vs_smoe"] = run_rbf_vs_smoe(args)
     if not args.no_long:
         out["long_lists"] = run_long_lists(args)
+    if not args.no_readings:
+        out["truncation_readings"] = run_truncation_readings(args)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -532,6 +534,41 @@ def run_rbf_vs_smoe(args):
                 row[f"psnr_{mode}_db"] = smoe.psnr(st.image, c)
                 row[f"iters_per_s_{mode}"] = steps / dt
             out["runs"].append(row)
+    return out
+
+
+def run_truncation_readings(args):
+    """The two readings of where Sec. IV-B's ellipse discard applies, on the headline
+    workload fitted for the paper's 10 000 iterations from the same initialisation: the
+    block lists deciding the render with the discard in the gradient (the default), and the
+    ellipse test in the render too.  PSNR against the clean image and the fraction of pixels
+    no kernel reaches (D = 0) along the way, and fit iterations/s."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    w = wl.workload(3)
+    H, W, C = w.target.shape
+    target = torch.from_numpy(w.target).cuda()
+    clean = torch.from_numpy(w.clean).cuda()
+    out = {}
+    for trunc in ("gradient", "render"):
+        st = smoe.FitState(target, torch.from_numpy(w.raw0).cuda(), 1,
+                           smoe.AdamConfig(total_steps=10000), max_steps=1, capacity=W * H,
+                           trunc=trunc)
+        rows, elapsed, done = [], 0.0, 0
+        for goal in (1000, 2000, 5000, 10000):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.run_graphed(goal - done)
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            done = goal
+            rows.append({"steps": goal, "psnr_vs_clean_db": smoe.psnr(st.image, clean),
+                         "stranded_px_frac": float((st.denom == 0).float().mean().item())})
+        out[trunc] = {"trace": rows, "iters_per_s": done / elapsed}
+        del st
     return out
 
 
@@ -798,6 +835,8 @@ def main():
     ap.add_argument("--no-rbf", action="store_true", help="skip the RBF vs SMoE run")
     ap.add_argument("--rbf-steps", type=int, default=10000)
     ap.add_argument("--no-long", action="store_true", help="skip the long-list render run")
+    ap.add_argument("--no-readings", action="store_true",
+                    help="skip the comparison of the two truncation readings")
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
