@@ -135,3 +135,27 @@ def test_long_lists_gradient(smoe, record_error):
         e = float(np.max(np.abs(g[:, cols] - g_o[:, cols]))) / scale
         record_error(f"long-list grad {name} rel", e, 1e-3)
         assert e <= 1e-3, name
+
+
+def test_long_lists_in_a_batch_equal_alone(smoe):
+    """A batch whose rasters mix long and short lists: each raster's image is bitwise the one
+    it gets rendered alone (the split render finds its blocks' rasters through the table)."""
+    import torch
+    say("long lists batched")
+    wide = wide_model(300, 3, 1, 48, 40, 730, 12.0, 25.0)
+    narrow = wl.random_model(120, 3, 1, 64, 48, 731, sig_lo=0.8, sig_hi=4.0)
+    params = dev(np.concatenate([wide, narrow]))
+    specs = [(0, 48, 40, 1, 0, 0), (1, 64, 48, 1, 0, 0), (0, 96, 80, 2, 0, 0), (1, 110, 90, 2, 9, 4)]
+    rasters = [dict(width=w, height=h, scale=s, origin_x=ox, origin_y=oy,
+                    num_kernels=(300 if i == 0 else 120), param_offset=(0 if i == 0 else 300))
+               for i, w, h, s, ox, oy in specs]
+    segs = smoe.Segments(rasters)
+    bins = smoe.bin_batched(params, 3, 1, segs)
+    out = torch.empty((segs.pixels, 3), dtype=torch.float32, device="cuda")
+    smoe.render_batched(params, 3, 1, segs, bins, out)
+    for (a, e, h, w), (i, _, _, s, ox, oy) in zip(segs.pixel_slices(), specs):
+        m = dev(wide if i == 0 else narrow)
+        alone, _, _, b = smoe.render(m, 3, 1, smoe.make_grid(w, h, s, ox, oy))
+        if i == 0:
+            assert b.read_status()[1][2] > 128
+        assert torch.equal(out[a:e].view(h, w, 3), alone), (i, s)
