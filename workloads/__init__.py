@@ -197,6 +197,21 @@ def grid_init(image: np.ndarray, gx: int, gy: int, sigma: float = 4.0, order: in
     return raw, model
 
 
+def random_init(image: np.ndarray, K: int, sigma: float = 5.0, seed: int = 0, order: int = 0):
+    """K round kernels at uniformly random centres with a fixed standard deviation (the
+    random initialisation with a fixed scaling of 5 pixels, Sec. VI-B), unit mixing weight,
+    expert constant = the image at the centre, zero slopes.  Returns the raw rows float32
+    [K, NP] (log-diagonal Cholesky)."""
+    rng = _rng(seed + 11)
+    H, W, C = image.shape
+    raw = np.zeros((K, num_params(C, order)), dtype=np.float32)
+    raw[:, 0] = rng.uniform(0.0, W, K)
+    raw[:, 1] = rng.uniform(0.0, H, K)
+    raw[:, 2] = raw[:, 4] = np.float32(math.log(sigma))
+    raw[:, 6:6 + C] = image[np.floor(raw[:, 1]).astype(int), np.floor(raw[:, 0]).astype(int), :]
+    return raw
+
+
 def random_model(K: int, C: int, order: int, W: int, H: int, seed: int,
                  sig_lo: float = 1.0, sig_hi: float = 10.0, margin: float = 12.0,
                  shear: float = 0.6, rho_std: float = 0.5, slope_std: float = 0.02):
