@@ -890,6 +890,9 @@ def main():
     ap.add_argument("--no-rbf", action="store_true", help="skip the RBF vs SMoE run")
     ap.add_argument("--rbf-steps", type=int, default=10000)
     ap.add_argument("--no-long", action="store_true", help="skip the long-list render run")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed fit, its roofline and profile (no CPU baseline and no "
+                         "other section); the profiles are taken this way")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the fits shaped like the paper's Table I")
     ap.add_argument("--no-readings", action="store_true",
@@ -897,6 +900,10 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
+    if args.headline_only:
+        for k in ("no_cpu_baseline", "no_serving", "no_batched_fit", "no_mm", "no_tight",
+                  "no_rbf", "no_long", "no_readings", "no_table1"):
+            setattr(args, k, True)
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.profile_command)
         return 0
