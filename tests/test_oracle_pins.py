@@ -774,3 +774,37 @@ def test_gradient_only_ellipse_per_pair_differences():
         rm = raw.copy(); rm[j, 6] -= h
         full[j, 6] = ((pixel_errors(rp) - pixel_errors(rm)) / (2 * h))[cover[j]].sum()
     assert np.max(np.abs(full[:, 6] - g[:, 6])) > 1e-3 * np.max(np.abs(g[:, 6]))
+
+
+# --------------------------------------------------------------------------- golden
+
+
+def _golden(name):
+    import os
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k1, v1, k2, v2 = line.split()
+                rows[(k1, float(v1))] = (k2, float(v2))
+    return rows
+
+
+def test_confidence_ellipse_mass_golden():
+    """Sec. IV-B's 99 % confidence ellipse: the fixture's radius and mass, checked by the
+    closed form and by integrating the oracle's untruncated single-kernel render over a fine
+    raster (the fraction of its mass inside q <= r^2, which the render-side ellipse test
+    keeps)."""
+    g = _golden("confidence_ellipse.txt")
+    r99 = g[("mass", 0.99)][1]
+    m3 = g[("radius", 3.0)][1]
+    assert r99 == pytest.approx(math.sqrt(-2 * math.log(0.01)), rel=1e-15)
+    assert m3 == pytest.approx(1 - math.exp(-4.5), rel=1e-15)
+    # one round kernel, sigma = 4 native px, on a raster reaching 6 sigma from its centre,
+    # sampled at scale 4 (pixel area 1/16)
+    s, sig, W = 4, 4.0, 192
+    m = np.array([[W / (2 * s), W / (2 * s), sig, 0.0, sig, 0.0, 1.0]])
+    _, D_all = oracle.render(m, 1, 0, W, W, s=s, truncated=False)
+    for r, mass in ((3.0, m3), (r99, 0.99)):
+        _, D_in = oracle.render(m, 1, 0, W, W, s=s, r=r, trunc="render")
+        assert D_in.sum() / D_all.sum() == pytest.approx(mass, abs=2e-3)
