@@ -86,7 +86,8 @@ typedef struct smoe_grid {
   int32_t width, height;       /* output pixels, 1 .. 65536 each */
   int32_t scale;               /* integer upscale factor, 1 .. 64 */
   int32_t origin_x, origin_y;  /* raster origin in output pixels, |.| <= 2^22 */
-  float radius;                /* Mahalanobis truncation radius r > 0 (3 = 98.9 % mass) */
+  float radius;                /* Mahalanobis truncation radius r in [2^-30, 2^30]
+                                  (3 = 98.9 % mass) */
   float sharpen;               /* native sharpening (Sec. II-B, VII): every kernel is rendered
                                   with its bandwidth divided by this factor, L -> L / f (the
                                   box and the truncation test follow); f > 0, 0 or 1 = none.
@@ -170,7 +171,7 @@ typedef struct smoe_batch {
   int32_t num_segments;               /* >= 1 */
   const smoe_segment* segments;       /* device copy of the laid-out table */
   const smoe_segment* segments_host;  /* host copy of the same table */
-  float radius;                       /* Mahalanobis truncation radius */
+  float radius;                       /* truncation radius, as in smoe_grid */
   int32_t box;                        /* SMOE_BOX_SQUARE or SMOE_BOX_TIGHT */
   int32_t mode;                       /* SMOE_MODE_SMOE or SMOE_MODE_RBF */
   int32_t trunc;                      /* SMOE_TRUNC_GRADIENT or SMOE_TRUNC_RENDER */

@@ -29,7 +29,9 @@ bool valid_raster(int32_t W, int32_t H, int32_t scale, int32_t ox, int32_t oy) {
   return std::abs(ox) <= (1 << 22) && std::abs(oy) <= (1 << 22);
 }
 
-bool valid_radius(float r) { return r > 0.0f && std::isfinite(r); }
+// Truncation radius in [2^-30, 2^30]: the render's bound (2r)^2 or r^2 is then a normal
+// binary32 number whose compare-free cut constants are exact.
+bool valid_radius(float r) { return r >= 0x1p-30f && r <= 0x1p30f; }
 // Sharpening factor: 0 (none) or a finite positive bandwidth divisor.
 bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f)); }
 bool no_sharpen(float f) { return f == 0.0f || f == 1.0f; }
@@ -42,6 +44,16 @@ bool valid_trunc(int32_t t) { return t == SMOE_TRUNC_RENDER || t == SMOE_TRUNC_G
 float render_bound(float r, int32_t trunc) {
   const float r2r = 2.0f * r;
   return trunc == SMOE_TRUNC_RENDER ? r * r : r2r * r2r;
+}
+
+// The render's bound and its compare-free form (Segs::cut_scale, cut_offset).  The radius
+// range keeps r2_render a normal binary32 number with a representable power-of-two scale.
+void set_render_bound(Segs& S) {
+  S.r2_render = render_bound(S.r, S.trunc);
+  int e = 0;
+  std::frexp(S.r2_render, &e);  // r2_render = f 2^e with f in [0.5, 1)
+  S.cut_scale = std::ldexp(1.0f, 61 - e);
+  S.cut_offset = -S.r2_render * S.cut_scale;
 }
 
 long long raster_tiles(int32_t W, int32_t H) {
@@ -70,7 +82,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   S.box = g->box;
   S.mode = g->mode;
   S.trunc = g->trunc;
-  S.r2_render = render_bound(S.r, S.trunc);
+  set_render_bound(S);
   S.T = (int)raster_tiles(g->width, g->height);
   S.K = m->K;
   *out = S;
@@ -116,7 +128,7 @@ bool batch_segs(const smoe_batch* b, Segs* out) {
   S.box = b->box;
   S.mode = b->mode;
   S.trunc = b->trunc;
-  S.r2_render = render_bound(S.r, S.trunc);
+  set_render_bound(S);
   *out = S;
   return true;
 }
@@ -190,7 +202,7 @@ bool fit_segs(const smoe_fit_state* st, Segs* S) {
     S->box = st->grid.box;
     S->mode = st->grid.mode;
     S->trunc = st->grid.trunc;
-    S->r2_render = render_bound(S->r, S->trunc);
+    set_render_bound(*S);
     return true;
   }
   const smoe_model m{st->K, st->C, st->order, st->model};

@@ -72,7 +72,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live = 0;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, rg, srec, D, N, live);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records, a.vals, rg,
+                               srec, D, N, live);
 
   PixelSeed<C> sd;
   float err = 0.0f;

@@ -80,8 +80,8 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.r2_render, a.records, a.vals, rg, srec, D, N,
-                               live);
+  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records, a.vals, rg,
+                               srec, D, N, live);
   render_epilogue<C, RBF>(a, sg, px, tile, D, N);
 }
 
@@ -107,6 +107,7 @@ __device__ __forceinline__ void render_wide_block(const RenderArgs& a, int tile,
   const int b = rg.x + min(len, wv * per), e = rg.x + min(len, (wv + 1) * per);
   float D[kRows], N[kRows][C];
   zero_sums<C>(D, N);
+  const float cut_scale = in_vgpr(a.S.cut_scale), cut_offset = in_vgpr(a.S.cut_offset);
   float4* my = srec[wv];
   for (int base = b; base < e; base += kChunk) {
     const int n = min(kChunk, e - base);
@@ -119,7 +120,7 @@ __device__ __forceinline__ void render_wide_block(const RenderArgs& a, int tile,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int k = 0; k < n; ++k)
-      forward_entry<C, ORDER>(px, a.S.r2, a.S.r2_render,
+      forward_entry<C, ORDER>(px, a.S.r2, cut_scale, cut_offset,
                               reinterpret_cast<const float*>(&my[k * Q]), D, N);
   }
   if (wv > 0) {

@@ -38,6 +38,12 @@ struct Segs {
   smoe_segment one;                      // the single raster when tab is null
   float r, r2;                           // truncation radius and r*r (binary32)
   float r2_render;                       // the render's bound on q: r2, or (2r)^2
+  // The render's bound applied without a compare: with cut_scale = 2^k such that
+  // r2_render * 2^k lies in [2^60, 2^61) and cut_offset = -r2_render * 2^k (both exact),
+  // u = fma(q, cut_scale, cut_offset) is <= 0 for q <= r2_render and >= 2^37 beyond it, so
+  // max(q, u) is q inside the bound and pushes the exponent of a term beyond it to about
+  // -2^36, whose exp2 is exactly zero.
+  float cut_scale, cut_offset;
   int box;                               // SMOE_BOX_SQUARE or SMOE_BOX_TIGHT
   int mode;                              // SMOE_MODE_SMOE or SMOE_MODE_RBF
   int trunc;                             // SMOE_TRUNC_RENDER or SMOE_TRUNC_GRADIENT

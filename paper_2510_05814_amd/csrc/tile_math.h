@@ -71,12 +71,19 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
 // the lane's four pixels, for the pixels with q <= r2_render: r^2 (the ellipse test in the
 // render) or (2r)^2 (the block lists decide the render; the cut keeps every term inside
 // FP32's accurate range).  Returns whether any of the lane's pixels passed the ellipse test
-// q <= r2.  r: the entry's render record.
+// q <= r2.  r: the entry's render record; cut_scale, cut_offset: the render's bound in the
+// compare-free form of Segs.
+//
+// Neither test is a per-row compare: a VALU instruction that writes or reads a scalar
+// register (a compare's lane mask, a select on it) issues at about 60 % of the rate of one
+// on vector registers alone.  The ellipse test compares the minimum of the four rows' q
+// once; the render's bound goes through the exponent (max(q, u) is q inside the bound, and
+// a term beyond it gets an exponent of about -2^36, whose exp2 is exactly zero), so every
+// kept term carries the same bits as with a select.
 template <int C, int ORDER>
-__device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, float r2_render,
-                                              const float* r, float (&D)[kRows],
-                                              float (&N)[kRows][C]) {
-  bool hit = false;
+__device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, float cut_scale,
+                                              float cut_offset, const float* r,
+                                              float (&D)[kRows], float (&N)[kRows][C]) {
   // Truncation test: the binary32 sequence of the ABI contract (no contraction).
   const float dx = px.x - r[0];
   const float z1 = dx * r[2];
@@ -88,27 +95,36 @@ __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, f
   for (int c = 0; c < C; ++c)
     mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
                        : r[kRecExpert + c];
+  float q[kRows], dy[kRows];
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
-    const float dy = px.y[i] - r[1];
-    const float w = dy - tt;
+    dy[i] = px.y[i] - r[1];
+    const float w = dy[i] - tt;
     const float z2 = w * r[4];
-    const float q = zz1 + z2 * z2;
-    hit |= q <= r2;
-    // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2); a pair beyond the render's
-    // bound adds exactly zero (no branch: nearly every tested pair is inside it when the
-    // block lists decide the render, and the four rows then interleave freely)
-    const float ex = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
-    const float e = q <= r2_render ? ex : 0.0f;
+    q[i] = zz1 + z2 * z2;
+  }
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
+    const float qc = __builtin_fmaxf(q[i], __builtin_fmaf(q[i], cut_scale, cut_offset));
+    const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(qc, -0.5f * kLog2e, r[5]));
     D[i] += e;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       float m = mx[c];
-      if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
+      if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy[i], m);
       N[i][c] = __builtin_fmaf(e, m, N[i][c]);
     }
   }
-  return hit;
+  static_assert(kRows == 4, "the ellipse test takes the minimum of four rows");
+  return __builtin_fminf(__builtin_fminf(q[0], q[1]), __builtin_fminf(q[2], q[3])) <= r2;
+}
+
+// A copy of x that the compiler must keep in a vector register: loop-invariant operands of
+// the forward's per-row arithmetic are read from VGPRs rather than SGPRs (see forward_entry).
+__device__ __forceinline__ float in_vgpr(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
 }
 
 template <int C>
@@ -127,7 +143,7 @@ __device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
 template <int C, int ORDER>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
-                                                   float r2_render,
+                                                   float cut_scale, float cut_offset,
                                                    const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int2 rg,
                                                    float4* srec, float (&D)[kRows],
@@ -135,13 +151,16 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   zero_sums<C>(D, N);
+  cut_scale = in_vgpr(cut_scale);
+  cut_offset = in_vgpr(cut_offset);
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     stage_records<RS>(srec, records, vals, base, n);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      if (__any(forward_entry<C, ORDER>(px, r2, r2_render, r, D, N))) live |= 1ull << k;
+      if (__any(forward_entry<C, ORDER>(px, r2, cut_scale, cut_offset, r, D, N)))
+        live |= 1ull << k;
     }
   }
 }
@@ -149,6 +168,20 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// m ? a : b for a per-lane mask m of all ones or all zeros, held in a vector register
+// (v_bfi_b32 instead of a select on a scalar lane mask: see forward_entry).
+__device__ __forceinline__ float lane_select(uint32_t m, float a, float b) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(__float_as_uint(a)),
+      "v"(__float_as_uint(b)));
+  return __uint_as_float(r);
+}
+
+// All ones in the lanes whose index has bit `bit` set, else zero.
+__device__ __forceinline__ uint32_t lane_bit_mask(int lane, int bit) {
+  return 0u - ((uint32_t)lane >> bit & 1u);
 }
 
 // Transposed wave reduction of 16 values: on return lane l holds the sum over all 64 lanes
@@ -202,24 +235,24 @@ __device__ __forceinline__ float wave_reduce16_transposed(float (&v)[16]) {
 // Every lane of the row must be active.
 __device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
   const int lane = threadIdx.x & 63;
-  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0,
-             b0 = (lane & 1) != 0;
+  const uint32_t b3 = lane_bit_mask(lane, 3), b2 = lane_bit_mask(lane, 2),
+                 b1 = lane_bit_mask(lane, 1), b0 = lane_bit_mask(lane, 0);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
+    const float keep = lane_select(b3, v[i + 8], v[i]), send = lane_select(b3, v[i], v[i + 8]);
     v[i] = keep + dpp<0x128>(send);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
+    const float keep = lane_select(b2, v[i + 4], v[i]), send = lane_select(b2, v[i], v[i + 4]);
     v[i] = keep + dpp<0x141>(send);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
+    const float keep = lane_select(b1, v[i + 2], v[i]), send = lane_select(b1, v[i], v[i + 2]);
     v[i] = keep + dpp<0x4E>(send);
   }
-  const float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
+  const float keep = lane_select(b0, v[1], v[0]), send = lane_select(b0, v[0], v[1]);
   return keep + dpp<0xB1>(send);
 }
 

@@ -97,7 +97,10 @@ def test_invalid_arguments_rejected_before_launch():
     m = C.SmoeModel(4, 3, 1, 1 << 20)
     for g in [C.SmoeGrid(0, 64, 1, 0, 0, 3.0), C.SmoeGrid(64, 64, 0, 0, 0, 3.0),
               C.SmoeGrid(64, 64, 1, 0, 0, 0.0), C.SmoeGrid(64, 64, 1, 0, 0, float("nan")),
-              C.SmoeGrid(64, 64, 1, 1 << 23, 0, 3.0), C.SmoeGrid(70000, 64, 1, 0, 0, 3.0)]:
+              C.SmoeGrid(64, 64, 1, 1 << 23, 0, 3.0), C.SmoeGrid(70000, 64, 1, 0, 0, 3.0),
+              # the radius range [2^-30, 2^30]
+              C.SmoeGrid(64, 64, 1, 0, 0, 2.0 ** -31), C.SmoeGrid(64, 64, 1, 0, 0, 2.0 ** 31),
+              C.SmoeGrid(64, 64, 1, 0, 0, float("inf"))]:
         assert lib.smoe_bin(ct.byref(m), ct.byref(g), ct.byref(b), None) == C.SMOE_ERR_INVALID
     # the rule's variants: sharpening factor, box, regression mode, truncation reading
     for fields in [dict(sharpen=-1.0), dict(sharpen=float("nan")), dict(sharpen=float("inf")),
