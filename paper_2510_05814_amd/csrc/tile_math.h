@@ -170,20 +170,6 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-// m ? a : b for a per-lane mask m of all ones or all zeros, held in a vector register
-// (v_bfi_b32 instead of a select on a scalar lane mask: see forward_entry).
-__device__ __forceinline__ float lane_select(uint32_t m, float a, float b) {
-  uint32_t r;
-  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(__float_as_uint(a)),
-      "v"(__float_as_uint(b)));
-  return __uint_as_float(r);
-}
-
-// All ones in the lanes whose index has bit `bit` set, else zero.
-__device__ __forceinline__ uint32_t lane_bit_mask(int lane, int bit) {
-  return 0u - ((uint32_t)lane >> bit & 1u);
-}
-
 // Transposed wave reduction of 16 values: on return lane l holds the sum over all 64 lanes
 // of v[(l >> 2) & 15].  Each stage pairs every lane with one whose index differs in the next
 // bit (5, 4, 3, 2); a lane keeps the half of its values selected by that bit and adds the
@@ -235,24 +221,24 @@ __device__ __forceinline__ float wave_reduce16_transposed(float (&v)[16]) {
 // Every lane of the row must be active.
 __device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
   const int lane = threadIdx.x & 63;
-  const uint32_t b3 = lane_bit_mask(lane, 3), b2 = lane_bit_mask(lane, 2),
-                 b1 = lane_bit_mask(lane, 1), b0 = lane_bit_mask(lane, 0);
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0,
+             b0 = (lane & 1) != 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float keep = lane_select(b3, v[i + 8], v[i]), send = lane_select(b3, v[i], v[i + 8]);
+    const float keep = b3 ? v[i + 8] : v[i], send = b3 ? v[i] : v[i + 8];
     v[i] = keep + dpp<0x128>(send);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float keep = lane_select(b2, v[i + 4], v[i]), send = lane_select(b2, v[i], v[i + 4]);
+    const float keep = b2 ? v[i + 4] : v[i], send = b2 ? v[i] : v[i + 4];
     v[i] = keep + dpp<0x141>(send);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float keep = lane_select(b1, v[i + 2], v[i]), send = lane_select(b1, v[i], v[i + 2]);
+    const float keep = b1 ? v[i + 2] : v[i], send = b1 ? v[i] : v[i + 2];
     v[i] = keep + dpp<0x4E>(send);
   }
-  const float keep = lane_select(b0, v[1], v[0]), send = lane_select(b0, v[0], v[1]);
+  const float keep = b0 ? v[1] : v[0], send = b0 ? v[0] : v[1];
   return keep + dpp<0xB1>(send);
 }
 
