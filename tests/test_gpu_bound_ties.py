@@ -1,0 +1,93 @@
+"""Ties at the render's bound and the ends of the radius range.  A unit-covariance kernel
+centred half a pixel off the grid puts pixel centres at q = r^2 and q = (2r)^2 exactly; a
+term kept or dropped at such a tie turns the pixel's value from the expert's into 0 (no other
+kernel covers it), so the image pins each decision: q <= bound keeps the term, the next pixel
+out drops it, on both readings of the truncation, as the oracle decides.  Radii at both ends
+of the accepted range [2^-30, 2^30] render as the oracle does."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smoe():
+    import torch  # noqa: F401
+
+    import paper_2510_05814_amd as smoe
+    return smoe
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+EXPERT = np.array([0.3, 0.6, 0.9])
+
+
+def unit_kernel(mx, my):
+    # [mu_x, mu_y, l11, l21, l22, rho, a_0..a_2]: unit covariance, pi = 1, constant expert
+    return np.array([[mx, my, 1.0, 0.0, 1.0, 0.0, *EXPERT]])
+
+
+@pytest.mark.parametrize("trunc,tie_u,bound", [("render", 8, 9.0), ("gradient", 11, 36.0)])
+def test_tie_at_the_bound_is_kept(smoe, trunc, tie_u, bound, record_error):
+    say("bound tie", trunc)
+    m_np = unit_kernel(5.5, 5.5)
+    grid = smoe.make_grid(16, 16, trunc=trunc)
+    img, D, _, _ = smoe.render(dev(m_np), 3, 0, grid)
+    img, D = host(img), host(D)
+    # pixel (tie_u, 5): x = tie_u + 0.5, so q = (tie_u - 5)^2 = the bound exactly
+    assert (tie_u - 5.0) ** 2 == bound
+    assert D[5, tie_u] > 0.0 and np.max(np.abs(img[5, tie_u] - EXPERT)) <= 1e-6
+    assert D[5, tie_u + 1] == 0.0 and not img[5, tie_u + 1].any()
+    y_o, D_o = oracle.render(m_np, 3, 0, 16, 16, trunc=trunc)
+    assert np.array_equal(D > 0, D_o > 0)
+    e = float(np.max(np.abs(img - y_o)))
+    record_error(f"bound tie {trunc} image", e, 1e-5)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("trunc", ["render", "gradient"])
+@pytest.mark.parametrize("radius", [2.0 ** -30, 2.0 ** 10])
+def test_radius_range_ends(smoe, radius, trunc, record_error):
+    say("radius", radius, trunc)
+    rng = np.random.default_rng(int(np.log2(radius)) + 40)
+    W, H = 40, 24
+    m_np = np.concatenate([unit_kernel(5.5, 5.5), unit_kernel(20.5, 11.5),
+                           unit_kernel(rng.uniform(0, W), rng.uniform(0, H))])
+    if radius < 1.0:
+        m_np[:, 2] = [1.0, 2.0, 0.5]
+        m_np[:, 3] = [0.0, 0.7, -0.3]
+    else:
+        # wide kernels: every pixel keeps terms far above binary32's underflow, so that the
+        # single-precision render covers the same pixels as the oracle's double precision
+        m_np[:, 2] = [15.0, 25.0, 12.0]
+        m_np[:, 3] = [0.0, 4.0, -3.0]
+        m_np[:, 4] = [15.0, 10.0, 20.0]
+    m_np[:, 6:] = rng.uniform(0, 1, (3, 3))
+    grid = smoe.make_grid(W, H, radius=radius, trunc=trunc)
+    img, D, _, b = smoe.render(dev(m_np), 3, 0, grid)
+    over, _ = b.read_status()
+    assert not over
+    y_o, D_o = oracle.render(m_np, 3, 0, W, H, r=radius, trunc=trunc)
+    assert np.array_equal(host(D) > 0, D_o > 0)
+    e = float(np.max(np.abs(host(img) - y_o)))
+    record_error(f"radius {radius} {trunc} image", e, 1e-5)
+    assert e <= 1e-5
+    if radius < 1.0:
+        # only the centre pixels of the first two kernels lie inside the tiny ellipse
+        assert int((D_o > 0).sum()) == 2
+    else:
+        assert (D_o > 0).all()
