@@ -156,6 +156,9 @@ hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s, const i
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
                               const smoe_bins& b, hipStream_t s) {
   k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
+  // A fresh fit starts from clear status words (P, overflow, longest list, step shadow and
+  // the overflow flags), whatever the workspace held before.
+  k_fill_i32<<<1, 64, 0, s>>>(b.status, 8, 0);
   if (S.K > 0) {
     k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects), b.counts,

@@ -1,0 +1,31 @@
+"""A fresh fit on a workspace holding arbitrary bytes: the first step clears the status
+words (overflow flags included) itself, so the fit proceeds exactly as on a zeroed
+workspace."""
+import pytest
+import torch
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fresh_fit_on_dirty_workspace():
+    import paper_2510_05814_amd as smoe
+
+    w = wl.workload(1)
+    target = torch.from_numpy(w.target).cuda()
+    raw0 = torch.from_numpy(w.raw0).cuda()
+    adam = smoe.AdamConfig.constant(1e-2, 20)
+    print("[case] fit 64x64 K=64 on a zeroed and on a 0xFF-filled workspace", flush=True)
+    a = smoe.FitState(target, raw0, w.order, adam, max_steps=20)
+    b = smoe.FitState(target, raw0, w.order, adam, max_steps=20)
+    b.bins.ws.fill_(0xFF)
+    for _ in range(20):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert a.steps_done() == b.steps_done() == 20
+    assert torch.equal(a.raw, b.raw)
+    assert torch.equal(a.losses(), b.losses())
+    over, _ = b.bins.read_status()
+    assert not over
