@@ -11,7 +11,8 @@
  * Conventions shared by every call
  * --------------------------------
  *  - Pointers marked "device" are HIP device pointers; all buffers are owned by the
- *    caller.  The library allocates no device memory and keeps no global state.
+ *    caller.  The library allocates no device memory and keeps no global state besides
+ *    the static workspace of smoe_render_noalloc (one array per GPU).
  *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*; NULL = the
  *    null stream) and returns a status.  Arguments are validated on the host before
  *    anything is launched; on SMOE_ERR_INVALID nothing was enqueued.
@@ -253,6 +254,23 @@ smoe_status smoe_render_backward(const smoe_model* model, const smoe_grid* grid,
 smoe_status smoe_bin_batched(const smoe_batch* batch, smoe_bins* bins, void* stream);
 smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, float* images,
                                 float* denoms, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): smoe_bin + smoe_render of one raster with
+ * no caller workspace.  The binning workspace lives in a static device array of the library
+ * (64 MiB per GPU, held until the process ends), laid out as a render-only workspace with
+ * max_tiles = the raster's blocks and the largest pair capacity that fits.  The caller
+ * passes the model, the raster and the outputs only: image (device [H][W][C]), denom
+ * (device [H][W], may be NULL) and status_out (device int32[4], may be NULL: receives the
+ * status words P needed, overflow flag, longest list, spare).  Images are bitwise those of
+ * smoe_bin + smoe_render with the same model and grid.  Returns SMOE_ERR_TOO_LARGE when the
+ * per-kernel and per-block arrays alone exceed the static array; a pair overflow is
+ * reported through status_out[1] (the image is then zeros), never by a host sync.  Nothing
+ * is allocated, and no hipMemset is issued.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  The library sets up a device's array on its first call there. */
+smoe_status smoe_render_noalloc(const smoe_model* model, const smoe_grid* grid, float* image,
+                                float* denom, int32_t* status_out, void* stream);
 
 /* raw -> materialized rows (l11 = exp(s1), l22 = exp(s2), the rest copied), device. */
 smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw,

@@ -139,6 +139,8 @@ def _load():
     L.smoe_render_batched.restype = _i32
     L.smoe_fit_segment_losses.argtypes = [P(SmoeFitState), _vp, _vp]
     L.smoe_fit_segment_losses.restype = _i32
+    L.smoe_render_noalloc.argtypes = [P(SmoeModel), P(SmoeGrid), _vp, _vp, _vp, _vp]
+    L.smoe_render_noalloc.restype = _i32
     return L
 
 
@@ -149,7 +151,8 @@ EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "sm
             "smoe_render", "smoe_render_backward", "smoe_materialize", "smoe_fit_step",
             "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status", "smoe_segments_layout",
             "smoe_bin_batched", "smoe_render_batched", "smoe_fit_segment_losses",
-            "smoe_render_workspace_bytes", "smoe_render_workspace_layout", "smoe_last_error"]
+            "smoe_render_workspace_bytes", "smoe_render_workspace_layout", "smoe_last_error",
+            "smoe_render_noalloc"]
 
 
 def _check(fn: str, code: int, allow=()):
@@ -253,3 +256,9 @@ def smoe_render_batched(batch: SmoeBatch, bins: SmoeBins, images_ptr, denoms_ptr
 def smoe_fit_segment_losses(state: SmoeFitState, out_ptr, stream):
     return _check("smoe_fit_segment_losses", lib.smoe_fit_segment_losses(ct.byref(state), out_ptr,
                                                                          stream))
+
+
+def smoe_render_noalloc(model, grid, image_ptr, denom_ptr, status_ptr, stream):
+    return _check("smoe_render_noalloc",
+                  lib.smoe_render_noalloc(ct.byref(model), ct.byref(grid), image_ptr, denom_ptr,
+                                          status_ptr, stream))

@@ -178,6 +178,30 @@ def render(params: torch.Tensor, C_: int, order: int, grid: C.SmoeGrid, bins: Bi
     return image, denom, loss, bins
 
 
+def render_noalloc(params: torch.Tensor, C_: int, order: int, grid: C.SmoeGrid, image=None,
+                   denom=None, status=None, stream=None):
+    """Bin + render through smoe_render_noalloc (the library's static workspace: no device
+    allocation inside the call).  image [H, W, C], denom [H, W] and status int32[4] may be
+    given preallocated (a caller that must not allocate passes all three); missing ones are
+    allocated here, outside the library call.  Returns (image, denom, status)."""
+    m = model_struct(params, C_, order)
+    dev = params.device
+    if image is None:
+        image = torch.empty((grid.height, grid.width, C_), dtype=torch.float32, device=dev)
+    if denom is None:
+        denom = torch.empty((grid.height, grid.width), dtype=torch.float32, device=dev)
+    if status is None:
+        status = torch.empty(4, dtype=torch.int32, device=dev)
+    for t, shape, dt in ((image, (grid.height, grid.width, C_), torch.float32),
+                         (denom, (grid.height, grid.width), torch.float32),
+                         (status, (4,), torch.int32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"output must be a contiguous cuda {dt} {shape} tensor")
+    C.smoe_render_noalloc(m, grid, image.data_ptr(), denom.data_ptr(), status.data_ptr(),
+                          _stream(stream))
+    return image, denom, status
+
+
 def render_backward(params, C_, order, grid, bins: Bins, image, denom, grad_image=None,
                     target=None, stream=None) -> torch.Tensor:
     """dL/dparams [K, NP] in raw order (mu, s1, l21, s2, rho, a, wx, wy)."""

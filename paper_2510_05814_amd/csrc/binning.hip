@@ -130,6 +130,11 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
@@ -181,6 +186,11 @@ hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s) {
         S, reinterpret_cast<const int4*>(b.tile_rects), reinterpret_cast<const int2*>(b.ranges),
         b.tile_counts, b.vals, b.status);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s) {
+  k_copy_i32<<<1, 64, 0, s>>>(b.status, out4, 4);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "smoe_internal.h"
 
@@ -242,6 +243,48 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
   return hip_status(e);
 }
 
+// Static workspace of smoe_render_noalloc: a file-scope device array (one copy per GPU,
+// held until the process ends).  In host code `scratch` names a host-side stand-in; the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (nullptr and a HIP error if it
+// cannot be had).
+hipError_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// The largest pair capacity whose render-only layout fits the static workspace (-1: the
+// per-kernel and per-block arrays alone do not fit).
+long long static_capacity(int32_t K, int32_t C, int32_t order, int32_t T) {
+  const size_t fixed = layout_of(K, C, order, T, 0, false).total;
+  if (fixed > kStaticScratchBytes) return -1;
+  // three u32 arrays per pair (keys, vals, vals_alt), each aligned up once
+  long long cap = (long long)((kStaticScratchBytes - fixed - 3 * kAlign) / (3 * sizeof(uint32_t)));
+  cap = std::min(cap, (long long)INT32_MAX / 16);
+  while (cap > 0 && layout_of(K, C, order, T, (int32_t)cap, false).total > kStaticScratchBytes)
+    cap -= 64;
+  return cap;
+}
+
 }  // namespace
 
 extern "C" {
@@ -399,6 +442,27 @@ smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, 
   if (S.T > bins->max_tiles) return SMOE_ERR_TOO_LARGE;
   return hip_status(launch_render(batch->C, batch->order, S, *bins, images, denoms, nullptr,
                                   static_cast<hipStream_t>(stream)));
+}
+
+smoe_status smoe_render_noalloc(const smoe_model* model, const smoe_grid* grid, float* image,
+                                float* denom, int32_t* status_out, void* stream) {
+  clear_stale_error();
+  Segs S;
+  if (!single_segs(model, grid, &S) || !image) return SMOE_ERR_INVALID;
+  const long long cap = static_capacity(model->K, model->C, model->order, S.T);
+  if (cap < 0) return SMOE_ERR_TOO_LARGE;
+  void* ws = nullptr;
+  hipError_t e = static_scratch(&ws);
+  if (e != hipSuccess) return hip_status(e);
+  smoe_bins b;
+  if (layout_into(&b, ws, kStaticScratchBytes, model->K, model->C, model->order, S.T, (int32_t)cap,
+                  false) != SMOE_OK)
+    return SMOE_ERR_TOO_LARGE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  e = launch_bin(model->C, model->order, model->params, S, b, s);
+  if (e == hipSuccess) e = launch_render(model->C, model->order, S, b, image, denom, nullptr, s);
+  if (e == hipSuccess && status_out) e = launch_copy_status(b, status_out, s);
+  return hip_status(e);
 }
 
 smoe_status smoe_materialize(int32_t K, int32_t C, int32_t order, const float* raw, float* model,

@@ -158,6 +158,8 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
 hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s,
                        const int32_t* fit_step = nullptr);
 hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s);
+// Copies the first four status words (P needed, overflow, longest list, spare) to out4.
+hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s);
 // Fit step: boxes and records of the current model with zeroed bucket cursors (the first
 // step), and the scatter into fixed-width buckets (every step).
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
