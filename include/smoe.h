@@ -31,24 +31,38 @@
  *    s1 = ln l11, s2 = ln l22, rho = ln pi (Eq. 4), and the expert is
  *    m(x) = a + wx (x - mu_x) + wy (y - mu_y) (order 1) or m = a (order 0).
  *    Gradients are reported in the raw order (d/ds1 = l11 d/dl11, d/ds2 = l22 d/dl22).
- *  - Truncation rule (Eq. 5 with the ellipse discard of Sec. IV-B): kernel j is in the
- *    list of every block its box covers; with the default reading (SMOE_TRUNC_GRADIENT,
- *    below) it takes part in the render at output pixel p iff p's block lies in j's block
- *    rectangle AND q_j(p) = |L_j^-1 (p - mu_j)|^2 <= (2r)^2, and in the gradient iff
- *    moreover q_j(p) <= r^2 (with SMOE_TRUNC_RENDER, q_j(p) <= r^2 for both).  The block
- *    rectangle comes from the square box of half-side r * sqrt(lambda_max(Sigma_j)) (side
- *    = major axis of the ellipse, Fig. 3b), or the tight box (SMOE_BOX_TIGHT).  Every
- *    decision is an exactly specified binary32 computation (q bounds compared the same way
- *    with (2r)*(2r)):
+ *  - Truncation rule (Eq. 5 with the ellipse discard of Sec. IV-B).  The model is a function
+ *    of native coordinates, and so is its truncation: blocks are the 16x16 blocks of the
+ *    native pixel grid, and kernel j's blocks are those its box covers on the native raster
+ *    (blocks holding a native pixel centre inside the box) -- the square box of half-side
+ *    R = r * sqrt(lambda_max(Sigma_j)) (side = major axis of the ellipse, Fig. 3b), or the
+ *    tight box (SMOE_BOX_TIGHT).  Kernel j is a member at a sample
+ *    point x iff x's native block (floor(x/16), floor(y/16)) is one of j's blocks, whatever
+ *    raster x was sampled on: a render at any scale and window re-samples the one regression
+ *    (Sec. II-B, VII-C).  With the default reading (SMOE_TRUNC_GRADIENT, below) a member
+ *    takes part in the render iff binary32 holds its term, i.e. its exponent
+ *    a = fma(q, -log2(e)/2, rho*log2(e)) is >= -125, and in the gradient iff moreover
+ *    q_j(x) = |L_j^-1 (x - mu_j)|^2 <= r^2 (with SMOE_TRUNC_RENDER, q <= r^2 for both).
+ *    Every decision is an exactly specified binary32 computation:
  *      i11 = 1/l11, i22 = 1/l22; dx = x - mu_x, dy = y - mu_y; z1 = dx*i11;
  *      z2 = (dy - l21*z1)*i22; q = z1*z1 + z2*z2 (each op rounded, no fma); q <= r*r;
+ *      log2(e) = 1.44269504f; rho*log2(e) rounded once; a by one fused multiply-add;
  *      sxx = l11*l11, sxy = l11*l21, syy = l21*l21 + l22*l22;
  *      lam = (sxx+syy)/2 + sqrt(((sxx-syy)/2)^2 + sxy^2); R = r*sqrt(lam);
- *      X0 = (mu_x - R)*scale - ox, X1 = (mu_x + R)*scale - ox;
- *      u0 = max(0, ceil(X0 - 0.5)), u1 = min(width-1, floor(X1 - 0.5)) (rows alike);
- *      block rect = [u0>>4, u1>>4] x [v0>>4, v1>>4], empty if u0 > u1 or v0 > v1.
+ *      native pixel centres in the box: c from ceil((mu_x - R) - 0.5) to
+ *      floor((mu_x + R) - 0.5); native blocks of j: floor(c/16) of those (x/16 computed as
+ *      x * 0.0625), empty if no centre lies inside; rows alike;
+ *      sample point of output pixel u: x(u) = ((ox + u) + 0.5) * inv_s.
+ *    The block lists of an output raster hold, per 16x16 output block, every kernel one of
+ *    whose native blocks holds a sample point of the block; at scale 1 and origin 0 these
+ *    are the kernels whose box overlaps the block.  An output block spans at most two
+ *    native blocks per axis; where it spans two, each pixel tests its own membership.
  *    Within a block, kernels are visited in increasing kernel id, which is also the
- *    summation order of every per-pixel sum (renders are bitwise reproducible).
+ *    summation order of every per-pixel sum (renders are bitwise reproducible).  One
+ *    exception: smoe_render and smoe_render_batched split a list longer than 128 entries
+ *    into four contiguous quarters, sum each in kernel order and add the four partial sums
+ *    in quarter order (still a fixed order), so on such blocks they are not bitwise equal to
+ *    the fit step's render, which sums every list whole.
  *  - A pixel where no kernel takes part renders 0 and receives no gradient.
  *
  * Status codes are negative on error.  Asynchronous conditions detected on the device
@@ -100,17 +114,16 @@ typedef struct smoe_grid {
 } smoe_grid;
 
 /* Where the ellipse test of the truncation rule applies (Sec. IV-B).
- * SMOE_TRUNC_GRADIENT (the default): the render takes every kernel whose box covers the
- * pixel's block (the block lists), up to q <= (2r)^2 (the same binary32 sequence as the
- * ellipse test with twice the radius: terms beyond are below e^(-2 r^2) of the kernel's
- * peak, and FP32 exp would lose them to underflow and rounding); pixels outside a kernel's
- * ellipse q <= r^2 are dropped from the gradient only, which is then the sum of the
- * in-ellipse (pixel, kernel) pairs' terms of the rendered loss's gradient, with the
- * render's y and D.
- * SMOE_TRUNC_RENDER: a kernel takes part at a pixel iff its box covers the pixel's block
- * and q <= r^2, in the render and in the gradient (the gradient is that of the rendered
- * loss).  Pixels that every ellipse has left render 0 and get no gradient, so a long fit
- * can strand them.  Any other value is rejected. */
+ * SMOE_TRUNC_GRADIENT (the default): the render takes every member of the point's block
+ * list whose term pi K binary32 can hold (exponent >= -125, so the term is a normal number;
+ * below that the FP32 term would be lost to underflow, and the uncut FP64 sum of the lists
+ * differs from this rule only by such terms); pixels outside a kernel's ellipse q <= r^2 are
+ * dropped from the gradient only, which is then the sum of the in-ellipse (pixel, kernel)
+ * pairs' terms of the rendered loss's gradient, with the render's y and D.
+ * SMOE_TRUNC_RENDER: a kernel takes part at a point iff it is a member there and q <= r^2,
+ * in the render and in the gradient (the gradient is that of the rendered loss).  Pixels
+ * that every ellipse has left render 0 and get no gradient, so a long fit can strand them.
+ * Any other value is rejected.  rho must stay below 88 (pi finite in binary32). */
 #define SMOE_TRUNC_GRADIENT 0
 #define SMOE_TRUNC_RENDER 1
 
@@ -130,9 +143,9 @@ typedef struct smoe_grid {
  * Rx = min(R, r |l11| (1 + 2^-10) + m), Ry = min(R, r sqrt(syy) (1 + 2^-10) + m) with
  * syy = l21 l21 + l22 l22 and m = (|mu_x| + |mu_y| + R) 2^-18, in binary32 in that order:
  * the extents of the r-ellipse along x and y, widened by a margin that covers the rounding
- * of the binary32 ellipse test and of the pixel coordinates.  Every pixel the ellipse test
- * accepts inside the square box lies in the tight box, so with SMOE_TRUNC_RENDER images and
- * losses are those of the square box, bit for bit; only blocks the ellipse cannot reach
+ * of the binary32 ellipse test and of the pixel coordinates.  Every point the ellipse test
+ * accepts lies in the tight box, so with SMOE_TRUNC_RENDER images and losses are those of
+ * the square box, bit for bit; only blocks the ellipse cannot reach
  * leave the block lists, and gradients are the same sums of fewer (zero-free) per-block
  * partials, grouped differently, so they agree up to that rounding.  With
  * SMOE_TRUNC_GRADIENT the render of the dropped blocks loses the kernel's far tail, so the
@@ -184,7 +197,9 @@ typedef struct smoe_bins {
   int32_t K, C, order;     /* model shape the workspace was laid out for */
   int32_t max_tiles;       /* largest block count T a raster may have */
   int32_t capacity;        /* largest number of (block, kernel) pairs P */
-  int32_t* tile_rects;     /* [K][4] (tx0, ty0, tx1, ty1); empty = (0, 0, -1, -1) */
+  int32_t* tile_rects;     /* [K][4] output blocks (tx0, ty0, tx1, ty1); empty = (0, 0, -1, -1) */
+  int32_t* native_rects;   /* [K][4] native blocks (bx0, by0, bx1, by1) clamped to those the
+                              raster's sample points reach; empty = (0, 0, -1, -1) */
   int32_t* counts;         /* [K] blocks covered by each kernel */
   float* records;          /* [K][record_stride] per-kernel render records */
   int32_t record_stride;   /* floats per record */
@@ -236,8 +251,10 @@ smoe_status smoe_render(const smoe_model* model, const smoe_grid* grid, const sm
                         float* image, float* denom, const float* target, float* loss_out,
                         void* stream);
 
-/* Backward (adjoint of smoe_render): writes grads (device [K][NP], raw order) =
- * dL/dparams, recomputing every gate from the saved image and denom.  Exactly one of
+/* Backward (adjoint of smoe_render; the parameters are fitted by descending the
+ * reconstruction error's gradient, Sec. II-A and VI-B, with the out-of-ellipse pixels of a
+ * kernel's blocks discarded from its gradient, Sec. IV-B): writes grads (device [K][NP], raw
+ * order) = dL/dparams, recomputing every gate from the saved image and denom.  Exactly one of
  * grad_image (device [H][W][C], upstream dL/dimage) and target (device [H][W][C]: L = the
  * mean squared error of image against target) must be non-NULL.  Gradients are
  * written, not accumulated.  Uses bins->pair_grads as scratch. */
@@ -320,7 +337,9 @@ typedef struct smoe_fit_state {
   smoe_bins bins;            /* laid out for (K, C, order) and all blocks */
 } smoe_fit_state;
 
-/* One fit iteration on `stream` with no host synchronisation: binning, forward render
+/* One fit iteration (Sec. VI-B: Adam on every kernel parameter, the centre rate decaying
+ * exponentially; the rasterized forward and backward of Sec. IV) on `stream` with no host
+ * synchronisation: binning, forward render
  * with the fused squared-error loss, backward, then per kernel the deterministic
  * reduction of its block partials, the Adam update of the raw row and its
  * re-materialization.  The step runs as three kernels: the scatter of the (block, kernel)
@@ -359,12 +378,12 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* state, float* out, voi
  * spare) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an overflow. */
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream);
 
-/* Library version, e.g. 100 for 0.1.0. */
 /* Name and description of the HIP error behind this thread's last SMOE_ERR_HIP ("no
  * error" if none).  The string is owned by the library and valid until the next failing
  * call on the thread. */
 const char* smoe_last_error(void);
 
+/* Library version, e.g. 100 for 0.1.0. */
 int32_t smoe_version(void);
 
 #ifdef __cplusplus

@@ -60,10 +60,12 @@ def lib():
         I, F, D, I64 = ct.c_int, ct.c_float, ct.c_double, ct.c_int64
         L.oracle_num_params.argtypes = [I, I]
         L.oracle_num_params.restype = I
-        L.oracle_bin.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, i32p, i32p, i32p, I64, u32p, u32p, i32p]
+        L.oracle_bin.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, i32p, i32p, i32p, I64, u32p, u32p, i32p]
         L.oracle_bin.restype = I64
         L.oracle_render.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, I, I, I64, i32p, dp, dp, I]
         L.oracle_render.restype = None
+        L.oracle_render_points.argtypes = [I, I, I, dp, F, I, I, I, I, I64, fp, dp, dp, I]
+        L.oracle_render_points.restype = None
         L.oracle_loss_grad.argtypes = [I, I, I, dp, I, I, I, I, I, F, I, I, I, dp, dp, I, i32p, dp, I]
         L.oracle_loss_grad.restype = D
         L.oracle_materialize.argtypes = [I, I, I, dp, dp]
@@ -108,9 +110,13 @@ def _KC(model, C, order):
     return model, model.shape[0]
 
 
-def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0):
-    """Block lists.  Returns dict(tile_rects, pix_rects, counts, P, keys, vals, ranges).
-    box: 0 = the square box of Sec. IV-B, 1 = the tight axis-aligned box."""
+def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0, trunc="gradient"):
+    """Block lists.  Returns dict(tile_rects, native_rects, counts, P, keys, vals, ranges):
+    tile_rects are output blocks of the raster, native_rects the kernels' native 16x16 blocks
+    clamped to those the raster's sample points reach.
+    box: 0 = the square box of Sec. IV-B, 1 = the tight axis-aligned box.  trunc: the reading
+    ("gradient": native blocks holding a pixel centre in the box; "render": blocks the box
+    overlaps)."""
     model, K = _KC(model, C, order)
     T = ((W + 15) // 16) * ((H + 15) // 16)
     tr = np.zeros((K, 4), np.int32)
@@ -119,43 +125,82 @@ def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0):
     rng = np.zeros((T, 2), np.int32)
     if capacity is None:
         P = lib().oracle_bin(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box,
-                             _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
+                             _trunc(trunc), _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
                              0, None, None, _ptr(rng, ct.c_int32))
         capacity = P
     keys = np.zeros(max(capacity, 1), np.uint32)
     vals = np.zeros(max(capacity, 1), np.uint32)
     P = lib().oracle_bin(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box,
-                         _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
+                         _trunc(trunc), _ptr(tr, ct.c_int32), _ptr(pr, ct.c_int32), _ptr(cnt, ct.c_int32),
                          capacity, _ptr(keys, ct.c_uint32), _ptr(vals, ct.c_uint32),
                          _ptr(rng, ct.c_int32))
     n = min(P, capacity)
-    return dict(tile_rects=tr, pix_rects=pr, counts=cnt, P=int(P), keys=keys[:n], vals=vals[:n],
-                ranges=rng)
+    return dict(tile_rects=tr, native_rects=pr, counts=cnt, P=int(P), keys=keys[:n],
+                vals=vals[:n], ranges=rng)
+
+
+def _truncated(truncated) -> int:
+    """True / 1: the truncation rule; False / 0: every kernel (the global model of Sec.
+    III-B); "lists" / 2: every kernel of the point's block list, with no cut."""
+    if truncated == "lists":
+        return 2
+    t = int(truncated)
+    assert t in (0, 1, 2), truncated
+    return t
 
 
 def render(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, truncated=True, pixels=None,
            threads=None, box=0, rbf=False, trunc="gradient"):
     """y [H, W, C] and D [H, W] (or [n, C], [n] at the listed (u, v) pixels).  rbf: the
     weighted sum of kernels of Eq. (1) instead of the gated regression of Eq. (2)-(4).
-    trunc: "gradient" (the render takes every kernel of the block's list; the ellipse test
-    applies to gradients only -- Sec. IV-B) or "render" (the ellipse test applies to the
-    render as well)."""
+    trunc: "gradient" (the render takes every representable term of the block's list; the
+    ellipse test applies to gradients only -- Sec. IV-B) or "render" (the ellipse test
+    applies to the render as well).  truncated: see _truncated."""
     model, K = _KC(model, C, order)
     threads = threads or default_threads()
     if pixels is None:
         y = np.zeros((H, W, C), np.float64)
         D = np.zeros((H, W), np.float64)
         lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box, int(rbf),
-                            _trunc(trunc), int(truncated), 0, None, _ptr(y, ct.c_double), _ptr(D, ct.c_double),
+                            _trunc(trunc), _truncated(truncated), 0, None, _ptr(y, ct.c_double), _ptr(D, ct.c_double),
                             threads)
     else:
         pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
         y = np.zeros((pix.shape[0], C), np.float64)
         D = np.zeros(pix.shape[0], np.float64)
         lib().oracle_render(K, C, order, _ptr(model, ct.c_double), W, H, s, ox, oy, r, box, int(rbf),
-                            _trunc(trunc), int(truncated), pix.shape[0], _ptr(pix, ct.c_int32),
+                            _trunc(trunc), _truncated(truncated), pix.shape[0], _ptr(pix, ct.c_int32),
                             _ptr(y, ct.c_double), _ptr(D, ct.c_double), threads)
     return y, D
+
+
+def render_points(model, C, order, points, r=3.0, truncated=True, threads=None, box=0,
+                  rbf=False, trunc="gradient"):
+    """y [n, C] and D [n] at arbitrary native points (float32 [n, 2] = (x, y)), with the
+    kernels' boxes on the native block grid: the regression itself, independent of any
+    raster."""
+    model, K = _KC(model, C, order)
+    pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 2)
+    n = pts.shape[0]
+    y = np.zeros((n, C), np.float64)
+    D = np.zeros(n, np.float64)
+    lib().oracle_render_points(K, C, order, _ptr(model, ct.c_double), r, box, int(rbf),
+                               _trunc(trunc), _truncated(truncated), n, _ptr(pts, ct.c_float),
+                               _ptr(y, ct.c_double), _ptr(D, ct.c_double),
+                               threads or default_threads())
+    return y, D
+
+
+def sample_points(W, H, s=1, ox=0, oy=0):
+    """float32 [H, W, 2] native sample points of an output raster: ((o + u) + 0.5) * (1/s),
+    with 1/s rounded to binary32 once."""
+    inv = np.float32(1.0) / np.float32(s)
+    xs = ((np.arange(W) + ox).astype(np.float32) + np.float32(0.5)) * inv
+    ys = ((np.arange(H) + oy).astype(np.float32) + np.float32(0.5)) * inv
+    P = np.zeros((H, W, 2), np.float32)
+    P[..., 0] = xs[None, :]
+    P[..., 1] = ys[:, None]
+    return P
 
 
 def loss_grad(model, C, order, W, H, target=None, grad_y=None, kernels=None, s=1, ox=0, oy=0,

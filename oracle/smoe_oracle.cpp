@@ -13,21 +13,30 @@
 //   * Soft gates, Eq. (4): w_j = pi_j K_j / sum_i pi_i K_i, with pi_j = exp(rho_j).
 //   * SMoE regression, Eq. (3): y(x) = sum_j m_j(x) w_j(x); experts are constant
 //     m_j = a_j (Sec. II-A) or linear ("steered") m_j(x) = a_j + W_j (x - mu_j).
-//   * Rasterized truncation, Eq. (5) with the discard rule of Sec. IV-B.  A kernel's 16x16
-//     blocks are those its square bounding box covers (side = major axis of its confidence
-//     ellipse, Fig. 3b); pixels of those blocks outside the ellipse q_j(x) <= r^2 are
-//     discarded in the gradient.  Two readings (trunc): 1 = as the section states, the
-//     render takes every kernel of the block's list and the ellipse test only removes
-//     (pixel, kernel) pairs from the gradient, which is then the sum of the in-ellipse
-//     pairs' terms of the rendered loss's gradient (with the render's D and y) -- the
-//     render stops at q <= (2r)^2, binary32 like the ellipse test (terms beyond are below
-//     e^(-2 r^2) of the kernel's peak, where FP32 exp underflows or loses accuracy); 0 = the
-//     ellipse test applies to the render too (kernel j takes part at x iff its box covers
-//     x's block AND q_j(x) <= r^2), so the gradient is exactly the rendered loss's.  Both
-//     conjuncts are discrete decisions evaluated in exactly specified IEEE binary32
-//     arithmetic (this file is built with -ffp-contract=off), the same precision as the GPU
-//     kernels, so that both take the same decisions.  Every continuous quantity (exp, sums,
-//     y, gradients) is FP64.
+//   * Rasterized truncation, Eq. (5) with the discard rule of Sec. IV-B.  The model is a
+//     function of native image coordinates, so the blocks are the 16x16 blocks of the
+//     native pixel grid: a kernel's blocks are the native blocks its square bounding box
+//     (side = major axis of its confidence ellipse, Fig. 3b) covers -- with the block lists
+//     deciding the render, those holding a native pixel centre inside the box (the lists of
+//     the native raster); with the ellipse test deciding, those the box overlaps, so that
+//     every point inside the ellipse is a member at any scale -- and the kernel belongs to the
+//     list of a sample point x iff x's native block
+//     (floor(x / 16), per axis) is one of them -- whatever raster (scale, window) x is
+//     sampled on, so super-resolution and windows re-sample one regression (Sec. II-B,
+//     VII-C).  Pixels of a kernel's blocks outside its ellipse q_j(x) <= r^2 are discarded
+//     in the gradient.  Two readings (trunc): 1 = as the section states, the render takes
+//     every kernel of the block's list and the ellipse test only removes (point, kernel)
+//     pairs from the gradient, which is then the sum of the in-ellipse pairs' terms of the
+//     rendered loss's gradient (with the render's D and y) -- a listed term is rendered
+//     whenever binary32 can hold it: its exponent rho log2(e) - q log2(e) / 2, rounded as
+//     the GPU forms it, is >= -125 (so pi K >= 2^-125 is a normal binary32 number); 0 = the
+//     ellipse test applies to the render too (kernel j takes part at x iff x's block is one
+//     of its blocks AND q_j(x) <= r^2), so the gradient is exactly the rendered loss's.
+//     Every conjunct is a discrete decision evaluated in exactly specified IEEE binary32
+//     arithmetic (this file is built with -ffp-contract=off; the exponent's one fused
+//     multiply-add is written as std::fmaf), the same precision as the GPU kernels, so that
+//     both take the same decisions.  Every continuous quantity (exp, sums, y, gradients) is
+//     FP64.
 //   * Optionally (box = 1) a tight axis-aligned box instead of the square one: half-widths
 //     r sqrt(Sigma_xx) and r sqrt(Sigma_yy), the extents of the r-ellipse along x and y,
 //     each widened by a small margin that covers the rounding of the binary32 ellipse test
@@ -40,8 +49,11 @@
 //     splatting) instead of the gates: y(x) = sum_j pi_j m_j(x) K_j(x), the kernel weight of
 //     Eq. (1) being pi_j m_j(x); no normalisation.  Same kernels, truncation and parameters.
 //   * The untruncated ("global") model of Sec. III-B: every kernel at every pixel.
-//   * Block lists of Sec. IV-C: per 16x16 block, the kernels whose box covers it, in
-//     increasing kernel id.
+//   * Block lists of Sec. IV-C: per 16x16 block of an output raster, the kernels one of
+//     whose native blocks holds a sample point of the block, in increasing kernel id.  At
+//     native resolution (scale 1, origin 0) these are the kernels whose box covers the block.
+//   * For the truncation report: the block-list sum without any cut (every listed kernel at
+//     every point of its blocks).
 //   * The analytic gradient of the mean-squared reconstruction error (Sec. II-A: the
 //     parameters are adjusted to minimise the error between reconstruction and image)
 //     with respect to every raw kernel parameter, and Adam (Sec. VI-B).
@@ -96,28 +108,69 @@ float coord32(int u, int o, int s) {
   return ((float)(o + u) + 0.5f) * inv_s;
 }
 
-// Range of output-pixel indices whose centres lie in [lo, hi] (already in output
-// units), clamped to [0, n-1].  Returns false when empty.
-bool axis_range(float lo, float hi, int n, int* i0, int* i1) {
-  const float a = std::ceil(lo - 0.5f);
-  const float b = std::floor(hi - 0.5f);
-  const float last = (float)(n - 1);
-  if (!(a <= last) || !(b >= 0.0f)) return false;
-  *i0 = (a < 0.0f) ? 0 : (int)a;
-  *i1 = (b > last) ? n - 1 : (int)b;
-  return *i0 <= *i1;
-}
+// Native 16x16 block index of a native coordinate, floor(x / 16) (x * 2^-4 is exact).
+float native_block(float x) { return std::floor(x * 0.0625f); }
+
+constexpr float kLog2eF = 1.44269504088896340736f;
 
 struct Rect32 {
   bool empty;
-  int u0, u1, v0, v1;      // pixel rect (inclusive)
-  int tx0, tx1, ty0, ty1;  // tile rect (inclusive)
+  float bx0, bx1, by0, by1;  // native block rect (integer-valued), clamped to the raster's
+  int tx0, tx1, ty0, ty1;    // output block rect of the raster (inclusive)
 };
+
+// The native blocks [b0, b1] of a box's extent [lo, hi] along one axis.  centres: the blocks
+// holding a native pixel centre c + 0.5 inside it, c from ceil(lo - 0.5) to floor(hi - 0.5) --
+// the blocks the box covers on the native raster (scale 1, origin 0), the block lists that
+// decide the render.  Otherwise: the blocks the box overlaps, floor(lo / 16) to
+// ceil(hi / 16) - 1 -- every block holding a point of the box (no sample point lies on a
+// block boundary), so that with the ellipse test deciding the render every point inside the
+// ellipse is a member at any scale.  False when empty (or NaN).
+bool native_axis(float lo, float hi, bool centres, float* b0, float* b1) {
+  if (centres) {
+    const float a = std::ceil(lo - 0.5f);
+    const float b = std::floor(hi - 0.5f);
+    if (!(a <= b)) return false;
+    *b0 = native_block(a);
+    *b1 = native_block(b);
+    return true;
+  }
+  *b0 = native_block(lo);
+  *b1 = std::ceil(hi * 0.0625f) - 1.0f;
+  return *b0 <= *b1;
+}
+
+// The output blocks [t0, t1] of an axis of n sample points (origin o, scale s) holding a
+// point whose native block lies in [b0, b1]: every block is scanned, each by its first and
+// last point (the native block index does not decrease along the axis).  The native rect
+// is clamped to the blocks the raster's points reach.  False when none does.
+bool output_axis(float* b0, float* b1, int n, int o, int s, int* t0, int* t1) {
+  const float first = native_block(coord32(0, o, s));
+  const float last = native_block(coord32(n - 1, o, s));
+  if (*b1 < first || *b0 > last) return false;
+  *b0 = std::max(*b0, first);
+  *b1 = std::min(*b1, last);
+  *t0 = -1;
+  *t1 = -2;
+  const int nt = (n + 15) / 16;
+  for (int t = 0; t < nt; ++t) {
+    const float a = native_block(coord32(16 * t, o, s));
+    const float b = native_block(coord32(std::min(16 * t + 15, n - 1), o, s));
+    if (a <= *b1 && b >= *b0) {
+      if (*t0 < 0) *t0 = t;
+      *t1 = t;
+    }
+  }
+  return *t0 >= 0;
+}
 
 // Square box centred on mu with half-side R = r * sqrt(lambda_max(Sigma)): its side is
 // the major axis of the r-ellipse (Fig. 3b).  lambda_max of the symmetric 2x2 matrix
-// by the closed form  (sxx+syy)/2 + sqrt(((sxx-syy)/2)^2 + sxy^2).
-Rect32 kernel_rect32(float mux, float muy, float l11, float l21, float l22, const Grid& g) {
+// by the closed form  (sxx+syy)/2 + sqrt(((sxx-syy)/2)^2 + sxy^2).  The box selects native
+// blocks; the raster's output blocks follow from them.
+// native_only: the native blocks alone, unclamped (no raster; output rect left empty).
+Rect32 kernel_rect32(float mux, float muy, float l11, float l21, float l22, const Grid& g,
+                     bool native_only = false) {
   const float sxx = l11 * l11;
   const float sxy = l11 * l21;
   const float syy = l21 * l21 + l22 * l22;
@@ -135,28 +188,29 @@ Rect32 kernel_rect32(float mux, float muy, float l11, float l21, float l22, cons
     Rx = std::fmin(R, g.r * std::fabs(l11) * 1.0009765625f + m);
     Ry = std::fmin(R, g.r * std::sqrt(syy) * 1.0009765625f + m);
   }
-  const float fs = (float)g.s;
-  const float X0 = (mux - Rx) * fs - (float)g.ox;
-  const float X1 = (mux + Rx) * fs - (float)g.ox;
-  const float Y0 = (muy - Ry) * fs - (float)g.oy;
-  const float Y1 = (muy + Ry) * fs - (float)g.oy;
   Rect32 rc{};
-  rc.empty = !(axis_range(X0, X1, g.W, &rc.u0, &rc.u1) && axis_range(Y0, Y1, g.H, &rc.v0, &rc.v1));
+  const bool centres = g.trunc == 1;
+  rc.empty = !(native_axis(mux - Rx, mux + Rx, centres, &rc.bx0, &rc.bx1) &&
+               native_axis(muy - Ry, muy + Ry, centres, &rc.by0, &rc.by1));
+  if (native_only) {
+    rc.tx0 = rc.ty0 = 0;
+    rc.tx1 = rc.ty1 = -1;
+    return rc;
+  }
+  rc.empty = rc.empty || !(output_axis(&rc.bx0, &rc.bx1, g.W, g.ox, g.s, &rc.tx0, &rc.tx1) &&
+                           output_axis(&rc.by0, &rc.by1, g.H, g.oy, g.s, &rc.ty0, &rc.ty1));
   if (rc.empty) {
     rc.tx0 = rc.ty0 = 0;
     rc.tx1 = rc.ty1 = -1;
-  } else {
-    rc.tx0 = rc.u0 >> 4;
-    rc.tx1 = rc.u1 >> 4;
-    rc.ty0 = rc.v0 >> 4;
-    rc.ty1 = rc.v1 >> 4;
+    rc.bx0 = rc.by0 = 0.0f;
+    rc.bx1 = rc.by1 = -1.0f;
   }
   return rc;
 }
 
-// Inside test of the truncation ellipse, q = |L^-1 (x - mu)|^2 <= r^2, as the exact
-// binary32 sequence: reciprocals of the diagonal, then z1 = dx/l11, z2 = (dy - l21 z1)/l22.
-bool inside32(float x, float y, float mux, float muy, float l11, float l21, float l22, float r2) {
+// q = |L^-1 (x - mu)|^2 as the exact binary32 sequence: reciprocals of the diagonal, then
+// z1 = dx/l11, z2 = (dy - l21 z1)/l22.
+float q32(float x, float y, float mux, float muy, float l11, float l21, float l22) {
   const float i11 = 1.0f / l11;
   const float i22 = 1.0f / l22;
   const float dx = x - mux;
@@ -165,38 +219,54 @@ bool inside32(float x, float y, float mux, float muy, float l11, float l21, floa
   const float t = l21 * z1;
   const float w = dy - t;
   const float z2 = w * i22;
-  const float q = z1 * z1 + z2 * z2;
-  return q <= r2;
+  return z1 * z1 + z2 * z2;
+}
+
+// Whether binary32 holds the term pi K = 2^arg with arg = rho log2(e) - q log2(e) / 2
+// formed as the GPU forms it (one rounded product, one fused multiply-add): arg >= -125.
+bool representable32(float q, float rho) {
+  const float rl = rho * kLog2eF;
+  const float arg = std::fmaf(q, -0.5f * kLog2eF, rl);
+  return arg >= -125.0f;
 }
 
 // ------------------------------------------------------------------------------------
 // FP64 model.
 // ------------------------------------------------------------------------------------
 
+// Which terms a point takes: RULE_ELLIPSE (block member and q <= r^2: the gradient, and the
+// render with the ellipse test in it), RULE_LISTS (block member and a representable term:
+// the render when the block lists decide it), RULE_UNCUT (block member: the report).
+enum Rule { RULE_ELLIPSE, RULE_LISTS, RULE_UNCUT };
+
 struct Model {
   int K, C, order, NP;
   const double* p;  // [K][NP] materialized
   std::vector<Rect32> rect;
-  std::vector<float> f32;  // [K][5] binary32 view: mux, muy, l11, l21, l22
+  std::vector<float> f32;  // [K][6] binary32 view: mux, muy, l11, l21, l22, rho
 
-  Model(int K_, int C_, int order_, const double* p_, const Grid& g)
-      : K(K_), C(C_), order(order_), NP(num_params(C_, order_)), p(p_), rect(K_), f32(5 * (size_t)K_) {
+  // native_only: boxes on the native grid alone (evaluation at arbitrary points).
+  Model(int K_, int C_, int order_, const double* p_, const Grid& g, bool native_only = false)
+      : K(K_), C(C_), order(order_), NP(num_params(C_, order_)), p(p_), rect(K_), f32(6 * (size_t)K_) {
     for (int j = 0; j < K; ++j) {
       const double* r = p + (size_t)j * NP;
-      float* f = &f32[5 * (size_t)j];
-      for (int k = 0; k < 5; ++k) f[k] = (float)r[k];
-      rect[j] = kernel_rect32(f[0], f[1], f[2], f[3], f[4], g);
+      float* f = &f32[6 * (size_t)j];
+      for (int k = 0; k < 6; ++k) f[k] = (float)r[k];
+      rect[j] = kernel_rect32(f[0], f[1], f[2], f[3], f[4], g, native_only);
     }
   }
 
-  // The participation rule at output pixel (u, v) whose sample point is (x32, y32).
-  bool participates(int j, int u, int v, float x32, float y32, float r2) const {
+  // Whether kernel j takes part at the sample point (x32, y32) under `rule`.  Only native
+  // quantities enter: the point's native block and the kernel's native blocks.
+  bool participates(int j, float x32, float y32, Rule rule, float r2) const {
     const Rect32& rc = rect[j];
     if (rc.empty) return false;
-    const int tx = u >> 4, ty = v >> 4;
-    if (tx < rc.tx0 || tx > rc.tx1 || ty < rc.ty0 || ty > rc.ty1) return false;
-    const float* f = &f32[5 * (size_t)j];
-    return inside32(x32, y32, f[0], f[1], f[2], f[3], f[4], r2);
+    const float bx = native_block(x32), by = native_block(y32);
+    if (bx < rc.bx0 || bx > rc.bx1 || by < rc.by0 || by > rc.by1) return false;
+    if (rule == RULE_UNCUT) return true;
+    const float* f = &f32[6 * (size_t)j];
+    const float q = q32(x32, y32, f[0], f[1], f[2], f[3], f[4]);
+    return rule == RULE_ELLIPSE ? q <= r2 : representable32(q, f[5]);
   }
 };
 
@@ -223,19 +293,20 @@ inline double expert(const double* r, int C, int order, int c, double dx, double
   return m;
 }
 
-// y(x) and D(x) = sum_j pi_j K_j(x) over the participating kernels (all K if !truncated);
-// y = N / D (Eq. 2-4) or, in the RBF mode, y = N (Eq. 1), with N_c = sum_j pi_j K_j m_jc.
-void eval_pixel(const Model& M, const Grid& g, bool truncated, int u, int v, double* y, double* D) {
-  const float x32 = coord32(u, g.ox, g.s);
-  const float y32 = coord32(v, g.oy, g.s);
+// y(x) and D(x) = sum_j pi_j K_j(x) at the native point (x32, y32) over the participating
+// kernels (truncated: 0 = all K, the global model of Sec. III-B; 1 = the truncation rule of
+// the reading; 2 = every kernel of the point's block list, uncut); y = N / D (Eq. 2-4) or,
+// in the RBF mode, y = N (Eq. 1), with N_c = sum_j pi_j K_j m_jc.  Nothing here depends on
+// the raster the point was sampled on.
+void eval_point(const Model& M, const Grid& g, int truncated, float x32, float y32, double* y,
+                double* D) {
   const float r2 = g.r * g.r;
-  const float r_twice = 2.0f * g.r;
-  const float r2_render = r_twice * r_twice;
+  const Rule rule = truncated == 2 ? RULE_UNCUT : (g.trunc == 1 ? RULE_LISTS : RULE_ELLIPSE);
   const double x = (double)x32, yy = (double)y32;
   double Dsum = 0.0;
   std::vector<double> N(M.C, 0.0);
   for (int j = 0; j < M.K; ++j) {
-    if (truncated && !M.participates(j, u, v, x32, y32, g.trunc == 1 ? r2_render : r2)) continue;
+    if (truncated && !M.participates(j, x32, y32, rule, r2)) continue;
     const double* r = M.p + (size_t)j * M.NP;
     const Term t = term(r, x, yy);
     Dsum += t.e;
@@ -243,6 +314,11 @@ void eval_pixel(const Model& M, const Grid& g, bool truncated, int u, int v, dou
   }
   *D = Dsum;
   for (int c = 0; c < M.C; ++c) y[c] = g.rbf ? N[c] : ((Dsum > 0.0) ? N[c] / Dsum : 0.0);
+}
+
+// The value at output pixel (u, v): the model at the pixel's native sample point.
+void eval_pixel(const Model& M, const Grid& g, int truncated, int u, int v, double* y, double* D) {
+  eval_point(M, g, truncated, coord32(u, g.ox, g.s), coord32(v, g.oy, g.s), y, D);
 }
 
 template <class F>
@@ -279,7 +355,7 @@ void grad_pixel(const Model& M, const Grid& g, int u, int v, const double* gy_in
   for (int j = 0; j < M.K; ++j) {
     const int32_t sj = slot ? slot[j] : j;
     if (sj < 0) continue;
-    if (!M.participates(j, u, v, x32, y32, r2)) continue;
+    if (!M.participates(j, x32, y32, RULE_ELLIPSE, r2)) continue;
     const double* r = M.p + (size_t)j * NP;
     const Term t = term(r, x, yy);
     // w = dy_c/dm_jc: the gate w_j(x) of Eq. (4), or pi_j K_j(x) in the RBF sum of Eq. (1).
@@ -323,18 +399,20 @@ extern "C" {
 
 int oracle_num_params(int C, int order) { return num_params(C, order); }
 
-// Per-kernel boxes and the per-block kernel lists of Sec. IV-C.
-//   tile_rects [K][4] = (tx0, ty0, tx1, ty1), empty = (0, 0, -1, -1)
-//   pix_rects  [K][4] = (u0, v0, u1, v1), empty = (0, 0, -1, -1)    (may be NULL)
-//   counts     [K]    = number of covered blocks
+// Per-kernel boxes and the per-block kernel lists of Sec. IV-C (trunc: the reading, which
+// decides how a box selects native blocks).
+//   tile_rects   [K][4] = output blocks (tx0, ty0, tx1, ty1), empty = (0, 0, -1, -1)
+//   native_rects [K][4] = native blocks (bx0, by0, bx1, by1) clamped to the blocks the
+//                         raster's sample points reach, empty = (0, 0, -1, -1) (may be NULL)
+//   counts       [K]    = number of output blocks in the kernel's rect
 //   keys/vals  [capacity] = (block id, kernel id) pairs ordered by block, then kernel id
 //   ranges     [T][2] = [begin, end) of each block's list in keys/vals
 // Returns the total number of pairs P (written only up to capacity).
 int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, int s, int ox,
-                   int oy, float r, int box, int32_t* tile_rects, int32_t* pix_rects,
+                   int oy, float r, int box, int trunc, int32_t* tile_rects, int32_t* native_rects,
                    int32_t* counts,
                    int64_t capacity, uint32_t* keys, uint32_t* vals, int32_t* ranges) {
-  const Grid g{W, H, s, ox, oy, r, box, 0};
+  const Grid g{W, H, s, ox, oy, r, box, 0, trunc};
   const Model M(K, C, order, model, g);
   const int ntx = g.ntx(), T = g.ntx() * g.nty();
   std::vector<std::vector<uint32_t>> lists(T);
@@ -342,10 +420,10 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
     const Rect32& rc = M.rect[j];
     int32_t* tr = tile_rects + 4 * (size_t)j;
     tr[0] = rc.tx0; tr[1] = rc.ty0; tr[2] = rc.tx1; tr[3] = rc.ty1;
-    if (pix_rects) {
-      int32_t* pr = pix_rects + 4 * (size_t)j;
-      if (rc.empty) { pr[0] = 0; pr[1] = 0; pr[2] = -1; pr[3] = -1; }
-      else { pr[0] = rc.u0; pr[1] = rc.v0; pr[2] = rc.u1; pr[3] = rc.v1; }
+    if (native_rects) {
+      int32_t* nr = native_rects + 4 * (size_t)j;
+      nr[0] = (int32_t)rc.bx0; nr[1] = (int32_t)rc.by0;
+      nr[2] = (int32_t)rc.bx1; nr[3] = (int32_t)rc.by1;
     }
     counts[j] = rc.empty ? 0 : (rc.tx1 - rc.tx0 + 1) * (rc.ty1 - rc.ty0 + 1);
     if (rc.empty) continue;
@@ -365,7 +443,8 @@ int64_t oracle_bin(int K, int C, int order, const double* model, int W, int H, i
 }
 
 // Renders y [npix][C] and D [npix] at the listed output pixels (pix [npix][2] = (u, v));
-// pix == NULL renders the whole raster in row-major order (npix ignored).
+// pix == NULL renders the whole raster in row-major order (npix ignored).  truncated: 0 =
+// every kernel (Sec. III-B), 1 = the truncation rule, 2 = the uncut block lists.
 void oracle_render(int K, int C, int order, const double* model, int W, int H, int s, int ox,
                    int oy, float r, int box, int rbf, int trunc, int truncated, int64_t npix,
                    const int32_t* pix,
@@ -377,7 +456,20 @@ void oracle_render(int K, int C, int order, const double* model, int W, int H, i
   parallel_for(n, threads, [&](int64_t i, int) {
     const int u = pix ? pix[2 * i] : (int)(i % W);
     const int v = pix ? pix[2 * i + 1] : (int)(i / W);
-    eval_pixel(M, g, truncated != 0, u, v, y + (size_t)i * C, D + i);
+    eval_pixel(M, g, truncated, u, v, y + (size_t)i * C, D + i);
+  });
+}
+
+// The model at arbitrary binary32 native points pts [npts][2] = (x, y), independent of any
+// raster: the kernel boxes are taken on the native grid (a raster of scale 1 and origin 0
+// spanning every native block), so the rule sees only the points and the model.
+void oracle_render_points(int K, int C, int order, const double* model, float r, int box,
+                          int rbf, int trunc, int truncated, int64_t npts, const float* pts,
+                          double* y, double* D, int threads) {
+  const Grid g{1, 1, 1, 0, 0, r, box, rbf, trunc};
+  const Model M(K, C, order, model, g, true);
+  parallel_for(npts, threads, [&](int64_t i, int) {
+    eval_point(M, g, truncated, pts[2 * i], pts[2 * i + 1], y + (size_t)i * C, D + i);
   });
 }
 
@@ -424,7 +516,7 @@ double oracle_loss_grad(int K, int C, int order, const double* model, int W, int
       const bool want = !sel || need[p];
       if (!want) continue;
       double D;
-      eval_pixel(M, g, true, u, (int)v, y.data(), &D);
+      eval_pixel(M, g, 1, u, (int)v, y.data(), &D);
       for (int c = 0; c < C; ++c) {
         if (grad_y) {
           gy[c] = grad_y[p * C + c];

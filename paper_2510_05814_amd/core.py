@@ -118,6 +118,9 @@ class Bins:
     def tile_rects(self):
         return self._view(self.c.tile_rects, 4 * self.K, torch.int32).view(self.K, 4)
 
+    def native_rects(self):
+        return self._view(self.c.native_rects, 4 * self.K, torch.int32).view(self.K, 4)
+
     def counts(self):
         return self._view(self.c.counts, self.K, torch.int32)
 

@@ -20,6 +20,7 @@ struct BackwardArgs {
   Segs S;
   int C;
   const float* __restrict__ records;
+  const int4* __restrict__ native_rects;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
   const float* __restrict__ image;
@@ -32,6 +33,7 @@ struct BackwardArgs {
 template <int C, int ORDER, bool RBF>
 __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
+  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
@@ -61,8 +63,12 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
       }
     }
   }
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.ranges[tile], srec, false, 0ull, sd,
-                                a.pair_grads);
+  if (px.straddle)
+    backward_accumulate<C, ORDER, true>(px, a.S.r2, a.records, a.vals, a.native_rects,
+                                        a.ranges[tile], srec, smask, false, 0ull, sd, a.pair_grads);
+  else
+    backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, nullptr, a.ranges[tile],
+                                         srec, nullptr, false, 0ull, sd, a.pair_grads);
 }
 
 struct GatherArgs {
@@ -92,8 +98,17 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
 hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
                            const float* image, const float* denom, const float* grad_image,
                            const float* target, hipStream_t s) {
-  BackwardArgs a{S,     C,     b.records, reinterpret_cast<const int2*>(b.ranges), b.vals,
-                 image, denom, grad_image, target, b.pair_grads};
+  BackwardArgs a{S,
+                 C,
+                 b.records,
+                 reinterpret_cast<const int4*>(b.native_rects),
+                 reinterpret_cast<const int2*>(b.ranges),
+                 b.vals,
+                 image,
+                 denom,
+                 grad_image,
+                 target,
+                 b.pair_grads};
   with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_backward<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);

@@ -16,11 +16,12 @@
 namespace smoe {
 namespace {
 
-// One thread per kernel row: block rectangle, count, render record, and (tile_counts not
-// null) one atomic increment per covered block.
+// One thread per kernel row: output-block and native-block rectangles, count, render
+// record, and (tile_counts not null) one atomic increment per covered block.
 __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
                                                     const float* __restrict__ params, Segs S,
                                                     int4* __restrict__ tile_rects,
+                                                    int4* __restrict__ native_rects,
                                                     int32_t* __restrict__ counts,
                                                     float* __restrict__ records, int rs,
                                                     int32_t* __restrict__ tile_counts) {
@@ -36,8 +37,10 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
     l21 = l21 / sg.sharpen;
     l22 = l22 / sg.sharpen;
   }
-  const int4 rc = kernel_block_rect(p[0], p[1], l11, l21, l22, sg, S.r, S.box);
+  const KernelRects kr = kernel_rects(p[0], p[1], l11, l21, l22, sg, S.r, S.box, S.trunc);
+  const int4 rc = kr.tile;
   tile_rects[j] = rc;
+  native_rects[j] = kr.native;
   counts[j] = rect_count(rc);
   write_record(records + (size_t)j * rs, p, ne, rs, l11, l21, l22);
   if (tile_counts) count_blocks(rc, sg, tile_counts);
@@ -146,7 +149,8 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
   k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
   if (S.K > 0) {
     k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
-                                                 reinterpret_cast<int4*>(b.tile_rects), b.counts,
+                                                 reinterpret_cast<int4*>(b.tile_rects),
+                                                 reinterpret_cast<int4*>(b.native_rects), b.counts,
                                                  b.records, b.record_stride, b.tile_counts);
   }
   return hipGetLastError();
@@ -166,7 +170,8 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
   k_fill_i32<<<1, 64, 0, s>>>(b.status, 8, 0);
   if (S.K > 0) {
     k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
-                                                 reinterpret_cast<int4*>(b.tile_rects), b.counts,
+                                                 reinterpret_cast<int4*>(b.tile_rects),
+                                                 reinterpret_cast<int4*>(b.native_rects), b.counts,
                                                  b.records, b.record_stride, nullptr);
   }
   return hipGetLastError();

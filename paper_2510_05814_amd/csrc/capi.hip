@@ -30,8 +30,8 @@ bool valid_raster(int32_t W, int32_t H, int32_t scale, int32_t ox, int32_t oy) {
   return std::abs(ox) <= (1 << 22) && std::abs(oy) <= (1 << 22);
 }
 
-// Truncation radius in [2^-30, 2^30]: the render's bound (2r)^2 or r^2 is then a normal
-// binary32 number whose compare-free cut constants are exact.
+// Truncation radius in [2^-30, 2^30]: the ellipse bound r^2 is then a normal binary32 number
+// whose compare-free cut constants are exact.
 bool valid_radius(float r) { return r >= 0x1p-30f && r <= 0x1p30f; }
 // Sharpening factor: 0 (none) or a finite positive bandwidth divisor.
 bool valid_sharpen(float f) { return f == 0.0f || (f > 0.0f && std::isfinite(f)); }
@@ -40,21 +40,22 @@ bool valid_box(int32_t b) { return b == SMOE_BOX_SQUARE || b == SMOE_BOX_TIGHT; 
 bool valid_mode(int32_t m) { return m == SMOE_MODE_SMOE || m == SMOE_MODE_RBF; }
 bool valid_trunc(int32_t t) { return t == SMOE_TRUNC_RENDER || t == SMOE_TRUNC_GRADIENT; }
 
-// The render's bound on q (binary32): the ellipse r^2 when the ellipse test applies to the
-// render; (2r)^2 when the block lists decide it.
-float render_bound(float r, int32_t trunc) {
-  const float r2r = 2.0f * r;
-  return trunc == SMOE_TRUNC_RENDER ? r * r : r2r * r2r;
-}
-
-// The render's bound and its compare-free form (Segs::cut_scale, cut_offset).  The radius
-// range keeps r2_render a normal binary32 number with a representable power-of-two scale.
+// The render's bound in its compare-free form (Segs::cut_scale, cut_offset).  With the ellipse
+// test in the render: q <= r^2, scale 2^k with r^2 2^k in [2^60, 2^61) (the radius range keeps
+// r^2 a normal binary32 number with a representable power-of-two scale).  With the block
+// lists deciding the render: the term's exponent a >= -125, as min(a, fma(a, 2^60, 125 2^60)).
 void set_render_bound(Segs& S) {
-  S.r2_render = render_bound(S.r, S.trunc);
-  int e = 0;
-  std::frexp(S.r2_render, &e);  // r2_render = f 2^e with f in [0.5, 1)
-  S.cut_scale = std::ldexp(1.0f, 61 - e);
-  S.cut_offset = -S.r2_render * S.cut_scale;
+  if (S.trunc == SMOE_TRUNC_RENDER) {
+    S.r2_render = S.r * S.r;
+    int e = 0;
+    std::frexp(S.r2_render, &e);  // r2_render = f 2^e with f in [0.5, 1)
+    S.cut_scale = std::ldexp(1.0f, 61 - e);
+    S.cut_offset = -S.r2_render * S.cut_scale;
+  } else {
+    S.r2_render = 0.0f;  // no bound on q
+    S.cut_scale = 0x1p60f;
+    S.cut_offset = 125.0f * 0x1p60f;
+  }
 }
 
 long long raster_tiles(int32_t W, int32_t H) {
@@ -136,11 +137,11 @@ bool batch_segs(const smoe_batch* b, Segs* out) {
 
 bool bins_match(const smoe_bins* b, int K, int C, int order) {
   return b && b->K == K && b->C == C && b->order == order && b->status && b->ranges && b->vals &&
-         b->records;
+         b->records && b->tile_rects && b->native_rects;
 }
 
 struct Layout {
-  size_t tile_rects, counts, records, tile_counts, ranges, keys, vals, vals_alt, pair_grads,
+  size_t tile_rects, native_rects, counts, records, tile_counts, ranges, keys, vals, vals_alt, pair_grads,
       tile_loss, status, total;
 };
 
@@ -152,6 +153,7 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   Layout L;
   size_t o = 0;
   L.tile_rects = o; o = align_up(o + (size_t)K * 4 * sizeof(int32_t));
+  L.native_rects = o; o = align_up(o + (size_t)K * 4 * sizeof(int32_t));
   L.counts = o;     o = align_up(o + (size_t)K * sizeof(int32_t));
   L.records = o;    o = align_up(o + (size_t)K * rs * sizeof(float));
   L.tile_counts = o; o = align_up(o + (size_t)max_tiles * sizeof(int32_t));
@@ -317,6 +319,7 @@ smoe_status layout_into(smoe_bins* out, void* workspace, size_t bytes, int32_t K
   b.max_tiles = max_tiles;
   b.capacity = capacity;
   b.tile_rects = reinterpret_cast<int32_t*>(base + L.tile_rects);
+  b.native_rects = reinterpret_cast<int32_t*>(base + L.native_rects);
   b.counts = reinterpret_cast<int32_t*>(base + L.counts);
   b.records = reinterpret_cast<float*>(base + L.records);
   b.record_stride = record_stride(C, order);

@@ -11,25 +11,67 @@ namespace smoe {
 constexpr int kStepShadow = 4;  // status word: completed steps, copied by the step's first kernel
 constexpr int kStepFlags = 5;   // status words 5, 6: the fit step's overflow flag by step parity
 
-// Output-pixel index range whose centres lie in [lo, hi] (output units), clamped to
-// [0, n-1]; false when empty.  NaN inputs give an empty range.
-__device__ __forceinline__ bool axis_range(float lo, float hi, int n, int& i0, int& i1) {
-  const float a = ceilf(lo - 0.5f);
-  const float b = floorf(hi - 0.5f);
-  const float last = (float)(n - 1);
-  if (!(a <= last) || !(b >= 0.0f)) return false;
-  i0 = (a < 0.0f) ? 0 : (int)a;
-  i1 = (b > last) ? n - 1 : (int)b;
-  return i0 <= i1;
+// Native 16x16 block index of a native coordinate, floor(x / 16) (x * 2^-4 is exact).
+__device__ __forceinline__ float native_block(float x) { return floorf(x * 0.0625f); }
+
+// Output-block range [t0, t1] of one axis of a raster (n points sampled at
+// ((o + u) + 0.5) * inv_s) holding a point whose native block lies in [b0, b1], and the
+// native range clamped to the blocks the raster's points reach.  The native block index does
+// not decrease along the axis, so the points form one run [u0, u1]: at scale 1 the block of
+// point u is (o + u) >> 4 exactly; otherwise both ends are found by binary search over the
+// exact binary32 sample coordinates.  False when no point is in [b0, b1] (or NaN).
+__device__ __forceinline__ bool output_axis(float b0, float b1, int n, int o, int scale,
+                                            float inv_s, int& t0, int& t1, int& nb0, int& nb1) {
+  const float first = native_block(sample_coord(0, o, inv_s));
+  const float last = native_block(sample_coord(n - 1, o, inv_s));
+  if (!(b1 >= first) || !(b0 <= last)) return false;
+  nb0 = (int)fmaxf(b0, first);
+  nb1 = (int)fminf(b1, last);
+  int u0, u1;
+  if (scale == 1) {
+    u0 = max(0, 16 * nb0 - o);
+    u1 = min(n - 1, 16 * nb1 + 15 - o);
+  } else {
+    // first point with native block >= nb0, and first point with native block > nb1
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (native_block(sample_coord(mid, o, inv_s)) >= (float)nb0) hi = mid;
+      else lo = mid + 1;
+    }
+    u0 = lo;
+    lo = 0;
+    hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (native_block(sample_coord(mid, o, inv_s)) > (float)nb1) hi = mid;
+      else lo = mid + 1;
+    }
+    u1 = lo - 1;
+  }
+  t0 = u0 >> 4;
+  t1 = u1 >> 4;
+  return true;
 }
 
-// Block rectangle (tx0, ty0, tx1, ty1) of one kernel, (0, 0, -1, -1) when empty: the pixel
-// centres inside the square box of half-side R = r sqrt(lambda_max(L L^T)) around mu, or
-// inside the tight axis-aligned box of the ellipse's x and y extents (widened by a rounding
-// margin, capped at R), as the exact binary32 sequences of the ABI contract.
-__device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l11, float l21,
-                                                  float l22, const SegGrid& g, float r,
-                                                  int box) {
+// A kernel's blocks on one raster: `tile` = its output-block rectangle (tx0, ty0, tx1, ty1)
+// and `native` = its native 16x16 blocks (bx0, by0, bx1, by1) clamped to those the raster's
+// points reach; both (0, 0, -1, -1) when empty.
+struct KernelRects {
+  int4 tile, native;
+};
+
+// The blocks of one kernel: the native blocks its square box of half-side
+// R = r sqrt(lambda_max(L L^T)) around mu covers -- with the block lists deciding the render
+// (SMOE_TRUNC_GRADIENT) those holding a native pixel centre inside the box, with the ellipse
+// deciding (SMOE_TRUNC_RENDER) those the box overlaps, so that every point inside the ellipse
+// is a member at any scale -- or those of its tight axis-aligned box of the
+// ellipse's x and y extents (widened by a rounding margin, capped at R) -- as the exact
+// binary32 sequences of the ABI contract; the raster's output blocks are those holding a
+// sample point in them.
+__device__ __forceinline__ KernelRects kernel_rects(float mux, float muy, float l11, float l21,
+                                                    float l22, const SegGrid& g, float r, int box,
+                                                    int trunc) {
   const float sxx = l11 * l11;
   const float sxy = l11 * l21;
   const float syy = l21 * l21 + l22 * l22;
@@ -43,14 +85,34 @@ __device__ __forceinline__ int4 kernel_block_rect(float mux, float muy, float l1
     Rx = fminf(R, r * fabsf(l11) * 1.0009765625f + m);
     Ry = fminf(R, r * sqrtf(syy) * 1.0009765625f + m);
   }
-  const float fs = (float)g.scale;
-  const float X0 = (mux - Rx) * fs - (float)g.ox;
-  const float X1 = (mux + Rx) * fs - (float)g.ox;
-  const float Y0 = (muy - Ry) * fs - (float)g.oy;
-  const float Y1 = (muy + Ry) * fs - (float)g.oy;
-  int u0, u1, v0, v1;
-  const bool ok = axis_range(X0, X1, g.W, u0, u1) && axis_range(Y0, Y1, g.H, v0, v1);
-  return ok ? make_int4(u0 >> 4, v0 >> 4, u1 >> 4, v1 >> 4) : make_int4(0, 0, -1, -1);
+  float bx0f, bx1f, by0f, by1f;
+  if (trunc == SMOE_TRUNC_GRADIENT) {
+    // the blocks of the native pixel centres c + 0.5 inside the box: c from ceil(lo - 0.5)
+    // to floor(hi - 0.5) (empty if none)
+    const float cx0 = ceilf((mux - Rx) - 0.5f), cx1 = floorf((mux + Rx) - 0.5f);
+    const float cy0 = ceilf((muy - Ry) - 0.5f), cy1 = floorf((muy + Ry) - 0.5f);
+    bx0f = cx0 <= cx1 ? native_block(cx0) : 1.0f;
+    bx1f = cx0 <= cx1 ? native_block(cx1) : 0.0f;
+    by0f = cy0 <= cy1 ? native_block(cy0) : 1.0f;
+    by1f = cy0 <= cy1 ? native_block(cy1) : 0.0f;
+  } else {
+    // the blocks the box overlaps: floor(lo/16) .. ceil(hi/16) - 1
+    bx0f = native_block(mux - Rx);
+    bx1f = ceilf((mux + Rx) * 0.0625f) - 1.0f;
+    by0f = native_block(muy - Ry);
+    by1f = ceilf((muy + Ry) * 0.0625f) - 1.0f;
+  }
+  KernelRects k;
+  k.tile = make_int4(0, 0, -1, -1);
+  k.native = make_int4(0, 0, -1, -1);
+  if (!(bx0f <= bx1f) || !(by0f <= by1f)) return k;
+  int tx0, tx1, ty0, ty1, bx0, bx1, by0, by1;
+  if (output_axis(bx0f, bx1f, g.W, g.ox, g.scale, g.inv_s, tx0, tx1, bx0, bx1) &&
+      output_axis(by0f, by1f, g.H, g.oy, g.scale, g.inv_s, ty0, ty1, by0, by1)) {
+    k.tile = make_int4(tx0, ty0, tx1, ty1);
+    k.native = make_int4(bx0, by0, bx1, by1);
+  }
+  return k;
 }
 
 // n / d from r = v_rcp_f32(d) (within 1 ulp of 1/d) and one Newton-Raphson correction of

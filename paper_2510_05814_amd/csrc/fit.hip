@@ -37,7 +37,7 @@ struct FitTileArgs {
   float* __restrict__ pair_grads;
 };
 
-template <int C, int ORDER, bool RBF>
+template <int C, int ORDER, bool RBF, int TRUNC>
 __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
   __shared__ float4 srec[LDS_FLOATS / 4];
@@ -72,8 +72,10 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live = 0;
-  forward_accumulate<C, ORDER>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records, a.vals, rg,
-                               srec, D, N, live);
+  // a fit raster has scale 1 and origin 0: its blocks are native blocks (no straddling)
+  forward_accumulate<C, ORDER, TRUNC, false>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
+                                             a.records, a.vals, nullptr, rg, srec, nullptr, D, N,
+                                             live);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -110,7 +112,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, rg, srec, true, live, sd, a.pair_grads);
+  backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, nullptr, rg, srec, nullptr,
+                                       true, live, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {
@@ -240,9 +243,11 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       f.records[(size_t)j * RS + i] = fld;
     }
     if (i == 0) {
-      const int4 rc = kernel_block_rect(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box);
-      f.tile_rects_out[j] = rc;
-      f.counts[j] = rect_count(rc);
+      // (a fit raster has scale 1 and origin 0: the output blocks are the native blocks,
+      // and no block straddles two, so the native rectangles are not kept up to date)
+      const KernelRects kr = kernel_rects(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box, f.S.trunc);
+      f.tile_rects_out[j] = kr.tile;
+      f.counts[j] = rect_count(kr.tile);
     }
   }
   // The counter itself is written once; every workgroup read the shadow copy instead.  The
@@ -290,7 +295,7 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
                 b.tile_loss, b.pair_grads};
   with_shape(st.C, st.order, S, [&](auto sh) {
     using T = decltype(sh);
-    k_fit_tile<T::C, T::ORDER, T::RBF><<<S.T, kWave, 0, s>>>(a);
+    k_fit_tile<T::C, T::ORDER, T::RBF, T::TRUNC><<<S.T, kWave, 0, s>>>(a);
   });
   return hipGetLastError();
 }

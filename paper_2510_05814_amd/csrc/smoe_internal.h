@@ -37,12 +37,16 @@ struct Segs {
   int n;
   smoe_segment one;                      // the single raster when tab is null
   float r, r2;                           // truncation radius and r*r (binary32)
-  float r2_render;                       // the render's bound on q: r2, or (2r)^2
-  // The render's bound applied without a compare: with cut_scale = 2^k such that
-  // r2_render * 2^k lies in [2^60, 2^61) and cut_offset = -r2_render * 2^k (both exact),
-  // u = fma(q, cut_scale, cut_offset) is <= 0 for q <= r2_render and >= 2^37 beyond it, so
-  // max(q, u) is q inside the bound and pushes the exponent of a term beyond it to about
-  // -2^36, whose exp2 is exactly zero.
+  float r2_render;                       // the render's bound on q: r2 (ellipse in the
+                                         // render), or 0 (no bound on q)
+  // The render's bound applied without a compare.  Ellipse in the render: with
+  // cut_scale = 2^k such that r2_render * 2^k lies in [2^60, 2^61) and
+  // cut_offset = -r2_render * 2^k (both exact), u = fma(q, cut_scale, cut_offset) is <= 0 for
+  // q <= r2_render and >= 2^37 beyond it, so max(q, u) is q inside the bound and pushes the
+  // exponent of a term beyond it to about -2^36, whose exp2 is exactly zero.  Block lists
+  // deciding the render: cut_scale = 2^60, cut_offset = 125 * 2^60, and for the term's
+  // exponent a, min(a, fma(a, cut_scale, cut_offset)) is a when a >= -125 (the term is a
+  // normal binary32 number) and below -2^43 otherwise.
   float cut_scale, cut_offset;
   int box;                               // SMOE_BOX_SQUARE or SMOE_BOX_TIGHT
   int mode;                              // SMOE_MODE_SMOE or SMOE_MODE_RBF

@@ -13,22 +13,31 @@ namespace smoe {
 
 constexpr int kWave = 64;
 
-// Compile-time shape of a launch: channels, expert order and regression mode (RBF: the
-// un-normalised sum of Eq. 1 instead of the gated SMoE of Eq. 2-4).
-template <int C_, int ORDER_, bool RBF_>
+// Compile-time shape of a launch: channels, expert order, regression mode (RBF: the
+// un-normalised sum of Eq. 1 instead of the gated SMoE of Eq. 2-4) and the reading of the
+// truncation (which bound the render applies).
+template <int C_, int ORDER_, bool RBF_, int TRUNC_>
 struct Shape {
-  static constexpr int C = C_, ORDER = ORDER_;
+  static constexpr int C = C_, ORDER = ORDER_, TRUNC = TRUNC_;
   static constexpr bool RBF = RBF_;
 };
 
-// Calls f(Shape<...>{}) for the run-time (C, order, mode); C is 1 or 3, order 0 or 1.
+// Calls f(Shape<...>{}) for the run-time (C, order, mode, reading); C is 1 or 3, order 0 or 1.
+template <int C, int ORDER, class F>
+inline void with_mode(const Segs& S, F&& f) {
+  const bool rbf = S.mode == SMOE_MODE_RBF;
+  if (S.trunc == SMOE_TRUNC_RENDER)
+    rbf ? f(Shape<C, ORDER, true, SMOE_TRUNC_RENDER>{}) : f(Shape<C, ORDER, false, SMOE_TRUNC_RENDER>{});
+  else
+    rbf ? f(Shape<C, ORDER, true, SMOE_TRUNC_GRADIENT>{})
+        : f(Shape<C, ORDER, false, SMOE_TRUNC_GRADIENT>{});
+}
 template <class F>
 inline void with_shape(int C, int order, const Segs& S, F&& f) {
-  const bool rbf = S.mode == SMOE_MODE_RBF;
-  if (C == 1 && order == 0) rbf ? f(Shape<1, 0, true>{}) : f(Shape<1, 0, false>{});
-  else if (C == 1 && order == 1) rbf ? f(Shape<1, 1, true>{}) : f(Shape<1, 1, false>{});
-  else if (C == 3 && order == 0) rbf ? f(Shape<3, 0, true>{}) : f(Shape<3, 0, false>{});
-  else rbf ? f(Shape<3, 1, true>{}) : f(Shape<3, 1, false>{});
+  if (C == 1 && order == 0) with_mode<1, 0>(S, f);
+  else if (C == 1 && order == 1) with_mode<1, 1>(S, f);
+  else if (C == 3 && order == 0) with_mode<3, 0>(S, f);
+  else with_mode<3, 1>(S, f);
 }
 constexpr int kChunk = 64;                     // records staged in LDS per chunk
 constexpr int kRows = kTilePixels / kWave;     // pixels per lane (4)
@@ -38,7 +47,21 @@ struct PixelCoords {
   int v0;           // output row of the lane's first pixel (rows v0 + 4i)
   float x;          // sampling coordinates
   float y[kRows];
+  // Native blocks.  A kernel takes part at a point only if the point's native 16x16 block is
+  // one of the kernel's.  An output block whose points all lie in one native block (every
+  // block at scale 1 with a block-aligned origin) needs no per-point test; one that straddles
+  // native blocks (at most two per axis: 16 output pixels span at most 16 native pixels)
+  // tests each point.  (bxb, byb): native block of the block's first column and row;
+  // lbit[i]: 1 << (dx + 2 dy) with (dx, dy) in {0, 1}^2 the native block of the lane's
+  // pixel i relative to it.
+  int bxb, byb;
+  bool straddle;    // wave-uniform
+  uint32_t lbit[kRows];
 };
+
+__device__ __forceinline__ int native_block_of(int u, int o, float inv_s) {
+  return (int)native_block(sample_coord(u, o, inv_s));
+}
 
 // `tile` is the block index inside the segment's raster.
 __device__ __forceinline__ PixelCoords lane_pixels(const SegGrid& g, int tile) {
@@ -50,40 +73,77 @@ __device__ __forceinline__ PixelCoords lane_pixels(const SegGrid& g, int tile) {
   p.x = sample_coord(p.u, g.ox, g.inv_s);
 #pragma unroll
   for (int i = 0; i < kRows; ++i) p.y[i] = sample_coord(p.v0 + 4 * i, g.oy, g.inv_s);
+  p.bxb = native_block_of(tx * kTile, g.ox, g.inv_s);
+  p.byb = native_block_of(ty * kTile, g.oy, g.inv_s);
+  p.straddle = native_block_of(tx * kTile + kTile - 1, g.ox, g.inv_s) != p.bxb ||
+               native_block_of(ty * kTile + kTile - 1, g.oy, g.inv_s) != p.byb;
+  const int dx = (int)native_block(p.x) - p.bxb;
+#pragma unroll
+  for (int i = 0; i < kRows; ++i)
+    p.lbit[i] = 1u << (dx + 2 * ((int)native_block(p.y[i]) - p.byb));
   return p;
 }
 
-// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS.
+// For a straddling block: entry k's native-block mask, inverted -- bit dx + 2 dy is set iff
+// the native block (bxb + dx, byb + dy) is NOT one of the kernel's.
+__device__ __forceinline__ uint32_t outside_mask(int4 nr, int bxb, int byb) {
+  const bool x0 = nr.x <= bxb && bxb <= nr.z, x1 = nr.x <= bxb + 1 && bxb + 1 <= nr.z;
+  const bool y0 = nr.y <= byb && byb <= nr.w, y1 = nr.y <= byb + 1 && byb + 1 <= nr.w;
+  const uint32_t in = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
+                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+  return ~in & 15u;
+}
+
+// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS, and for a
+// straddling block (smask not null) each entry's outside_mask.
 template <int RS>
 __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
                                               const float* __restrict__ records,
-                                              const uint32_t* __restrict__ vals, int base, int n) {
+                                              const uint32_t* __restrict__ vals, int base, int n,
+                                              uint32_t* __restrict__ smask = nullptr,
+                                              const int4* __restrict__ native_rects = nullptr,
+                                              int bxb = 0, int byb = 0) {
   constexpr int Q = RS / 4;
   __syncthreads();
   for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
     const int k = i / Q, c = i - k * Q;
     srec[i] = reinterpret_cast<const float4*>(records + (size_t)vals[base + k] * RS)[c];
   }
+  if (smask)
+    for (int k = threadIdx.x & 63; k < n; k += kWave)
+      smask[k] = outside_mask(native_rects[vals[base + k]], bxb, byb);
   __syncthreads();
 }
 
+// Pushes q beyond every bound at the lane's pixels outside the entry's native blocks
+// (STRADDLE only): q + 2^100 * (outside & lbit), with `big` = 2^100 in a vector register.
+template <bool STRADDLE>
+__device__ __forceinline__ float member_q(float q, uint32_t outside, uint32_t lbit, float big) {
+  if (!STRADDLE) return q;
+  return __builtin_fmaf((float)(outside & lbit), big, q);
+}
+
 // One list entry of the forward: adds its terms to D = sum pi K and N_c = sum pi K m_c of
-// the lane's four pixels, for the pixels with q <= r2_render: r^2 (the ellipse test in the
-// render) or (2r)^2 (the block lists decide the render; the cut keeps every term inside
-// FP32's accurate range).  Returns whether any of the lane's pixels passed the ellipse test
-// q <= r2.  r: the entry's render record; cut_scale, cut_offset: the render's bound in the
-// compare-free form of Segs.
+// the lane's four pixels that the render's rule keeps.  TRUNC == SMOE_TRUNC_RENDER: the
+// ellipse q <= r^2.  TRUNC == SMOE_TRUNC_GRADIENT (the block lists decide the render): every
+// term binary32 holds, i.e. whose exponent a = rho log2(e) - q log2(e)/2 is >= -125.  Returns
+// whether any of the lane's pixels passed the ellipse test q <= r2.  r: the entry's render
+// record; cut_scale, cut_offset: the render's bound in the compare-free form of Segs;
+// outside, big: the native-block test of a straddling block (member_q).
 //
-// Neither test is a per-row compare: a VALU instruction that writes or reads a scalar
+// Neither bound is a per-row compare: a VALU instruction that writes or reads a scalar
 // register (a compare's lane mask, a select on it) issues at about 60 % of the rate of one
 // on vector registers alone.  The ellipse test compares the minimum of the four rows' q
-// once; the render's bound goes through the exponent (max(q, u) is q inside the bound, and
-// a term beyond it gets an exponent of about -2^36, whose exp2 is exactly zero), so every
-// kept term carries the same bits as with a select.
-template <int C, int ORDER>
+// once; the render's bound goes through the exponent: with the ellipse, max(q, u) with
+// u = fma(q, cut_scale, cut_offset) is q inside the bound and gives a term beyond it an
+// exponent of about -2^36; with the representable range, min(a, fma(a, 2^60, 125 * 2^60)) is
+// a for a >= -125 and below -2^43 otherwise.  Either way exp2 of an excluded term is exactly
+// zero and every kept term carries the same bits as with a compare-and-select.
+template <int C, int ORDER, int TRUNC, bool STRADDLE>
 __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, float cut_scale,
-                                              float cut_offset, const float* r,
-                                              float (&D)[kRows], float (&N)[kRows][C]) {
+                                              float cut_offset, float big, const float* r,
+                                              uint32_t outside, float (&D)[kRows],
+                                              float (&N)[kRows][C]) {
   // Truncation test: the binary32 sequence of the ABI contract (no contraction).
   const float dx = px.x - r[0];
   const float z1 = dx * r[2];
@@ -101,13 +161,20 @@ __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, f
     dy[i] = px.y[i] - r[1];
     const float w = dy[i] - tt;
     const float z2 = w * r[4];
-    q[i] = zz1 + z2 * z2;
+    q[i] = member_q<STRADDLE>(zz1 + z2 * z2, outside, px.lbit[i], big);
   }
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
-    const float qc = __builtin_fmaxf(q[i], __builtin_fmaf(q[i], cut_scale, cut_offset));
-    const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(qc, -0.5f * kLog2e, r[5]));
+    float a;
+    if (TRUNC == SMOE_TRUNC_RENDER) {
+      const float qc = __builtin_fmaxf(q[i], __builtin_fmaf(q[i], cut_scale, cut_offset));
+      a = __builtin_fmaf(qc, -0.5f * kLog2e, r[5]);
+    } else {
+      const float a0 = __builtin_fmaf(q[i], -0.5f * kLog2e, r[5]);
+      a = __builtin_fminf(a0, __builtin_fmaf(a0, cut_scale, cut_offset));
+    }
+    const float e = __builtin_amdgcn_exp2f(a);
     D[i] += e;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -141,25 +208,33 @@ __device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C
 // entry, records staged through LDS in chunks).
 // live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
-template <int C, int ORDER>
+// STRADDLE: the block straddles native blocks (smask: kChunk words of LDS; native_rects: the
+// kernels' native rectangles); otherwise both may be null.
+template <int C, int ORDER, int TRUNC, bool STRADDLE>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
                                                    float cut_scale, float cut_offset,
                                                    const float* __restrict__ records,
-                                                   const uint32_t* __restrict__ vals, int2 rg,
-                                                   float4* srec, float (&D)[kRows],
-                                                   float (&N)[kRows][C], uint64_t& live) {
+                                                   const uint32_t* __restrict__ vals,
+                                                   const int4* __restrict__ native_rects, int2 rg,
+                                                   float4* srec, uint32_t* smask,
+                                                   float (&D)[kRows], float (&N)[kRows][C],
+                                                   uint64_t& live) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   zero_sums<C>(D, N);
   cut_scale = in_vgpr(cut_scale);
   cut_offset = in_vgpr(cut_offset);
+  const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    stage_records<RS>(srec, records, vals, base, n);
+    stage_records<RS>(srec, records, vals, base, n, STRADDLE ? smask : nullptr, native_rects,
+                      px.bxb, px.byb);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      if (__any(forward_entry<C, ORDER>(px, r2, cut_scale, cut_offset, r, D, N)))
+      const uint32_t outside = STRADDLE ? smask[k] : 0u;
+      if (__any(forward_entry<C, ORDER, TRUNC, STRADDLE>(px, r2, cut_scale, cut_offset, big, r,
+                                                          outside, D, N)))
         live |= 1ull << k;
     }
   }
@@ -302,22 +377,26 @@ struct PixelSeed {
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 // The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
 // 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel.
-template <int C, int ORDER>
+template <int C, int ORDER, bool STRADDLE>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
-                                                    const uint32_t* __restrict__ vals, int2 rg,
-                                                    float4* srec, bool staged, uint64_t live,
-                                                    const PixelSeed<C>& sd,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const int4* __restrict__ native_rects, int2 rg,
+                                                    float4* srec, uint32_t* smask, bool staged,
+                                                    uint64_t live, const PixelSeed<C>& sd,
                                                     float* __restrict__ pair_grads) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   constexpr int NP = num_params(C, ORDER);
   static_assert(NP <= 16, "16 accumulators per kernel");
   const int lane = threadIdx.x & 63;
+  const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     const bool reuse = staged && rg.y - rg.x <= kChunk;
-    if (!reuse) stage_records<RS>(srec, records, vals, base, n);
+    if (!reuse)
+      stage_records<RS>(srec, records, vals, base, n, STRADDLE ? smask : nullptr, native_rects,
+                        px.bxb, px.byb);
     for (int k = 0; k < n; ++k) {
       if (reuse && !((live >> k) & 1ull)) {
         // no pixel of the block passed the forward's test: the partial row is zero
@@ -326,6 +405,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         continue;
       }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
+      const uint32_t outside = STRADDLE ? smask[k] : 0u;
       const float dx = px.x - r[0];
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
@@ -349,7 +429,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         const float dy = px.y[i] - r[1];
         const float w_ = dy - tt;
         const float z2 = w_ * r[4];
-        const float q = zz1 + z2 * z2;
+        const float q = member_q<STRADDLE>(zz1 + z2 * z2, outside, px.lbit[i], big);
         if (sd.valid[i] && q <= r2) {
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
           const float w = e * sd.invD[i];

@@ -73,7 +73,9 @@ class RenderResult:
 
 class BoxSpans:
     """Host-side upper bounds of the (block, kernel) pairs a render creates, from each
-    kernel's square box (half-side r sqrt(lambda_max) of its covariance, Sec. IV-B).
+    kernel's square box (half-side r sqrt(lambda_max) of its covariance, Sec. IV-B): the
+    native 16x16 blocks the box overlaps, and the output blocks holding a sample point in
+    them.
 
     models: float64/float32 [K_i, NP] materialized rows, one array per model."""
 
@@ -93,11 +95,13 @@ class BoxSpans:
         f = 1.0 if sharpen in (0.0, 1.0) else float(sharpen)
         key = (i, scale, f)
         if key not in self._spans:
-            # pixels spanned <= floor(2 R s / f) + 1 (sharpening divides L, hence R, by f);
-            # 2 more absorb the binary32 rounding of the box edges; n pixels at any
-            # alignment touch <= ceil((n - 1) / 16) + 1 blocks.
-            n = np.floor(2.0 * self._R[i] * scale / f * (1.0 + 1e-5)).astype(np.int64) + 3
-            b = np.sort((n + TILE - 2) // TILE + 1)
+            # native blocks overlapped per axis: nb <= floor(2 R / (16 f)) + 2 (sharpening
+            # divides L, hence R, by f; the 1e-5 absorbs the binary32 rounding of the box
+            # edges); their sample points at scale s are 16 s nb consecutive output pixels
+            # (points sit half a spacing off every block boundary), which touch at most
+            # s nb + 1 output blocks.
+            nb = np.floor(2.0 * self._R[i] / (TILE * f) * (1.0 + 1e-5)).astype(np.int64) + 2
+            b = np.sort(nb * scale + 1)
             self._spans[key] = (b, np.concatenate([[0], np.cumsum(b)]),
                                 np.concatenate([[0], np.cumsum(b * b)]))
         return self._spans[key]

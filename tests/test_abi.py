@@ -69,7 +69,7 @@ def test_workspace_layout_host_only():
     base = 1 << 20  # a fake, 256-aligned address: layout only does pointer arithmetic
     b = C.SmoeBins()
     C.smoe_bins_layout(b, base, n, 100, 3, 1, 64, 1000)
-    ptrs = [b.tile_rects, b.counts, b.records, b.tile_counts, b.ranges, b.keys, b.vals,
+    ptrs = [b.tile_rects, b.native_rects, b.counts, b.records, b.tile_counts, b.ranges, b.keys, b.vals,
             b.vals_alt, b.pair_grads, b.tile_loss, b.status]
     assert all(p % 256 == 0 for p in ptrs)
     assert ptrs == sorted(ptrs) and ptrs[-1] + 16 <= base + n

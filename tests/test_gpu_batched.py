@@ -158,3 +158,64 @@ def test_batched_fit_rejects_scaled_segments():
     st.segments.host[0].scale = 2
     with pytest.raises(C.SmoeError):
         st.step()
+
+
+@pytest.mark.parametrize("mode", ["smoe", "rbf"])
+def test_batched_fit_steps_against_oracle(mode, record_error):
+    """The batched fit (four images of uneven sizes fitted together, the shape of the batched
+    workload) against the FP64 oracle image by image: from the GPU's state before a step --
+    the initial one, then after 6 more steps replayed from a HIP graph -- each image's loss, every
+    gradient (per parameter group) and the Adam update of that step (the oracle's Adam from
+    the GPU's own state and gradient, so that the update itself is checked)."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    say("batched fit vs oracle", mode)
+    imgs = wl.config5_images(n=4, lo=40, hi=160)
+    raws = wl.batched_fit_inits(imgs)
+    total = 100
+    adam = smoe.AdamConfig(total_steps=total)
+    bst = smoe.FitState([dev(i) for i in imgs], [dev(r) for r in raws], 1, adam, max_steps=16,
+                        mode=mode)
+    lr_col = None
+    for phase in range(2):
+        if phase == 1:
+            bst.replay(bst.capture(6))
+        torch.cuda.synchronize()
+        t = bst.steps_done()
+        assert t == (0 if phase == 0 else 7)
+        raw0 = host(bst.raw).astype(np.float64)
+        m0, v0 = host(bst.m).astype(np.float64), host(bst.v).astype(np.float64)
+        bst.step()
+        torch.cuda.synchronize()
+        seg = host(bst.segment_losses()).astype(np.float64)
+        g_gpu = host(bst.grads).astype(np.float64)
+        raw1, m1 = host(bst.raw).astype(np.float64), host(bst.m).astype(np.float64)
+        lrs = oracle.step_lrs(t, total, adam.lr_mu, adam.lr_mu_final, adam.lr_chol, adam.lr_rho,
+                              adam.lr_expert)
+        lr_col = np.array([lrs[0]] * 2 + [lrs[1]] * 3 + [lrs[2]] + [lrs[3]] * 9)
+        for i, im in enumerate(imgs):
+            sg = bst.segments.host[i]
+            k0, K = sg.kernel_offset, sg.num_kernels
+            H, W, _ = im.shape
+            rows = slice(k0, k0 + K)
+            model = oracle.materialize(raw0[rows], 3, 1)
+            l_o, g_o = oracle.loss_grad(model, 3, 1, W, H, target=im, rbf=(mode == "rbf"))
+            el = abs(seg[i] - l_o) / l_o
+            record_error(f"batched {mode} step {t} image {i} loss rel", el, 1e-5)
+            assert el <= 1e-5, (i, t)
+            for name, cols in {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5],
+                               "a": [6, 7, 8], "wx": [9, 10, 11], "wy": [12, 13, 14]}.items():
+                ref = g_o[:, cols]
+                e = float(np.max(np.abs(g_gpu[rows][:, cols] - ref)) / np.max(np.abs(ref)))
+                record_error(f"batched {mode} step {t} image {i} grad {name} rel", e, 1e-3)
+                assert e <= 1e-3, (i, t, name)
+            p, mm, vv = raw0[rows].copy(), m0[rows].copy(), v0[rows].copy()
+            oracle.adam(p, g_gpu[rows], mm, vv, t + 1, lrs, 3, 1)
+            ulp = np.spacing(np.abs(p).astype(np.float32)).astype(np.float64)
+            d = float(np.max((np.abs(raw1[rows] - p) - ulp) / lr_col))
+            record_error(f"batched {mode} step {t} image {i} Adam update beyond 1 ulp (lr)",
+                         max(d, 0.0), 1e-4)
+            assert d <= 1e-4, (i, t)
+            em = float(np.max(np.abs(m1[rows] - mm)) / max(np.max(np.abs(mm)), 1e-30))
+            assert em <= 1e-5, (i, t)

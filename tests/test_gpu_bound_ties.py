@@ -1,9 +1,11 @@
 """Ties at the render's bound and the ends of the radius range.  A unit-covariance kernel
-centred half a pixel off the grid puts pixel centres at q = r^2 and q = (2r)^2 exactly; a
-term kept or dropped at such a tie turns the pixel's value from the expert's into 0 (no other
-kernel covers it), so the image pins each decision: q <= bound keeps the term, the next pixel
-out drops it, on both readings of the truncation, as the oracle decides.  Radii at both ends
-of the accepted range [2^-30, 2^30] render as the oracle does."""
+centred half a pixel off the grid puts pixel centres at integer q.  With the ellipse test in
+the render the tie is q = r^2; with the block lists deciding the render it is a term whose
+binary32 exponent rho log2(e) - q log2(e)/2 is exactly -125 (the mixing weight chosen so
+that this happens at q = 16).  A term kept or dropped at such a tie turns the pixel's value
+from the expert's into 0 (no other kernel covers it), so the image pins each decision: the
+tie keeps the term, the next pixel out drops it, as the oracle decides.  Radii at both ends of
+the accepted range [2^-30, 2^30] render as the oracle does."""
 import numpy as np
 import pytest
 
@@ -41,16 +43,32 @@ def unit_kernel(mx, my):
     return np.array([[mx, my, 1.0, 0.0, 1.0, 0.0, *EXPERT]])
 
 
-@pytest.mark.parametrize("trunc,tie_u,bound", [("render", 8, 9.0), ("gradient", 11, 36.0)])
-def test_tie_at_the_bound_is_kept(smoe, trunc, tie_u, bound, record_error):
+# rho (binary32 0xc29d496c) for which fma(16, -log2(e)/2, rho log2(e)) rounds to -125 exactly
+RHO_TIE16 = np.float32(-78.64340209960938)
+TIE_EXPERT = np.array([1.0, 1.25, 1.5])  # pi K m stays a normal binary32 number at 2^-125
+
+
+def test_representable_exponent_tie_constants():
+    L = np.float32(1.44269504088896340736)
+    r5 = np.float32(RHO_TIE16 * L)
+    assert np.float32(16.0 * np.float64(np.float32(-0.5) * L) + np.float64(r5)) == np.float32(-125.0)
+    assert np.float32(25.0 * np.float64(np.float32(-0.5) * L) + np.float64(r5)) < -125.0
+
+
+@pytest.mark.parametrize("trunc,tie_u", [("render", 8), ("gradient", 9)])
+def test_tie_at_the_bound_is_kept(smoe, trunc, tie_u, record_error):
     say("bound tie", trunc)
     m_np = unit_kernel(5.5, 5.5)
+    expert = EXPERT
+    if trunc == "gradient":
+        m_np[0, 5] = RHO_TIE16
+        m_np[0, 6:] = expert = TIE_EXPERT
     grid = smoe.make_grid(16, 16, trunc=trunc)
     img, D, _, _ = smoe.render(dev(m_np), 3, 0, grid)
     img, D = host(img), host(D)
-    # pixel (tie_u, 5): x = tie_u + 0.5, so q = (tie_u - 5)^2 = the bound exactly
-    assert (tie_u - 5.0) ** 2 == bound
-    assert D[5, tie_u] > 0.0 and np.max(np.abs(img[5, tie_u] - EXPERT)) <= 1e-6
+    # pixel (tie_u, 5): x = tie_u + 0.5, so q = (tie_u - 5)^2: r^2 = 9, or 16 where the
+    # exponent is -125
+    assert D[5, tie_u] > 0.0 and np.max(np.abs(img[5, tie_u] - expert)) <= 1e-6
     assert D[5, tie_u + 1] == 0.0 and not img[5, tie_u + 1].any()
     y_o, D_o = oracle.render(m_np, 3, 0, 16, 16, trunc=trunc)
     assert np.array_equal(D > 0, D_o > 0)
@@ -86,8 +104,12 @@ def test_radius_range_ends(smoe, radius, trunc, record_error):
     e = float(np.max(np.abs(host(img) - y_o)))
     record_error(f"radius {radius} {trunc} image", e, 1e-5)
     assert e <= 1e-5
-    if radius < 1.0:
+    if radius >= 1.0:
+        assert (D_o > 0).all()
+    elif trunc == "render":
         # only the centre pixels of the first two kernels lie inside the tiny ellipse
         assert int((D_o > 0).sum()) == 2
     else:
-        assert (D_o > 0).all()
+        # the tiny boxes still list their kernels in the native blocks holding the centres,
+        # where every representable term is rendered
+        assert int((D_o > 0).sum()) > 2

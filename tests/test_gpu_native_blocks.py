@@ -1,0 +1,116 @@
+"""The render is a function of native coordinates (Sec. II-B, VII-C: super-resolution and
+windows re-sample one regression): the truncation's blocks are native 16x16 blocks, so a
+window at any origin is a crop of the full raster, bit for bit, at every scale and under both
+readings, and a scale-3 raster samples the native raster's points (up to the rounding of 1/3).
+Output blocks that straddle native blocks test each pixel's membership; their renders and
+gradients match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smoe():
+    import torch  # noqa: F401
+
+    import paper_2510_05814_amd as smoe
+    return smoe
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+W0, H0 = 61, 47
+
+
+@pytest.fixture(scope="module")
+def model():
+    # lists stay at most 128 long on every raster here (a straddling output block lists the
+    # kernels of up to four native blocks): longer lists are split over four waves, whose
+    # partial sums add in another (fixed) order
+    return wl.stretched_model(150, 3, 1, W0, H0, seed=501, size_hi=5.0)
+
+
+def longest_list(bins, grid):
+    T = ((grid.width + 15) // 16) * ((grid.height + 15) // 16)
+    r = host(bins.ranges(T))
+    return int((r[:, 1] - r[:, 0]).max())
+
+
+@pytest.mark.parametrize("trunc", ["gradient", "render"])
+@pytest.mark.parametrize("s", [1, 2, 3, 4])
+def test_windows_are_crops_bitwise(smoe, model, s, trunc, record_error):
+    print(f"[case] windows s={s} {trunc}", flush=True)
+    m = dev(model)
+    FW, FH = W0 * s, H0 * s
+    fg = smoe.make_grid(FW, FH, s, trunc=trunc)
+    full, fD, _, fb = smoe.render(m, 3, 1, fg)
+    full, fD = host(full), host(fD)
+    assert longest_list(fb, fg) <= 128
+    y_o, _ = oracle.render(model, 3, 1, FW, FH, s, trunc=trunc)
+    e = float(np.max(np.abs(full - y_o)))
+    record_error(f"full raster s={s} {trunc} image", e, 1e-5)
+    assert e <= 1e-5
+    rng = np.random.default_rng(10 * s + (trunc == "render"))
+    for _ in range(6):
+        w, h = int(rng.integers(1, FW)), int(rng.integers(1, FH))
+        ox, oy = int(rng.integers(0, FW - w + 1)), int(rng.integers(0, FH - h + 1))
+        g = smoe.make_grid(w, h, s, ox, oy, trunc=trunc)
+        img, D, _, b = smoe.render(m, 3, 1, g)
+        assert longest_list(b, g) <= 128
+        assert np.array_equal(host(img), full[oy:oy + h, ox:ox + w]), (w, h, ox, oy)
+        assert np.array_equal(host(D), fD[oy:oy + h, ox:ox + w]), (w, h, ox, oy)
+
+
+@pytest.mark.parametrize("trunc", ["gradient", "render"])
+def test_scale3_samples_the_native_points(smoe, model, trunc, record_error):
+    print(f"[case] scale 3 vs 1 {trunc}", flush=True)
+    m = dev(model)
+    y1, _, _, _ = smoe.render(m, 3, 1, smoe.make_grid(W0, H0, trunc=trunc))
+    y3, _, _, _ = smoe.render(m, 3, 1, smoe.make_grid(3 * W0, 3 * H0, 3, trunc=trunc))
+    e = float(np.max(np.abs(host(y3)[1::3, 1::3] - host(y1))))
+    record_error(f"s=3 pixels 3i+1 vs s=1 {trunc}", e, 1e-5)
+    assert e <= 1e-5
+
+
+def _groups(C, order):
+    g = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": list(range(6, 6 + C))}
+    if order == 1:
+        g["wx"] = list(range(6 + C, 6 + 2 * C))
+        g["wy"] = list(range(6 + 2 * C, 6 + 3 * C))
+    return g
+
+
+@pytest.mark.parametrize("trunc", ["gradient", "render"])
+@pytest.mark.parametrize("s,ox,oy", [(1, 5, 9), (2, 3, 21), (3, 7, 2)])
+def test_backward_on_straddling_rasters(smoe, s, ox, oy, trunc, record_error):
+    """Every output block of these rasters straddles native blocks: the per-pixel membership
+    test runs in the backward as in the render."""
+    print(f"[case] backward s={s} origin=({ox},{oy}) {trunc}", flush=True)
+    W, H = 40, 36
+    m_np = wl.random_model(80, 3, 1, W, H, seed=510 + s, sig_lo=0.8, sig_hi=8.0)
+    OW, OH = s * W - ox, s * H - oy
+    grid = smoe.make_grid(OW, OH, s, ox, oy, trunc=trunc)
+    m = dev(m_np)
+    tgt = np.random.default_rng(s).uniform(0, 1, (OH, OW, 3))
+    img, D, _, b = smoe.render(m, 3, 1, grid)
+    y_o, _ = oracle.render(m_np, 3, 1, OW, OH, s, ox, oy, trunc=trunc)
+    ey = float(np.max(np.abs(host(img) - y_o)))
+    g = host(smoe.render_backward(m, 3, 1, grid, b, img, D, target=dev(tgt)))
+    _, g_o = oracle.loss_grad(m_np.astype(np.float64), 3, 1, OW, OH, target=tgt, s=s, ox=ox,
+                              oy=oy, trunc=trunc)
+    err = max(float(np.max(np.abs(g[:, c] - g_o[:, c])) / np.max(np.abs(g_o[:, c])))
+              for c in _groups(3, 1).values())
+    record_error(f"straddling s={s} {trunc} image", ey, 1e-5)
+    record_error(f"straddling s={s} {trunc} grad rel (per group)", err, 1e-3)
+    assert ey <= 1e-5 and err <= 1e-3

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import workloads as wl
+from tests._tol import d_rel_error
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +90,7 @@ def test_rbf_render_against_oracle(smoe, case, record_error):
     ey = float(np.max(np.abs(host(img) - y_o))) / peak
     record_error("rbf image abs / peak", ey, Y_TOL)
     assert ey <= Y_TOL
-    eD = float(np.max(np.abs(host(D) - D_o) / np.maximum(D_o, 1e-30)))
+    eD = d_rel_error(host(D), D_o)
     assert eD <= 1e-5
     # the same block lists as the gated mode
     _, st = b.read_status()

@@ -51,7 +51,7 @@ def test_sweep_against_oracle(case, record_error):
     assert not over
     ms = oracle.sharpen(m_np.astype(np.float64), f)
     boxi = 1 if box == "tight" else 0
-    ob = oracle.bin(ms, C, order, OW, OH, s, ox, oy, box=boxi)
+    ob = oracle.bin(ms, C, order, OW, OH, s, ox, oy, box=boxi, trunc=trunc)
     P = st[0]
     assert P == ob["P"]
     assert np.array_equal(b.tile_rects().cpu().numpy(), ob["tile_rects"])

@@ -31,10 +31,25 @@ MUTANTS = [
      [pins.test_single_kernel_reproduces_linear_expert]),
     ("box from sxx instead of lambda_max", "const float lam = h + std::sqrt(d * d + sxy * sxy);",
      "const float lam = sxx;", [pins.test_box_half_side_is_r_sqrt_lambda_max]),
-    ("ellipse radius off", "return q <= r2;", "return q <= 1.1f * r2;",
+    ("ellipse radius off", "return rule == RULE_ELLIPSE ? q <= r2 :",
+     "return rule == RULE_ELLIPSE ? q <= 1.1f * r2 :",
      [pins.test_truncation_rule_matches_ellipse_and_stays_in_box]),
-    ("block rect off by one", "rc.tx1 = rc.u1 >> 4;", "rc.tx1 = (rc.u1 + 1) >> 4;",
+    ("native block rect off by one", "*b1 = native_block(b);", "*b1 = native_block(b) + 1.0f;",
      [pins.test_box_half_side_is_r_sqrt_lambda_max]),
+    ("overlapped blocks one short under the ellipse reading",
+     "*b1 = std::ceil(hi * 0.0625f) - 1.0f;", "*b1 = std::floor(hi * 0.0625f) - 1.0f;",
+     [pins.test_tight_box_keeps_every_value_and_shortens_lists]),
+    ("native blocks of 8 pixels", "return std::floor(x * 0.0625f);",
+     "return std::floor(x * 0.125f);", [pins.test_render_points_block_membership_bruteforce]),
+    ("output block rect from the last point of the first block only",
+     "const float b = native_block(coord32(std::min(16 * t + 15, n - 1), o, s));",
+     "const float b = a;", [pins.test_box_half_side_is_r_sqrt_lambda_max]),
+    ("membership from the raster's pixel instead of the native point",
+     "const float bx = native_block(x32), by = native_block(y32);",
+     "const float bx = native_block(x32 - 0.5f), by = native_block(y32 - 0.5f);",
+     [pins.test_render_points_block_membership_bruteforce]),
+    ("representable exponent bound off", "return arg >= -125.0f;", "return arg >= -25.0f;",
+     [pins.test_blocklist_render_bruteforce]),
     ("no normalisation of the gates", "((Dsum > 0.0) ? N[c] / Dsum : 0.0);",
      "((Dsum > 0.0) ? N[c] : 0.0);", [pins.test_untruncated_gates_are_softmax]),
     ("z2 chain term sign in the gradient", "const double bz1 = -Hh * t.z1 - bz2 * r[3] / r[4];",
@@ -61,8 +76,8 @@ MUTANTS = [
      [pins.test_tight_box_keeps_every_value_and_shortens_lists,
       pins.test_tight_box_is_the_ellipse_extent]),
     ("tight box axes swapped",
-     "const float X0 = (mux - Rx) * fs - (float)g.ox;\n  const float X1 = (mux + Rx)",
-     "const float X0 = (mux - Ry) * fs - (float)g.ox;\n  const float X1 = (mux + Ry)",
+     "native_axis(mux - Rx, mux + Rx, centres, &rc.bx0, &rc.bx1)",
+     "native_axis(mux - Ry, mux + Ry, centres, &rc.bx0, &rc.bx1)",
      [pins.test_tight_box_keeps_every_value_and_shortens_lists,
       pins.test_tight_box_is_the_ellipse_extent]),
     ("RBF sum still normalised", "y[c] = g.rbf ? N[c] : ((Dsum",
@@ -71,10 +86,11 @@ MUTANTS = [
     ("RBF gradient through the gate", "const double w = g.rbf ? t.e : t.e / D;",
      "const double w = t.e / D;", [pins.test_rbf_gradient_central_differences]),
     ("render drops out-of-ellipse pairs under the block-list reading",
-     "g.trunc == 1 ? r2_render : r2", "r2",
+     "(g.trunc == 1 ? RULE_LISTS : RULE_ELLIPSE)", "RULE_ELLIPSE",
      [pins.test_blocklist_render_bruteforce]),
-    ("gradient keeps out-of-ellipse pairs", "if (!M.participates(j, u, v, x32, y32, r2)) continue;",
-     "if (!M.participates(j, u, v, x32, y32, 4.0f * r2)) continue;",
+    ("gradient keeps out-of-ellipse pairs",
+     "if (!M.participates(j, x32, y32, RULE_ELLIPSE, r2)) continue;",
+     "if (!M.participates(j, x32, y32, RULE_LISTS, r2)) continue;",
      [pins.test_gradient_only_ellipse_per_pair_differences]),
     ("block list not in kernel order",
      "for (int j = 0; j < K; ++j) {\n    const Rect32& rc = M.rect[j];\n    int32_t* tr",

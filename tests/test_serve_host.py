@@ -35,13 +35,14 @@ def test_pair_bound_covers_oracle_pairs():
 
 
 def test_pair_bound_single_kernel_closed_form():
-    # one round kernel, l = 2: R = 6, box 12 px at s = 1 -> n <= 15 px -> <= 2 blocks/axis
+    # one round kernel, l = 2: R = 6, a 12 px box overlaps <= 2 native blocks per axis, whose
+    # 32 s sample points touch <= 2 s + 1 output blocks per axis
     m = np.zeros((1, 15), np.float64)
     m[0, 2] = m[0, 4] = 2.0
     spans = BoxSpans([m], 3.0)
-    assert spans.pair_bound(0, 1, 256, 256) == 4
-    assert spans.pair_bound(0, 1, 16, 256) == 2      # one block across
-    assert spans.pair_bound(0, 4, 256, 256) == 5 * 5  # 48 px box -> n <= 51 -> 5 blocks
+    assert spans.pair_bound(0, 1, 256, 256) == 3 * 3
+    assert spans.pair_bound(0, 1, 16, 256) == 3      # one block across
+    assert spans.pair_bound(0, 4, 256, 256) == 9 * 9
     for ox in range(16):
         P = oracle.bin(np.array([[8.0 + ox / 4, 8.0, 2.0, 0.0, 2.0, 0.0] + [0.5] * 9]), 3, 1,
                        64, 64)["P"]
