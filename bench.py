@@ -35,15 +35,17 @@ METRIC = "SMoE fit iters/s (fwd+bwd) 2048² K=65536; render p50/p99 latency vs p
 WORKLOAD = "fit-2048x2048-rgb-K65536-linear-denoise"
 
 # Algorithmic FP32 work per (pixel, kernel) pair, in VALU operations (one add, mul, fma,
-# compare or exp each), C = 3 linear experts:
+# compare or exp each), C = 3 linear experts, counted on the plain per-pair formulas (not on
+# this implementation, which shares column terms between a lane's pixels):
 #   tested pair (the truncation test):  dx, dy, z1, l21*z1, w, z2, z1^2, z2^2, q, compare = 10
 #   forward, every tested pair: exponent fma, exp, D add, 6 fma expert, 3 fma numerators = 12
-#   backward, pair inside the ellipse: exponent fma, exp, w, 6 expert fma, 3 G fma, 3 g*w,
-#     H, bz2, 2 bz1, 2 chain fma, 6 slope-chain fma, 6 slope products, s1, 2 l21, s2,
-#     15 accumulations = 52
+#   backward, pair inside the ellipse: exponent fma, exp, w = e/D, 6 expert fma, 3 G fma,
+#     H = w G, drho += H, 3 g w products and 3 da adds, 6 dW fma, bz2, 2 bz1, 2 x 4 for
+#     bdx / bdy (1/l, 3 slope fma), 2 dmu, ds1 fma, 2 dl21, ds2 fma = 43, rounded up to the
+#     45 of the hot-path survey
 OPS_TESTED = 10
 OPS_ACTIVE_FWD = 12
-OPS_ACTIVE_BWD = 52
+OPS_ACTIVE_BWD = 45
 # MI355X FP32 vector peak: 157.3 TFLOP/s counting an FMA as 2 flops = 256 CUs x 4 SIMDs x
 # 32 lanes x 2.4 GHz = 78.6e12 lane-operations/s (one FP32 instruction per lane).  The
 # counters agree: the fused kernel issues more than one wave64 VALU instruction per 4 cycles
@@ -157,13 +159,21 @@ def run(args):
     P0 = b0.read_status()[1][0]
     del b0
     # generous pair capacity (HBM is plentiful): an overflowed step would be a no-op
-    st = smoe.FitState(target, raw0, 1, adam, max_steps=args.warmup + args.steps + 16,
-                       capacity=8 * P0 + 65536)
+    # The timed steps need only the loss, the gradient and the update: the render is not
+    # stored (write_render off); the PSNR below comes from a render of the model afterwards.
+    st = smoe.FitState(target, raw0, 1, adam,
+                       max_steps=args.prefit + args.warmup + args.steps + 16,
+                       capacity=8 * P0 + 65536, write_render=False)
     ev = HipEvents()
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
-    # warm-up (advances the fit), then make sure the pair capacity is sufficient
+    # The window is timed late in the fit: the block lists grow from the initial geometry
+    # (P = 260 100) over the first few hundred steps and then stay long, so steps after the
+    # pre-fit are the ones a fit spends most of its time in.  Pre-fit steps replay from
+    # graphs; then warm-up steps, then a check that the pair capacity is sufficient.
+    if args.prefit:
+        st.run_graphed(args.prefit)
     for _ in range(args.warmup):
         st.step()
     st.grow_if_needed()
@@ -249,15 +259,19 @@ def run(args):
     except (OSError, ValueError, KeyError):
         pass
 
-    psnr_clean = smoe.psnr(st.image, clean)
+    img_now, _, _, _ = smoe.render(st.model, C, 1, st.grid)
+    psnr_clean = smoe.psnr(img_now, clean)
+    steps_before = args.prefit + args.warmup + nprof
     out = {
         "metric": METRIC, "value": args.steps / elapsed, "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "image": f"{W}x{H}x{C}", "K": st.K, "experts": "linear",
-                   "tile": 16, "radius": 3.0, "fit_steps_before_timing": args.warmup,
-                   "truncation": "block lists in the render, ellipse in the gradient"},
+                   "tile": 16, "radius": 3.0, "fit_steps_before_timing": steps_before,
+                   "timed_steps": [steps_before, steps_before + args.steps],
+                   "truncation": "block lists in the render, ellipse in the gradient",
+                   "render_stored_per_step": False},
         "roofline": roofline,
         "stages_ms": stage_avg,
         "pairs": {"P_init": P0, "P": P, "mean_list": P / T, "longest_list": status[2], "tested": tested,
@@ -266,6 +280,7 @@ def run(args):
         "psnr_vs_clean_db": psnr_clean,
         "cpu_baseline": None,
     }
+    out["early_window"] = run_early_window(args, w, P0)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
         out["cpu_baseline"] = cb
@@ -283,8 +298,10 @@ def run(args):
         out["long_lists"] = run_long_lists(args)
     if not args.no_readings:
         out["truncation_readings"] = run_truncation_readings(args)
-    if not args.no_table1:
-        out["paper_table1_shape"] = run_table1_shape(args)
+    if not args.no_small:
+        out["small_fits"] = run_small_fits(args)
+    if not args.no_trunc_report:
+        out["truncation_error"] = truncation_report(w)
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -295,6 +312,90 @@ def run(args):
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = CALIB_BYTES
     print(json.dumps(out), flush=True)
+
+
+def run_small_fits(args):
+    """The two smaller fit workloads, each fitted for its full length: 64^2 grey with K = 64
+    constant experts for 100 Adam steps (lr 1e-2; launch-bound), and 512^2 RGB with K = 4096
+    linear experts for 2000 steps (the paper's rates).  Iterations/s over the whole fit (after
+    the first, eager step) and the final PSNR against the target."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    import workloads as wl
+
+    out = {}
+    for n, adam in ((1, smoe.AdamConfig.constant(1e-2, 100)), (2, None)):
+        w = wl.workload(n)
+        steps = w.steps
+        adam = adam or smoe.AdamConfig(total_steps=steps)
+        t = torch.from_numpy(w.target).cuda()
+        st = smoe.FitState(t, torch.from_numpy(w.raw0).cuda(), w.order, adam, max_steps=steps)
+        st.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run_graphed(steps - 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        img, _, _, _ = smoe.render(st.model, t.shape[2], w.order, st.grid)
+        out[w.name] = {"steps": steps, "iters_per_s": (steps - 1) / dt,
+                       "fit_s": dt * steps / (steps - 1), "final_mse": float(st.losses()[-1]),
+                       "psnr_db": smoe.psnr(img, t)}
+    return out
+
+
+def truncation_report(w):
+    """Truncation error of the rasterized model (Sec. IV-B) against the global model of
+    Sec. III-B (every kernel at every pixel), on a 256^2 crop of the headline workload with
+    its K = 1024 kernels at the initial geometry, by the FP64 oracle: the image error of each
+    reading and of the uncut block lists against the untruncated render."""
+    import numpy as np
+
+    import oracle
+
+    t0 = time.perf_counter()
+    gx = 32                                  # 32 x 32 kernels (spacing 8) over 256^2
+    raw = w.raw0.reshape(256, 256, -1)[:gx, :gx].reshape(gx * gx, -1).astype(np.float64)
+    model = oracle.materialize(raw, 3, 1)
+    S = 256
+    y_all, _ = oracle.render(model, 3, 1, S, S, truncated=False)
+    rows = {}
+    for name, kw in (("block_lists_representable", dict(trunc="gradient")),
+                     ("ellipse_in_render", dict(trunc="render")),
+                     ("block_lists_uncut", dict(truncated="lists"))):
+        y, D = oracle.render(model, 3, 1, S, S, **kw)
+        d = y - y_all
+        rows[name] = {"max_abs": float(np.max(np.abs(d))), "rms": float(np.sqrt(np.mean(d * d))),
+                      "psnr_vs_untruncated_db": float(10 * np.log10(1.0 / max(np.mean(d * d), 1e-300))),
+                      "uncovered_px": int((D == 0).sum())}
+    return {"crop": f"{S}x{S}", "K": int(model.shape[0]), "geometry": "initial (sigma 4, spacing 8)",
+            "radius": 3.0, "vs_untruncated": rows, "seconds": time.perf_counter() - t0}
+
+
+def run_early_window(args, w, P0):
+    """The same fit timed early, over steps [20, 220) from the initial geometry (shorter block
+    lists than later in the fit), all steps replayed from graphs: context for the headline."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+
+    target = torch.from_numpy(w.target).cuda()
+    st = smoe.FitState(target, torch.from_numpy(w.raw0).cuda(), 1,
+                       smoe.AdamConfig(total_steps=10000), max_steps=256,
+                       capacity=8 * P0 + 65536, write_render=False)
+    for _ in range(20):
+        st.step()
+    st.grow_if_needed()
+    g = st.capture(50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        st.replay(g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if st.bins.read_status()[0]:
+        raise RuntimeError("pair capacity overflow in the early window")
+    return {"timed_steps": [20, 220], "iters_per_s": 200 / dt, "ms_per_step": 1e3 * dt / 200}
 
 
 # ----------------------------------------------------------------------------- serving
@@ -397,21 +498,34 @@ def run_batched_fit(args):
     if st.bins.read_status()[0]:
         raise RuntimeError("pair capacity overflow in the batched fit")
     psnr_b = [smoe.psnr(im, t) for im, t in zip(st.images(), tg)]
-    # the unbatched path: every image fitted alone for the same steps
+    # the unbatched path: every image fitted alone for the same steps, its steps replayed
+    # from graphs as well (first step eager), timed the same way (graph replays only)
     psnr_u = []
-    t0 = time.perf_counter()
+    t_unb = 0.0
     for t, r in zip(tg, raws):
         s1 = smoe.FitState(t, torch.from_numpy(r).cuda(), 1, adam, max_steps=steps + 1)
-        s1.run(steps)
+        s1.step()
+        g1 = s1.capture(spg) if n_full else None
+        g1_rem = s1.capture(rem) if rem else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_full):
+            s1.replay(g1)
+        if g1_rem is not None:
+            s1.replay(g1_rem)
+        torch.cuda.synchronize()
+        t_unb += time.perf_counter() - t0
+        if s1.bins.read_status()[0]:
+            raise RuntimeError("pair capacity overflow in an unbatched fit")
         psnr_u.append(smoe.psnr(s1.image, t))
-    torch.cuda.synchronize()
-    t_unb = time.perf_counter() - t0
+        del g1, g1_rem, s1
     d = np.abs(np.array(psnr_b) - np.array(psnr_u))
     px = sum(i.shape[0] * i.shape[1] for i in imgs)
     return {"images": len(imgs), "pixels": int(px), "K": int(st.K), "steps": steps,
             "timed_steps": steps - 1, "iters_per_s": (steps - 1) / elapsed,
             "ms_per_step": 1e3 * elapsed / (steps - 1),
-            "unbatched_iters_per_s": steps / t_unb,
+            "unbatched_iters_per_s": (steps - 1) / t_unb,
+            "unbatched_timing": "each image alone, steps 1.. replayed from graphs, summed",
             "psnr_mean_db": float(np.mean(psnr_b)), "psnr_min_db": float(np.min(psnr_b)),
             "psnr_max_abs_diff_vs_unbatched_db": float(d.max())}
 
@@ -541,57 +655,6 @@ def run_rbf_vs_smoe(args):
 
 # The paper's R-SMoE rows of Table I (Kodak 768x512, constant experts, 10 000 Adam
 # iterations, NVIDIA RTX A4000): context only -- another GPU and real photographs.
-PAPER_TABLE1 = {"2000": {"fit_s": 69.0, "iters_per_s": 10000 / 69.0, "decode_ms": 1.8,
-                         "avg_kernels_per_block": 40, "psnr_db_kodak": 27.99},
-                "10000": {"fit_s": 81.0, "iters_per_s": 10000 / 81.0, "decode_ms": 2.2,
-                          "avg_kernels_per_block": 51, "psnr_db_kodak": 33.13}}
-
-
-def run_table1_shape(args):
-    """The shape of the paper's Table I fits: a synthetic 768x512 RGB image (the 512^2
-    edge/texture generator at that size), L = 2000 and 10000 constant-expert kernels at
-    random centres with a fixed 5 px scale (Sec. VI-B), Adam for 10 000 iterations with the
-    paper's rates.  Reports the fit's iterations/s and seconds, PSNR, the mean block-list
-    length after training (the paper's "avg. kernels"), and one decode (bin + render)."""
-    import torch
-
-    import paper_2510_05814_amd as smoe
-    import workloads as wl
-
-    img = wl.config2_image(H=512, W=768, n_edges=60)
-    t = torch.from_numpy(img).cuda()
-    H, W, C = img.shape
-    out = {"image": f"{W}x{H}x{C} synthetic", "experts": "constant", "iterations": 10000,
-           "paper_context_a4000": PAPER_TABLE1, "runs": []}
-    for L in (2000, 10000):
-        raw = torch.from_numpy(wl.random_init(img, L, 5.0, seed=L)).cuda()
-        st = smoe.FitState(t, raw, 0, smoe.AdamConfig(total_steps=10000), max_steps=1,
-                           capacity=4 * W * H)
-        st.step()                      # the first step eagerly, then graphs
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st.run_graphed(9999)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        grid = smoe.make_grid(W, H)
-        b = smoe.bin(st.model, C, 0, grid)
-        _, sb = b.read_status()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        for i in range(25):
-            if i == 5:
-                ev[0].record()
-            smoe.render(st.model, C, 0, grid, bins=smoe.bin(st.model, C, 0, grid, bins=b,
-                                                            grow=False))
-        ev[1].record()
-        torch.cuda.synchronize()
-        out["runs"].append({"L": L, "iters_per_s": 9999 / dt, "fit_s_10k": 10000 * dt / 9999,
-                            "psnr_db": smoe.psnr(st.image, t),
-                            "avg_kernels_per_block": sb[0] / smoe.tiles(W, H),
-                            "decode_ms": ev[0].elapsed_time(ev[1]) / 20})
-        del st, b
-    return out
-
-
 def run_truncation_readings(args):
     """The two readings of where Sec. IV-B's ellipse discard applies, on the headline
     workload fitted for the paper's 10 000 iterations from the same initialisation: the
@@ -866,6 +929,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prefit", type=int, default=950,
+                    help="fit steps (graph replays) before the warm-up and the timed window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle CPU work")
     ap.add_argument("--eager", action="store_true",
@@ -893,16 +958,18 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed fit, its roofline and profile (no CPU baseline and no "
                          "other section); the profiles are taken this way")
-    ap.add_argument("--no-table1", action="store_true",
-                    help="skip the fits shaped like the paper's Table I")
     ap.add_argument("--no-readings", action="store_true",
                     help="skip the comparison of the two truncation readings")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 64^2 and 512^2 fit workloads")
+    ap.add_argument("--no-trunc-report", action="store_true",
+                    help="skip the truncation-error report (oracle, untruncated vs truncated)")
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
     if args.headline_only:
         for k in ("no_cpu_baseline", "no_serving", "no_batched_fit", "no_mm", "no_tight",
-                  "no_rbf", "no_long", "no_readings", "no_table1"):
+                  "no_rbf", "no_long", "no_readings", "no_small", "no_trunc_report"):
             setattr(args, k, True)
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.profile_command)

@@ -209,6 +209,8 @@ typedef struct smoe_bins {
   uint32_t* vals;          /* [capacity] kernel id of each pair, ascending within a block */
   uint32_t* vals_alt;      /* [capacity] scratch for very long block lists */
   float* pair_grads;       /* [capacity][NP] per-(block, kernel) gradient partials */
+  int32_t* pair_slots;     /* [K][16] fit step: the pair slot of each kernel's first 16 blocks
+                              (NULL in a render-only workspace) */
   float* tile_loss;        /* [max_tiles] per-block squared error */
   int32_t* status;         /* [8]: pairs needed P, overflow flag, longest list, spare,
                               then internal counters (kept zero between calls) */
@@ -315,7 +317,7 @@ typedef struct smoe_fit_state {
   float* adam_v;             /* [K][NP] */
   float* model;              /* [K][NP] materialized rows of `raw` */
   float* grads;              /* [K][NP] gradient of the last step (raw order), or NULL */
-  float* image;              /* [H][W][C] render of the last step */
+  float* image;              /* [H][W][C] render of the last step that wrote it */
   float* denom;              /* [H][W] */
   float* loss_history;       /* [max_steps] loss before each update, or NULL */
   int32_t max_steps;
@@ -323,6 +325,10 @@ typedef struct smoe_fit_state {
                                 counts and ranges of `model` (each step leaves them for the
                                 next); set 0 for a fresh fit, a new workspace, or after
                                 changing raw/model outside smoe_fit_step */
+  int32_t write_render;      /* 1: the step writes its render to image and denom; 0: it
+                                leaves them as they are (the loss, the gradient and the
+                                update need neither, so a fit loop skips 16 B per pixel of
+                                stores on all but the steps whose render it wants) */
   int32_t* step;             /* [1] completed steps */
   float* scalars;            /* [4] per-step scratch */
   /* Batched fit (num_segments > 0): num_segments images fitted together, each with its own
@@ -348,11 +354,15 @@ typedef struct smoe_fit_state {
  * step's boxes and records (so the first step, state->prepared == 0, computes those first
  * and then sets state->prepared = 1).  The workspace's pair storage is used as fixed-width
  * buckets: each of the T blocks gets floor(bins.capacity / T) entries, so the capacity must
- * cover T times the longest block list.  A fuller bucket is a capacity overflow: the step
+ * cover T times the longest block list; with W = floor(capacity / T) rounded up to a power
+ * of two 2^b, the total kernel count must stay below 2^(32 - b) (each bucket entry holds the
+ * kernel id and its slot in 32 bits), else the call returns SMOE_ERR_TOO_LARGE.  A fuller
+ * bucket is a capacity overflow: the step
  * changes nothing (the step counter included) and smoe_read_status() reports it, with
  * status[0] = T x the longest list and status[2] = the longest list.  loss_out (device
- * float[1], may be NULL) and loss_history[step] receive the loss before the update.  image,
- * denom and grads hold the last step's render, denominator and gradient. */
+ * float[1], may be NULL) and loss_history[step] receive the loss before the update.  grads
+ * holds the last step's gradient; image and denom its render and denominator when
+ * write_render is set. */
 smoe_status smoe_fit_step(smoe_fit_state* state, const float* target, float* loss_out,
                           void* stream);
 

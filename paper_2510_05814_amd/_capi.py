@@ -62,7 +62,8 @@ class SmoeBins(ct.Structure):
     _fields_ = [("K", _i32), ("C", _i32), ("order", _i32), ("max_tiles", _i32),
                 ("capacity", _i32), ("tile_rects", _vp), ("native_rects", _vp), ("counts", _vp), ("records", _vp),
                 ("record_stride", _i32), ("tile_counts", _vp), ("ranges", _vp), ("keys", _vp),
-                ("vals", _vp), ("vals_alt", _vp), ("pair_grads", _vp), ("tile_loss", _vp),
+                ("vals", _vp), ("vals_alt", _vp), ("pair_grads", _vp), ("pair_slots", _vp),
+                ("tile_loss", _vp),
                 ("status", _vp)]
 
 
@@ -76,7 +77,8 @@ class SmoeFitState(ct.Structure):
     _fields_ = [("K", _i32), ("C", _i32), ("order", _i32), ("grid", SmoeGrid),
                 ("adam", SmoeAdamConfig), ("raw", _vp), ("adam_m", _vp), ("adam_v", _vp),
                 ("model", _vp), ("grads", _vp), ("image", _vp), ("denom", _vp),
-                ("loss_history", _vp), ("max_steps", _i32), ("prepared", _i32), ("step", _vp),
+                ("loss_history", _vp), ("max_steps", _i32), ("prepared", _i32),
+                ("write_render", _i32), ("step", _vp),
                 ("scalars", _vp), ("num_segments", _i32), ("segments", _vp),
                 ("segments_host", _vp), ("bins", SmoeBins)]
 

@@ -329,11 +329,13 @@ class FitState:
     list of images with a list of raw0 arrays (one per image): the images are fitted together
     in lock-step, each by its own kernels, with one launch per stage for all of them.
     radius, box, mode, trunc: the rule's settings, as in make_grid (mode "rbf" fits the
-    weighted sum of kernels of Eq. 1)."""
+    weighted sum of kernels of Eq. 1).  write_render: whether each step stores its render in
+    `image` / `denom` (set_write_render changes it; a graph captures the value it had)."""
 
     def __init__(self, target, raw0, order: int, adam: AdamConfig, max_steps: int = 0,
                  capacity: int | None = None, radius: float = 3.0, box="square",
-                 mode="smoe", trunc="gradient"):
+                 mode="smoe", trunc="gradient", write_render: bool = True):
+        self.write_render = bool(write_render)
         batched = isinstance(target, (list, tuple))
         targets = list(target) if batched else [target]
         raws = list(raw0) if batched else [raw0]
@@ -397,9 +399,15 @@ class FitState:
             self.K, self.C, self.order, self.grid, self.adam.c(), self.raw.data_ptr(),
             self.m.data_ptr(), self.v.data_ptr(), self.model.data_ptr(), self.grads.data_ptr(),
             self.image.data_ptr(), self.denom.data_ptr(), self.loss_history.data_ptr(),
-            self.max_steps, 0, self.step_counter.data_ptr(), self.scalars.data_ptr(),
+            self.max_steps, 0, 1 if self.write_render else 0, self.step_counter.data_ptr(),
+            self.scalars.data_ptr(),
             0 if seg is None else seg.n, None if seg is None else seg.dev.data_ptr(),
             None if seg is None else ct.addressof(seg.host), self.bins.c)
+
+    def set_write_render(self, on: bool):
+        """Whether the following steps store their render in image / denom."""
+        self.write_render = bool(on)
+        self.c.write_render = 1 if on else 0
 
     def segment_losses(self, stream=None) -> torch.Tensor:
         """Each image's MSE at the last step (a single-image fit gives one value)."""

@@ -64,11 +64,12 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
     }
   }
   if (px.straddle)
-    backward_accumulate<C, ORDER, true>(px, a.S.r2, a.records, a.vals, a.native_rects,
+    backward_accumulate<C, ORDER, true>(px, a.S.r2, a.records, a.vals, 0, false, a.native_rects,
                                         a.ranges[tile], srec, smask, false, 0ull, sd, a.pair_grads);
   else
-    backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, nullptr, a.ranges[tile],
-                                         srec, nullptr, false, 0ull, sd, a.pair_grads);
+    backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, 0, false, nullptr,
+                                         a.ranges[tile], srec, nullptr, false, 0ull, sd,
+                                         a.pair_grads);
 }
 
 struct GatherArgs {

@@ -82,14 +82,18 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
   }
 }
 
-// The fit step's scatter into fixed-width buckets: the kernel id goes to entry t W + c of
-// the pair storage, c the block's cursor; a bucket that fills up sets the step's overflow
-// flag (status word kStepFlags + parity of the step counter) and drops the entry -- the
-// step then changes nothing.  The cursors start at zero (the fused render resets them).
-// Thread 0 copies the step counter into the status words for the step's later kernels.
+// The fit step's scatter into fixed-width buckets: entry t W + c of the pair storage, c the
+// block's cursor, receives (kernel id << shift) | c, and for the kernel's first kSlots blocks
+// (row-major) slots[j][q] = t W + c -- the slot where the block's partial row of the kernel
+// will be written and read back, so that no later pass has to search the sorted lists.  A
+// bucket that fills up sets the step's overflow flag (status word kStepFlags + parity of the
+// step counter) and drops the entry -- the step then changes nothing.  The cursors start at
+// zero (the fused render resets them).  Thread 0 copies the step counter into the status
+// words for the step's later kernels.
 __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __restrict__ tile_rects,
                                                        int32_t* __restrict__ cursors,
                                                        uint32_t* __restrict__ vals, int width,
+                                                       int shift, int32_t* __restrict__ slots,
                                                        int32_t* __restrict__ status,
                                                        const int32_t* __restrict__ step) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -105,8 +109,12 @@ __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __res
   for (int q = q0; q < n; q += kScatterLanes) {
     const int t = sg.tile_offset + (rc.y + q / w) * sg.ntx + rc.x + q % w;
     const int pos = atomicAdd(&cursors[t], 1);
-    if (pos < width) vals[(size_t)t * width + pos] = (uint32_t)j;
-    else status[kStepFlags + (t0 & 1)] = 1;
+    if (pos < width) {
+      vals[(size_t)t * width + pos] = ((uint32_t)j << shift) | (uint32_t)pos;
+      if (q < kSlots) slots[(size_t)j * kSlots + q] = t * width + pos;
+    } else {
+      status[kStepFlags + (t0 & 1)] = 1;
+    }
   }
 }
 
@@ -177,11 +185,11 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width,
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
                                 const int32_t* step, hipStream_t s) {
   k_scatter_fixed<<<max(1, cdiv((long long)S.K * kScatterLanes, 256)), 256, 0, s>>>(
-      S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, b.status,
-      step);
+      S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, shift,
+      b.pair_slots, b.status, step);
   return hipGetLastError();
 }
 

@@ -141,7 +141,8 @@ bool bins_match(const smoe_bins* b, int K, int C, int order) {
 }
 
 struct Layout {
-  size_t tile_rects, native_rects, counts, records, tile_counts, ranges, keys, vals, vals_alt, pair_grads,
+  size_t tile_rects, native_rects, counts, records, tile_counts, ranges, keys, vals, vals_alt,
+      pair_grads, pair_slots,
       tile_loss, status, total;
 };
 
@@ -162,6 +163,7 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   L.vals = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals_alt = o;   o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.pair_grads = o; o = align_up(o + (grads ? (size_t)capacity * np * sizeof(float) : 0));
+  L.pair_slots = o; o = align_up(o + (grads ? (size_t)K * kSlots * sizeof(int32_t) : 0));
   L.tile_loss = o;  o = align_up(o + (size_t)max_tiles * sizeof(float));
   L.status = o;     o = align_up(o + 8 * sizeof(int32_t));
   L.total = o;
@@ -223,23 +225,29 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
       !bins_match(&st->bins, S.K, st->C, st->order))
     return SMOE_ERR_INVALID;
   if (!st->raw || !st->adam_m || !st->adam_v || !st->image || !st->denom || !st->step ||
-      !st->scalars || !st->bins.pair_grads || !st->bins.tile_loss || st->max_steps < 0)
+      !st->scalars || !st->bins.pair_grads || !st->bins.pair_slots || !st->bins.tile_loss ||
+      st->max_steps < 0)
     return SMOE_ERR_INVALID;
   if (S.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto mark = [&](int i) -> hipError_t {
     return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
   };
-  // The pair storage as fixed-width block buckets: block t owns entries [t W, t W + W).
+  // The pair storage as fixed-width block buckets: block t owns entries [t W, t W + W).  An
+  // entry is (kernel id << shift) | its slot in the bucket, W <= 2^shift, so the kernel ids
+  // must fit in 32 - shift bits.
   const int width = st->bins.capacity / S.T;
+  int shift = 0;
+  while ((1LL << shift) < (long long)width) ++shift;
+  if (((long long)S.K << shift) > (1LL << 32)) return SMOE_ERR_TOO_LARGE;
   hipError_t e = mark(0);
   if (e == hipSuccess && !st->prepared)
     e = launch_prepare_fit(st->C, st->order, st->model, S, st->bins, s);
-  if (e == hipSuccess) e = launch_scatter_fixed(S, st->bins, width, st->step, s);
+  if (e == hipSuccess) e = launch_scatter_fixed(S, st->bins, width, shift, st->step, s);
   if (e == hipSuccess) e = mark(1);
-  if (e == hipSuccess) e = launch_fit_tile(*st, S, width, target, s);
+  if (e == hipSuccess) e = launch_fit_tile(*st, S, width, shift, target, s);
   if (e == hipSuccess) e = mark(2);
-  if (e == hipSuccess) e = launch_adam_fit(*st, S, loss_out, s);
+  if (e == hipSuccess) e = launch_adam_fit(*st, S, shift, loss_out, s);
   if (e == hipSuccess) e = mark(3);
   if (e == hipSuccess) st->prepared = 1;
   return hip_status(e);
@@ -329,6 +337,7 @@ smoe_status layout_into(smoe_bins* out, void* workspace, size_t bytes, int32_t K
   b.vals = reinterpret_cast<uint32_t*>(base + L.vals);
   b.vals_alt = reinterpret_cast<uint32_t*>(base + L.vals_alt);
   b.pair_grads = grads ? reinterpret_cast<float*>(base + L.pair_grads) : nullptr;
+  b.pair_slots = grads ? reinterpret_cast<int32_t*>(base + L.pair_slots) : nullptr;
   b.tile_loss = reinterpret_cast<float*>(base + L.tile_loss);
   b.status = reinterpret_cast<int32_t*>(base + L.status);
   *out = b;

@@ -23,6 +23,7 @@ namespace {
 
 struct FitTileArgs {
   Segs S;
+  int shift;  // bucket entries: kernel id << shift | slot
   const float* __restrict__ records;
   int2* __restrict__ ranges;
   uint32_t* __restrict__ vals;
@@ -31,7 +32,7 @@ struct FitTileArgs {
   int32_t* __restrict__ status;
   int width;
   const float* __restrict__ target;
-  float* __restrict__ image;
+  float* __restrict__ image;  // null: the step's render is not stored
   float* __restrict__ denom;
   float* __restrict__ tile_loss;
   float* __restrict__ pair_grads;
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   uint64_t live = 0;
   // a fit raster has scale 1 and origin 0: its blocks are native blocks (no straddling)
   forward_accumulate<C, ORDER, TRUNC, false>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                             a.records, a.vals, nullptr, rg, srec, nullptr, D, N,
-                                             live);
+                                             a.records, a.vals, a.shift, nullptr, rg, srec,
+                                             nullptr, D, N, live);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
       for (int c = 0; c < C; ++c) {
         // Eq. (2)-(4): y = N / D; Eq. (1): y = N
         const float yc = RBF ? N[i][c] : (cov ? div_refined(N[i][c], D[i], invD) : 0.0f);
-        a.image[p * C + c] = yc;
+        if (a.image) a.image[p * C + c] = yc;
         const float d = yc - a.target[p * C + c];
         err = __builtin_fmaf(d, d, err);
         if (cov) {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
           if (!RBF) sd.gy[i] = __builtin_fmaf(sd.g[i][c], yc, sd.gy[i]);
         }
       }
-      a.denom[p] = D[i];
+      if (a.image) a.denom[p] = D[i];
       sd.valid[i] = cov;
       sd.invD[i] = invD;
     }
@@ -112,12 +113,15 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, nullptr, rg, srec, nullptr,
-                                       true, live, sd, a.pair_grads);
+  // each partial row goes to the slot its entry got in the scatter, where Adam reads it
+  backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, a.shift, true, nullptr, rg,
+                                       srec, nullptr, true, live, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {
   Segs S;
+  int shift;  // bucket entries: kernel id << shift | slot
+  const int32_t* __restrict__ slots;  // [K][kSlots] bucket slots of each kernel's blocks
   const int4* __restrict__ tile_rects_in;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const float m0 = upd ? f.m[e] : 0.0f, v0 = upd ? f.v[e] : 0.0f, raw0 = upd ? f.raw[e] : 0.0f;
   // every lane takes part in the gather's row reduction
   const float gi = gather_param<NP>(j, live && !skip, sg, f.tile_rects_in, f.ranges, f.vals,
-                                    f.pair_grads);
+                                    f.pair_grads, f.slots, f.shift);
   if (upd) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;
@@ -286,12 +290,13 @@ __global__ __launch_bounds__(128) void k_materialize(int n_rows, int NP,
 
 }  // namespace
 
-hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width, int shift,
                            const float* target, hipStream_t s) {
   const smoe_bins& b = st.bins;
-  FitTileArgs a{S,        b.records, reinterpret_cast<int2*>(b.ranges),
+  FitTileArgs a{S,        shift,     b.records, reinterpret_cast<int2*>(b.ranges),
                 b.vals,   b.vals_alt, b.tile_counts, b.status, width,
-                target,   st.image,  st.denom,
+                target,   st.write_render ? st.image : nullptr,
+                st.write_render ? st.denom : nullptr,
                 b.tile_loss, b.pair_grads};
   with_shape(st.C, st.order, S, [&](auto sh) {
     using T = decltype(sh);
@@ -300,10 +305,12 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
   return hipGetLastError();
 }
 
-hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_out,
+hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, float* loss_out,
                            hipStream_t s) {
   const smoe_bins& b = st.bins;
   AdamFitArgs f{S,
+                shift,
+                b.pair_slots,
                 reinterpret_cast<const int4*>(b.tile_rects),
                 reinterpret_cast<const int2*>(b.ranges),
                 b.vals,

@@ -84,12 +84,12 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   uint64_t live;
   if (px.straddle)
     forward_accumulate<C, ORDER, TRUNC, true>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                              a.records, a.vals, a.native_rects, rg, srec, smask,
-                                              D, N, live);
+                                              a.records, a.vals, 0, a.native_rects, rg, srec,
+                                              smask, D, N, live);
   else
     forward_accumulate<C, ORDER, TRUNC, false>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                               a.records, a.vals, nullptr, rg, srec, nullptr, D,
-                                               N, live);
+                                               a.records, a.vals, 0, nullptr, rg, srec, nullptr,
+                                               D, N, live);
   render_epilogue<C, RBF>(a, sg, px, tile, D, N);
 }
 

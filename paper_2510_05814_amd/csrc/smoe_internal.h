@@ -124,17 +124,23 @@ __device__ __forceinline__ int xcd_block(int b, int T) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Position of kernel j in a block's ascending kernel list vals[lo, hi); -1 if absent.
+// Position of kernel j in a block's ascending kernel list vals[lo, hi); -1 if absent.  An
+// entry holds the kernel id shifted left by `shift` (the fit step's buckets keep the entry's
+// slot in the low bits).
 __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, int lo, int hi,
-                                            uint32_t j) {
+                                            uint32_t j, int shift = 0) {
   int a = lo, b = hi;
   while (a < b) {
     const int mid = (a + b) >> 1;
-    if (vals[mid] < j) a = mid + 1;
+    if ((vals[mid] >> shift) < j) a = mid + 1;
     else b = mid;
   }
-  return (a < hi && vals[a] == j) ? a : -1;
+  return (a < hi && (vals[a] >> shift) == j) ? a : -1;
 }
+
+// The fit step records, for each kernel's first kSlots blocks (row-major in its block
+// rectangle), the bucket slot its entry was appended at.
+constexpr int kSlots = 16;
 
 // Launchers.  `params` rows are addressed through each segment's param_offset; every
 // per-kernel workspace array through kernel_offset; images through pixel_offset.
@@ -168,12 +174,13 @@ hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s);
 // step), and the scatter into fixed-width buckets (every step).
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
                               const smoe_bins& b, hipStream_t s);
-hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width,
+// The fit step's bucket entries: kernel id << shift | slot within the bucket (width <=
+// 2^shift).
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
                                 const int32_t* step, hipStream_t s);
-hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width,
-                           const float* target,
-                           hipStream_t s);
-hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, float* loss_out,
+hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width, int shift,
+                           const float* target, hipStream_t s);
+hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, float* loss_out,
                            hipStream_t s);
 hipError_t launch_segment_losses(const Segs& S, const smoe_bins& b, float* out, hipStream_t s);
 

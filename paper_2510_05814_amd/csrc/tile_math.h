@@ -95,23 +95,24 @@ __device__ __forceinline__ uint32_t outside_mask(int4 nr, int bxb, int byb) {
 }
 
 // Stages the records of list entries [base, base + n) (n <= kChunk) into LDS, and for a
-// straddling block (smask not null) each entry's outside_mask.
+// straddling block (smask not null) each entry's outside_mask.  An entry holds the kernel id
+// shifted left by `shift` (the fit step's packed bucket entries; 0 elsewhere).
 template <int RS>
 __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
                                               const float* __restrict__ records,
                                               const uint32_t* __restrict__ vals, int base, int n,
-                                              uint32_t* __restrict__ smask = nullptr,
+                                              int shift, uint32_t* __restrict__ smask = nullptr,
                                               const int4* __restrict__ native_rects = nullptr,
                                               int bxb = 0, int byb = 0) {
   constexpr int Q = RS / 4;
   __syncthreads();
   for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
     const int k = i / Q, c = i - k * Q;
-    srec[i] = reinterpret_cast<const float4*>(records + (size_t)vals[base + k] * RS)[c];
+    srec[i] = reinterpret_cast<const float4*>(records + (size_t)(vals[base + k] >> shift) * RS)[c];
   }
   if (smask)
     for (int k = threadIdx.x & 63; k < n; k += kWave)
-      smask[k] = outside_mask(native_rects[vals[base + k]], bxb, byb);
+      smask[k] = outside_mask(native_rects[vals[base + k] >> shift], bxb, byb);
   __syncthreads();
 }
 
@@ -209,12 +210,13 @@ __device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C
 // live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
 // STRADDLE: the block straddles native blocks (smask: kChunk words of LDS; native_rects: the
-// kernels' native rectangles); otherwise both may be null.
+// kernels' native rectangles); otherwise both may be null.  shift: list entries hold the
+// kernel id << shift.
 template <int C, int ORDER, int TRUNC, bool STRADDLE>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
                                                    float cut_scale, float cut_offset,
                                                    const float* __restrict__ records,
-                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ vals, int shift,
                                                    const int4* __restrict__ native_rects, int2 rg,
                                                    float4* srec, uint32_t* smask,
                                                    float (&D)[kRows], float (&N)[kRows][C],
@@ -227,8 +229,8 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
   const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    stage_records<RS>(srec, records, vals, base, n, STRADDLE ? smask : nullptr, native_rects,
-                      px.bxb, px.byb);
+    stage_records<RS>(srec, records, vals, base, n, shift, STRADDLE ? smask : nullptr,
+                      native_rects, px.bxb, px.byb);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
@@ -318,17 +320,22 @@ __device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
 }
 
 // Gradient of kernel row j: the sum of its per-block partial rows over its block rectangle.
-// A group of 16 lanes (one 16-lane row of the wave) serves one kernel: lane b finds the
-// kernel's position in the lists of blocks b, b + 16, ... of the rectangle (row-major) by a
-// binary search and adds those partial rows; the row reduction then leaves parameter i's
-// gradient in lane i.  The summation order is fixed, so the result is reproducible.  All 16
-// lanes must call it (live = false: the kernel contributes nothing).
+// A group of 16 lanes (one 16-lane row of the wave) serves one kernel: lane b adds the partial
+// rows of blocks b, b + 16, ... of the rectangle (row-major); the row reduction then leaves
+// parameter i's gradient in lane i.  The summation order is fixed, so the result is
+// reproducible.  A partial row is found through `slots` (the fit step: the bucket slot each
+// of the kernel's first kSlots blocks got in the scatter, the row's index) or else by a binary
+// search for j in the block's sorted list (its position, or -- packed fit-step entries,
+// shift > 0 -- the slot held in the entry's low bits).  All 16 lanes must call it (live =
+// false: the kernel contributes nothing).
 template <int NP>
 __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& sg,
                                               const int4* __restrict__ rects,
                                               const int2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals,
-                                              const float* __restrict__ pair_grads) {
+                                              const float* __restrict__ pair_grads,
+                                              const int32_t* __restrict__ slots = nullptr,
+                                              int shift = 0) {
   static_assert(NP <= 16, "16 lanes per kernel");
   float v[16];
 #pragma unroll
@@ -338,11 +345,17 @@ __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& s
     const int n = rect_count(rc);
     const int w = rc.z - rc.x + 1;
     for (int b = threadIdx.x & 15; b < n; b += 16) {
-      const int dy = b / w;
-      const int2 rg = ranges[sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w)];
-      if (rg.y <= rg.x) continue;
-      const int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j);
-      if (p < 0) continue;
+      int p;
+      if (slots && b < kSlots) {
+        p = slots[(size_t)j * kSlots + b];
+      } else {
+        const int dy = b / w;
+        const int2 rg = ranges[sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w)];
+        if (rg.y <= rg.x) continue;
+        p = find_in_list(vals, rg.x, rg.y, (uint32_t)j, shift);
+        if (p < 0) continue;
+        if (shift) p = rg.x + (int)(vals[p] & ((1u << shift) - 1u));
+      }
       const float* row = pair_grads + (size_t)p * NP;
 #pragma unroll
       for (int q = 0; q < NP; ++q) v[q] += row[q];
@@ -377,10 +390,14 @@ struct PixelSeed {
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 // The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
 // 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel.
+// packed (the fit step): list entries hold kernel id << shift | slot, and the partial row of
+// an entry goes to its slot, rg.x + slot, where the scatter recorded it; otherwise to the
+// entry's list position.
 template <int C, int ORDER, bool STRADDLE>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
-                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ vals, int shift,
+                                                    bool packed,
                                                     const int4* __restrict__ native_rects, int2 rg,
                                                     float4* srec, uint32_t* smask, bool staged,
                                                     uint64_t live, const PixelSeed<C>& sd,
@@ -395,13 +412,19 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
     const int n = min(kChunk, rg.y - base);
     const bool reuse = staged && rg.y - rg.x <= kChunk;
     if (!reuse)
-      stage_records<RS>(srec, records, vals, base, n, STRADDLE ? smask : nullptr, native_rects,
-                        px.bxb, px.byb);
+      stage_records<RS>(srec, records, vals, base, n, shift, STRADDLE ? smask : nullptr,
+                        native_rects, px.bxb, px.byb);
+    const uint32_t slot_mask = (1u << shift) - 1u;
+    // the row of entry k: its slot (packed) or its list position
+    auto out_row = [&](int k) -> size_t {
+      return packed ? (size_t)rg.x + (__builtin_amdgcn_readfirstlane(vals[base + k]) & slot_mask)
+                    : (size_t)(base + k);
+    };
     for (int k = 0; k < n; ++k) {
       if (reuse && !((live >> k) & 1ull)) {
         // no pixel of the block passed the forward's test: the partial row is zero
         const int idx = lane >> 2;
-        if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = 0.0f;
+        if ((lane & 3) == 0 && idx < NP) pair_grads[out_row(k) * NP + idx] = 0.0f;
         continue;
       }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
@@ -474,7 +497,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
       for (int i = 6 + C * (1 + 2 * ORDER); i < 16; ++i) acc[i] = 0.0f;
       const float tot = wave_reduce16_transposed(acc);
       const int idx = lane >> 2;
-      if ((lane & 3) == 0 && idx < NP) pair_grads[(size_t)(base + k) * NP + idx] = tot;
+      if ((lane & 3) == 0 && idx < NP) pair_grads[out_row(k) * NP + idx] = tot;
     }
   }
 }

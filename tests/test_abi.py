@@ -70,7 +70,7 @@ def test_workspace_layout_host_only():
     b = C.SmoeBins()
     C.smoe_bins_layout(b, base, n, 100, 3, 1, 64, 1000)
     ptrs = [b.tile_rects, b.native_rects, b.counts, b.records, b.tile_counts, b.ranges, b.keys, b.vals,
-            b.vals_alt, b.pair_grads, b.tile_loss, b.status]
+            b.vals_alt, b.pair_grads, b.pair_slots, b.tile_loss, b.status]
     assert all(p % 256 == 0 for p in ptrs)
     assert ptrs == sorted(ptrs) and ptrs[-1] + 16 <= base + n
     assert b.record_stride == 16 and b.capacity == 1000 and b.max_tiles == 64

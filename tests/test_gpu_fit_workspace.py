@@ -29,3 +29,31 @@ def test_fresh_fit_on_dirty_workspace():
     assert torch.equal(a.losses(), b.losses())
     over, _ = b.bins.read_status()
     assert not over
+
+
+def test_steps_without_render_output_are_bitwise_the_same():
+    """write_render = 0 skips only the stores of image and denom: losses, gradients and
+    parameters are bitwise those of steps that store them, and image / denom are untouched."""
+    import paper_2510_05814_amd as smoe
+
+    w = wl.workload(2)
+    target = torch.from_numpy(w.target).cuda()
+    raw0 = torch.from_numpy(w.raw0).cuda()
+    adam = smoe.AdamConfig(total_steps=100)
+    print("[case] fit 512^2 with and without render output", flush=True)
+    a = smoe.FitState(target, raw0, w.order, adam, max_steps=8)
+    b = smoe.FitState(target, raw0, w.order, adam, max_steps=8, write_render=False)
+    b.image.fill_(-1.0)
+    b.denom.fill_(-1.0)
+    for _ in range(6):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.raw, b.raw) and torch.equal(a.grads, b.grads)
+    assert torch.equal(a.losses(), b.losses())
+    assert bool((b.image == -1.0).all()) and bool((b.denom == -1.0).all())
+    b.set_write_render(True)
+    a.step()
+    b.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.image, b.image) and torch.equal(a.denom, b.denom)
