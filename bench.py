@@ -437,10 +437,20 @@ def run_serving(args):
            "budget_bytes": 8 << 30, "mean_output_px": float(np.mean([r["width"] * r["height"]
                                                                     for r in reqs])),
            "setup_s": setup_s, "fit_steps_per_model": args.serve_fit_steps}
-    srv = Server(bank, budget_bytes=8 << 30, streams=2)
+    srv = Server(bank, budget_bytes=8 << 30, streams=2, overlap_backlog=args.serve_overlap_backlog,
+                 fill_blocks=args.serve_fill_blocks, reserve_for=(4096, 4096, (1, 2, 3, 4)))
     plain = PlainServer(bank)
-    srv.serve(warm, realtime=False)
-    plain.serve(warm, realtime=False)
+    # warm-up, the same for both servers: the largest window of every model at every scale
+    # (so that the allocator's cache holds blocks of every output and workspace size), then a
+    # random mix
+    largest = [dict(model=i, scale=sc, width=min(4096, sides[i] * sc),
+                    height=min(4096, sides[i] * sc), arrival=0.0)
+               for i in range(len(sides)) for sc in (1, 2, 3, 4)]
+    for wq in (largest, warm):
+        srv.serve(wq, realtime=False)
+        plain.serve(wq, realtime=False)
+        srv.serve(wq, realtime=True)
+        plain.serve(wq, realtime=True)
     _, out["batched"] = srv.serve(reqs)
     _, out["plain"] = plain.serve(reqs)
     if args.serve_one_stream:
@@ -942,6 +952,11 @@ def main():
     ap.add_argument("--serve-saturation", type=int, default=300)
     ap.add_argument("--serve-fit-steps", type=int, default=50)
     ap.add_argument("--serve-sweep-requests", type=int, default=600)
+    ap.add_argument("--serve-fill-blocks", type=int, default=4096,
+                    help="a batch starts beside those in flight only while they hold fewer "
+                         "blocks than this")
+    ap.add_argument("--serve-overlap-backlog", type=int, default=2,
+                    help="queued requests needed to start a batch beside one in flight")
     ap.add_argument("--serve-one-stream", action="store_true",
                     help="also serve the Poisson stream with a one-stream batched server")
     ap.add_argument("--no-batched-fit", action="store_true")

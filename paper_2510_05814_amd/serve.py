@@ -217,6 +217,72 @@ class _Clock:
         return self.ref.elapsed_time(ev) * 1e-3
 
 
+class _Hip:
+    """The HIP runtime calls the batched loop makes for every batch -- event record, query,
+    elapsed time and the status-word copy -- made directly through the runtime torch already
+    loaded (each a plain C call, a few microseconds less than torch's wrappers)."""
+
+    _lib = None
+
+    def __init__(self):
+        if _Hip._lib is None:
+            L = ct.CDLL("libamdhip64.so.7")
+            vp = ct.c_void_p
+            L.hipEventCreate.argtypes = [ct.POINTER(vp)]
+            L.hipEventRecord.argtypes = [vp, vp]
+            L.hipEventQuery.argtypes = [vp]
+            L.hipEventSynchronize.argtypes = [vp]
+            L.hipEventElapsedTime.argtypes = [ct.POINTER(ct.c_float), vp, vp]
+            L.hipMemcpyAsync.argtypes = [vp, vp, ct.c_size_t, ct.c_int, vp]
+            _Hip._lib = L
+        self.L = _Hip._lib
+
+    def event(self) -> int:
+        e = ct.c_void_p()
+        if self.L.hipEventCreate(ct.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return e.value
+
+    def record(self, ev: int, stream: int):
+        if self.L.hipEventRecord(ev, stream) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def done(self, ev: int) -> bool:
+        return self.L.hipEventQuery(ev) == 0  # hipSuccess; hipErrorNotReady while pending
+
+    def sync(self, ev: int):
+        if self.L.hipEventSynchronize(ev) != 0:
+            raise RuntimeError("hipEventSynchronize failed")
+
+    def elapsed_s(self, a: int, b: int) -> float:
+        f = ct.c_float()
+        if self.L.hipEventElapsedTime(ct.byref(f), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return f.value * 1e-3
+
+    def copy_d2h(self, dst: int, src: int, n: int, stream: int):
+        if self.L.hipMemcpyAsync(dst, src, n, 2, stream) != 0:  # hipMemcpyDeviceToHost
+            raise RuntimeError("hipMemcpyAsync failed")
+
+
+class _HipClock:
+    """_Clock with a raw HIP reference event (for the batched loop's raw events)."""
+
+    def __init__(self, hip: _Hip, stream):
+        torch.cuda.synchronize()
+        self.hip = hip
+        self.ref = hip.event()
+        hip.record(self.ref, stream.cuda_stream)
+        self.t0 = time.perf_counter()
+        hip.sync(self.ref)
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def at(self, ev: int) -> float:
+        return self.hip.elapsed_s(self.ref, ev)
+
+
 @contextlib.contextmanager
 def _no_gc():
     """The collector paused for a serving run (its pauses would land on request latencies)."""
@@ -254,19 +320,37 @@ class _Batch:
 
 
 class _Slot:
-    """Per-stream resources reused by every batch the stream runs: a pinned staging area and
-    a device copy of the segment table."""
+    """Per-stream resources reused by every batch the stream runs (a stream runs one batch at
+    a time): a pinned staging area and a device copy of the segment table, the batch's
+    timing events, and one binning workspace buffer that grows to the largest batch the
+    stream has run and is laid out afresh (a host-only call) for each batch."""
 
-    def __init__(self, max_batch: int, device):
+    def __init__(self, max_batch: int, device, hip: _Hip):
         self.stream = torch.cuda.Stream()
+        self.device = device
         nbytes = max_batch * ct.sizeof(C.SmoeSegment)
         self.table_host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         self.table_dev = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.start, self.done, self.status_ready = hip.event(), hip.event(), hip.event()
+        self.ws = torch.empty(0, dtype=torch.uint8, device=device)
+        self.bins = C.SmoeBins()
         self.batch = None
 
+    def layout(self, K: int, C_: int, order: int, T: int, P: int) -> C.SmoeBins:
+        n = C.smoe_render_workspace_bytes(K, C_, order, T, P)
+        if n > self.ws.numel():
+            # the old buffer may still be read by this stream's last batch: the caching
+            # allocator keeps it until the stream has passed this point
+            self.ws.record_stream(self.stream)
+            self.ws = torch.empty(max(n, 2 * self.ws.numel()), dtype=torch.uint8,
+                                  device=self.device)
+        C.smoe_render_workspace_layout(self.bins, self.ws.data_ptr(), self.ws.numel(), K, C_,
+                                       order, T, P)
+        return self.bins
 
-def _check(bt):
-    bt.status_ready.synchronize()
+
+def _check(hip, bt):
+    hip.sync(bt.status_ready)
     if int(bt.status[1]) != 0:
         raise RuntimeError("pair bound exceeded: a batch overflowed its workspace")
 
@@ -276,14 +360,17 @@ class Server:
 
     def __init__(self, bank: ModelBank, budget_bytes: int = 8 << 30, streams: int = 2,
                  max_batch: int = 32, max_batch_pixels: int = 1 << 26,
-                 fill_blocks: int = 4096, overlap_backlog: int = 2):
+                 fill_blocks: int = 4096, overlap_backlog: int = 2, reserve_for=None):
         """fill_blocks: a further batch is started beside those in flight only while they
         hold fewer 16x16 blocks than this -- about half of what the GPU renders at once
         (256 CUs x 4 SIMDs x 7-8 one-wave blocks).  A batch that fills the GPU runs alone;
         requests that arrive meanwhile queue and leave together in the next batch.
         overlap_backlog: a batch is started beside one in flight only when at least this many
         requests wait; a lone request waits for the batch in flight instead (measured: at
-        light load, overlapping a lone request lengthens the tail of the larger renders)."""
+        light load, overlapping a lone request lengthens the tail of the larger renders).
+        reserve_for: optional (width, height, scales) of the largest requests to expect: every
+        stream's workspace is then sized up front for the largest of them on any resident
+        model, so that no request pays for growing it."""
         if streams < 1 or max_batch < 1:
             raise ValueError("at least one stream and one request per batch")
         self.fill_blocks = int(fill_blocks)
@@ -293,11 +380,20 @@ class Server:
         self.max_batch = int(max_batch)
         self.max_batch_pixels = int(max_batch_pixels)
         self.nbytes_px = 4 * bank.C
-        self.slots = [_Slot(self.max_batch, bank.params.device) for _ in range(streams)]
+        self.hip = _Hip()
+        self.slots = [_Slot(self.max_batch, bank.params.device, self.hip) for _ in range(streams)]
         # pinned status words of recent batches (a ring: a row is read before it is reused)
         self._status = torch.zeros((256, 4), dtype=torch.int32, pin_memory=True)
         self.streams = [sl.stream for sl in self.slots]
         self._models = [model_struct(bank.rows(i), bank.C, bank.order) for i in range(len(bank))]
+        if reserve_for is not None:
+            w, h, scales = reserve_for
+            t = _tiles(w, h)
+            shapes = [(bank.K[i], t, bank.pair_bound(i, s, w, h)) for i in range(len(bank))
+                      for s in scales]
+            for sl in self.slots:
+                for k, tt, p in shapes:
+                    sl.layout(k, bank.C, bank.order, tt, p)
 
     def _info(self, r):
         """(kernels, blocks, pair bound, pixels, bytes alone) of one request, computed once."""
@@ -320,16 +416,16 @@ class Server:
         ws = C.smoe_render_workspace_bytes(K, self.bank.C, self.bank.order, T, P)
         return ws + px * self.nbytes_px + 64 * len(reqs), K, T, P
 
-    def _launch(self, batch: _Batch, keep_outputs: bool):
+    def _launch(self, batch: _Batch, keep_outputs: bool, K: int, T: int, P: int):
         b = self.bank
         sl = self.slots[batch.slot]
         st = sl.stream
-        _, K, T, P = self.footprint(batch.reqs)
         dev = b.params.device
+        hip = self.hip
         with torch.cuda.stream(st):
-            batch.start = torch.cuda.Event(enable_timing=True)
-            batch.start.record(st)
-            bins = Bins(K, b.C, b.order, T, P, device=dev, render_only=True, zero=False)
+            batch.start = sl.start
+            hip.record(batch.start, st.cuda_stream)
+            bins = sl.layout(K, b.C, b.order, T, P)
             if len(batch.reqs) == 1:
                 # one request: the single-raster calls, no segment table
                 r = batch.reqs[0]
@@ -337,8 +433,8 @@ class Server:
                                  r.sharpen, b.box, mode=b.mode, trunc=b.trunc)
                 images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
                 m = self._models[r.model]
-                C.smoe_bin(m, grid, bins.c, st.cuda_stream)
-                C.smoe_render(m, grid, bins.c, images.data_ptr(), None, None, None, st.cuda_stream)
+                C.smoe_bin(m, grid, bins, st.cuda_stream)
+                C.smoe_render(m, grid, bins, images.data_ptr(), None, None, None, st.cuda_stream)
                 slices = [(0, r.height * r.width, r.height, r.width)]
             else:
                 n = len(batch.reqs)
@@ -355,19 +451,19 @@ class Server:
                 cb = C.SmoeBatch(b.C, b.order, b.params.data_ptr(), b.params.shape[0], n,
                                  sl.table_dev.data_ptr(), ct.addressof(host), b.radius, b.box,
                                  b.mode, b.trunc)
-                C.smoe_bin_batched(cb, bins.c, st.cuda_stream)
-                C.smoe_render_batched(cb, bins.c, images.data_ptr(), None, st.cuda_stream)
+                C.smoe_bin_batched(cb, bins, st.cuda_stream)
+                C.smoe_render_batched(cb, bins, images.data_ptr(), None, st.cuda_stream)
                 slices = [(sg.pixel_offset, sg.pixel_offset + sg.width * sg.height, sg.height,
                            sg.width) for sg in host]
             # the images are complete at `done`; the status words follow and are checked once
             # their copy has landed (the batch's slot is released at `done`)
-            batch.done = torch.cuda.Event(enable_timing=True)
-            batch.done.record(st)
+            batch.done = sl.done
+            hip.record(batch.done, st.cuda_stream)
             batch.status = self._status[batch.bid % len(self._status)]
-            batch.status.copy_(bins._view(bins.c.status, 4, torch.int32), non_blocking=True)
-            batch.status_ready = torch.cuda.Event()
-            batch.status_ready.record(st)
-        batch.keep = [bins, images]
+            hip.copy_d2h(batch.status.data_ptr(), bins.status, 16, st.cuda_stream)
+            batch.status_ready = sl.status_ready
+            hip.record(batch.status_ready, st.cuda_stream)
+        batch.keep = [images]
         if keep_outputs:
             batch.slices = [images[a:e].view(h, w, b.C) for a, e, h, w in slices]
 
@@ -392,7 +488,8 @@ class Server:
         nxt = nb = 0
         sizes = []
         checks = []  # finished batches whose status words are still to be read
-        clock = _Clock(self.streams[0])
+        hip = self.hip
+        clock = _HipClock(hip, self.streams[0])
         footprint = lambda q: self.footprint(q)[0]  # noqa: E731
         while nxt < len(order) or pending or inflight:
             now = clock.now()
@@ -404,7 +501,7 @@ class Server:
             if inflight:
                 for si, sl in enumerate(self.slots):
                     bt = sl.batch
-                    if bt is None or not bt.done.query():
+                    if bt is None or not hip.done(bt.done):
                         continue
                     t = clock.at(bt.done)
                     t_start = clock.at(bt.start)
@@ -421,25 +518,27 @@ class Server:
             while (free and pending and inflight_blocks < self.fill_blocks
                    and (not inflight or len(pending) >= self.overlap_backlog)):
                 if len(pending) == 1:  # the common case at low load
-                    need = pending[0]._smoe_info[4]
+                    k, t, p, _, need = pending[0]._smoe_info
                     if in_use + need > self.budget:
                         if need > self.budget:
                             raise ValueError(f"request needs {need} bytes, over the budget")
                         break
                     got = [pending.popleft()]
+                    shape = (k, t, p)
                 else:
                     got = admit(pending, in_use, self.budget, footprint, self.max_batch,
                                 self.max_batch_pixels)
                     if not got:
                         break
-                    need = footprint(got)
+                    need, k, t, p = self.footprint(got)
+                    shape = (k, t, p)
                 while checks and checks[0].bid <= nb - len(self._status):
-                    _check(checks.pop(0))  # its status row is about to be reused
+                    _check(hip, checks.pop(0))  # its status row is about to be reused
                 si = min(free)  # the lowest free stream: at low load always the same one
                 free.remove(si)
-                bt = _Batch(nb, si, got, need, blocks=sum(self._info(r)[1] for r in got))
+                bt = _Batch(nb, si, got, need, blocks=shape[1])
                 nb += 1
-                self._launch(bt, keep_outputs)
+                self._launch(bt, keep_outputs, *shape)
                 self.slots[si].batch = bt
                 inflight += 1
                 inflight_blocks += bt.blocks
@@ -450,7 +549,7 @@ class Server:
                 _wait_until(clock, reqs[order[nxt]].arrival)
         torch.cuda.synchronize()
         for bt in checks:
-            _check(bt)
+            _check(hip, bt)
         return results, _summary(results, "batched", {
             "batches": nb, "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
             "max_batch": int(max(sizes)) if sizes else 0, "streams": len(self.slots),
