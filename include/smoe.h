@@ -22,8 +22,12 @@
  *    inv_s = 1/scale rounded to binary32 once: scale > 1 is super-resolution by
  *    re-sampling the continuous regression (Sec. II-B, Sec. VII-C).
  *  - Images are float32 [height][width][C] (channel-interleaved); per-pixel scalars
- *    are float32 [height][width].  Blocks (tiles) are 16x16 output pixels numbered
- *    row-major, T = ceil(width/16) * ceil(height/16).
+ *    are float32 [height][width].  Blocks (tiles) are the 16x16 blocks of the output grid
+ *    of the raster's scale, aligned to multiples of 16 in the output coordinate (ox + u,
+ *    oy + v): the raster's blocks are those its pixels touch, numbered row-major from the
+ *    one holding pixel (0, 0); T = ntx * nty with ntx = floor((ox + width - 1)/16) -
+ *    floor(ox/16) + 1 (rows alike), i.e. ceil(width/16) for a block-aligned origin.  Blocks
+ *    at the edges of a window may hang over it; their outside pixels are not written.
  *  - Kernel parameter rows are float32 [K][NP], NP = 6 + C * (1 + 2 * order):
  *      materialized row: mu_x, mu_y, l11, l21, l22, rho, a[C], wx[C], wy[C]
  *      raw row:          mu_x, mu_y, s1,  l21, s2,  rho, a[C], wx[C], wy[C]
@@ -53,10 +57,12 @@
  *      floor((mu_x + R) - 0.5); native blocks of j: floor(c/16) of those (x/16 computed as
  *      x * 0.0625), empty if no centre lies inside; rows alike;
  *      sample point of output pixel u: x(u) = ((ox + u) + 0.5) * inv_s.
- *    The block lists of an output raster hold, per 16x16 output block, every kernel one of
- *    whose native blocks holds a sample point of the block; at scale 1 and origin 0 these
- *    are the kernels whose box overlaps the block.  An output block spans at most two
- *    native blocks per axis; where it spans two, each pixel tests its own membership.
+ *    The block lists of an output raster hold, per output block, every kernel one of whose
+ *    native blocks holds a sample point of the block; at scale 1 and origin 0 these are the
+ *    native raster's lists.  A native block is 16*scale output pixels and begins on a
+ *    multiple of 16 of the output coordinate -- the binary32 sample coordinates included,
+ *    over the whole accepted range of origins, sizes and scales -- so every point of an
+ *    output block lies in one native block and every kernel of its list is a member there.
  *    Within a block, kernels are visited in increasing kernel id, which is also the
  *    summation order of every per-pixel sum (renders are bitwise reproducible).  One
  *    exception: smoe_render and smoe_render_batched split a list longer than 128 entries

@@ -118,7 +118,7 @@ def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0, tru
     ("gradient": native blocks holding a pixel centre in the box; "render": blocks the box
     overlaps)."""
     model, K = _KC(model, C, order)
-    T = ((W + 15) // 16) * ((H + 15) // 16)
+    T = blocks(W, ox) * blocks(H, oy)
     tr = np.zeros((K, 4), np.int32)
     pr = np.zeros((K, 4), np.int32)
     cnt = np.zeros(K, np.int32)
@@ -137,6 +137,12 @@ def bin(model, C, order, W, H, s=1, ox=0, oy=0, r=3.0, capacity=None, box=0, tru
     n = min(P, capacity)
     return dict(tile_rects=tr, native_rects=pr, counts=cnt, P=int(P), keys=keys[:n],
                 vals=vals[:n], ranges=rng)
+
+
+def blocks(n: int, o: int = 0) -> int:
+    """Blocks along an axis of n output pixels at origin o: the 16-pixel blocks of the output
+    grid, aligned to multiples of 16 in o + u, that the pixels touch."""
+    return (o + n - 1) // 16 - o // 16 + 1
 
 
 def _truncated(truncated) -> int:

@@ -92,8 +92,14 @@ struct Grid {
   int box;      // 0: square box of Sec. IV-B; 1: tight axis-aligned box
   int rbf;      // 0: gated SMoE regression, Eq. (2)-(4); 1: weighted sum of kernels, Eq. (1)
   int trunc;    // 1: the ellipse test applies to the gradient only; 0: render and gradient
-  int ntx() const { return (W + 15) / 16; }
-  int nty() const { return (H + 15) / 16; }
+  // Blocks: the 16x16 blocks of the output grid of this scale, aligned to multiples of 16 in
+  // the output coordinate o + u; the raster's blocks are those its pixels touch, numbered
+  // from the one holding its first pixel.
+  int ntx() const { return first_block(ox + W - 1) - first_block(ox) + 1; }
+  int nty() const { return first_block(oy + H - 1) - first_block(oy) + 1; }
+  static int first_block(int g) { return (int)std::floor(g / 16.0); }
+  // The first output pixel (window coordinate, may be negative) of block t along an axis.
+  static int block_start(int t, int o) { return 16 * (first_block(o) + t) - o; }
 };
 
 int num_params(int C, int order) { return 6 + C * (1 + 2 * order); }
@@ -140,10 +146,11 @@ bool native_axis(float lo, float hi, bool centres, float* b0, float* b1) {
   return *b0 <= *b1;
 }
 
-// The output blocks [t0, t1] of an axis of n sample points (origin o, scale s) holding a
-// point whose native block lies in [b0, b1]: every block is scanned, each by its first and
-// last point (the native block index does not decrease along the axis).  The native rect
-// is clamped to the blocks the raster's points reach.  False when none does.
+// The output blocks [t0, t1] of an axis of n sample points (origin o, scale s; blocks of 16
+// aligned to multiples of 16 in o + u, Grid) holding a point whose native block lies in
+// [b0, b1]: every block is scanned, each by its first and last point inside the raster (the
+// native block index does not decrease along the axis).  The native rect is clamped to the
+// blocks the raster's points reach.  False when none does.
 bool output_axis(float* b0, float* b1, int n, int o, int s, int* t0, int* t1) {
   const float first = native_block(coord32(0, o, s));
   const float last = native_block(coord32(n - 1, o, s));
@@ -152,10 +159,12 @@ bool output_axis(float* b0, float* b1, int n, int o, int s, int* t0, int* t1) {
   *b1 = std::min(*b1, last);
   *t0 = -1;
   *t1 = -2;
-  const int nt = (n + 15) / 16;
+  const int nt = Grid::first_block(o + n - 1) - Grid::first_block(o) + 1;
   for (int t = 0; t < nt; ++t) {
-    const float a = native_block(coord32(16 * t, o, s));
-    const float b = native_block(coord32(std::min(16 * t + 15, n - 1), o, s));
+    const int u0 = std::max(0, Grid::block_start(t, o));
+    const int u1 = std::min(n - 1, Grid::block_start(t, o) + 15);
+    const float a = native_block(coord32(u0, o, s));
+    const float b = native_block(coord32(u1, o, s));
     if (a <= *b1 && b >= *b0) {
       if (*t0 < 0) *t0 = t;
       *t1 = t;
@@ -500,8 +509,12 @@ double oracle_loss_grad(int K, int C, int order, const double* model, int W, int
       slot[j] = i;
       const Rect32& rc = M.rect[j];
       if (rc.empty) continue;
-      for (int v = rc.ty0 * 16; v < std::min(H, rc.ty1 * 16 + 16); ++v)
-        for (int u = rc.tx0 * 16; u < std::min(W, rc.tx1 * 16 + 16); ++u) need[(size_t)v * W + u] = 1;
+      const int v0 = std::max(0, Grid::block_start(rc.ty0, oy));
+      const int v1 = std::min(H, Grid::block_start(rc.ty1, oy) + 16);
+      const int u0 = std::max(0, Grid::block_start(rc.tx0, ox));
+      const int u1 = std::min(W, Grid::block_start(rc.tx1, ox) + 16);
+      for (int v = v0; v < v1; ++v)
+        for (int u = u0; u < u1; ++u) need[(size_t)v * W + u] = 1;
     }
   }
   threads = std::max(1, threads);

@@ -21,8 +21,12 @@ def num_params(C_: int, order: int) -> int:
     return 6 + C_ * (1 + 2 * order)
 
 
-def tiles(width: int, height: int) -> int:
-    return ((width + TILE - 1) // TILE) * ((height + TILE - 1) // TILE)
+def tiles(width: int, height: int, origin_x: int = 0, origin_y: int = 0) -> int:
+    """Blocks of a raster: the 16x16 blocks of its scale's output grid, aligned to multiples of
+    16 in the output coordinate, that its pixels touch."""
+    def across(n, o):
+        return (o + n - 1) // TILE - o // TILE + 1
+    return across(width, origin_x) * across(height, origin_y)
 
 
 BOXES = {"square": C.SMOE_BOX_SQUARE, "tight": C.SMOE_BOX_TIGHT}
@@ -147,7 +151,7 @@ def bin(params: torch.Tensor, C_: int, order: int, grid: C.SmoeGrid, bins: Bins 
         capacity: int | None = None, stream=None, grow: bool = True) -> Bins:
     """smoe_bin; with grow=True the workspace is re-made until the pairs fit (host sync)."""
     m = model_struct(params, C_, order)
-    T = tiles(grid.width, grid.height)
+    T = tiles(grid.width, grid.height, grid.origin_x, grid.origin_y)
     if bins is None:
         bins = Bins(m.K, C_, order, T, capacity or initial_capacity(m.K, T), params.device)
     C.smoe_bin(m, grid, bins.c, _stream(stream))

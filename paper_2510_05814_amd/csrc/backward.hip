@@ -20,7 +20,6 @@ struct BackwardArgs {
   Segs S;
   int C;
   const float* __restrict__ records;
-  const int4* __restrict__ native_rects;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
   const float* __restrict__ image;
@@ -33,7 +32,6 @@ struct BackwardArgs {
 template <int C, int ORDER, bool RBF>
 __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const SegGrid sg = seg_of_tile(a.S, tile);
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
@@ -48,7 +46,7 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
     sd.gy[i] = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) sd.g[i][c] = 0.0f;
-    if (px.u < sg.W && v < sg.H) {
+    if (in_raster(px.u, v, sg)) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const float D = a.denom[p];
       if (D > 0.0f) {
@@ -63,13 +61,8 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
       }
     }
   }
-  if (px.straddle)
-    backward_accumulate<C, ORDER, true>(px, a.S.r2, a.records, a.vals, 0, false, a.native_rects,
-                                        a.ranges[tile], srec, smask, false, 0ull, sd, a.pair_grads);
-  else
-    backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, 0, false, nullptr,
-                                         a.ranges[tile], srec, nullptr, false, 0ull, sd,
-                                         a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, 0, false, a.ranges[tile], srec,
+                                false, 0ull, sd, a.pair_grads);
 }
 
 struct GatherArgs {
@@ -102,7 +95,6 @@ hipError_t launch_backward(int C, int order, const Segs& S, const smoe_bins& b,
   BackwardArgs a{S,
                  C,
                  b.records,
-                 reinterpret_cast<const int4*>(b.native_rects),
                  reinterpret_cast<const int2*>(b.ranges),
                  b.vals,
                  image,

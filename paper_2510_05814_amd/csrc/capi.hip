@@ -58,8 +58,10 @@ void set_render_bound(Segs& S) {
   }
 }
 
-long long raster_tiles(int32_t W, int32_t H) {
-  return (long long)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+// Blocks of a raster: the 16x16 blocks of its scale's output grid (aligned to multiples of
+// 16 in the output coordinate) that its pixels touch.
+long long raster_tiles(int32_t W, int32_t H, int32_t ox, int32_t oy) {
+  return (long long)blocks_across(W, ox) * blocks_across(H, oy);
 }
 
 // The single raster of a non-batched call as a one-segment Segs.
@@ -85,7 +87,7 @@ bool single_segs(const smoe_model* m, const smoe_grid* g, Segs* out) {
   S.mode = g->mode;
   S.trunc = g->trunc;
   set_render_bound(S);
-  S.T = (int)raster_tiles(g->width, g->height);
+  S.T = (int)raster_tiles(g->width, g->height, g->origin_x, g->origin_y);
   S.K = m->K;
   *out = S;
   return true;
@@ -105,7 +107,7 @@ bool check_segments(const smoe_segment* h, int32_t n, int32_t rows, int* T, int*
     if ((long long)s.param_offset + s.num_kernels > rows) return false;
     if (s.kernel_offset != k || s.tile_offset != t || s.pixel_offset != px) return false;
     k += s.num_kernels;
-    t += raster_tiles(s.width, s.height);
+    t += raster_tiles(s.width, s.height, s.origin_x, s.origin_y);
     px += (long long)s.width * s.height;
   }
   if (t >= (1LL << 31) || k * 16 >= (1LL << 31)) return false;
@@ -376,7 +378,7 @@ smoe_status smoe_segments_layout(smoe_segment* segs, int32_t n, int32_t* total_k
     s.tile_offset = (int32_t)t;
     s.pixel_offset = px;
     k += s.num_kernels;
-    t += raster_tiles(s.width, s.height);
+    t += raster_tiles(s.width, s.height, s.origin_x, s.origin_y);
     px += (long long)s.width * s.height;
     if (t >= (1LL << 31) || k * 16 >= (1LL << 31)) return SMOE_ERR_INVALID;
   }

@@ -15,7 +15,8 @@ constexpr int kStepFlags = 5;   // status words 5, 6: the fit step's overflow fl
 __device__ __forceinline__ float native_block(float x) { return floorf(x * 0.0625f); }
 
 // Output-block range [t0, t1] of one axis of a raster (n points sampled at
-// ((o + u) + 0.5) * inv_s) holding a point whose native block lies in [b0, b1], and the
+// ((o + u) + 0.5) * inv_s; blocks aligned to multiples of 16 in o + u) holding a point whose
+// native block lies in [b0, b1], and the
 // native range clamped to the blocks the raster's points reach.  The native block index does
 // not decrease along the axis, so the points form one run [u0, u1]: at scale 1 the block of
 // point u is (o + u) >> 4 exactly; otherwise both ends are found by binary search over the
@@ -49,8 +50,9 @@ __device__ __forceinline__ bool output_axis(float b0, float b1, int n, int o, in
     }
     u1 = lo - 1;
   }
-  t0 = u0 >> 4;
-  t1 = u1 >> 4;
+  // blocks of the grid aligned to multiples of 16 in o + u, numbered from the raster's first
+  t0 = first_block(o + u0) - first_block(o);
+  t1 = first_block(o + u1) - first_block(o);
   return true;
 }
 

@@ -73,10 +73,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live = 0;
-  // a fit raster has scale 1 and origin 0: its blocks are native blocks (no straddling)
-  forward_accumulate<C, ORDER, TRUNC, false>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                             a.records, a.vals, a.shift, nullptr, rg, srec,
-                                             nullptr, D, N, live);
+  forward_accumulate<C, ORDER, TRUNC>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records,
+                                      a.vals, a.shift, rg, srec, D, N, live);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -88,7 +86,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
     sd.gy[i] = 0.0f;
 #pragma unroll
     for (int c = 0; c < C; ++c) sd.g[i][c] = 0.0f;
-    if (px.u < sg.W && v < sg.H) {
+    if (in_raster(px.u, v, sg)) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
       const bool cov = D[i] > 0.0f;
       // 1/D by v_rcp_f32 (1 ulp); y = N / D refined from it, as in the render
@@ -114,8 +112,8 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
   // each partial row goes to the slot its entry got in the scatter, where Adam reads it
-  backward_accumulate<C, ORDER, false>(px, a.S.r2, a.records, a.vals, a.shift, true, nullptr, rg,
-                                       srec, nullptr, true, live, sd, a.pair_grads);
+  backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.shift, true, rg, srec, true,
+                                live, sd, a.pair_grads);
 }
 
 struct AdamFitArgs {
@@ -247,8 +245,8 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       f.records[(size_t)j * RS + i] = fld;
     }
     if (i == 0) {
-      // (a fit raster has scale 1 and origin 0: the output blocks are the native blocks,
-      // and no block straddles two, so the native rectangles are not kept up to date)
+      // (nothing in the fit step reads the native rectangles: at scale 1 and origin 0 the
+      // output blocks are the native blocks; they are not kept up to date)
       const KernelRects kr = kernel_rects(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box, f.S.trunc);
       f.tile_rects_out[j] = kr.tile;
       f.counts[j] = rect_count(kr.tile);
@@ -269,7 +267,7 @@ __global__ __launch_bounds__(256) void k_segment_losses(Segs S, const float* __r
   __shared__ float s_red[4];
   const smoe_segment seg = S.tab ? S.tab[blockIdx.x] : S.one;
   const int T0 = seg.tile_offset;
-  const int Ts = ((seg.width + 15) >> 4) * ((seg.height + 15) >> 4);
+  const int Ts = blocks_across(seg.width, seg.origin_x) * blocks_across(seg.height, seg.origin_y);
   float acc = 0.0f;
   for (int t = threadIdx.x; t < Ts; t += 256) acc += tile_loss[T0 + t];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);

@@ -24,7 +24,6 @@ namespace {
 struct RenderArgs {
   Segs S;
   const float* __restrict__ records;
-  const int4* __restrict__ native_rects;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
   float* __restrict__ image;
@@ -47,7 +46,7 @@ __device__ __forceinline__ void render_epilogue(const RenderArgs& a, const SegGr
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
     const int v = px.v0 + 4 * i;
-    if (px.u < sg.W && v < sg.H) {
+    if (in_raster(px.u, v, sg)) {
       const size_t p = (size_t)sg.pixel_offset + (size_t)v * sg.W + px.u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -74,7 +73,6 @@ __device__ __forceinline__ void render_epilogue(const RenderArgs& a, const SegGr
 template <int C, int ORDER, bool RBF, int TRUNC>
 __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   __shared__ float4 srec[kChunk * record_stride(C, ORDER) / 4];
-  __shared__ uint32_t smask[kChunk];
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const int2 rg = a.ranges[tile];
   if (rg.y - rg.x > kSplitMin) return;  // a long list: k_render_wide renders this block
@@ -82,14 +80,8 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live;
-  if (px.straddle)
-    forward_accumulate<C, ORDER, TRUNC, true>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                              a.records, a.vals, 0, a.native_rects, rg, srec,
-                                              smask, D, N, live);
-  else
-    forward_accumulate<C, ORDER, TRUNC, false>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset,
-                                               a.records, a.vals, 0, nullptr, rg, srec, nullptr,
-                                               D, N, live);
+  forward_accumulate<C, ORDER, TRUNC>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records,
+                                      a.vals, 0, rg, srec, D, N, live);
   render_epilogue<C, RBF>(a, sg, px, tile, D, N);
 }
 
@@ -101,24 +93,22 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
 // same for the four waves, so each barrier is reached by all of them.
 constexpr int kWideGroups = 1024;
 
-template <int C, int ORDER, bool RBF, int TRUNC, bool STRADDLE>
-__device__ __forceinline__ void render_wide_block(const RenderArgs& a, const SegGrid& sg,
-                                                  const PixelCoords& px, int tile, int2 rg,
+template <int C, int ORDER, bool RBF, int TRUNC>
+__device__ __forceinline__ void render_wide_block(const RenderArgs& a, int tile, int2 rg,
                                                   float4 (*srec)[kChunk * record_stride(C, ORDER) / 4],
-                                                  uint32_t (*smask)[kChunk],
                                                   float (*part)[kRows * (1 + C)][kWave]) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   const int len = rg.y - rg.x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const SegGrid sg = seg_of_tile(a.S, tile);
+  const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   const int per = (len + kSplitWaves - 1) / kSplitWaves;
   const int b = rg.x + min(len, wv * per), e = rg.x + min(len, (wv + 1) * per);
   float D[kRows], N[kRows][C];
   zero_sums<C>(D, N);
   const float cut_scale = in_vgpr(a.S.cut_scale), cut_offset = in_vgpr(a.S.cut_offset);
-  const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   float4* my = srec[wv];
-  uint32_t* mymask = smask[wv];
   for (int base = b; base < e; base += kChunk) {
     const int n = min(kChunk, e - base);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -127,15 +117,11 @@ __device__ __forceinline__ void render_wide_block(const RenderArgs& a, const Seg
       const int k = i / Q, c = i - k * Q;
       my[i] = reinterpret_cast<const float4*>(a.records + (size_t)a.vals[base + k] * RS)[c];
     }
-    if (STRADDLE)
-      for (int k = lane; k < n; k += kWave)
-        mymask[k] = outside_mask(a.native_rects[a.vals[base + k]], px.bxb, px.byb);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int k = 0; k < n; ++k)
-      forward_entry<C, ORDER, TRUNC, STRADDLE>(px, a.S.r2, cut_scale, cut_offset, big,
-                                               reinterpret_cast<const float*>(&my[k * Q]),
-                                               STRADDLE ? mymask[k] : 0u, D, N);
+      forward_entry<C, ORDER, TRUNC>(px, a.S.r2, cut_scale, cut_offset,
+                                     reinterpret_cast<const float*>(&my[k * Q]), D, N);
   }
   if (wv > 0) {
 #pragma unroll
@@ -164,17 +150,11 @@ __device__ __forceinline__ void render_wide_block(const RenderArgs& a, const Seg
 template <int C, int ORDER, bool RBF, int TRUNC>
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs a) {
   __shared__ float4 srec[kSplitWaves][kChunk * record_stride(C, ORDER) / 4];
-  __shared__ uint32_t smask[kSplitWaves][kChunk];
   __shared__ float part[kSplitWaves - 1][kRows * (1 + C)][kWave];
   for (int tile = blockIdx.x; tile < a.S.T; tile += gridDim.x) {
     const int2 rg = a.ranges[tile];
     if (rg.y - rg.x <= kSplitMin) continue;  // k_render renders this block
-    const SegGrid sg = seg_of_tile(a.S, tile);
-    const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
-    if (px.straddle)
-      render_wide_block<C, ORDER, RBF, TRUNC, true>(a, sg, px, tile, rg, srec, smask, part);
-    else
-      render_wide_block<C, ORDER, RBF, TRUNC, false>(a, sg, px, tile, rg, srec, smask, part);
+    render_wide_block<C, ORDER, RBF, TRUNC>(a, tile, rg, srec, part);
   }
 }
 
@@ -200,9 +180,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_reduce(const float* __r
 // q <= r^2, added atomically into out2 = (tested, active).
 constexpr int kStatThreads = kTilePixels;
 __global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float* __restrict__ records,
-                                                             int rs,
-                                                             const int4* __restrict__ native_rects,
-                                                             const int2* __restrict__ ranges,
+                                                             int rs, const int2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ vals,
                                                              unsigned long long* __restrict__ out2) {
   __shared__ unsigned long long s_act[kStatThreads / 64];
@@ -211,17 +189,14 @@ __global__ __launch_bounds__(kStatThreads) void k_pair_stats(Segs S, const float
   const SegGrid g = seg_of_tile(S, tile);
   const int lt = tile - g.tile_offset;
   const int tx = lt % g.ntx, ty = lt / g.ntx;
-  const int u = tx * kTile + (threadIdx.x & 15);
-  const int v = ty * kTile + (threadIdx.x >> 4);
-  const bool inside = u < g.W && v < g.H;
+  const int u = kTile * (g.bx0 + tx) - g.ox + (threadIdx.x & 15);
+  const int v = kTile * (g.by0 + ty) - g.oy + (threadIdx.x >> 4);
+  const bool inside = (unsigned)u < (unsigned)g.W && (unsigned)v < (unsigned)g.H;
   const float x = sample_coord(u, g.ox, g.inv_s);
   const float y = sample_coord(v, g.oy, g.inv_s);
-  const int bx = (int)native_block(x), by = (int)native_block(y);
   const int2 rg = ranges[tile];
   unsigned long long act = 0;
   for (int i = rg.x; i < rg.y && inside; ++i) {
-    const int4 nr = native_rects[vals[i]];
-    if (bx < nr.x || bx > nr.z || by < nr.y || by > nr.w) continue;
     const float* r = records + (size_t)vals[i] * rs;
     const float dx = x - r[0];
     const float dy = y - r[1];
@@ -259,7 +234,6 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
                          float* denom, const float* target, hipStream_t s) {
   RenderArgs a{S,
                b.records,
-               reinterpret_cast<const int4*>(b.native_rects),
                reinterpret_cast<const int2*>(b.ranges),
                b.vals,
                image,
@@ -278,7 +252,6 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
 hipError_t launch_pair_stats(const Segs& S, const smoe_bins& b, uint64_t* out2, hipStream_t s) {
   k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(out2), 2);
   k_pair_stats<<<S.T, kStatThreads, 0, s>>>(S, b.records, b.record_stride,
-                                            reinterpret_cast<const int4*>(b.native_rects),
                                             reinterpret_cast<const int2*>(b.ranges), b.vals,
                                             reinterpret_cast<unsigned long long*>(out2));
   return hipGetLastError();

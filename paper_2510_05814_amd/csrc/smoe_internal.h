@@ -55,9 +55,20 @@ struct Segs {
   int K;                                 // kernel rows of all segments
 };
 
+// Blocks of a raster: the 16x16 blocks of the output grid of its scale, aligned to
+// multiples of 16 in the output coordinate o + u (so that at scale s a native block, 16 s
+// output pixels, is a whole number of blocks); a window's first and last blocks may be
+// partial on either side.  first_block(o) = floor(o / 16) is the grid block of the raster's
+// first pixel; blocks_across(n, o) the blocks its n pixels touch.
+__host__ __device__ constexpr int first_block(int o) { return o >= 0 ? o / 16 : -((15 - o) / 16); }
+__host__ __device__ constexpr int blocks_across(int n, int o) {
+  return first_block(o + n - 1) - first_block(o) + 1;
+}
+
 // One segment's raster, as the kernels use it.
 struct SegGrid {
   int W, H, scale, ox, oy, ntx;
+  int bx0, by0;                // grid block of the raster's first pixel, per axis
   float inv_s;                 // 1/scale, binary32
   int tile_offset, kernel_offset, param_offset, K;
   long long pixel_offset;
@@ -71,7 +82,9 @@ __host__ __device__ inline SegGrid seg_grid_of(const smoe_segment& s) {
   g.scale = s.scale;
   g.ox = s.origin_x;
   g.oy = s.origin_y;
-  g.ntx = (s.width + 15) >> 4;
+  g.ntx = blocks_across(s.width, s.origin_x);
+  g.bx0 = first_block(s.origin_x);
+  g.by0 = first_block(s.origin_y);
   g.inv_s = 1.0f / (float)s.scale;
   g.tile_offset = s.tile_offset;
   g.kernel_offset = s.kernel_offset;

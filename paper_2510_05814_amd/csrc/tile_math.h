@@ -43,85 +43,51 @@ constexpr int kChunk = 64;                     // records staged in LDS per chun
 constexpr int kRows = kTilePixels / kWave;     // pixels per lane (4)
 
 struct PixelCoords {
-  int u;            // output column of the lane (within its raster)
+  int u;            // output column of the lane (within its raster; < 0 or >= W: outside)
   int v0;           // output row of the lane's first pixel (rows v0 + 4i)
   float x;          // sampling coordinates
   float y[kRows];
-  // Native blocks.  A kernel takes part at a point only if the point's native 16x16 block is
-  // one of the kernel's.  An output block whose points all lie in one native block (every
-  // block at scale 1 with a block-aligned origin) needs no per-point test; one that straddles
-  // native blocks (at most two per axis: 16 output pixels span at most 16 native pixels)
-  // tests each point.  (bxb, byb): native block of the block's first column and row;
-  // lbit[i]: 1 << (dx + 2 dy) with (dx, dy) in {0, 1}^2 the native block of the lane's
-  // pixel i relative to it.
-  int bxb, byb;
-  bool straddle;    // wave-uniform
-  uint32_t lbit[kRows];
 };
 
-__device__ __forceinline__ int native_block_of(int u, int o, float inv_s) {
-  return (int)native_block(sample_coord(u, o, inv_s));
+// Whether output pixel (u, v) lies in the raster (the first and last blocks of a window may
+// hang over its edges).
+__device__ __forceinline__ bool in_raster(int u, int v, const SegGrid& g) {
+  return (unsigned)u < (unsigned)g.W && (unsigned)v < (unsigned)g.H;
 }
 
-// `tile` is the block index inside the segment's raster.
+// `tile` is the block index inside the segment's raster.  The raster's blocks are aligned
+// to multiples of 16 in the output coordinate o + u (SegGrid), so the block's first column
+// is u = 16 (bx0 + tx) - ox.  A native block is 16 s output pixels and begins on such a
+// multiple (binary32 sample coordinates included, over the whole accepted range of origins,
+// sizes and scales), so all of a block's points lie in one native block and every kernel of
+// its list is a member at every one of them: no per-point membership test.
 __device__ __forceinline__ PixelCoords lane_pixels(const SegGrid& g, int tile) {
   PixelCoords p;
   const int lane = threadIdx.x & 63;
   const int tx = tile % g.ntx, ty = tile / g.ntx;
-  p.u = tx * kTile + (lane & 15);
-  p.v0 = ty * kTile + (lane >> 4);
+  p.u = kTile * (g.bx0 + tx) - g.ox + (lane & 15);
+  p.v0 = kTile * (g.by0 + ty) - g.oy + (lane >> 4);
   p.x = sample_coord(p.u, g.ox, g.inv_s);
 #pragma unroll
   for (int i = 0; i < kRows; ++i) p.y[i] = sample_coord(p.v0 + 4 * i, g.oy, g.inv_s);
-  p.bxb = native_block_of(tx * kTile, g.ox, g.inv_s);
-  p.byb = native_block_of(ty * kTile, g.oy, g.inv_s);
-  p.straddle = native_block_of(tx * kTile + kTile - 1, g.ox, g.inv_s) != p.bxb ||
-               native_block_of(ty * kTile + kTile - 1, g.oy, g.inv_s) != p.byb;
-  const int dx = (int)native_block(p.x) - p.bxb;
-#pragma unroll
-  for (int i = 0; i < kRows; ++i)
-    p.lbit[i] = 1u << (dx + 2 * ((int)native_block(p.y[i]) - p.byb));
   return p;
 }
 
-// For a straddling block: entry k's native-block mask, inverted -- bit dx + 2 dy is set iff
-// the native block (bxb + dx, byb + dy) is NOT one of the kernel's.
-__device__ __forceinline__ uint32_t outside_mask(int4 nr, int bxb, int byb) {
-  const bool x0 = nr.x <= bxb && bxb <= nr.z, x1 = nr.x <= bxb + 1 && bxb + 1 <= nr.z;
-  const bool y0 = nr.y <= byb && byb <= nr.w, y1 = nr.y <= byb + 1 && byb + 1 <= nr.w;
-  const uint32_t in = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
-                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
-  return ~in & 15u;
-}
-
-// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS, and for a
-// straddling block (smask not null) each entry's outside_mask.  An entry holds the kernel id
-// shifted left by `shift` (the fit step's packed bucket entries; 0 elsewhere).
+// Stages the records of list entries [base, base + n) (n <= kChunk) into LDS.  An entry
+// holds the kernel id shifted left by `shift` (the fit step's packed bucket entries; 0
+// elsewhere).
 template <int RS>
 __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
                                               const float* __restrict__ records,
                                               const uint32_t* __restrict__ vals, int base, int n,
-                                              int shift, uint32_t* __restrict__ smask = nullptr,
-                                              const int4* __restrict__ native_rects = nullptr,
-                                              int bxb = 0, int byb = 0) {
+                                              int shift) {
   constexpr int Q = RS / 4;
   __syncthreads();
   for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
     const int k = i / Q, c = i - k * Q;
     srec[i] = reinterpret_cast<const float4*>(records + (size_t)(vals[base + k] >> shift) * RS)[c];
   }
-  if (smask)
-    for (int k = threadIdx.x & 63; k < n; k += kWave)
-      smask[k] = outside_mask(native_rects[vals[base + k] >> shift], bxb, byb);
   __syncthreads();
-}
-
-// Pushes q beyond every bound at the lane's pixels outside the entry's native blocks
-// (STRADDLE only): q + 2^100 * (outside & lbit), with `big` = 2^100 in a vector register.
-template <bool STRADDLE>
-__device__ __forceinline__ float member_q(float q, uint32_t outside, uint32_t lbit, float big) {
-  if (!STRADDLE) return q;
-  return __builtin_fmaf((float)(outside & lbit), big, q);
 }
 
 // One list entry of the forward: adds its terms to D = sum pi K and N_c = sum pi K m_c of
@@ -129,8 +95,7 @@ __device__ __forceinline__ float member_q(float q, uint32_t outside, uint32_t lb
 // ellipse q <= r^2.  TRUNC == SMOE_TRUNC_GRADIENT (the block lists decide the render): every
 // term binary32 holds, i.e. whose exponent a = rho log2(e) - q log2(e)/2 is >= -125.  Returns
 // whether any of the lane's pixels passed the ellipse test q <= r2.  r: the entry's render
-// record; cut_scale, cut_offset: the render's bound in the compare-free form of Segs;
-// outside, big: the native-block test of a straddling block (member_q).
+// record; cut_scale, cut_offset: the render's bound in the compare-free form of Segs.
 //
 // Neither bound is a per-row compare: a VALU instruction that writes or reads a scalar
 // register (a compare's lane mask, a select on it) issues at about 60 % of the rate of one
@@ -140,10 +105,9 @@ __device__ __forceinline__ float member_q(float q, uint32_t outside, uint32_t lb
 // exponent of about -2^36; with the representable range, min(a, fma(a, 2^60, 125 * 2^60)) is
 // a for a >= -125 and below -2^43 otherwise.  Either way exp2 of an excluded term is exactly
 // zero and every kept term carries the same bits as with a compare-and-select.
-template <int C, int ORDER, int TRUNC, bool STRADDLE>
+template <int C, int ORDER, int TRUNC>
 __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, float cut_scale,
-                                              float cut_offset, float big, const float* r,
-                                              uint32_t outside, float (&D)[kRows],
+                                              float cut_offset, const float* r, float (&D)[kRows],
                                               float (&N)[kRows][C]) {
   // Truncation test: the binary32 sequence of the ABI contract (no contraction).
   const float dx = px.x - r[0];
@@ -162,7 +126,7 @@ __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, f
     dy[i] = px.y[i] - r[1];
     const float w = dy[i] - tt;
     const float z2 = w * r[4];
-    q[i] = member_q<STRADDLE>(zz1 + z2 * z2, outside, px.lbit[i], big);
+    q[i] = zz1 + z2 * z2;
   }
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
@@ -209,34 +173,26 @@ __device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C
 // entry, records staged through LDS in chunks).
 // live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
-// STRADDLE: the block straddles native blocks (smask: kChunk words of LDS; native_rects: the
-// kernels' native rectangles); otherwise both may be null.  shift: list entries hold the
-// kernel id << shift.
-template <int C, int ORDER, int TRUNC, bool STRADDLE>
+// shift: list entries hold the kernel id << shift.
+template <int C, int ORDER, int TRUNC>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
                                                    float cut_scale, float cut_offset,
                                                    const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int shift,
-                                                   const int4* __restrict__ native_rects, int2 rg,
-                                                   float4* srec, uint32_t* smask,
-                                                   float (&D)[kRows], float (&N)[kRows][C],
-                                                   uint64_t& live) {
+                                                   int2 rg, float4* srec, float (&D)[kRows],
+                                                   float (&N)[kRows][C], uint64_t& live) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   zero_sums<C>(D, N);
   cut_scale = in_vgpr(cut_scale);
   cut_offset = in_vgpr(cut_offset);
-  const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    stage_records<RS>(srec, records, vals, base, n, shift, STRADDLE ? smask : nullptr,
-                      native_rects, px.bxb, px.byb);
+    stage_records<RS>(srec, records, vals, base, n, shift);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      const uint32_t outside = STRADDLE ? smask[k] : 0u;
-      if (__any(forward_entry<C, ORDER, TRUNC, STRADDLE>(px, r2, cut_scale, cut_offset, big, r,
-                                                          outside, D, N)))
+      if (__any(forward_entry<C, ORDER, TRUNC>(px, r2, cut_scale, cut_offset, r, D, N)))
         live |= 1ull << k;
     }
   }
@@ -393,27 +349,23 @@ struct PixelSeed {
 // packed (the fit step): list entries hold kernel id << shift | slot, and the partial row of
 // an entry goes to its slot, rg.x + slot, where the scatter recorded it; otherwise to the
 // entry's list position.
-template <int C, int ORDER, bool STRADDLE>
+template <int C, int ORDER>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
                                                     const uint32_t* __restrict__ vals, int shift,
-                                                    bool packed,
-                                                    const int4* __restrict__ native_rects, int2 rg,
-                                                    float4* srec, uint32_t* smask, bool staged,
-                                                    uint64_t live, const PixelSeed<C>& sd,
+                                                    bool packed, int2 rg, float4* srec,
+                                                    bool staged, uint64_t live,
+                                                    const PixelSeed<C>& sd,
                                                     float* __restrict__ pair_grads) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   constexpr int NP = num_params(C, ORDER);
   static_assert(NP <= 16, "16 accumulators per kernel");
   const int lane = threadIdx.x & 63;
-  const float big = STRADDLE ? in_vgpr(0x1p100f) : 0.0f;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     const bool reuse = staged && rg.y - rg.x <= kChunk;
-    if (!reuse)
-      stage_records<RS>(srec, records, vals, base, n, shift, STRADDLE ? smask : nullptr,
-                        native_rects, px.bxb, px.byb);
+    if (!reuse) stage_records<RS>(srec, records, vals, base, n, shift);
     const uint32_t slot_mask = (1u << shift) - 1u;
     // the row of entry k: its slot (packed) or its list position
     auto out_row = [&](int k) -> size_t {
@@ -428,7 +380,6 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         continue;
       }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
-      const uint32_t outside = STRADDLE ? smask[k] : 0u;
       const float dx = px.x - r[0];
       const float z1 = dx * r[2];
       const float tt = r[3] * z1;
@@ -452,7 +403,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         const float dy = px.y[i] - r[1];
         const float w_ = dy - tt;
         const float z2 = w_ * r[4];
-        const float q = member_q<STRADDLE>(zz1 + z2 * z2, outside, px.lbit[i], big);
+        const float q = zz1 + z2 * z2;
         if (sd.valid[i] && q <= r2) {
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
           const float w = e * sd.invD[i];

@@ -108,10 +108,11 @@ class BoxSpans:
 
     def pair_bound(self, i: int, scale: int, width: int, height: int,
                    sharpen: float = 1.0) -> int:
-        """Sum over model i's kernels of min(span, blocks across) * min(span, blocks down)."""
+        """Sum over model i's kernels of min(span, blocks across) * min(span, blocks down),
+        with the most blocks a window of this size touches at any origin."""
         b, s1, s2 = self._span_table(i, scale, sharpen)
-        a = (width + TILE - 1) // TILE
-        c = (height + TILE - 1) // TILE
+        a = (width + TILE - 2) // TILE + 1
+        c = (height + TILE - 2) // TILE + 1
         a, c = min(a, c), max(a, c)
         ia = int(np.searchsorted(b, a, side="right"))
         ic = int(np.searchsorted(b, c, side="right"))
@@ -173,8 +174,9 @@ def admit(pending, in_use: int, budget: int, footprint, max_batch: int, max_pixe
     return batch
 
 
-def _tiles(w: int, h: int) -> int:
-    return ((w + TILE - 1) // TILE) * ((h + TILE - 1) // TILE)
+def _tiles(w: int, h: int, ox: int = 0, oy: int = 0) -> int:
+    """Blocks of a raster (16x16 blocks of the output grid aligned to multiples of 16)."""
+    return ((ox + w - 1) // TILE - ox // TILE + 1) * ((oy + h - 1) // TILE - oy // TILE + 1)
 
 
 def _to_requests(reqs):
@@ -388,7 +390,7 @@ class Server:
         self._models = [model_struct(bank.rows(i), bank.C, bank.order) for i in range(len(bank))]
         if reserve_for is not None:
             w, h, scales = reserve_for
-            t = _tiles(w, h)
+            t = _tiles(w, h, TILE - 1, TILE - 1)  # the most blocks such a window touches
             shapes = [(bank.K[i], t, bank.pair_bound(i, s, w, h)) for i in range(len(bank))
                       for s in scales]
             for sl in self.slots:
@@ -399,7 +401,7 @@ class Server:
         """(kernels, blocks, pair bound, pixels, bytes alone) of one request, computed once."""
         inf = getattr(r, "_smoe_info", None)
         if inf is None:
-            k, t = self.bank.K[r.model], _tiles(r.width, r.height)
+            k, t = self.bank.K[r.model], _tiles(r.width, r.height, r.origin_x, r.origin_y)
             p = self.bank.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen)
             n = r.width * r.height
             nbytes = (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
@@ -587,7 +589,8 @@ class PlainServer:
             with torch.cuda.stream(st):
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev0.record(st)
-                bins = Bins(b.K[r.model], b.C, b.order, _tiles(r.width, r.height),
+                bins = Bins(b.K[r.model], b.C, b.order,
+                            _tiles(r.width, r.height, r.origin_x, r.origin_y),
                             b.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen),
                             device=rows.device, render_only=True, zero=False)
                 image = torch.empty((r.height, r.width, b.C), dtype=torch.float32,

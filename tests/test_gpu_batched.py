@@ -73,7 +73,7 @@ def test_bin_batched_matches_oracle_per_segment(C, order):
     for sg, (w, h, s, ox, oy, K, mi) in zip(segs.host, RASTERS):
         m = models[mi][1].astype(np.float64)
         o = oracle.bin(m, C, order, w, h, s, ox, oy)
-        k0, t0, T = sg.kernel_offset, sg.tile_offset, ((w + 15) // 16) * ((h + 15) // 16)
+        k0, t0, T = sg.kernel_offset, sg.tile_offset, oracle.blocks(w, ox) * oracle.blocks(h, oy)
         assert np.array_equal(rects[k0:k0 + K], o["tile_rects"])
         assert np.array_equal(counts[k0:k0 + K], o["counts"])
         assert np.array_equal(keys[p0:p0 + o["P"]], o["keys"] + t0)

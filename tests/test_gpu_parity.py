@@ -55,7 +55,7 @@ def gpu_bins(smoe, model_np, C, order, grid):
     over, st = b.read_status()
     assert not over
     P = st[0]
-    T = smoe.tiles(grid.width, grid.height)
+    T = smoe.tiles(grid.width, grid.height, grid.origin_x, grid.origin_y)
     return m, b, dict(tile_rects=host(b.tile_rects()), native_rects=host(b.native_rects()),
                       counts=host(b.counts()), P=P,
                       keys=host(b.keys(P)).view(np.uint32), vals=host(b.vals(P)).view(np.uint32),

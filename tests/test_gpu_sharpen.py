@@ -58,7 +58,7 @@ def test_sharpened_bins_and_render_against_oracle(smoe, f, s, ox, oy, record_err
     assert not over
     ms = oracle.sharpen(m_np, f)
     ob = oracle.bin(ms, 3, 1, OW, OH, s, ox, oy)
-    T = smoe.tiles(OW, OH)
+    T = smoe.tiles(OW, OH, ox, oy)
     P = st[0]
     assert P == ob["P"]
     assert np.array_equal(host(b.tile_rects()), ob["tile_rects"])

@@ -56,7 +56,7 @@ def test_sweep_against_oracle(case, record_error):
     assert P == ob["P"]
     assert np.array_equal(b.tile_rects().cpu().numpy(), ob["tile_rects"])
     assert np.array_equal(b.vals(P).cpu().numpy().view(np.uint32), ob["vals"])
-    assert np.array_equal(b.ranges(smoe.tiles(OW, OH)).cpu().numpy(), ob["ranges"])
+    assert np.array_equal(b.ranges(smoe.tiles(OW, OH, ox, oy)).cpu().numpy(), ob["ranges"])
     t_np = rng.uniform(0, 1, (OH, OW, C)).astype(np.float32)
     t = torch.from_numpy(t_np).cuda()
     img, D, loss, b = smoe.render(m, C, order, grid, bins=b, target=t)

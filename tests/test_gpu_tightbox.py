@@ -65,7 +65,7 @@ def test_tight_bins_against_oracle_and_images_equal_square(smoe, case, record_er
     say("tight box", case)
     m_np = wl.stretched_model(K, 3, 1, W, H, seed)
     OW, OH = s * W - ox, s * H - oy
-    T = smoe.tiles(OW, OH)
+    T = smoe.tiles(OW, OH, ox, oy)
     m = dev(m_np)
     gt = smoe.make_grid(OW, OH, s, ox, oy, sharpen=f, box="tight", trunc="render")
     gs = smoe.make_grid(OW, OH, s, ox, oy, sharpen=f, box="square", trunc="render")
@@ -198,7 +198,7 @@ def test_all_rule_settings_combined(smoe, mode, trunc, record_error):
     OW, OH = s * W - ox, s * H - oy
     m = dev(m_np)
     grid = smoe.make_grid(OW, OH, s, ox, oy, sharpen=f, box="tight", mode=mode, trunc=trunc)
-    b, got = _bins(smoe, m, grid, smoe.tiles(OW, OH))
+    b, got = _bins(smoe, m, grid, smoe.tiles(OW, OH, ox, oy))
     ms = oracle.sharpen(m_np, f)
     ob = oracle.bin(ms, 3, 1, OW, OH, s, ox, oy, box=1, trunc=trunc)
     assert got["P"] == ob["P"]

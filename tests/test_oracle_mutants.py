@@ -41,9 +41,10 @@ MUTANTS = [
      [pins.test_tight_box_keeps_every_value_and_shortens_lists]),
     ("native blocks of 8 pixels", "return std::floor(x * 0.0625f);",
      "return std::floor(x * 0.125f);", [pins.test_render_points_block_membership_bruteforce]),
-    ("output block rect from the last point of the first block only",
-     "const float b = native_block(coord32(std::min(16 * t + 15, n - 1), o, s));",
-     "const float b = a;", [pins.test_box_half_side_is_r_sqrt_lambda_max]),
+    ("output blocks counted from the window's first pixel",
+     "static int block_start(int t, int o) { return 16 * (first_block(o) + t) - o; }",
+     "static int block_start(int t, int o) { return 16 * t; }",
+     [pins.test_box_half_side_is_r_sqrt_lambda_max]),
     ("membership from the raster's pixel instead of the native point",
      "const float bx = native_block(x32), by = native_block(y32);",
      "const float bx = native_block(x32 - 0.5f), by = native_block(y32 - 0.5f);",

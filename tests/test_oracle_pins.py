@@ -86,15 +86,18 @@ def _np_native_blocks(lo, hi):
 
 def _np_output_blocks(blocks, n, s=1, o=0):
     """The output blocks (first, last) of an axis of n points sampled at ((o + u) + 0.5) / s
-    whose native block floor(x / 16) lies in `blocks`, and the native blocks clamped to those
-    the points reach -- by brute force over every point; None if no point is in them."""
+    whose native block floor(x / 16) lies in `blocks` -- output blocks of 16 aligned to
+    multiples of 16 in o + u, numbered from the one holding the first point -- and the native
+    blocks clamped to those the points reach, by brute force over every point; None if no
+    point is in them."""
     if blocks is None:
         return None
     nb = np.floor((np.arange(n) + o + 0.5) / s / 16).astype(np.int64)
     hit = np.nonzero((nb >= blocks[0]) & (nb <= blocks[1]))[0]
     if hit.size == 0:
         return None
-    return (hit[0] >> 4, hit[-1] >> 4), (max(blocks[0], nb[0]), min(blocks[1], nb[-1]))
+    first = (o + hit[0]) // 16 - o // 16, (o + hit[-1]) // 16 - o // 16
+    return first, (max(blocks[0], nb[0]), min(blocks[1], nb[-1]))
 
 
 def test_box_half_side_is_r_sqrt_lambda_max():
@@ -342,7 +345,8 @@ def test_tight_box_keeps_every_value_and_shortens_lists():
             hit = q[j] <= R * R * (1 - 1e-6)
             if not hit.any():
                 continue
-            bx, by = u.ravel()[hit] >> 4, v.ravel()[hit] >> 4
+            bx = (ox + u.ravel()[hit]) // 16 - ox // 16
+            by = (oy + v.ravel()[hit]) // 16 - oy // 16
             assert b[j, 0] <= bx.min() and bx.max() <= b[j, 2], (s, j)
             assert b[j, 1] <= by.min() and by.max() <= b[j, 3], (s, j)
 
@@ -917,3 +921,22 @@ def test_render_cut_loses_nothing_against_the_uncut_block_lists():
         yc = ((e[..., None] * ex).sum(axis=0) / Dc[:, None]).reshape(H, W, C)
         worst_2r = max(worst_2r, float(np.max(np.abs(yc - yu))))
     assert worst_2r > 1e-6
+
+
+def test_output_blocks_never_straddle_native_blocks():
+    """Output blocks are aligned to multiples of 16 in o + u, so that at every integer scale a
+    native block (16 s output pixels) begins on an output block boundary: the sample point of
+    output coordinate G = o + u, fl(fl(G + 1/2) fl(1/s)) in binary32, lies in native block
+    floor(G / (16 s)).  Exhaustively, for every scale the ABI accepts (1-64) and every native
+    boundary G = 16 k s over the accepted coordinate range (|o| <= 2^22, widths <= 65536): the
+    points on both sides of each boundary fall in the blocks on their sides.  The GPU renders
+    a block's list without a per-point membership test on the strength of this."""
+    lo, hi = -(1 << 22), (1 << 22) + 65536
+    for s in range(1, 65):
+        inv = np.float32(1.0) / np.float32(s)
+        k = np.arange(lo // (16 * s) - 1, hi // (16 * s) + 2, dtype=np.int64)
+        for g, want in ((16 * k * s - 1, k - 1), (16 * k * s, k)):
+            m = (g >= lo) & (g < hi)
+            x = (g[m].astype(np.float32) + np.float32(0.5)) * inv
+            nb = np.floor(x * np.float32(0.0625)).astype(np.int64)
+            assert np.array_equal(nb, want[m]), s

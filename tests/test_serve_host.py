@@ -41,7 +41,7 @@ def test_pair_bound_single_kernel_closed_form():
     m[0, 2] = m[0, 4] = 2.0
     spans = BoxSpans([m], 3.0)
     assert spans.pair_bound(0, 1, 256, 256) == 3 * 3
-    assert spans.pair_bound(0, 1, 16, 256) == 3      # one block across
+    assert spans.pair_bound(0, 1, 16, 256) == 2 * 3  # 16 px touch at most two blocks
     assert spans.pair_bound(0, 4, 256, 256) == 9 * 9
     for ox in range(16):
         P = oracle.bin(np.array([[8.0 + ox / 4, 8.0, 2.0, 0.0, 2.0, 0.0] + [0.5] * 9]), 3, 1,
