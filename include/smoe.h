@@ -70,10 +70,15 @@
  *    in quarter order (still a fixed order), so on such blocks they are not bitwise equal to
  *    the fit step's render, which sums every list whole.
  *  - A pixel where no kernel takes part renders 0 and receives no gradient.
+ *  - A kernel row with a NaN or infinite parameter (after sharpening) covers no block: it
+ *    takes part nowhere, so the other kernels render and fit exactly as without it, and
+ *    receives a zero gradient.  The binning (and, in a fit, each Adam step) raises the
+ *    non-finite status word for it; smoe_read_status() reports SMOE_ERR_NONFINITE.
  *
  * Status codes are negative on error.  Asynchronous conditions detected on the device
- * (pair-capacity overflow) are reported through the workspace status words and read
- * back with smoe_read_status(), so that a whole fit step stays free of host syncs.
+ * (pair-capacity overflow, non-finite parameters) are reported through the workspace status
+ * words and read back with smoe_read_status(), so that a whole fit step stays free of host
+ * syncs.
  */
 #ifndef SMOE_H_
 #define SMOE_H_
@@ -91,6 +96,7 @@ typedef int32_t smoe_status;
 #define SMOE_ERR_CAPACITY (-2)  /* pair capacity too small (from smoe_read_status) */
 #define SMOE_ERR_HIP (-3)       /* a HIP launch or copy failed */
 #define SMOE_ERR_TOO_LARGE (-4) /* raster needs more blocks than the workspace holds */
+#define SMOE_ERR_NONFINITE (-5) /* a kernel row holds NaN or infinity (from smoe_read_status) */
 
 #define SMOE_TILE 16
 
@@ -218,8 +224,10 @@ typedef struct smoe_bins {
   int32_t* pair_slots;     /* [K][16] fit step: the pair slot of each kernel's first 16 blocks
                               (NULL in a render-only workspace) */
   float* tile_loss;        /* [max_tiles] per-block squared error */
-  int32_t* status;         /* [8]: pairs needed P, overflow flag, longest list, spare,
-                              then internal counters (kept zero between calls) */
+  int32_t* status;         /* [8]: pairs needed P, overflow flag, longest list, non-finite
+                              flag of the last binning, then internal words (the fit step's
+                              counter copy and overflow flags, the non-finite flag; a binning
+                              clears the last one, a fit keeps it from its first step on) */
 } smoe_bins;
 
 /* Bytes of workspace needed for the given shape and limits (host only). */
@@ -287,7 +295,7 @@ smoe_status smoe_render_batched(const smoe_batch* batch, const smoe_bins* bins, 
  * max_tiles = the raster's blocks and the largest pair capacity that fits.  The caller
  * passes the model, the raster and the outputs only: image (device [H][W][C]), denom
  * (device [H][W], may be NULL) and status_out (device int32[4], may be NULL: receives the
- * status words P needed, overflow flag, longest list, spare).  Images are bitwise those of
+ * status words P needed, overflow flag, longest list, non-finite flag).  Images are bitwise those of
  * smoe_bin + smoe_render with the same model and grid.  Returns SMOE_ERR_TOO_LARGE when the
  * per-kernel and per-block arrays alone exceed the static array; a pair overflow is
  * reported through status_out[1] (the image is then zeros), never by a host sync.  Nothing
@@ -390,8 +398,29 @@ smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
  * fit step. */
 smoe_status smoe_fit_segment_losses(const smoe_fit_state* state, float* out, void* stream);
 
+/* Multi-model fusion (Sec. V-C, Eq. (10)-(11)): the estimate at each pixel is the mean of the
+ * predictions of every window model that covers it.  Windows of window x window pixels are
+ * shifted by the displacement d (window % d == 0) along both axes; along an axis of n pixels
+ * window k covers [max(0, (k+1)d - window), min(n, (k+1)d)), so the first window starts
+ * window - d pixels before the image, windows are clipped to it, and every pixel lies in
+ * exactly m = window/d windows per axis (H = m^2 hypotheses; window 16 and d = 16, 8, 4, 2
+ * give H = 1, 4, 16, 64).
+ * window_images (device float) holds every window's render, concatenated in window order --
+ * rows of windows top to bottom, each row left to right -- each window's clipped pixels
+ * row-major with C channels interleaved: m^2 * width * height * C floats in all (the layout
+ * of smoe_render_batched over the windows' rasters in that order).  image (device float
+ * [height][width][C]) receives, per pixel and channel, the binary32 sum of the m^2 covering
+ * windows in (window row, window column) order divided by m^2: one fixed order, no atomics,
+ * bitwise reproducible.  C is 1 or 3; 1 <= width, height <= 65536; 1 <= window <= 1024.
+ * SMOE_ERR_INVALID on a bad argument (nothing launched). */
+smoe_status smoe_fuse_windows(const float* window_images, int32_t C, int32_t width,
+                              int32_t height, int32_t window, int32_t displacement,
+                              float* image, void* stream);
+
 /* Synchronises `stream`, copies the status words (P needed, overflow flag, longest list,
- * spare) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an overflow. */
+ * non-finite flag) into host out4 (may be NULL) and returns SMOE_ERR_CAPACITY after an
+ * overflow, else SMOE_ERR_NONFINITE when the last binning -- or, in a fit workspace, any step
+ * of the fit so far -- met a kernel row with a NaN or infinite parameter. */
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream);
 
 /* Name and description of the HIP error behind this thread's last SMOE_ERR_HIP ("no

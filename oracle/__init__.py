@@ -284,3 +284,40 @@ def fit(raw0, C, order, target, steps, total_steps=None, lr_mu=1e-2, lr_mu_final
                      lr_chol, lr_rho, lr_expert, beta1, beta2, eps, _ptr(hist, ct.c_double),
                      _ptr(out, ct.c_double), threads or default_threads())
     return hist, out
+
+
+def window_rects(H, W, d, window=16):
+    """The windows of the multi-model estimator (Sec. V-C): window-sized squares shifted by d
+    over the image, placed so that every pixel has the same number of windows covering it --
+    window / d along each axis; the first window therefore starts window - d pixels before the
+    image -- and clipped to the image.  [(y0, x0, h, w)], window rows top to bottom, each row
+    left to right.  Each axis is enumerated by brute force: every start that reaches into
+    the image."""
+    assert window % d == 0
+
+    def spans(n):
+        out = []
+        for start in range(-(window - d), n, d):
+            cover = [p for p in range(start, start + window) if 0 <= p < n]
+            out.append((cover[0], len(cover)))
+        return out
+
+    return [(y0, x0, h, w) for (y0, h) in spans(H) for (x0, w) in spans(W)]
+
+
+def fuse_windows(models, C, order, H, W, d, window=16, r=3.0, trunc="gradient", threads=None):
+    """The multi-model estimate of Eq. (10)-(11): at each pixel, the mean of the predictions
+    y_h of the window models h whose window covers it.  models: one model (rows) per window
+    of window_rects(H, W, d, window), in that order, each in its window's own pixel
+    coordinates (the window's top-left pixel at (0, 0)).  Each window model is rendered on
+    its window's raster by render(); the sum and the count run in float64.  Returns y
+    [H, W, C] float64."""
+    rects = window_rects(H, W, d, window)
+    assert len(models) == len(rects), "one model per window"
+    acc = np.zeros((H, W, C), np.float64)
+    cnt = np.zeros((H, W), np.float64)
+    for (y0, x0, h, w), model in zip(rects, models):
+        y, _ = render(model, C, order, w, h, r=r, trunc=trunc, threads=threads)
+        acc[y0:y0 + h, x0:x0 + w] += y
+        cnt[y0:y0 + h, x0:x0 + w] += 1.0
+    return acc / cnt[..., None]

@@ -6,7 +6,7 @@ Importing the package requires the built library: there is no CPU fallback.
 """
 from . import _capi  # noqa: F401  (fails loudly when libsmoe.so is missing)
 from .core import (AdamConfig, Bins, FitState, Segments, bin, bin_batched,  # noqa: F401
-                   make_grid, materialize, num_params, psnr, render, render_backward, render_noalloc,
-                   render_batched, tiles)
+                   fuse_windows, make_grid, materialize, num_params, psnr, render,
+                   render_backward, render_batched, render_noalloc, tiles)
 
 __version__ = "0.1.0"

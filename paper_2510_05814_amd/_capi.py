@@ -23,6 +23,7 @@ SMOE_ERR_INVALID = -1
 SMOE_ERR_CAPACITY = -2
 SMOE_ERR_HIP = -3
 SMOE_ERR_TOO_LARGE = -4
+SMOE_ERR_NONFINITE = -5
 
 SMOE_BOX_SQUARE = 0
 SMOE_BOX_TIGHT = 1
@@ -86,7 +87,8 @@ class SmoeFitState(ct.Structure):
 class SmoeError(RuntimeError):
     def __init__(self, fn: str, code: int):
         names = {SMOE_ERR_INVALID: "SMOE_ERR_INVALID", SMOE_ERR_CAPACITY: "SMOE_ERR_CAPACITY",
-                 SMOE_ERR_HIP: "SMOE_ERR_HIP", SMOE_ERR_TOO_LARGE: "SMOE_ERR_TOO_LARGE"}
+                 SMOE_ERR_HIP: "SMOE_ERR_HIP", SMOE_ERR_TOO_LARGE: "SMOE_ERR_TOO_LARGE",
+                 SMOE_ERR_NONFINITE: "SMOE_ERR_NONFINITE"}
         msg = f"{fn} failed: {names.get(code, code)}"
         if code == SMOE_ERR_HIP:
             try:
@@ -143,6 +145,8 @@ def _load():
     L.smoe_fit_segment_losses.restype = _i32
     L.smoe_render_noalloc.argtypes = [P(SmoeModel), P(SmoeGrid), _vp, _vp, _vp, _vp]
     L.smoe_render_noalloc.restype = _i32
+    L.smoe_fuse_windows.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp]
+    L.smoe_fuse_windows.restype = _i32
     return L
 
 
@@ -154,7 +158,7 @@ EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "sm
             "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status", "smoe_segments_layout",
             "smoe_bin_batched", "smoe_render_batched", "smoe_fit_segment_losses",
             "smoe_render_workspace_bytes", "smoe_render_workspace_layout", "smoe_last_error",
-            "smoe_render_noalloc"]
+            "smoe_render_noalloc", "smoe_fuse_windows"]
 
 
 def _check(fn: str, code: int, allow=()):
@@ -231,10 +235,11 @@ def smoe_pair_stats(model, grid, bins, out2_ptr, stream):
 
 
 def smoe_read_status(bins: SmoeBins, stream):
-    """Returns (code, [P needed, overflow, longest list, spare]); code may be CAPACITY."""
+    """Returns (code, [P needed, overflow, longest list, non-finite flag]); code may be
+    CAPACITY or NONFINITE."""
     out = (_i32 * 4)()
     code = _check("smoe_read_status", lib.smoe_read_status(ct.byref(bins), out, stream),
-                  allow=(SMOE_ERR_CAPACITY,))
+                  allow=(SMOE_ERR_CAPACITY, SMOE_ERR_NONFINITE))
     return code, list(out)
 
 
@@ -264,3 +269,9 @@ def smoe_render_noalloc(model, grid, image_ptr, denom_ptr, status_ptr, stream):
     return _check("smoe_render_noalloc",
                   lib.smoe_render_noalloc(ct.byref(model), ct.byref(grid), image_ptr, denom_ptr,
                                           status_ptr, stream))
+
+
+def smoe_fuse_windows(windows_ptr, C_, width, height, window, displacement, image_ptr, stream):
+    return _check("smoe_fuse_windows",
+                  lib.smoe_fuse_windows(windows_ptr, C_, width, height, window, displacement,
+                                        image_ptr, stream))

@@ -138,7 +138,9 @@ class Bins:
         return self._view(self.c.vals, P, torch.int32)
 
     def read_status(self, stream=None):
-        """Synchronises the stream; returns (overflowed, [P needed, overflow, longest, 0])."""
+        """Synchronises the stream; returns (overflowed, [P needed, overflow, longest,
+        non-finite]): the last word is 1 when a kernel row with a NaN or infinite parameter
+        was met (it then takes part nowhere)."""
         code, st = C.smoe_read_status(self.c, _stream(stream))
         return code == C.SMOE_ERR_CAPACITY, st
 
@@ -301,6 +303,26 @@ def render_batched(params: torch.Tensor, C_: int, order: int, segs: Segments, bi
                         _trunc(trunc))
     C.smoe_render_batched(batch, bins.c, images.data_ptr(), _ptr(denoms), _stream(stream))
     return images
+
+
+def fuse_windows(window_images: torch.Tensor, C_: int, width: int, height: int,
+                 displacement: int, window: int = 16, out: torch.Tensor | None = None,
+                 stream=None) -> torch.Tensor:
+    """smoe_fuse_windows: the mean over the covering windows (Sec. V-C, Eq. (11)) of the
+    window renders [m^2 width height, C] (window order, as smoe_fuse_windows documents)
+    into out [height, width, C]."""
+    m = window // displacement if displacement > 0 else 0
+    if not (window_images.is_cuda and window_images.dtype == torch.float32
+            and window_images.is_contiguous()):
+        raise ValueError("window_images must be a contiguous cuda float32 tensor")
+    if window_images.numel() != m * m * width * height * C_:
+        raise ValueError("window_images must hold (window/displacement)^2 * width * height * C "
+                         "floats")
+    if out is None:
+        out = torch.empty((height, width, C_), dtype=torch.float32, device=window_images.device)
+    C.smoe_fuse_windows(window_images.data_ptr(), C_, width, height, window, displacement,
+                        out.data_ptr(), _stream(stream))
+    return out
 
 
 @dataclass

@@ -17,14 +17,17 @@ namespace smoe {
 namespace {
 
 // One thread per kernel row: output-block and native-block rectangles, count, render
-// record, and (tile_counts not null) one atomic increment per covered block.
+// record, and (tile_counts not null) one atomic increment per covered block.  A row with a
+// NaN or infinite parameter covers no block (it takes part nowhere) and sets the
+// non-finite status word.
 __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
                                                     const float* __restrict__ params, Segs S,
                                                     int4* __restrict__ tile_rects,
                                                     int4* __restrict__ native_rects,
                                                     int32_t* __restrict__ counts,
                                                     float* __restrict__ records, int rs,
-                                                    int32_t* __restrict__ tile_counts) {
+                                                    int32_t* __restrict__ tile_counts,
+                                                    int32_t* __restrict__ status) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= S.K) return;
   const SegGrid sg = seg_of_kernel(S, j);
@@ -37,7 +40,15 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
     l21 = l21 / sg.sharpen;
     l22 = l22 / sg.sharpen;
   }
-  const KernelRects kr = kernel_rects(p[0], p[1], l11, l21, l22, sg, S.r, S.box, S.trunc);
+  bool finite = __builtin_isfinite(l11) && __builtin_isfinite(l21) && __builtin_isfinite(l22);
+  for (int k = 0; k < 6 + ne; ++k) finite = finite && __builtin_isfinite(p[k]);
+  KernelRects kr;
+  if (finite) {
+    kr = kernel_rects(p[0], p[1], l11, l21, l22, sg, S.r, S.box, S.trunc);
+  } else {
+    kr.tile = kr.native = make_int4(0, 0, -1, -1);
+    status[kNonfinite] = 1;
+  }
   const int4 rc = kr.tile;
   tile_rects[j] = rc;
   native_rects[j] = kr.native;
@@ -141,6 +152,13 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// The binning's first kernel: zero the per-block counters and the non-finite flag.
+__global__ void k_fill_counts(int32_t* __restrict__ counts, int n, int32_t* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = 0;
+  if (i == 0) status[kNonfinite] = 0;
+}
+
 __global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
   const int i = threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -152,14 +170,15 @@ inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
 hipError_t launch_count(int C, int order, const float* params, const Segs& S,
                         const smoe_bins& b, hipStream_t s) {
-  // Counters start from zero (a fill kernel rather than a memset node, so that the step
-  // can be captured into a graph).
-  k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
+  // Counters and the non-finite flag start from zero (a fill kernel rather than a memset
+  // node, so that the step can be captured into a graph).
+  k_fill_counts<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, b.status);
   if (S.K > 0) {
     k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects),
                                                  reinterpret_cast<int4*>(b.native_rects), b.counts,
-                                                 b.records, b.record_stride, b.tile_counts);
+                                                 b.records, b.record_stride, b.tile_counts,
+                                                 b.status);
   }
   return hipGetLastError();
 }
@@ -173,14 +192,14 @@ hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s, const i
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
                               const smoe_bins& b, hipStream_t s) {
   k_fill_i32<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, 0);
-  // A fresh fit starts from clear status words (P, overflow, longest list, step shadow and
-  // the overflow flags), whatever the workspace held before.
+  // A fresh fit starts from clear status words (P, overflow, longest list, step shadow, the
+  // overflow flags and the non-finite flag), whatever the workspace held before.
   k_fill_i32<<<1, 64, 0, s>>>(b.status, 8, 0);
   if (S.K > 0) {
     k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects),
                                                  reinterpret_cast<int4*>(b.native_rects), b.counts,
-                                                 b.records, b.record_stride, nullptr);
+                                                 b.records, b.record_stride, nullptr, b.status);
   }
   return hipGetLastError();
 }

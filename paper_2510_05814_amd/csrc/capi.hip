@@ -504,6 +504,18 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* 
   return hip_status(launch_segment_losses(S, st->bins, out, static_cast<hipStream_t>(stream)));
 }
 
+smoe_status smoe_fuse_windows(const float* window_images, int32_t C, int32_t width,
+                              int32_t height, int32_t window, int32_t displacement,
+                              float* image, void* stream) {
+  clear_stale_error();
+  if ((C != 1 && C != 3) || width < 1 || height < 1 || width > 65536 || height > 65536 ||
+      window < 1 || window > 1024 || displacement < 1 || window % displacement != 0 ||
+      !window_images || !image)
+    return SMOE_ERR_INVALID;
+  return hip_status(launch_fuse_windows(window_images, C, width, height, window, displacement,
+                                        image, static_cast<hipStream_t>(stream)));
+}
+
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
                             const smoe_bins* bins, uint64_t* out2, void* stream) {
   clear_stale_error();
@@ -517,13 +529,15 @@ smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
 
 smoe_status smoe_read_status(const smoe_bins* bins, int32_t* out4, void* stream) {
   if (!bins || !bins->status) return SMOE_ERR_INVALID;
-  int32_t h[4] = {0, 0, 0, 0};
+  int32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipStreamSynchronize(s) != hipSuccess) return SMOE_ERR_HIP;
   if (hipMemcpy(h, bins->status, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
     return SMOE_ERR_HIP;
-  if (out4) std::memcpy(out4, h, sizeof(h));
-  return h[1] ? SMOE_ERR_CAPACITY : SMOE_OK;
+  // word 3: the last binning's non-finite flag; word 7: the fit's (sticky) one
+  h[3] = (h[3] || h[7]) ? 1 : 0;
+  if (out4) std::memcpy(out4, h, 4 * sizeof(int32_t));
+  return h[1] ? SMOE_ERR_CAPACITY : (h[3] ? SMOE_ERR_NONFINITE : SMOE_OK);
 }
 
 }  // extern "C"

@@ -10,6 +10,10 @@ namespace smoe {
 // Status word holding the fit step counter as the step began (written by the scan).
 constexpr int kStepShadow = 4;  // status word: completed steps, copied by the step's first kernel
 constexpr int kStepFlags = 5;   // status words 5, 6: the fit step's overflow flag by step parity
+constexpr int kNonfinite = 7;   // status word: a kernel row with a NaN or infinite parameter was
+                                // seen (cleared by each binning's first kernel and at the start
+                                // of a fit; sticky over a fit's steps)
+constexpr int kNonfiniteOut = 3;  // status word: the binning's copy of kNonfinite
 
 // Native 16x16 block index of a native coordinate, floor(x / 16) (x * 2^-4 is exact).
 __device__ __forceinline__ float native_block(float x) { return floorf(x * 0.0625f); }
@@ -277,6 +281,7 @@ __device__ void block_scan_ranges(int T, int32_t* __restrict__ tile_counts,
     status[0] = (int)min(P, (long long)INT32_MAX);
     status[1] = over ? 1 : 0;
     status[2] = longest;
+    status[kNonfiniteOut] = status[kNonfinite];
   }
 }
 

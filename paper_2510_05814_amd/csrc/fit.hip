@@ -229,6 +229,10 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const float mux = __shfl(pm, 0, 16), muy = __shfl(pm, 1, 16), l11 = __shfl(pm, 2, 16);
   const float l21 = __shfl(pm, 3, 16), l22 = __shfl(pm, 4, 16), rho = __shfl(pm, 5, 16);
   const float prev = __shfl_up(pm, 1, 16);  // parameter i - 1
+  // A row with a NaN or infinite parameter covers no block in the next step (it takes part
+  // nowhere) and sets the non-finite status word.
+  const unsigned long long nf = __ballot(i < NP && !__builtin_isfinite(pm));
+  const bool row_nonfinite = ((nf >> (threadIdx.x & 48)) & 0xFFFFull) != 0;
   if (live) {
     if (i < RS) {
       const float i22 = 1.0f / l22;
@@ -247,9 +251,11 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
     if (i == 0) {
       // (nothing in the fit step reads the native rectangles: at scale 1 and origin 0 the
       // output blocks are the native blocks; they are not kept up to date)
-      const KernelRects kr = kernel_rects(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box, f.S.trunc);
-      f.tile_rects_out[j] = kr.tile;
-      f.counts[j] = rect_count(kr.tile);
+      int4 rc = make_int4(0, 0, -1, -1);
+      if (!row_nonfinite) rc = kernel_rects(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box, f.S.trunc).tile;
+      else f.status[kNonfinite] = 1;
+      f.tile_rects_out[j] = rc;
+      f.counts[j] = rect_count(rc);
     }
   }
   // The counter itself is written once; every workgroup read the shadow copy instead.  The

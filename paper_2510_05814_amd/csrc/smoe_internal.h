@@ -196,5 +196,7 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width, i
 hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, float* loss_out,
                            hipStream_t s);
 hipError_t launch_segment_losses(const Segs& S, const smoe_bins& b, float* out, hipStream_t s);
+hipError_t launch_fuse_windows(const float* windows, int C, int width, int height, int window,
+                               int d, float* image, hipStream_t s);
 
 }  // namespace smoe

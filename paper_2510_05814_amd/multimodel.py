@@ -9,14 +9,14 @@ give H = 1, 4, 16, 64 hypotheses per pixel.
 
 All windows are fitted together as one batched fit (each window is a segment of the
 segment table, with its own kernels), one launch sequence per step for all of them; the
-averaging is a scatter-add of the window renders.
+average of Eq. (11) is smoe_fuse_windows, a fixed-order gather over the window renders.
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from .core import AdamConfig, FitState, bin_batched, render_batched
+from .core import AdamConfig, FitState, bin_batched, fuse_windows, render_batched
 
 WINDOW = 16
 
@@ -58,8 +58,7 @@ class MultiModelDenoiser:
     """Fits every window of displacement d to its noisy pixels and fuses the predictions."""
 
     def __init__(self, noisy: np.ndarray, d: int, spacing: int = 8, sigma: float = 4.0,
-                 order: int = 1, adam: AdamConfig | None = None, max_steps: int = 0,
-                 device="cuda"):
+                 order: int = 1, adam: AdamConfig | None = None, max_steps: int = 0):
         noisy = np.ascontiguousarray(noisy, dtype=np.float32)
         self.H, self.W, self.C = noisy.shape
         self.d = d
@@ -74,14 +73,6 @@ class MultiModelDenoiser:
         blocks = sum(((h + 15) // 16) * ((w + 15) // 16) for (_, _, h, w) in self.windows)
         self.state = FitState(tg, rw, order, adam or AdamConfig(), max_steps=max_steps,
                               capacity=blocks * width)
-        # pixel p of the concatenated window images -> its index in the full image
-        idx = []
-        for (y0, x0, h, w) in self.windows:
-            yy, xx = np.mgrid[y0:y0 + h, x0:x0 + w]
-            idx.append((yy * self.W + xx).ravel())
-        self.index = torch.from_numpy(np.concatenate(idx)).to(device)
-        self.count = torch.bincount(self.index, minlength=self.H * self.W).to(torch.float32)
-
     @property
     def hypotheses(self) -> int:
         return (WINDOW // self.d) ** 2
@@ -103,9 +94,6 @@ class MultiModelDenoiser:
         return out
 
     def image(self) -> torch.Tensor:
-        """The fused estimate [H, W, C] (Eq. 10): the mean over the windows covering each pixel
+        """The fused estimate [H, W, C] (Eq. 11): the mean over the windows covering each pixel
         of their current models' predictions."""
-        acc = torch.zeros((self.H * self.W, self.C), dtype=torch.float32,
-                          device=self.index.device)
-        acc.index_add_(0, self.index, self.window_images())
-        return (acc / self.count[:, None]).view(self.H, self.W, self.C)
+        return fuse_windows(self.window_images(), self.C, self.W, self.H, self.d, WINDOW)

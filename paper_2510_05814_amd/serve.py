@@ -131,6 +131,9 @@ class ModelBank:
                  box="square", trunc="gradient", mode="smoe"):
         rows = [m.detach().float().cpu() if torch.is_tensor(m) else
                 torch.as_tensor(np.asarray(m, dtype=np.float32)) for m in models]
+        for i, r in enumerate(rows):
+            if not bool(torch.isfinite(r).all()):
+                raise ValueError(f"model {i} holds NaN or infinite parameters")
         self.C, self.order, self.radius = C_, order, float(radius)
         self.box = _box(box)
         self.trunc = _trunc(trunc)

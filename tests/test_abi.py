@@ -135,6 +135,11 @@ def test_invalid_arguments_rejected_before_launch():
                                     None) == C.SMOE_ERR_INVALID
     assert lib.smoe_materialize(4, 3, 1, None, None, None) == C.SMOE_ERR_INVALID
     assert lib.smoe_fit_step(None, p, None, None) == C.SMOE_ERR_INVALID
+    # window fusion: the displacement must divide the window; sizes and pointers checked
+    for args in [(p, 3, 40, 40, 16, 3, p), (p, 3, 40, 40, 16, 0, p), (p, 2, 40, 40, 16, 4, p),
+                 (p, 3, 0, 40, 16, 4, p), (p, 3, 40, 40, 2048, 4, p), (None, 3, 40, 40, 16, 4, p),
+                 (p, 3, 40, 40, 16, 4, None), (p, 3, 40, 70000, 16, 4, p)]:
+        assert lib.smoe_fuse_windows(*args, None) == C.SMOE_ERR_INVALID, args
 
 
 def test_segments_layout_host_only():

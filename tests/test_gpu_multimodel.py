@@ -39,6 +39,53 @@ def test_fused_image_is_the_mean_of_window_predictions():
     assert torch.isfinite(mm.image()).all()
 
 
+@pytest.mark.parametrize("H,W,d", [(40, 40, 8), (37, 45, 4), (20, 33, 2)])
+def test_fused_image_matches_oracle(H, W, d, record_error):
+    """The GPU's window models, rendered and fused by the FP64 oracle (Eq. (10)-(11)),
+    against the fused image of the HIP path."""
+    import oracle
+    from paper_2510_05814_amd.multimodel import MultiModelDenoiser
+    say("mm fused vs oracle", H, W, d)
+    clean, noisy = wl.config3_images(5, H=H, W=W)
+    mm = MultiModelDenoiser(noisy.astype(np.float32), d, max_steps=5).fit(5, graphed=False)
+    assert mm.windows == oracle.window_rects(H, W, d)
+    model = mm.state.model.cpu().numpy().astype(np.float64)
+    models = [model[sg.kernel_offset:sg.kernel_offset + sg.num_kernels]
+              for sg in mm.state.segments.host]
+    want = oracle.fuse_windows(models, 3, 1, H, W, d)
+    got = mm.image().cpu().numpy()
+    e = float(np.max(np.abs(got - want)))
+    record_error(f"mm fused image vs oracle {H}x{W} d={d}", e, 1e-5)
+    assert e <= 1e-5
+
+
+def test_fusion_is_a_fixed_order_binary32_mean():
+    """smoe_fuse_windows sums the covering windows in (window row, window column) order in
+    binary32 and divides by the hypothesis count: bitwise the same sums done on the host in
+    that order, and bitwise the same on every call."""
+    import torch
+
+    import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd.multimodel import window_layout
+    say("mm fusion fixed order")
+    rng = np.random.default_rng(11)
+    for (H, W, d, C) in [(37, 45, 4, 3), (20, 33, 2, 1), (16, 16, 16, 3), (5, 7, 4, 1)]:
+        m = 16 // d
+        rects = window_layout(H, W, d)
+        wins = [rng.uniform(-1, 1, (h, w, C)).astype(np.float32) for (_, _, h, w) in rects]
+        flat = np.concatenate([x.reshape(-1, C) for x in wins])
+        assert flat.shape[0] == m * m * W * H
+        acc = np.zeros((H, W, C), np.float32)
+        for (y0, x0, h, w), x in zip(rects, wins):
+            acc[y0:y0 + h, x0:x0 + w] += x
+        want = acc / np.float32(m * m)
+        dev = torch.from_numpy(flat).cuda()
+        a = smoe.fuse_windows(dev, C, W, H, d)
+        b = smoe.fuse_windows(dev, C, W, H, d)
+        assert torch.equal(a, b)
+        assert np.array_equal(a.cpu().numpy(), want), (H, W, d, C)
+
+
 def test_each_window_fit_is_its_own_fit():
     """Window fits in the batch equal fitting each window alone, bitwise."""
     import torch

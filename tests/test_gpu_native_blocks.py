@@ -35,9 +35,8 @@ W0, H0 = 61, 47
 
 @pytest.fixture(scope="module")
 def model():
-    # lists stay at most 128 long on every raster here (a straddling output block lists the
-    # kernels of up to four native blocks): longer lists are split over four waves, whose
-    # partial sums add in another (fixed) order
+    # lists stay at most 128 long on every raster here: longer lists are split over four
+    # waves, whose partial sums add in another (fixed) order
     return wl.stretched_model(150, 3, 1, W0, H0, seed=501, size_hi=5.0)
 
 

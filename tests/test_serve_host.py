@@ -110,3 +110,15 @@ def test_window_layout_covers_every_pixel_h_times():
             assert np.all(cover == (16 // d) ** 2), (H, W, d)
     with pytest.raises(ValueError):
         window_layout(16, 16, 3)
+
+
+def test_model_bank_rejects_nonfinite_rows():
+    import numpy as np
+    import pytest as _pt
+
+    from paper_2510_05814_amd.serve import ModelBank
+    m = np.zeros((3, 15), np.float32)
+    m[:, 2] = m[:, 4] = 1.0
+    m[1, 7] = np.nan
+    with _pt.raises(ValueError, match="model 0"):
+        ModelBank([m], 3, 1, device="cpu")
