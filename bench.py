@@ -285,7 +285,8 @@ def run(args):
         "cpu_baseline": None,
     }
     out["bin_render"] = run_bin_render(st, C)
-    out["early_window"] = run_early_window(args, w, P0)
+    if not args.no_early_window:
+        out["early_window"] = run_early_window(args, w, P0)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
         out["cpu_baseline"] = cb
@@ -307,6 +308,8 @@ def run(args):
         out["small_fits"] = run_small_fits(args)
     if not args.no_autograd:
         out["autograd"] = run_autograd(args, w)
+    if not args.no_peaks:
+        out["peaks"] = run_peaks()
     if not args.no_trunc_report:
         out["truncation_error"] = truncation_report(w)
     if args.copy_calibration:
@@ -360,6 +363,51 @@ def run_bin_render(st, C):
         raise RuntimeError("standalone binning overflowed its workspace")
     return {"bin_ms": float(np.median(t_bin)), "render_ms": float(np.median(t_ren)),
             "P": int(stat[0]), "longest_list": int(stat[2]), "iterations": n}
+
+
+def run_peaks():
+    """Measured ceilings beside the published peaks.  The issue-rate probe (smoe_issue_probe):
+    8 waves per SIMD on all 1024 SIMDs, each lane running 8 independent chains of one FP32
+    instruction -- fma on vector registers, fma reading a scalar register, v_exp_f32 -- timed
+    with events on the launch's stream; and a 1 GiB device-to-device copy (HBM read + write)."""
+    import torch
+
+    from paper_2510_05814_amd import _capi
+
+    sh = torch.cuda.current_stream().cuda_stream
+    wg = 1024 * 8 // 4                      # 256-thread workgroups: 4 waves each
+    out = torch.empty(wg * 256, dtype=torch.float32, device="cuda")
+    res = {"waves_per_simd": 8, "chains_per_lane": 8}
+    for kind, name in ((0, "fma_vector"), (1, "fma_scalar_operand"), (2, "exp")):
+        iters = 2048
+        _capi.smoe_issue_probe(kind, 64, wg, out.data_ptr(), sh)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _capi.smoe_issue_probe(kind, iters, wg, out.data_ptr(), sh)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        instr = wg * 4 * iters * 8
+        r = {"ms": t * 1e3, "wave_instr_per_simd_cycle_at_2.4GHz": instr / (N_SIMD * CLOCK_HZ * t),
+             "of_published_rate": instr / (N_SIMD * CLOCK_HZ * t) / 0.5}
+        if kind < 2:
+            r["tflops"] = instr * 64 * 2 / t / 1e12
+        res[name] = r
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 5
+    res["hbm_copy_gbps"] = 2 * a.numel() * 4 / t / 1e9
+    res["hbm_copy_of_peak"] = res["hbm_copy_gbps"] * 1e9 / HBM_PEAK
+    del a, b
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_small_fits(args):
@@ -498,7 +546,10 @@ def run_serving(args):
     import numpy as np
     import torch
 
+    import tempfile
+
     import paper_2510_05814_amd as smoe
+    from paper_2510_05814_amd import checkpoint as ck
     from paper_2510_05814_amd.serve import ModelBank, PlainServer, Server
     import workloads as wl
 
@@ -511,8 +562,14 @@ def run_serving(args):
     for _ in range(args.serve_fit_steps):
         st.step()
     st.grow_if_needed()
-    models = [st.model[sg.kernel_offset:sg.kernel_offset + sg.num_kernels]
-              for sg in st.segments.host]
+    # the server loads the fitted models from model files, as a deployment would
+    with tempfile.TemporaryDirectory() as td:
+        paths = []
+        for i, (sg, m) in enumerate(zip(st.segments.host, ms)):
+            paths.append(os.path.join(td, f"model{i}.safetensors"))
+            ck.save_model(paths[-1], st.raw[sg.kernel_offset:sg.kernel_offset + sg.num_kernels],
+                          3, 1, m["side"], m["side"])
+        models, _ = ck.load_models_materialized(paths)
     bank = ModelBank(models, 3, 1)
     del st
     torch.cuda.empty_cache()
@@ -896,7 +953,7 @@ def _rocpd_gaps(db_path, names):
         con.close()
     short = []
     for name, t0, t1 in rows:
-        k = next((n for n in names if n in name), None)
+        k = _kernel_base(name) if _kernel_base(name) in names else None
         short.append((k, t0, t1))
     gaps = {}
     for (a, _, a1), (b, b0, _) in zip(short, short[1:]):
@@ -950,7 +1007,23 @@ N_SIMD = 256 * 4
 CLOCK_HZ = 2.4e9
 
 
-def summarize_profile(prof_dir, cmd):
+def _rocpd_last(db_path, base, n):
+    """Average duration (ns) of the last n dispatches of the kernel whose base name is
+    `base`, in dispatch order, or None."""
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    try:
+        rows = con.execute("select name, start, duration from kernels order by start").fetchall()
+    except sqlite3.Error:
+        return None
+    finally:
+        con.close()
+    d = [dur for name, _, dur in rows if _kernel_base(name) == base][-n:]
+    return sum(d) / len(d) if d else None
+
+
+def summarize_profile(prof_dir, cmd, last=0):
     """Writes profiles/ summaries from rocprofv3 SQLite outputs under prof_dir: trace/
     (--kernel-trace --stats) and, if present, one pmc_*/ directory per --pmc run
     (FETCH_SIZE and WRITE_SIZE runs need the calibration kernel, --copy-calibration)."""
@@ -972,6 +1045,14 @@ def summarize_profile(prof_dir, cmd):
             if len(short) > 60:
                 short = short[:57] + "..."
             lines.append(f"| `{short}` | {calls} | {avg / 1e3:.2f} | {tot / 1e3:.1f} | {pct:.1f} |")
+        if last:
+            lines += ["", f"Average of the last {last} dispatches of each step kernel (the timed "
+                      "steps):", "", "| kernel | avg us |", "|---|---|"]
+            for k in STEP_KERNELS:
+                a = _rocpd_last(dbs[0], k, last)
+                if a is not None:
+                    lines.append(f"| `{k}` | {a / 1e3:.2f} |")
+                    durations[k] = (a * 1e-9, float("inf"))
         gaps = _rocpd_gaps(dbs[0], list(STEP_KERNELS))
         if gaps:
             lines += ["", "Idle time between consecutive step kernels (end of one dispatch to the "
@@ -1105,21 +1186,28 @@ def main():
                     help="skip the comparison of the two truncation readings")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 64^2 and 512^2 fit workloads")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the issue-rate / copy probe")
     ap.add_argument("--no-autograd", action="store_true",
                     help="skip the autograd.Function run")
     ap.add_argument("--autograd-steps", type=int, default=50)
     ap.add_argument("--no-trunc-report", action="store_true",
                     help="skip the truncation-error report (oracle, untruncated vs truncated)")
+    ap.add_argument("--no-early-window", action="store_true",
+                    help="skip the second fit timed from the grid init")
     ap.add_argument("--summarize-profile", metavar="DIR")
+    ap.add_argument("--profile-last", type=int, default=0,
+                    help="also average each step kernel over its last N dispatches of the trace "
+                         "(the timed steps of a run whose timed region ends the program's fit "
+                         "kernels)")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
     if args.headline_only:
         for k in ("no_cpu_baseline", "no_serving", "no_batched_fit", "no_mm", "no_tight",
                   "no_rbf", "no_long", "no_readings", "no_small", "no_trunc_report",
-                  "no_autograd"):
+                  "no_autograd", "no_peaks"):
             setattr(args, k, True)
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.profile_command)
+        summarize_profile(args.summarize_profile, args.profile_command, args.profile_last)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

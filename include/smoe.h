@@ -220,7 +220,8 @@ typedef struct smoe_bins {
   uint32_t* keys;          /* [capacity] block id of each pair, ascending */
   uint32_t* vals;          /* [capacity] kernel id of each pair, ascending within a block */
   uint32_t* vals_alt;      /* [capacity] scratch for very long block lists */
-  float* pair_grads;       /* [capacity][NP] per-(block, kernel) gradient partials */
+  float* pair_grads;       /* [capacity][NP rounded up to a multiple of 4] per-(block,
+                              kernel) gradient partials */
   int32_t* pair_slots;     /* [K][16] fit step: the pair slot of each kernel's first 16 blocks
                               (NULL in a render-only workspace) */
   float* tile_loss;        /* [max_tiles] per-block squared error */
@@ -393,6 +394,16 @@ smoe_status smoe_fit_step_timed(smoe_fit_state* state, const float* target, floa
  * overwritten.  Uses atomics; the counts are exact integers. */
 smoe_status smoe_pair_stats(const smoe_model* model, const smoe_grid* grid,
                             const smoe_bins* bins, uint64_t* out2, void* stream);
+
+/* Diagnostic (not part of the method): the issue-rate probe behind the compute roofline's
+ * peak.  Launches `workgroups` workgroups of 256 threads; each thread runs 8 independent
+ * chains of `iters` iterations of one binary32 instruction -- kind 0: fma with all operands in
+ * vector registers, 1: fma reading a scalar register, 2: v_exp_f32 -- and writes
+ * their sum to out (device float[workgroups * 256]).  The caller times the launch on
+ * `stream`; the kernel issues workgroups * 4 * iters * 8 wave64 instructions of that kind.
+ * 1 <= iters, 1 <= workgroups <= 2^20, kind in 0..2, else SMOE_ERR_INVALID. */
+smoe_status smoe_issue_probe(int32_t kind, int32_t iters, int32_t workgroups, float* out,
+                             void* stream);
 
 /* Reporting: out (device float[max(1, num_segments)]) = each image's MSE at the state's last
  * fit step. */

@@ -147,6 +147,8 @@ def _load():
     L.smoe_render_noalloc.restype = _i32
     L.smoe_fuse_windows.argtypes = [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp]
     L.smoe_fuse_windows.restype = _i32
+    L.smoe_issue_probe.argtypes = [_i32, _i32, _i32, _vp, _vp]
+    L.smoe_issue_probe.restype = _i32
     return L
 
 
@@ -158,7 +160,7 @@ EXPORTED = ["smoe_version", "smoe_bins_workspace_bytes", "smoe_bins_layout", "sm
             "smoe_fit_step_timed", "smoe_pair_stats", "smoe_read_status", "smoe_segments_layout",
             "smoe_bin_batched", "smoe_render_batched", "smoe_fit_segment_losses",
             "smoe_render_workspace_bytes", "smoe_render_workspace_layout", "smoe_last_error",
-            "smoe_render_noalloc", "smoe_fuse_windows"]
+            "smoe_render_noalloc", "smoe_fuse_windows", "smoe_issue_probe"]
 
 
 def _check(fn: str, code: int, allow=()):
@@ -275,3 +277,7 @@ def smoe_fuse_windows(windows_ptr, C_, width, height, window, displacement, imag
     return _check("smoe_fuse_windows",
                   lib.smoe_fuse_windows(windows_ptr, C_, width, height, window, displacement,
                                         image_ptr, stream))
+
+
+def smoe_issue_probe(kind, iters, workgroups, out_ptr, stream):
+    return _check("smoe_issue_probe", lib.smoe_issue_probe(kind, iters, workgroups, out_ptr, stream))

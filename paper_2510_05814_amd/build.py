@@ -22,7 +22,8 @@ INCLUDE = ROOT / "include"
 LIB = PKG / "libsmoe.so"
 BUILD_DIR = ROOT / "_build"
 
-SOURCES = ["binning.hip", "render.hip", "backward.hip", "fit.hip", "fuse.hip", "capi.hip"]
+SOURCES = ["binning.hip", "render.hip", "backward.hip", "fit.hip", "fuse.hip", "probe.hip",
+           "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

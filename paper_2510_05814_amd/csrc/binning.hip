@@ -144,7 +144,8 @@ __global__ __launch_bounds__(64) void k_sort_buckets(const int2* __restrict__ ra
   if (threadIdx.x == 0) cursors[t] = 0;
   if (n <= 0) return;
   for (int i = threadIdx.x; i < n; i += 64) keys[rg.x + i] = (uint32_t)t;
-  sort_bucket(vals + rg.x, vals_alt + rg.x, n, s, kSortRun);
+  if (n <= 64) rank_sort64(vals + rg.x, n, s, nullptr);
+  else sort_bucket(vals + rg.x, vals_alt + rg.x, n, s, kSortRun);
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {

@@ -164,7 +164,8 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   L.keys = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals_alt = o;   o = align_up(o + (size_t)capacity * sizeof(uint32_t));
-  L.pair_grads = o; o = align_up(o + (grads ? (size_t)capacity * np * sizeof(float) : 0));
+  L.pair_grads = o;
+  o = align_up(o + (grads ? (size_t)capacity * partial_stride((int)np) * sizeof(float) : 0));
   L.pair_slots = o; o = align_up(o + (grads ? (size_t)K * kSlots * sizeof(int32_t) : 0));
   L.tile_loss = o;  o = align_up(o + (size_t)max_tiles * sizeof(float));
   L.status = o;     o = align_up(o + 8 * sizeof(int32_t));
@@ -502,6 +503,15 @@ smoe_status smoe_fit_segment_losses(const smoe_fit_state* st, float* out, void* 
   Segs S;
   if (!st || !out || !st->bins.tile_loss || !fit_segs(st, &S)) return SMOE_ERR_INVALID;
   return hip_status(launch_segment_losses(S, st->bins, out, static_cast<hipStream_t>(stream)));
+}
+
+smoe_status smoe_issue_probe(int32_t kind, int32_t iters, int32_t workgroups, float* out,
+                             void* stream) {
+  clear_stale_error();
+  if (kind < 0 || kind > 2 || iters < 1 || workgroups < 1 || workgroups > (1 << 20) || !out)
+    return SMOE_ERR_INVALID;
+  return hip_status(launch_issue_probe(kind, iters, workgroups, out,
+                                       static_cast<hipStream_t>(stream)));
 }
 
 smoe_status smoe_fuse_windows(const float* window_images, int32_t C, int32_t width,

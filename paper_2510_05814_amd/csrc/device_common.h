@@ -151,15 +151,20 @@ __device__ __forceinline__ void write_record(float* __restrict__ rec, const floa
                                              int ne, int rs, float l11, float l21, float l22) {
   const float i11 = 1.0f / l11;
   const float i22 = 1.0f / l22;
-  rec[0] = p[0];
-  rec[1] = p[1];
-  rec[2] = i11;
-  rec[3] = l21;
-  rec[4] = i22;
-  rec[5] = p[5] * kLog2e;
-  rec[6] = l21 * i22;
-  for (int i = 0; i < ne; ++i) rec[kRecExpert + i] = p[6 + i];
-  for (int i = kRecExpert + ne; i < rs; ++i) rec[i] = 0.0f;
+  // stored as float4 (the record is 16-byte aligned, rs a multiple of 4); field 7 + i is
+  // expert float i = p[6 + i], padding zero
+  float4* r4 = reinterpret_cast<float4*>(rec);
+  r4[0] = make_float4(p[0], p[1], i11, l21);
+  r4[1] = make_float4(i22, p[5] * kLog2e, l21 * i22, ne > 0 ? p[6] : 0.0f);
+  for (int q = 2; q < rs / 4; ++q) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int f = 4 * q + k;
+      v[k] = f < kRecExpert + ne ? p[f - 1] : 0.0f;
+    }
+    r4[q] = make_float4(v[0], v[1], v[2], v[3]);
+  }
 }
 
 // Exclusive scan of per-block counts into [begin, end) ranges by one workgroup of NT
@@ -294,6 +299,31 @@ __device__ __forceinline__ void snapshot_step(const int32_t* step, int32_t* stat
 // wave: bitonic sort in LDS for runs of up to `run` ids (lds holds `run` u32), then
 // pairwise merges of sorted runs in global memory through alt[0, n) for longer buckets.
 // Only wave-level barriers are used (the caller's workgroup is this one wave).
+// Sorts a bucket of n <= 64 distinct entries seg[0, n) ascending with one wave: each lane
+// takes one entry, counts the bucket's entries below it (its rank) from broadcast reads of
+// the whole bucket in LDS, and stores it at its rank, into `out` (LDS, kept for the caller)
+// (if not null) and back into seg.  scratch: 64 u32 of LDS.
+__device__ __forceinline__ void rank_sort64(uint32_t* __restrict__ seg, int n,
+                                            uint32_t* __restrict__ scratch,
+                                            uint32_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t e = lane < n ? seg[lane] : 0xFFFFFFFFu;
+  scratch[lane] = e;  // padding above n: no entry is greater
+  __syncthreads();
+  int rank = 0;
+  const uint4* s4 = reinterpret_cast<const uint4*>(scratch);
+  for (int j = 0; j < (n + 3) >> 2; ++j) {
+    const uint4 q = s4[j];
+    rank += (q.x < e ? 1 : 0) + (q.y < e ? 1 : 0) + (q.z < e ? 1 : 0) + (q.w < e ? 1 : 0);
+  }
+  if (lane < n) {
+    if (out) out[rank] = e;
+    seg[rank] = e;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
 __device__ __forceinline__ void sort_bucket(uint32_t* __restrict__ seg, uint32_t* __restrict__ alt,
                                             int n, uint32_t* lds, int run) {
   const int lane = threadIdx.x & 63;

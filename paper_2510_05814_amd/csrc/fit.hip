@@ -41,7 +41,9 @@ struct FitTileArgs {
 template <int C, int ORDER, bool RBF, int TRUNC>
 __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   constexpr int LDS_FLOATS = kChunk * record_stride(C, ORDER);
+  static_assert(LDS_FLOATS >= 64, "the rank sort's scratch lives in the record buffer");
   __shared__ float4 srec[LDS_FLOATS / 4];
+  __shared__ uint32_t s_ent[kChunk];  // the entries of the chunk being staged
   const int tile = xcd_block(blockIdx.x, a.S.T);
   const int t0 = a.status[kStepShadow];
   // The bucket's fill count; the cursor is then reset for the next step's scatter (the store
@@ -65,16 +67,21 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   // divided by W H C, so that the sum over all blocks is the sum of the rasters' MSEs.
   const float inv_n2 = 2.0f / ((float)sg.W * (float)sg.H * (float)C);
   const float inv_n = 1.0f / ((float)sg.W * (float)sg.H * (float)C);
-  // Order the bucket (the scatter appended in arbitrary order).
+  // Order the bucket (the scatter appended in arbitrary order).  A bucket of one chunk is
+  // ranked in registers and kept in LDS for the forward's staging.
   constexpr int run = LDS_FLOATS >= 1024 ? 1024 : (LDS_FLOATS >= 512 ? 512 : 256);
-  sort_bucket(a.vals + rg.x, a.vals_alt + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec),
-              run);
+  if (rg.y - rg.x <= kChunk) {
+    rank_sort64(a.vals + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec), s_ent);
+  } else {
+    sort_bucket(a.vals + rg.x, a.vals_alt + rg.x, rg.y - rg.x, reinterpret_cast<uint32_t*>(srec),
+                run);
+  }
 
   const PixelCoords px = lane_pixels(sg, tile - sg.tile_offset);
   float D[kRows], N[kRows][C];
   uint64_t live = 0;
   forward_accumulate<C, ORDER, TRUNC>(px, a.S.r2, a.S.cut_scale, a.S.cut_offset, a.records,
-                                      a.vals, a.shift, rg, srec, D, N, live);
+                                      a.vals, a.shift, rg, srec, D, N, live, s_ent);
 
   PixelSeed<C> sd;
   float err = 0.0f;
@@ -155,8 +162,28 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   __shared__ float s_sc[3];
   __shared__ float s_red[kAdamThreads / 64];
   const smoe_adam_config& ad = f.step.adam;
-  const int t0_ = f.status[kStepShadow];  // completed steps, copied by this step's scatter
-  const bool skip = f.status[kStepFlags + (t0_ & 1)] != 0;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gid >> 4, i = gid & 15;
+  const bool live = j < f.S.K;
+  const size_t e = (size_t)j * NP + i;
+  // Every load that depends on no other is issued before the first wait: the status words
+  // (the completed steps, copied by this step's scatter, and both overflow flags), the
+  // kernel's block rectangle, the bucket slot of its block i, and Adam's state.
+  const int t0_ = f.status[kStepShadow];
+  const int flag0 = f.status[kStepFlags], flag1 = f.status[kStepFlags + 1];
+  int4 rc = make_int4(0, 0, -1, -1);
+  int slot0 = 0;
+  float m0 = 0.0f, v0 = 0.0f, raw0 = 0.0f;
+  if (live) {
+    rc = f.tile_rects_in[j];
+    slot0 = f.slots[(size_t)j * kSlots + i];  // read only for blocks the kernel covers
+    if (i < NP) {
+      m0 = f.m[e];
+      v0 = f.v[e];
+      raw0 = f.raw[e];
+    }
+  }
+  const bool skip = ((t0_ & 1) ? flag1 : flag0) != 0;
   if (threadIdx.x == 0) {
     const int t0 = t0_;
     float lr_mu = ad.lr_mu;
@@ -199,20 +226,13 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
     }
   }
 
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = gid >> 4, i = gid & 15;
-  const bool live = j < f.S.K;
   const SegGrid sg = seg_of_kernel(f.S, live ? j : 0);
   float pm = 0.0f;  // materialized value of parameter i after the step
-  if (live && skip && i < NP) pm = f.model[(size_t)j * NP + i];
-  // Adam's state is loaded before the gather, so that these loads overlap its chain of
-  // dependent loads instead of following it.
-  const size_t e = (size_t)j * NP + i;
+  if (live && skip && i < NP) pm = f.model[e];
   const bool upd = live && !skip && i < NP;
-  const float m0 = upd ? f.m[e] : 0.0f, v0 = upd ? f.v[e] : 0.0f, raw0 = upd ? f.raw[e] : 0.0f;
   // every lane takes part in the gather's row reduction
-  const float gi = gather_param<NP>(j, live && !skip, sg, f.tile_rects_in, f.ranges, f.vals,
-                                    f.pair_grads, f.slots, f.shift);
+  const float gi = gather_param_slotted<NP>(j, live && !skip, sg, rc, slot0, f.ranges, f.vals,
+                                            f.pair_grads, f.shift);
   if (upd) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;

@@ -16,6 +16,9 @@ constexpr float kLog2e = 1.44269504088896340736f;
 // Expert coefficients per kernel: a[C] (+ wx[C], wy[C] for linear experts).
 __host__ __device__ constexpr int expert_floats(int C, int order) { return C * (1 + 2 * order); }
 __host__ __device__ constexpr int num_params(int C, int order) { return 6 + expert_floats(C, order); }
+// Floats per per-(block, kernel) gradient partial row: NP rounded up to a multiple of 4, so
+// that every row starts on 16 bytes and moves as float4.
+__host__ __device__ constexpr int partial_stride(int np) { return (np + 3) & ~3; }
 
 // Render record of one kernel, written by the binning pass and staged in LDS by the render
 // and backward passes.  Everything a (pixel, kernel) evaluation needs, precomputed once:
@@ -196,6 +199,7 @@ hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width, i
 hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, float* loss_out,
                            hipStream_t s);
 hipError_t launch_segment_losses(const Segs& S, const smoe_bins& b, float* out, hipStream_t s);
+hipError_t launch_issue_probe(int kind, int iters, int workgroups, float* out, hipStream_t s);
 hipError_t launch_fuse_windows(const float* windows, int C, int width, int height, int window,
                                int d, float* image, hipStream_t s);
 

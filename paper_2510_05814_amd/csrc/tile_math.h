@@ -90,6 +90,28 @@ __device__ __forceinline__ void stage_records(float4* __restrict__ srec,
   __syncthreads();
 }
 
+// The same with the entries in LDS: ent[k] is entry base + k, copied there from vals first
+// unless `ready` (the caller's sort left the list there).
+template <int RS>
+__device__ __forceinline__ void stage_records_lds(float4* __restrict__ srec,
+                                                  const float* __restrict__ records,
+                                                  const uint32_t* __restrict__ vals, int base,
+                                                  int n, int shift, uint32_t* __restrict__ ent,
+                                                  bool ready) {
+  constexpr int Q = RS / 4;
+  __syncthreads();
+  if (!ready) {
+    const int lane = threadIdx.x & 63;
+    if (lane < n) ent[lane] = vals[base + lane];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x & 63; i < n * Q; i += kWave) {
+    const int k = i / Q, c = i - k * Q;
+    srec[i] = reinterpret_cast<const float4*>(records + (size_t)(ent[k] >> shift) * RS)[c];
+  }
+  __syncthreads();
+}
+
 // One list entry of the forward: adds its terms to D = sum pi K and N_c = sum pi K m_c of
 // the lane's four pixels that the render's rule keeps.  TRUNC == SMOE_TRUNC_RENDER: the
 // ellipse q <= r^2.  TRUNC == SMOE_TRUNC_GRADIENT (the block lists decide the render): every
@@ -173,14 +195,17 @@ __device__ __forceinline__ void zero_sums(float (&D)[kRows], float (&N)[kRows][C
 // entry, records staged through LDS in chunks).
 // live: bit k set if any pixel of the block passed the ellipse test q <= r2 for entry k of
 // the last staged chunk (the only chunk for lists of up to kChunk entries).
-// shift: list entries hold the kernel id << shift.
+// shift: list entries hold the kernel id << shift.  ent: null, or LDS room for one chunk of
+// entries, which the staging then reads from there (a single-chunk list already holds them,
+// sorted; longer lists copy each chunk's entries in).
 template <int C, int ORDER, int TRUNC>
 __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float r2,
                                                    float cut_scale, float cut_offset,
                                                    const float* __restrict__ records,
                                                    const uint32_t* __restrict__ vals, int shift,
                                                    int2 rg, float4* srec, float (&D)[kRows],
-                                                   float (&N)[kRows][C], uint64_t& live) {
+                                                   float (&N)[kRows][C], uint64_t& live,
+                                                   uint32_t* ent = nullptr) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   zero_sums<C>(D, N);
@@ -188,7 +213,8 @@ __device__ __forceinline__ void forward_accumulate(const PixelCoords& px, float 
   cut_offset = in_vgpr(cut_offset);
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
-    stage_records<RS>(srec, records, vals, base, n, shift);
+    if (ent) stage_records_lds<RS>(srec, records, vals, base, n, shift, ent, rg.y - rg.x <= kChunk);
+    else stage_records<RS>(srec, records, vals, base, n, shift);
     live = 0;
     for (int k = 0; k < n; ++k) {
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
@@ -275,23 +301,47 @@ __device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
   return keep + dpp<0xB1>(send);
 }
 
+// Adds the partial row at slot p (NP values of a row of partial_stride(NP) floats) to v.
+template <int NP>
+__device__ __forceinline__ void add_partial_row(float (&v)[16], const float* __restrict__ pair_grads,
+                                                int p) {
+  constexpr int PS = partial_stride(NP);
+  const float4* row = reinterpret_cast<const float4*>(pair_grads + (size_t)p * PS);
+#pragma unroll
+  for (int q4 = 0; q4 < PS / 4; ++q4) {
+    const float4 x = row[q4];
+    if (4 * q4 + 0 < NP) v[4 * q4 + 0] += x.x;
+    if (4 * q4 + 1 < NP) v[4 * q4 + 1] += x.y;
+    if (4 * q4 + 2 < NP) v[4 * q4 + 2] += x.z;
+    if (4 * q4 + 3 < NP) v[4 * q4 + 3] += x.w;
+  }
+}
+
+// The slot of kernel j's partial row in block t = (ty, tx) of its rectangle: a binary search
+// for j in the block's sorted list (its position, or -- packed fit-step entries, shift > 0 --
+// the slot held in the entry's low bits); -1 if the list does not hold j.
+__device__ __forceinline__ int search_slot(int j, int t, const int2* __restrict__ ranges,
+                                           const uint32_t* __restrict__ vals, int shift) {
+  const int2 rg = ranges[t];
+  if (rg.y <= rg.x) return -1;
+  int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j, shift);
+  if (p < 0) return -1;
+  if (shift) p = rg.x + (int)(vals[p] & ((1u << shift) - 1u));
+  return p;
+}
+
 // Gradient of kernel row j: the sum of its per-block partial rows over its block rectangle.
 // A group of 16 lanes (one 16-lane row of the wave) serves one kernel: lane b adds the partial
 // rows of blocks b, b + 16, ... of the rectangle (row-major); the row reduction then leaves
 // parameter i's gradient in lane i.  The summation order is fixed, so the result is
-// reproducible.  A partial row is found through `slots` (the fit step: the bucket slot each
-// of the kernel's first kSlots blocks got in the scatter, the row's index) or else by a binary
-// search for j in the block's sorted list (its position, or -- packed fit-step entries,
-// shift > 0 -- the slot held in the entry's low bits).  All 16 lanes must call it (live =
+// reproducible.  A partial row is found by search_slot.  All 16 lanes must call it (live =
 // false: the kernel contributes nothing).
 template <int NP>
 __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& sg,
                                               const int4* __restrict__ rects,
                                               const int2* __restrict__ ranges,
                                               const uint32_t* __restrict__ vals,
-                                              const float* __restrict__ pair_grads,
-                                              const int32_t* __restrict__ slots = nullptr,
-                                              int shift = 0) {
+                                              const float* __restrict__ pair_grads) {
   static_assert(NP <= 16, "16 lanes per kernel");
   float v[16];
 #pragma unroll
@@ -301,20 +351,40 @@ __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& s
     const int n = rect_count(rc);
     const int w = rc.z - rc.x + 1;
     for (int b = threadIdx.x & 15; b < n; b += 16) {
-      int p;
-      if (slots && b < kSlots) {
-        p = slots[(size_t)j * kSlots + b];
-      } else {
-        const int dy = b / w;
-        const int2 rg = ranges[sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w)];
-        if (rg.y <= rg.x) continue;
-        p = find_in_list(vals, rg.x, rg.y, (uint32_t)j, shift);
-        if (p < 0) continue;
-        if (shift) p = rg.x + (int)(vals[p] & ((1u << shift) - 1u));
-      }
-      const float* row = pair_grads + (size_t)p * NP;
+      const int dy = b / w;
+      const int p = search_slot(j, sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w),
+                                ranges, vals, 0);
+      if (p >= 0) add_partial_row<NP>(v, pair_grads, p);
+    }
+  }
+  return row_reduce16_transposed(v);
+}
+
+// The fit step's gather, in the same order, with the kernel's rectangle rc and the slot of
+// block (lane & 15) of it (slot0, recorded by the scatter for the kernel's first kSlots
+// blocks) already loaded by the caller; blocks beyond the first kSlots are searched.
+template <int NP>
+__device__ __forceinline__ float gather_param_slotted(int j, bool live, const SegGrid& sg,
+                                                      int4 rc, int slot0,
+                                                      const int2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const float* __restrict__ pair_grads,
+                                                      int shift) {
+  static_assert(NP <= 16, "16 lanes per kernel");
+  float v[16];
 #pragma unroll
-      for (int q = 0; q < NP; ++q) v[q] += row[q];
+  for (int q = 0; q < 16; ++q) v[q] = 0.0f;
+  if (live) {
+    const int n = rect_count(rc);
+    const int w = rc.z - rc.x + 1;
+    for (int b = threadIdx.x & 15; b < n; b += 16) {
+      int p = slot0;
+      if (b >= kSlots) {
+        const int dy = b / w;
+        p = search_slot(j, sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w), ranges,
+                        vals, shift);
+      }
+      if (p >= 0) add_partial_row<NP>(v, pair_grads, p);
     }
   }
   return row_reduce16_transposed(v);
@@ -360,7 +430,8 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   constexpr int NP = num_params(C, ORDER);
-  static_assert(NP <= 16, "16 accumulators per kernel");
+  constexpr int PS = partial_stride(NP);
+  static_assert(PS <= 16, "16 accumulators per kernel");
   const int lane = threadIdx.x & 63;
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
@@ -376,7 +447,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
       if (reuse && !((live >> k) & 1ull)) {
         // no pixel of the block passed the forward's test: the partial row is zero
         const int idx = lane >> 2;
-        if ((lane & 3) == 0 && idx < NP) pair_grads[out_row(k) * NP + idx] = 0.0f;
+        if ((lane & 3) == 0 && idx < PS) pair_grads[out_row(k) * PS + idx] = 0.0f;
         continue;
       }
       const float* r = reinterpret_cast<const float*>(&srec[k * Q]);
@@ -448,7 +519,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
       for (int i = 6 + C * (1 + 2 * ORDER); i < 16; ++i) acc[i] = 0.0f;
       const float tot = wave_reduce16_transposed(acc);
       const int idx = lane >> 2;
-      if ((lane & 3) == 0 && idx < NP) pair_grads[out_row(k) * NP + idx] = tot;
+      if ((lane & 3) == 0 && idx < PS) pair_grads[out_row(k) * PS + idx] = tot;
     }
   }
 }

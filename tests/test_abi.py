@@ -74,6 +74,8 @@ def test_workspace_layout_host_only():
     assert all(p % 256 == 0 for p in ptrs)
     assert ptrs == sorted(ptrs) and ptrs[-1] + 16 <= base + n
     assert b.record_stride == 16 and b.capacity == 1000 and b.max_tiles == 64
+    # partial rows of NP = 15 floats are padded to 16 (float4-aligned rows)
+    assert b.pair_slots - b.pair_grads >= 1000 * 16 * 4
     with pytest.raises(C.SmoeError):
         C.smoe_bins_layout(b, base, n - 1, 100, 3, 1, 64, 1000)
     with pytest.raises(C.SmoeError):
@@ -140,6 +142,10 @@ def test_invalid_arguments_rejected_before_launch():
                  (p, 3, 0, 40, 16, 4, p), (p, 3, 40, 40, 2048, 4, p), (None, 3, 40, 40, 16, 4, p),
                  (p, 3, 40, 40, 16, 4, None), (p, 3, 40, 70000, 16, 4, p)]:
         assert lib.smoe_fuse_windows(*args, None) == C.SMOE_ERR_INVALID, args
+    # the issue-rate probe
+    for args in [(3, 16, 8, p), (-1, 16, 8, p), (0, 0, 8, p), (0, 16, 0, p), (0, 16, 8, None),
+                 (0, 16, (1 << 20) + 1, p)]:
+        assert lib.smoe_issue_probe(*args, None) == C.SMOE_ERR_INVALID, args
 
 
 def test_segments_layout_host_only():
