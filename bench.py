@@ -144,6 +144,9 @@ def cpu_baseline(target, raw0, budget_s=20.0):
 
 # ----------------------------------------------------------------------------- main bench
 
+_T0 = time.perf_counter()
+
+
 def run(args):
     import numpy as np
     import torch
@@ -284,34 +287,48 @@ def run(args):
         "psnr_vs_clean_db": psnr_clean,
         "cpu_baseline": None,
     }
+    _progress(f"headline {out['value']:.1f} it/s")
     out["bin_render"] = run_bin_render(st, C)
     if not args.no_early_window:
         out["early_window"] = run_early_window(args, w, P0)
+        _progress("early_window")
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w.target, w.raw0, budget_s=args.cpu_budget)
         out["cpu_baseline"] = cb
+        _progress("cpu_baseline")
     if not args.no_serving:
         out["serving"] = run_serving(args)
+        _progress("serving")
     if not args.no_batched_fit:
         out["batched_fit"] = run_batched_fit(args)
+        _progress("batched_fit")
     if not args.no_mm:
         out["mm_denoise"] = run_mm_denoise(args)
+        _progress("mm_denoise")
     if not args.no_tight:
         out["tight_box"] = run_tight_box(args)
+        _progress("tight_box")
     if not args.no_rbf:
         out["rbf_vs_smoe"] = run_rbf_vs_smoe(args)
+        _progress("rbf_vs_smoe")
     if not args.no_long:
         out["long_lists"] = run_long_lists(args)
+        _progress("long_lists")
     if not args.no_readings:
         out["truncation_readings"] = run_truncation_readings(args)
+        _progress("truncation_readings")
     if not args.no_small:
         out["small_fits"] = run_small_fits(args)
+        _progress("small_fits")
     if not args.no_autograd:
         out["autograd"] = run_autograd(args, w)
+        _progress("autograd")
     if not args.no_peaks:
         out["peaks"] = run_peaks()
+        _progress("peaks")
     if not args.no_trunc_report:
         out["truncation_error"] = truncation_report(w)
+        _progress("truncation_error")
     if args.copy_calibration:
         # One-dispatch streaming kernel of known size (reads and writes CALIB_BYTES each),
         # for scaling the FETCH_SIZE / WRITE_SIZE counters.  Sized above the 256 MB MALL.
@@ -322,6 +339,11 @@ def run(args):
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = CALIB_BYTES
     print(json.dumps(out), flush=True)
+
+
+def _progress(what):
+    """One line on stderr per finished section (the JSON result goes to stdout)."""
+    print(f"[bench] {what} done at {time.perf_counter() - _T0:.0f} s", file=sys.stderr, flush=True)
 
 
 def run_bin_render(st, C):
