@@ -136,10 +136,19 @@ def cpu_baseline(target, raw0, budget_s=20.0):
         rows = int(min(H, max(rows + 8, rows * 0.9 * budget_s / max(dt, 1e-3))))
         rows -= rows % 8
     full_s = dt * H / rows
-    return {"value": 1.0 / full_s, "unit": "iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 loss+gradient over rows 0..{rows - 1} ({W}x{rows} px) with all "
-                      f"{raw0.shape[0]} kernels, {dt:.1f} s, scaled by {H}/{rows} rows",
-            "seconds_per_iter": full_s}
+    out = {"value": 1.0 / full_s, "unit": "iters/s", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 loss+gradient over rows 0..{rows - 1} ({W}x{rows} px) with all "
+                     f"{raw0.shape[0]} kernels, {dt:.1f} s, scaled by {H}/{rows} rows",
+           "seconds_per_iter": full_s}
+    # the small fit workload, whole: 64^2 grey, K = 64 constant experts, 100 Adam steps at 1e-2
+    import workloads as wl
+    w1 = wl.workload(1)
+    t0 = time.perf_counter()
+    hist, _ = oracle.fit(w1.raw0.astype(np.float64), 1, 0, w1.target, 100, threads=threads)
+    dt1 = time.perf_counter() - t0
+    out["fit_64x64_K64_100_steps"] = {"seconds": dt1, "iters_per_s": 100.0 / dt1,
+                                      "final_loss": float(hist[-1])}
+    return out
 
 
 # ----------------------------------------------------------------------------- main bench

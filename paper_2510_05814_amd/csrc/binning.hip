@@ -16,11 +16,14 @@
 namespace smoe {
 namespace {
 
-// One thread per kernel row: output-block and native-block rectangles, count, render
-// record, and (tile_counts not null) one atomic increment per covered block.  A row with a
-// NaN or infinite parameter covers no block (it takes part nowhere) and sets the
-// non-finite status word.
-__global__ __launch_bounds__(128) void k_preprocess(int C, int order,
+// Four lanes per kernel row (so that a wave covers 16 kernels and a launch has four times the
+// waves to hide its loads): every lane of the quad reads the row and computes the
+// output-block and native-block rectangles; lane 0 writes them and the count, lane q the
+// q-th float4 of the render record, and (tile_counts not null) lane q adds one to the counts
+// of the kernel's covered blocks q, q + 4, ... (row-major).  A row with a NaN or infinite
+// parameter covers no block (it takes part nowhere) and sets the non-finite status word.
+constexpr int kPreLanes = 4;
+__global__ __launch_bounds__(256) void k_preprocess(int C, int order,
                                                     const float* __restrict__ params, Segs S,
                                                     int4* __restrict__ tile_rects,
                                                     int4* __restrict__ native_rects,
@@ -28,7 +31,8 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
                                                     float* __restrict__ records, int rs,
                                                     int32_t* __restrict__ tile_counts,
                                                     int32_t* __restrict__ status) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = gid / kPreLanes, lq = gid % kPreLanes;
   if (j >= S.K) return;
   const SegGrid sg = seg_of_kernel(S, j);
   const int ne = expert_floats(C, order);
@@ -47,14 +51,16 @@ __global__ __launch_bounds__(128) void k_preprocess(int C, int order,
     kr = kernel_rects(p[0], p[1], l11, l21, l22, sg, S.r, S.box, S.trunc);
   } else {
     kr.tile = kr.native = make_int4(0, 0, -1, -1);
-    status[kNonfinite] = 1;
   }
   const int4 rc = kr.tile;
-  tile_rects[j] = rc;
-  native_rects[j] = kr.native;
-  counts[j] = rect_count(rc);
-  write_record(records + (size_t)j * rs, p, ne, rs, l11, l21, l22);
-  if (tile_counts) count_blocks(rc, sg, tile_counts);
+  if (lq == 0) {
+    tile_rects[j] = rc;
+    native_rects[j] = kr.native;
+    counts[j] = rect_count(rc);
+    if (!finite) status[kNonfinite] = 1;
+  }
+  if (lq < rs / 4) write_record_quad(records + (size_t)j * rs, p, ne, lq, l11, l21, l22);
+  if (tile_counts) count_blocks(rc, sg, tile_counts, lq, kPreLanes);
 }
 
 constexpr int kScanThreads = 1024;
@@ -175,7 +181,7 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
   // node, so that the step can be captured into a graph).
   k_fill_counts<<<cdiv(S.T, 256), 256, 0, s>>>(b.tile_counts, S.T, b.status);
   if (S.K > 0) {
-    k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
+    k_preprocess<<<cdiv((long long)S.K * kPreLanes, 256), 256, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects),
                                                  reinterpret_cast<int4*>(b.native_rects), b.counts,
                                                  b.records, b.record_stride, b.tile_counts,
@@ -197,7 +203,7 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
   // overflow flags and the non-finite flag), whatever the workspace held before.
   k_fill_i32<<<1, 64, 0, s>>>(b.status, 8, 0);
   if (S.K > 0) {
-    k_preprocess<<<cdiv(S.K, 128), 128, 0, s>>>(C, order, params, S,
+    k_preprocess<<<cdiv((long long)S.K * kPreLanes, 256), 256, 0, s>>>(C, order, params, S,
                                                  reinterpret_cast<int4*>(b.tile_rects),
                                                  reinterpret_cast<int4*>(b.native_rects), b.counts,
                                                  b.records, b.record_stride, nullptr, b.status);

@@ -137,33 +137,35 @@ __device__ __forceinline__ int rect_count(int4 rc) {
 
 // One increment per covered block (global block ids): the histogram of the block-id digit.
 __device__ __forceinline__ void count_blocks(int4 rc, const SegGrid& g,
-                                             int32_t* __restrict__ tile_counts) {
-  for (int ty = rc.y; ty <= rc.w; ++ty)
-    for (int tx = rc.x; tx <= rc.z; ++tx)
-      atomicAdd(&tile_counts[g.tile_offset + ty * g.ntx + tx], 1);
+                                             int32_t* __restrict__ tile_counts, int first = 0,
+                                             int stride = 1) {
+  const int n = rect_count(rc), w = rc.z - rc.x + 1;
+  for (int q = first; q < n; q += stride)
+    atomicAdd(&tile_counts[g.tile_offset + (rc.y + q / w) * g.ntx + rc.x + q % w], 1);
 }
 
-// Render record of kernel row j from its materialized parameter row p (layout in
-// smoe_internal.h).
+// Float4 number `quad` of the render record of a kernel row from its materialized parameter
+// row p (layout in smoe_internal.h; the record is 16-byte aligned): field f holds, beyond the
+// seven geometry fields, expert float f - 7 = p[f - 1], and zero padding after the experts.
 // (l11, l21, l22): the Cholesky factor the record is built for (the row's own, or divided by
 // a sharpening factor).
-__device__ __forceinline__ void write_record(float* __restrict__ rec, const float* __restrict__ p,
-                                             int ne, int rs, float l11, float l21, float l22) {
-  const float i11 = 1.0f / l11;
-  const float i22 = 1.0f / l22;
-  // stored as float4 (the record is 16-byte aligned, rs a multiple of 4); field 7 + i is
-  // expert float i = p[6 + i], padding zero
+__device__ __forceinline__ void write_record_quad(float* __restrict__ rec,
+                                                  const float* __restrict__ p, int ne, int quad,
+                                                  float l11, float l21, float l22) {
   float4* r4 = reinterpret_cast<float4*>(rec);
-  r4[0] = make_float4(p[0], p[1], i11, l21);
-  r4[1] = make_float4(i22, p[5] * kLog2e, l21 * i22, ne > 0 ? p[6] : 0.0f);
-  for (int q = 2; q < rs / 4; ++q) {
+  if (quad == 0) {
+    r4[0] = make_float4(p[0], p[1], 1.0f / l11, l21);
+  } else if (quad == 1) {
+    const float i22 = 1.0f / l22;
+    r4[1] = make_float4(i22, p[5] * kLog2e, l21 * i22, ne > 0 ? p[6] : 0.0f);
+  } else {
     float v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int f = 4 * q + k;
+      const int f = 4 * quad + k;
       v[k] = f < kRecExpert + ne ? p[f - 1] : 0.0f;
     }
-    r4[q] = make_float4(v[0], v[1], v[2], v[3]);
+    r4[quad] = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
