@@ -174,12 +174,14 @@ def run(args):
     b0 = smoe.bin(smoe.materialize(raw0, C, 1), C, 1, smoe.make_grid(W, H))
     P0 = b0.read_status()[1][0]
     del b0
-    # generous pair capacity (HBM is plentiful): an overflowed step would be a no-op
+    # The fit state's own bucket width: twice the initial longest list, at least 64 (the
+    # lists of this fit stay below 50 entries, so every block's list is one chunk and the
+    # single-chunk fit kernel runs; an overflowed step would be a no-op and is checked below).
     # The timed steps need only the loss, the gradient and the update: the render is not
     # stored (write_render off); the PSNR below comes from a render of the model afterwards.
     st = smoe.FitState(target, raw0, 1, adam,
                        max_steps=args.prefit + args.warmup + args.steps + 16,
-                       capacity=8 * P0 + 65536, write_render=False)
+                       write_render=False)
     ev = HipEvents()
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
@@ -548,8 +550,7 @@ def run_early_window(args, w, P0):
 
     target = torch.from_numpy(w.target).cuda()
     st = smoe.FitState(target, torch.from_numpy(w.raw0).cuda(), 1,
-                       smoe.AdamConfig(total_steps=10000), max_steps=256,
-                       capacity=8 * P0 + 65536, write_render=False)
+                       smoe.AdamConfig(total_steps=10000), max_steps=256, write_render=False)
     for _ in range(20):
         st.step()
     st.grow_if_needed()

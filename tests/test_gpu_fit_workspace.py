@@ -57,3 +57,30 @@ def test_steps_without_render_output_are_bitwise_the_same():
     b.step()
     torch.cuda.synchronize()
     assert torch.equal(a.image, b.image) and torch.equal(a.denom, b.denom)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_bucket_width_does_not_change_the_fit(n):
+    """The fit step's bucket width (pair capacity / blocks) moves where entries and partial
+    rows are stored, never the sorted lists or any summation order: fits with 64- and
+    96-entry buckets are bitwise the same."""
+    import paper_2510_05814_amd as smoe
+
+    w = wl.workload(n)
+    H, W, _ = w.target.shape
+    target = torch.from_numpy(w.target).cuda()
+    raw0 = torch.from_numpy(w.raw0).cuda()
+    adam = smoe.AdamConfig(total_steps=1000)
+    T = smoe.tiles(W, H)
+    print(f"[case] bucket widths 64 and 96, workload {n}", flush=True)
+    a = smoe.FitState(target, raw0, w.order, adam, max_steps=8, capacity=T * 64)
+    b = smoe.FitState(target, raw0, w.order, adam, max_steps=8, capacity=T * 96)
+    for _ in range(8):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert not a.bins.read_status()[0] and not b.bins.read_status()[0]
+    assert torch.equal(a.raw, b.raw) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+    assert torch.equal(a.grads, b.grads)
+    assert torch.equal(a.losses(), b.losses())
+    assert torch.equal(a.image, b.image)

@@ -326,7 +326,7 @@ def test_backward_full_size_sampled_kernels(smoe, record_error):
 
 def test_fit_step_full_size_after_graphed_steps(smoe, record_error):
     """The fused fit step in the configuration the benchmark times (2048^2 RGB, K = 65536,
-    pair capacity 8 P0 + 65536, steps replayed from HIP graphs): after 40 steps, one more
+    the fit state's own bucket width, steps replayed from HIP graphs): after 40 steps, one more
     step's render (of the model it starts from) at every pixel and its gradient of 24
     sampled kernels against the oracle on that model."""
     import torch
@@ -337,8 +337,9 @@ def test_fit_step_full_size_after_graphed_steps(smoe, record_error):
     raw0 = dev(w.raw0)
     b0 = smoe.bin(smoe.materialize(raw0, C, 1), C, 1, smoe.make_grid(W, H))
     P0 = b0.read_status()[1][0]
-    st = smoe.FitState(target, raw0, 1, smoe.AdamConfig(total_steps=10000), max_steps=64,
-                       capacity=8 * P0 + 65536)
+    st = smoe.FitState(target, raw0, 1, smoe.AdamConfig(total_steps=10000), max_steps=64)
+    assert st.bins.capacity == smoe.tiles(W, H) * 64  # one-chunk buckets: the short kernel
+    assert P0 > 0
     st.run_graphed(40)
     model_np = host(st.model).copy()
     st.step()
