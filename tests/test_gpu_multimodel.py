@@ -61,17 +61,19 @@ def test_fused_image_matches_oracle(H, W, d, record_error):
 
 def test_fusion_is_a_fixed_order_binary32_mean():
     """smoe_fuse_windows sums the covering windows in (window row, window column) order in
-    binary32 and divides by the hypothesis count: bitwise the same sums done on the host in
-    that order, and bitwise the same on every call."""
+    binary32 and divides by the hypothesis count (correctly rounded, also for a count that is
+    not a power of two): bitwise the same sums done on the host in that order, and bitwise the
+    same on every call."""
     import torch
 
     import paper_2510_05814_amd as smoe
     from paper_2510_05814_amd.multimodel import window_layout
     say("mm fusion fixed order")
     rng = np.random.default_rng(11)
-    for (H, W, d, C) in [(37, 45, 4, 3), (20, 33, 2, 1), (16, 16, 16, 3), (5, 7, 4, 1)]:
-        m = 16 // d
-        rects = window_layout(H, W, d)
+    for (H, W, d, C, win) in [(37, 45, 4, 3, 16), (20, 33, 2, 1, 16), (16, 16, 16, 3, 16),
+                              (5, 7, 4, 1, 16), (29, 31, 4, 3, 12)]:
+        m = win // d
+        rects = window_layout(H, W, d, win)
         wins = [rng.uniform(-1, 1, (h, w, C)).astype(np.float32) for (_, _, h, w) in rects]
         flat = np.concatenate([x.reshape(-1, C) for x in wins])
         assert flat.shape[0] == m * m * W * H
@@ -80,10 +82,10 @@ def test_fusion_is_a_fixed_order_binary32_mean():
             acc[y0:y0 + h, x0:x0 + w] += x
         want = acc / np.float32(m * m)
         dev = torch.from_numpy(flat).cuda()
-        a = smoe.fuse_windows(dev, C, W, H, d)
-        b = smoe.fuse_windows(dev, C, W, H, d)
+        a = smoe.fuse_windows(dev, C, W, H, d, win)
+        b = smoe.fuse_windows(dev, C, W, H, d, win)
         assert torch.equal(a, b)
-        assert np.array_equal(a.cpu().numpy(), want), (H, W, d, C)
+        assert np.array_equal(a.cpu().numpy(), want), (H, W, d, C, win)
 
 
 def test_each_window_fit_is_its_own_fit():

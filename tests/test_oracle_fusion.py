@@ -12,16 +12,16 @@ import pytest
 import oracle
 
 
-@pytest.mark.parametrize("H,W,d", [(40, 37, 8), (16, 16, 16), (33, 50, 4), (21, 18, 2),
-                                   (5, 7, 4)])
-def test_every_pixel_has_the_same_number_of_windows(H, W, d):
-    m = 16 // d
-    rects = oracle.window_rects(H, W, d)
-    if H >= 16 and W >= 16:
+@pytest.mark.parametrize("H,W,d,window", [(40, 37, 8, 16), (16, 16, 16, 16), (33, 50, 4, 16),
+                                          (21, 18, 2, 16), (5, 7, 4, 16), (29, 31, 4, 12)])
+def test_every_pixel_has_the_same_number_of_windows(H, W, d, window):
+    m = window // d
+    rects = oracle.window_rects(H, W, d, window)
+    if H >= window and W >= window:
         assert len(set(rects)) == len(rects)
     cnt = np.zeros((H, W), np.int64)
     for (y0, x0, h, w) in rects:
-        assert 0 <= y0 and 0 <= x0 and 1 <= h <= 16 and 1 <= w <= 16
+        assert 0 <= y0 and 0 <= x0 and 1 <= h <= window and 1 <= w <= window
         assert y0 + h <= H and x0 + w <= W
         cnt[y0:y0 + h, x0:x0 + w] += 1
     assert np.all(cnt == m * m)
@@ -62,27 +62,29 @@ def test_identical_hypotheses_average_to_the_hypothesis(d):
     assert np.max(np.abs(fused - y)) <= 1e-12
 
 
-def _constant_window_models(H, W, d):
+def _constant_window_models(H, W, d, window=16):
     """Window (ky, kx) -- counted from the window whose span ends d pixels into the image --
     predicts the constant kx + 100 ky everywhere in it (one broad kernel with a constant
     expert; C = 1, order 0)."""
     models = []
-    for (y0, x0, h, w) in oracle.window_rects(H, W, d):
+    for (y0, x0, h, w) in oracle.window_rects(H, W, d, window):
         # unclipped start: the clipped start if the window begins inside the image, else
-        # 16 pixels before its end (the images are at least 16 pixels wide here)
-        sx = x0 if x0 > 0 else x0 + w - 16
-        sy = y0 if y0 > 0 else y0 + h - 16
-        kx, ky = (sx + 16) // d - 1, (sy + 16) // d - 1
+        # `window` pixels before its end (the images are at least a window wide here)
+        sx = x0 if x0 > 0 else x0 + w - window
+        sy = y0 if y0 > 0 else y0 + h - window
+        kx, ky = (sx + window) // d - 1, (sy + window) // d - 1
         models.append(np.array([[w / 2, h / 2, 100.0, 0.0, 100.0, 0.0, kx + 100.0 * ky]]))
     return models
 
 
-@pytest.mark.parametrize("H,W,d", [(40, 37, 8), (16, 16, 16), (33, 50, 4), (20, 18, 2)])
-def test_constant_hypotheses_average_in_closed_form(H, W, d):
+@pytest.mark.parametrize("H,W,d,window", [(40, 37, 8, 16), (16, 16, 16, 16), (33, 50, 4, 16),
+                                          (20, 18, 2, 16), (29, 31, 4, 12)])
+def test_constant_hypotheses_average_in_closed_form(H, W, d, window):
     """The windows covering pixel x along an axis are k = floor(x/d) ... floor(x/d) + m - 1
-    (m = 16/d), so the mean of the window indices is floor(x/d) + (m - 1)/2."""
-    m = 16 // d
-    fused = oracle.fuse_windows(_constant_window_models(H, W, d), 1, 0, H, W, d)
+    (m = window/d), so the mean of the window indices is floor(x/d) + (m - 1)/2."""
+    m = window // d
+    fused = oracle.fuse_windows(_constant_window_models(H, W, d, window), 1, 0, H, W, d,
+                                window)
     ys, xs = np.mgrid[0:H, 0:W]
     want = (xs // d + (m - 1) / 2) + 100.0 * (ys // d + (m - 1) / 2)
     assert np.max(np.abs(fused[..., 0] - want)) <= 1e-9
@@ -124,11 +126,11 @@ def test_planted_fusion_mistakes_fail_a_pin(monkeypatch, label, old, new):
     if fn is oracle.fuse_windows:
         # fuse_windows looks window_rects up in the module namespace: keep the real one
         mut.__globals__["window_rects"] = oracle.window_rects
-    pinned = [lambda: test_every_pixel_has_the_same_number_of_windows(40, 37, 8),
-              lambda: test_every_pixel_has_the_same_number_of_windows(21, 18, 2),
+    pinned = [lambda: test_every_pixel_has_the_same_number_of_windows(40, 37, 8, 16),
+              lambda: test_every_pixel_has_the_same_number_of_windows(21, 18, 2, 16),
               lambda: test_identical_hypotheses_average_to_the_hypothesis(8),
-              lambda: test_constant_hypotheses_average_in_closed_form(40, 37, 8),
-              lambda: test_constant_hypotheses_average_in_closed_form(33, 50, 4)]
+              lambda: test_constant_hypotheses_average_in_closed_form(40, 37, 8, 16),
+              lambda: test_constant_hypotheses_average_in_closed_form(33, 50, 4, 16)]
     failed = 0
     for pin in pinned:
         try:
