@@ -63,7 +63,7 @@ class SmoeBins(ct.Structure):
     _fields_ = [("K", _i32), ("C", _i32), ("order", _i32), ("max_tiles", _i32),
                 ("capacity", _i32), ("tile_rects", _vp), ("native_rects", _vp), ("counts", _vp), ("records", _vp),
                 ("record_stride", _i32), ("tile_counts", _vp), ("ranges", _vp), ("keys", _vp),
-                ("vals", _vp), ("vals_alt", _vp), ("pair_grads", _vp), ("pair_slots", _vp),
+                ("vals", _vp), ("vals_alt", _vp), ("pair_grads", _vp),
                 ("tile_loss", _vp),
                 ("status", _vp)]
 

@@ -100,18 +100,18 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
 }
 
 // The fit step's scatter into fixed-width buckets: entry t W + c of the pair storage, c the
-// block's cursor, receives (kernel id << shift) | c, and for the kernel's first kSlots blocks
-// (row-major) slots[j][q] = t W + c -- the slot where the block's partial row of the kernel
-// will be written and read back, so that no later pass has to search the sorted lists.  A
-// bucket that fills up sets the step's overflow flag (status word kStepFlags + parity of the
-// step counter) and drops the entry -- the step then changes nothing.  The cursors start at
-// zero (the fused render resets them).  Thread 0 copies the step counter into the status
-// words for the step's later kernels.
+// block's cursor, receives (kernel id << shift) | low, where low names the row the block's
+// partial row of the kernel will be written to and read back from, so that no later pass has
+// to search the sorted lists: low = q, the block's row-major index in the kernel's rectangle,
+// for q < kSlots (row kSlots j + q), else kSlots + c (row kSlots K + t W + c).  A bucket that
+// fills up sets the step's overflow flag (status word kStepFlags + parity of the step
+// counter) and drops the entry -- the step then changes nothing.  The cursors start at zero
+// (the fused render resets them).  Thread 0 copies the step counter into the status words
+// for the step's later kernels.
 __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __restrict__ tile_rects,
                                                        int32_t* __restrict__ cursors,
                                                        uint32_t* __restrict__ vals, int width,
-                                                       int shift, int32_t* __restrict__ slots,
-                                                       int32_t* __restrict__ status,
+                                                       int shift, int32_t* __restrict__ status,
                                                        const int32_t* __restrict__ step) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int t0 = step[0];
@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __res
     const int t = sg.tile_offset + (rc.y + q / w) * sg.ntx + rc.x + q % w;
     const int pos = atomicAdd(&cursors[t], 1);
     if (pos < width) {
-      vals[(size_t)t * width + pos] = ((uint32_t)j << shift) | (uint32_t)pos;
-      if (q < kSlots) slots[(size_t)j * kSlots + q] = t * width + pos;
+      const uint32_t low = q < kSlots ? (uint32_t)q : (uint32_t)(kSlots + pos);
+      vals[(size_t)t * width + pos] = ((uint32_t)j << shift) | low;
     } else {
       status[kStepFlags + (t0 & 1)] = 1;
     }
@@ -215,7 +215,7 @@ hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, in
                                 const int32_t* step, hipStream_t s) {
   k_scatter_fixed<<<max(1, cdiv((long long)S.K * kScatterLanes, 256)), 256, 0, s>>>(
       S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, shift,
-      b.pair_slots, b.status, step);
+      b.status, step);
   return hipGetLastError();
 }
 

@@ -144,8 +144,7 @@ bool bins_match(const smoe_bins* b, int K, int C, int order) {
 
 struct Layout {
   size_t tile_rects, native_rects, counts, records, tile_counts, ranges, keys, vals, vals_alt,
-      pair_grads, pair_slots,
-      tile_loss, status, total;
+      pair_grads, tile_loss, status, total;
 };
 
 // grads = false: a render-only workspace, without the per-pair gradient partials.
@@ -164,9 +163,11 @@ Layout layout_of(int32_t K, int32_t C, int32_t order, int32_t max_tiles, int32_t
   L.keys = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals = o;       o = align_up(o + (size_t)capacity * sizeof(uint32_t));
   L.vals_alt = o;   o = align_up(o + (size_t)capacity * sizeof(uint32_t));
+  // partial rows: kSlots per kernel (the fit step's kernel-major rows), then one per pair
   L.pair_grads = o;
-  o = align_up(o + (grads ? (size_t)capacity * partial_stride((int)np) * sizeof(float) : 0));
-  L.pair_slots = o; o = align_up(o + (grads ? (size_t)K * kSlots * sizeof(int32_t) : 0));
+  o = align_up(o + (grads ? ((size_t)K * kSlots + (size_t)capacity) * partial_stride((int)np) *
+                                sizeof(float)
+                          : 0));
   L.tile_loss = o;  o = align_up(o + (size_t)max_tiles * sizeof(float));
   L.status = o;     o = align_up(o + 8 * sizeof(int32_t));
   L.total = o;
@@ -228,7 +229,7 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
       !bins_match(&st->bins, S.K, st->C, st->order))
     return SMOE_ERR_INVALID;
   if (!st->raw || !st->adam_m || !st->adam_v || !st->image || !st->denom || !st->step ||
-      !st->scalars || !st->bins.pair_grads || !st->bins.pair_slots || !st->bins.tile_loss ||
+      !st->scalars || !st->bins.pair_grads || !st->bins.tile_loss ||
       st->max_steps < 0)
     return SMOE_ERR_INVALID;
   if (S.T > st->bins.max_tiles) return SMOE_ERR_TOO_LARGE;
@@ -237,11 +238,11 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
     return (ev && ev[i]) ? hipEventRecord(static_cast<hipEvent_t>(ev[i]), s) : hipSuccess;
   };
   // The pair storage as fixed-width block buckets: block t owns entries [t W, t W + W).  An
-  // entry is (kernel id << shift) | its slot in the bucket, W <= 2^shift, so the kernel ids
-  // must fit in 32 - shift bits.
+  // entry is (kernel id << shift) | low with low < kSlots + W <= 2^shift (the row of its
+  // partial, k_scatter_fixed), so the kernel ids must fit in 32 - shift bits.
   const int width = st->bins.capacity / S.T;
   int shift = 0;
-  while ((1LL << shift) < (long long)width) ++shift;
+  while ((1LL << shift) < (long long)width + kSlots) ++shift;
   if (((long long)S.K << shift) > (1LL << 32)) return SMOE_ERR_TOO_LARGE;
   hipError_t e = mark(0);
   if (e == hipSuccess && !st->prepared)
@@ -340,7 +341,6 @@ smoe_status layout_into(smoe_bins* out, void* workspace, size_t bytes, int32_t K
   b.vals = reinterpret_cast<uint32_t*>(base + L.vals);
   b.vals_alt = reinterpret_cast<uint32_t*>(base + L.vals_alt);
   b.pair_grads = grads ? reinterpret_cast<float*>(base + L.pair_grads) : nullptr;
-  b.pair_slots = grads ? reinterpret_cast<int32_t*>(base + L.pair_slots) : nullptr;
   b.tile_loss = reinterpret_cast<float*>(base + L.tile_loss);
   b.status = reinterpret_cast<int32_t*>(base + L.status);
   *out = b;

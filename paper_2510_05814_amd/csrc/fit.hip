@@ -118,15 +118,14 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
   for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
   if (threadIdx.x == 0) a.tile_loss[tile] = err * inv_n;
 
-  // each partial row goes to the slot its entry got in the scatter, where Adam reads it
+  // each partial row goes to the row its entry names, where Adam reads it
   backward_accumulate<C, ORDER>(px, a.S.r2, a.records, a.vals, a.shift, true, rg, srec, true,
-                                live, sd, a.pair_grads);
+                                live, sd, a.pair_grads, a.S.K);
 }
 
 struct AdamFitArgs {
   Segs S;
-  int shift;  // bucket entries: kernel id << shift | slot
-  const int32_t* __restrict__ slots;  // [K][kSlots] bucket slots of each kernel's blocks
+  int shift;  // bucket entries: kernel id << shift | row of the partial (k_scatter_fixed)
   const int4* __restrict__ tile_rects_in;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -168,15 +167,13 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const size_t e = (size_t)j * NP + i;
   // Every load that depends on no other is issued before the first wait: the status words
   // (the completed steps, copied by this step's scatter, and both overflow flags), the
-  // kernel's block rectangle, the bucket slot of its block i, and Adam's state.
+  // kernel's block rectangle and Adam's state.
   const int t0_ = f.status[kStepShadow];
   const int flag0 = f.status[kStepFlags], flag1 = f.status[kStepFlags + 1];
   int4 rc = make_int4(0, 0, -1, -1);
-  int slot0 = 0;
   float m0 = 0.0f, v0 = 0.0f, raw0 = 0.0f;
   if (live) {
     rc = f.tile_rects_in[j];
-    slot0 = f.slots[(size_t)j * kSlots + i];  // read only for blocks the kernel covers
     if (i < NP) {
       m0 = f.m[e];
       v0 = f.v[e];
@@ -231,8 +228,8 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   if (live && skip && i < NP) pm = f.model[e];
   const bool upd = live && !skip && i < NP;
   // every lane takes part in the gather's row reduction
-  const float gi = gather_param_slotted<NP>(j, live && !skip, sg, rc, slot0, f.ranges, f.vals,
-                                            f.pair_grads, f.shift);
+  const float gi = gather_param_fit<NP>(j, live && !skip, sg, rc, f.S.K, f.ranges, f.vals,
+                                        f.pair_grads, f.shift);
   if (upd) {
     const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;
@@ -334,7 +331,6 @@ hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, f
   const smoe_bins& b = st.bins;
   AdamFitArgs f{S,
                 shift,
-                b.pair_slots,
                 reinterpret_cast<const int4*>(b.tile_rects),
                 reinterpret_cast<const int2*>(b.ranges),
                 b.vals,

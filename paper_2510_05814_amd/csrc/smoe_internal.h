@@ -154,8 +154,10 @@ __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, i
   return (a < hi && (vals[a] >> shift) == j) ? a : -1;
 }
 
-// The fit step records, for each kernel's first kSlots blocks (row-major in its block
-// rectangle), the bucket slot its entry was appended at.
+// The fit step stores the gradient partial row of kernel j in its block q (row-major in its
+// block rectangle) at row kSlots j + q of the pair storage when q < kSlots -- each kernel's
+// first blocks are kernel-major, so its gradient gather reads them contiguously -- and at row
+// kSlots K + the entry's bucket slot for the kernel's further blocks.
 constexpr int kSlots = 16;
 
 // Launchers.  `params` rows are addressed through each segment's param_offset; every

@@ -317,25 +317,22 @@ __device__ __forceinline__ void add_partial_row(float (&v)[16], const float* __r
   }
 }
 
-// The slot of kernel j's partial row in block t = (ty, tx) of its rectangle: a binary search
-// for j in the block's sorted list (its position, or -- packed fit-step entries, shift > 0 --
-// the slot held in the entry's low bits); -1 if the list does not hold j.
-__device__ __forceinline__ int search_slot(int j, int t, const int2* __restrict__ ranges,
-                                           const uint32_t* __restrict__ vals, int shift) {
+// The position of kernel j in block t's sorted list (a binary search; entries hold the
+// kernel id << shift), or -1 if the list does not hold j.
+__device__ __forceinline__ int list_position(int j, int t, const int2* __restrict__ ranges,
+                                             const uint32_t* __restrict__ vals, int shift) {
   const int2 rg = ranges[t];
   if (rg.y <= rg.x) return -1;
-  int p = find_in_list(vals, rg.x, rg.y, (uint32_t)j, shift);
-  if (p < 0) return -1;
-  if (shift) p = rg.x + (int)(vals[p] & ((1u << shift) - 1u));
-  return p;
+  return find_in_list(vals, rg.x, rg.y, (uint32_t)j, shift);
 }
 
 // Gradient of kernel row j: the sum of its per-block partial rows over its block rectangle.
 // A group of 16 lanes (one 16-lane row of the wave) serves one kernel: lane b adds the partial
 // rows of blocks b, b + 16, ... of the rectangle (row-major); the row reduction then leaves
 // parameter i's gradient in lane i.  The summation order is fixed, so the result is
-// reproducible.  A partial row is found by search_slot.  All 16 lanes must call it (live =
-// false: the kernel contributes nothing).
+// reproducible.  The standalone backward's partial row of a (block, kernel) pair is at the
+// pair's list position, found by a search.  All 16 lanes must call it (live = false: the
+// kernel contributes nothing).
 template <int NP>
 __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& sg,
                                               const int4* __restrict__ rects,
@@ -352,24 +349,24 @@ __device__ __forceinline__ float gather_param(int j, bool live, const SegGrid& s
     const int w = rc.z - rc.x + 1;
     for (int b = threadIdx.x & 15; b < n; b += 16) {
       const int dy = b / w;
-      const int p = search_slot(j, sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w),
-                                ranges, vals, 0);
+      const int p = list_position(j, sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w),
+                                  ranges, vals, 0);
       if (p >= 0) add_partial_row<NP>(v, pair_grads, p);
     }
   }
   return row_reduce16_transposed(v);
 }
 
-// The fit step's gather, in the same order, with the kernel's rectangle rc and the slot of
-// block (lane & 15) of it (slot0, recorded by the scatter for the kernel's first kSlots
-// blocks) already loaded by the caller; blocks beyond the first kSlots are searched.
+// The fit step's gather, in the same order, with the kernel's rectangle rc already loaded by
+// the caller.  The partial row of the kernel's block b is at row kSlots j + b for b < kSlots
+// (contiguous per kernel); beyond, at row kSlots K + the bucket slot that the entry's low bits
+// hold, found by a search of the block's sorted list.
 template <int NP>
-__device__ __forceinline__ float gather_param_slotted(int j, bool live, const SegGrid& sg,
-                                                      int4 rc, int slot0,
-                                                      const int2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const float* __restrict__ pair_grads,
-                                                      int shift) {
+__device__ __forceinline__ float gather_param_fit(int j, bool live, const SegGrid& sg, int4 rc,
+                                                  int K, const int2* __restrict__ ranges,
+                                                  const uint32_t* __restrict__ vals,
+                                                  const float* __restrict__ pair_grads,
+                                                  int shift) {
   static_assert(NP <= 16, "16 lanes per kernel");
   float v[16];
 #pragma unroll
@@ -378,13 +375,16 @@ __device__ __forceinline__ float gather_param_slotted(int j, bool live, const Se
     const int n = rect_count(rc);
     const int w = rc.z - rc.x + 1;
     for (int b = threadIdx.x & 15; b < n; b += 16) {
-      int p = slot0;
+      int p = j * kSlots + b;
       if (b >= kSlots) {
         const int dy = b / w;
-        p = search_slot(j, sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w), ranges,
-                        vals, shift);
+        const int t = sg.tile_offset + (rc.y + dy) * sg.ntx + rc.x + (b - dy * w);
+        const int pos = list_position(j, t, ranges, vals, shift);
+        if (pos < 0) continue;
+        const int low = (int)(vals[pos] & ((1u << shift) - 1u));
+        p = K * kSlots + ranges[t].x + (low - kSlots);
       }
-      if (p >= 0) add_partial_row<NP>(v, pair_grads, p);
+      add_partial_row<NP>(v, pair_grads, p);
     }
   }
   return row_reduce16_transposed(v);
@@ -416,9 +416,10 @@ struct PixelSeed {
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 // The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
 // 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel.
-// packed (the fit step): list entries hold kernel id << shift | slot, and the partial row of
-// an entry goes to its slot, rg.x + slot, where the scatter recorded it; otherwise to the
-// entry's list position.
+// packed (the fit step): list entries hold kernel id << shift | low, and the partial row of
+// the entry goes to row kSlots j + low for low < kSlots (the block's index in the kernel's
+// rectangle: kernel-major rows), else to row kSlots K + rg.x + low - kSlots (its bucket
+// slot), where the fit step's gather reads it; otherwise to the entry's list position.
 template <int C, int ORDER>
 __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float r2,
                                                     const float* __restrict__ records,
@@ -426,7 +427,8 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
                                                     bool packed, int2 rg, float4* srec,
                                                     bool staged, uint64_t live,
                                                     const PixelSeed<C>& sd,
-                                                    float* __restrict__ pair_grads) {
+                                                    float* __restrict__ pair_grads,
+                                                    int K = 0) {
   constexpr int RS = record_stride(C, ORDER);
   constexpr int Q = RS / 4;
   constexpr int NP = num_params(C, ORDER);
@@ -440,8 +442,11 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
     const uint32_t slot_mask = (1u << shift) - 1u;
     // the row of entry k: its slot (packed) or its list position
     auto out_row = [&](int k) -> size_t {
-      return packed ? (size_t)rg.x + (__builtin_amdgcn_readfirstlane(vals[base + k]) & slot_mask)
-                    : (size_t)(base + k);
+      if (!packed) return (size_t)(base + k);
+      const uint32_t e = __builtin_amdgcn_readfirstlane(vals[base + k]);
+      const uint32_t low = e & slot_mask;
+      return low < (uint32_t)kSlots ? (size_t)(e >> shift) * kSlots + low
+                                    : (size_t)K * kSlots + (size_t)rg.x + (low - kSlots);
     };
     for (int k = 0; k < n; ++k) {
       if (reuse && !((live >> k) & 1ull)) {

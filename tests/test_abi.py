@@ -70,12 +70,13 @@ def test_workspace_layout_host_only():
     b = C.SmoeBins()
     C.smoe_bins_layout(b, base, n, 100, 3, 1, 64, 1000)
     ptrs = [b.tile_rects, b.native_rects, b.counts, b.records, b.tile_counts, b.ranges, b.keys, b.vals,
-            b.vals_alt, b.pair_grads, b.pair_slots, b.tile_loss, b.status]
+            b.vals_alt, b.pair_grads, b.tile_loss, b.status]
     assert all(p % 256 == 0 for p in ptrs)
     assert ptrs == sorted(ptrs) and ptrs[-1] + 16 <= base + n
     assert b.record_stride == 16 and b.capacity == 1000 and b.max_tiles == 64
-    # partial rows of NP = 15 floats are padded to 16 (float4-aligned rows)
-    assert b.pair_slots - b.pair_grads >= 1000 * 16 * 4
+    # partial rows of NP = 15 floats padded to 16 (float4-aligned rows): 16 per kernel for the
+    # fit step's kernel-major rows, then one per pair
+    assert b.tile_loss - b.pair_grads >= (100 * 16 + 1000) * 16 * 4
     with pytest.raises(C.SmoeError):
         C.smoe_bins_layout(b, base, n - 1, 100, 3, 1, 64, 1000)
     with pytest.raises(C.SmoeError):

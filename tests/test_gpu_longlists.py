@@ -160,3 +160,34 @@ def test_long_lists_in_a_batch_equal_alone(smoe):
         if i == 0:
             assert b.read_status()[1][2] > 128
         assert torch.equal(out[a:e].view(h, w, 3), alone), (i, s)
+
+
+def test_fit_step_gradient_with_kernels_over_many_blocks(smoe, record_error):
+    """The fit step's gather takes a kernel's first 16 block partials from its kernel-major
+    rows and the rest through a search of the block lists: one fit step on a model whose
+    kernels cover up to ~80 blocks, its gradient per group against the oracle."""
+    import torch
+
+    say("fit step, kernels over many blocks")
+    W, H = 160, 128
+    m_np = wide_model(60, 3, 1, W, H, 731, 4.0, 24.0)
+    t_np = np.random.default_rng(9).uniform(0, 1, (H, W, 3)).astype(np.float32)
+    b = smoe.bin(dev(m_np), 3, 1, smoe.make_grid(W, H))
+    counts = host(b.counts())
+    assert counts.max() > 16 and (counts <= 16).any()
+    raw = m_np.astype(np.float64).copy()
+    raw[:, 2], raw[:, 4] = np.log(m_np[:, 2]), np.log(m_np[:, 4])
+    st = smoe.FitState(dev(t_np), dev(raw), 1, smoe.AdamConfig(total_steps=10), max_steps=2)
+    model_np = host(st.model).astype(np.float64)
+    st.step()
+    torch.cuda.synchronize()
+    assert not st.bins.read_status()[0]
+    g = host(st.grads)
+    _, g_o = oracle.loss_grad(model_np, 3, 1, W, H, target=t_np)
+    groups = {"mu": [0, 1], "s1": [2], "l21": [3], "s2": [4], "rho": [5], "a": [6, 7, 8],
+              "wx": [9, 10, 11], "wy": [12, 13, 14]}
+    for name, cols in groups.items():
+        scale = float(np.max(np.abs(g_o[:, cols])))
+        e = float(np.max(np.abs(g[:, cols] - g_o[:, cols]))) / scale
+        record_error(f"fit step many-block grad {name} rel", e, 1e-3)
+        assert e <= 1e-3, name
