@@ -346,7 +346,8 @@ typedef struct smoe_fit_state {
                                 update need neither, so a fit loop skips 16 B per pixel of
                                 stores on all but the steps whose render it wants) */
   int32_t* step;             /* [1] completed steps */
-  float* scalars;            /* [4] per-step scratch */
+  float* scalars;            /* [4] per-step scratch (the step's Adam learning rate and bias
+                                corrections) */
   /* Batched fit (num_segments > 0): num_segments images fitted together, each with its own
    * kernels, as independent fits stepped in lock-step (the loss is the sum of the images'
    * MSEs, so every image's gradient is its own).  Segments laid out by

@@ -107,15 +107,20 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
 // fills up sets the step's overflow flag (status word kStepFlags + parity of the step
 // counter) and drops the entry -- the step then changes nothing.  The cursors start at zero
 // (the fused render resets them).  Thread 0 copies the step counter into the status words
-// for the step's later kernels.
+// and writes the step's Adam scalars, for the step's later kernels.
 __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __restrict__ tile_rects,
                                                        int32_t* __restrict__ cursors,
                                                        uint32_t* __restrict__ vals, int width,
                                                        int shift, int32_t* __restrict__ status,
-                                                       const int32_t* __restrict__ step) {
+                                                       const int32_t* __restrict__ step,
+                                                       smoe_adam_config adam,
+                                                       float* __restrict__ scalars) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int t0 = step[0];
-  if (gid == 0) status[kStepShadow] = t0;
+  if (gid == 0) {
+    status[kStepShadow] = t0;
+    adam_step_scalars(adam, t0, scalars);
+  }
   const int j = gid / kScatterLanes, q0 = gid % kScatterLanes;
   if (j >= S.K) return;
   const int4 rc = tile_rects[j];
@@ -212,10 +217,11 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
 }
 
 hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
-                                const int32_t* step, hipStream_t s) {
+                                const int32_t* step, const smoe_adam_config& adam,
+                                float* scalars, hipStream_t s) {
   k_scatter_fixed<<<max(1, cdiv((long long)S.K * kScatterLanes, 256)), 256, 0, s>>>(
       S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, shift,
-      b.status, step);
+      b.status, step, adam, scalars);
   return hipGetLastError();
 }
 

@@ -403,4 +403,17 @@ inline StepScalarsArgs make_step_scalars_args(const smoe_fit_state& st, float* l
   return StepScalarsArgs{st.step, st.scalars, loss_out, st.loss_history, st.max_steps, st.adam};
 }
 
+// The per-step Adam scalars of step t0 (Sec. VI-B): out[0] = the centre learning rate,
+// decaying exponentially from lr_mu to lr_mu_final over total_steps; out[1], out[2] = the bias
+// corrections 1 - beta1^(t0+1), 1 - beta2^(t0+1).  Computed once per step by one thread.
+__device__ __forceinline__ void adam_step_scalars(const smoe_adam_config& ad, int t0,
+                                                  float* __restrict__ out) {
+  float lr_mu = ad.lr_mu;
+  if (ad.total_steps > 0 && ad.lr_mu > 0.0f && ad.lr_mu_final > 0.0f)
+    lr_mu = ad.lr_mu * powf(ad.lr_mu_final / ad.lr_mu, (float)t0 / (float)ad.total_steps);
+  out[0] = lr_mu;
+  out[1] = 1.0f - powf(ad.beta1, (float)(t0 + 1));
+  out[2] = 1.0f - powf(ad.beta2, (float)(t0 + 1));
+}
+
 }  // namespace smoe

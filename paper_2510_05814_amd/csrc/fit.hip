@@ -157,8 +157,6 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   constexpr int NP = num_params(C, ORDER);
   constexpr int NE = expert_floats(C, ORDER);
   constexpr int RS = record_stride(C, ORDER);
-  __shared__ int s_t0;
-  __shared__ float s_sc[3];
   __shared__ float s_red[kAdamThreads / 64];
   const smoe_adam_config& ad = f.step.adam;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,10 +164,11 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const bool live = j < f.S.K;
   const size_t e = (size_t)j * NP + i;
   // Every load that depends on no other is issued before the first wait: the status words
-  // (the completed steps, copied by this step's scatter, and both overflow flags), the
-  // kernel's block rectangle and Adam's state.
-  const int t0_ = f.status[kStepShadow];
+  // (the completed steps, copied by this step's scatter, and both overflow flags), the step's
+  // Adam scalars (written by the scatter), the kernel's block rectangle and Adam's state.
+  const int t0 = f.status[kStepShadow];
   const int flag0 = f.status[kStepFlags], flag1 = f.status[kStepFlags + 1];
+  const float lr_mu = f.step.scalars[0], bc1 = f.step.scalars[1], bc2 = f.step.scalars[2];
   int4 rc = make_int4(0, 0, -1, -1);
   float m0 = 0.0f, v0 = 0.0f, raw0 = 0.0f;
   if (live) {
@@ -180,19 +179,7 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
       raw0 = f.raw[e];
     }
   }
-  const bool skip = ((t0_ & 1) ? flag1 : flag0) != 0;
-  if (threadIdx.x == 0) {
-    const int t0 = t0_;
-    float lr_mu = ad.lr_mu;
-    if (ad.total_steps > 0 && ad.lr_mu > 0.0f && ad.lr_mu_final > 0.0f)
-      lr_mu = ad.lr_mu * powf(ad.lr_mu_final / ad.lr_mu, (float)t0 / (float)ad.total_steps);
-    s_t0 = t0;
-    s_sc[0] = lr_mu;
-    s_sc[1] = 1.0f - powf(ad.beta1, (float)(t0 + 1));
-    s_sc[2] = 1.0f - powf(ad.beta2, (float)(t0 + 1));
-  }
-  __syncthreads();
-  const int t0 = s_t0;
+  const bool skip = ((t0 & 1) ? flag1 : flag0) != 0;
   if (blockIdx.x == 0 && !skip) {
     // Loss: the whole workgroup sums the per-block squared errors in a fixed order, four
     // independent float4 streams per thread so that the loads overlap.
@@ -231,12 +218,12 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   const float gi = gather_param_fit<NP>(j, live && !skip, sg, rc, f.S.K, f.ranges, f.vals,
                                         f.pair_grads, f.shift);
   if (upd) {
-    const float lr = i < 2 ? s_sc[0] : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
+    const float lr = i < 2 ? lr_mu : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;
     const float vi = ad.beta2 * v0 + (1.0f - ad.beta2) * gi * gi;
     f.m[e] = mi;
     f.v[e] = vi;
-    const float p = raw0 - lr * (mi / s_sc[1]) / (sqrtf(vi / s_sc[2]) + ad.eps);
+    const float p = raw0 - lr * (mi / bc1) / (sqrtf(vi / bc2) + ad.eps);
     f.raw[e] = p;
     pm = (i == 2 || i == 4) ? expf(p) : p;
     f.model[e] = pm;
