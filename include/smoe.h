@@ -371,9 +371,10 @@ typedef struct smoe_fit_state {
  * step's boxes and records (so the first step, state->prepared == 0, computes those first
  * and then sets state->prepared = 1).  The workspace's pair storage is used as fixed-width
  * buckets: each of the T blocks gets floor(bins.capacity / T) entries, so the capacity must
- * cover T times the longest block list; with W = floor(capacity / T) rounded up to a power
- * of two 2^b, the total kernel count must stay below 2^(32 - b) (each bucket entry holds the
- * kernel id and its slot in 32 bits), else the call returns SMOE_ERR_TOO_LARGE.  A fuller
+ * cover T times the longest block list; with W = floor(capacity / T) and 16 + W rounded up
+ * to a power of two 2^b, the total kernel count must stay below 2^(32 - b) (each bucket entry
+ * holds the kernel id and the row of its gradient partial in 32 bits), else the call returns
+ * SMOE_ERR_TOO_LARGE.  A fuller
  * bucket is a capacity overflow: the step
  * changes nothing (the step counter included) and smoe_read_status() reports it, with
  * status[0] = T x the longest list and status[2] = the longest list.  loss_out (device

@@ -23,7 +23,7 @@ namespace {
 
 struct FitTileArgs {
   Segs S;
-  int shift;  // bucket entries: kernel id << shift | slot
+  int shift;  // bucket entries: kernel id << shift | row of the entry's partial
   const float* __restrict__ records;
   int2* __restrict__ ranges;
   uint32_t* __restrict__ vals;

@@ -141,8 +141,8 @@ __device__ __forceinline__ int xcd_block(int b, int T) {
 }
 
 // Position of kernel j in a block's ascending kernel list vals[lo, hi); -1 if absent.  An
-// entry holds the kernel id shifted left by `shift` (the fit step's buckets keep the entry's
-// slot in the low bits).
+// entry holds the kernel id shifted left by `shift` (the fit step's buckets keep the row of
+// the entry's gradient partial in the low bits).
 __device__ __forceinline__ int find_in_list(const uint32_t* __restrict__ vals, int lo, int hi,
                                             uint32_t j, int shift = 0) {
   int a = lo, b = hi;
@@ -192,8 +192,8 @@ hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s);
 // step), and the scatter into fixed-width buckets (every step).
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
                               const smoe_bins& b, hipStream_t s);
-// The fit step's bucket entries: kernel id << shift | slot within the bucket (width <=
-// 2^shift).
+// The fit step's bucket entries: kernel id << shift | the row of the entry's gradient
+// partial (kSlots + width <= 2^shift).
 hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
                                 const int32_t* step, const smoe_adam_config& adam,
                                 float* scalars, hipStream_t s);

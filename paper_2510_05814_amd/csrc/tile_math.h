@@ -301,7 +301,7 @@ __device__ __forceinline__ float row_reduce16_transposed(float (&v)[16]) {
   return keep + dpp<0xB1>(send);
 }
 
-// Adds the partial row at slot p (NP values of a row of partial_stride(NP) floats) to v.
+// Adds partial row p (NP values of a row of partial_stride(NP) floats) to v.
 template <int NP>
 __device__ __forceinline__ void add_partial_row(float (&v)[16], const float* __restrict__ pair_grads,
                                                 int p) {
@@ -440,7 +440,7 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
     const bool reuse = staged && rg.y - rg.x <= kChunk;
     if (!reuse) stage_records<RS>(srec, records, vals, base, n, shift);
     const uint32_t slot_mask = (1u << shift) - 1u;
-    // the row of entry k: its slot (packed) or its list position
+    // the row of entry k's partial: the one its low bits name (packed) or its list position
     auto out_row = [&](int k) -> size_t {
       if (!packed) return (size_t)(base + k);
       const uint32_t e = __builtin_amdgcn_readfirstlane(vals[base + k]);
