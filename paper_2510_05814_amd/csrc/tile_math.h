@@ -490,16 +490,18 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
             if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
             Gs = __builtin_fmaf(sd.g[i][c], m, Gs);
             const float gw = sd.g[i][c] * w;
-            A[c] += gw;
-            if (ORDER == 1) Y[c] = __builtin_fmaf(gw, dy, Y[c]);
+            // the first row's terms start the sums (the other lanes keep their zeros): no
+            // additions of zero
+            A[c] = i == 0 ? gw : A[c] + gw;
+            if (ORDER == 1) Y[c] = i == 0 ? gw * dy : __builtin_fmaf(gw, dy, Y[c]);
           }
           const float Hh = w * Gs;
           const float bz2 = -Hh * z2;
           const float bz1 = __builtin_fmaf(-bz2, r[6], -Hh * z1);
-          B1 += bz1;
-          B2 += bz2;
-          S2 = __builtin_fmaf(-bz2, z2, S2);
-          R += Hh;
+          B1 = i == 0 ? bz1 : B1 + bz1;
+          B2 = i == 0 ? bz2 : B2 + bz2;
+          S2 = i == 0 ? -bz2 * z2 : __builtin_fmaf(-bz2, z2, S2);
+          R = i == 0 ? Hh : R + Hh;
         }
       }
       float acc[16];
