@@ -66,11 +66,9 @@ __global__ __launch_bounds__(256) void k_preprocess(int C, int order,
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_scan(int T, int32_t* __restrict__ tile_counts,
                                                        int2* __restrict__ ranges, int capacity,
-                                                       int32_t* __restrict__ status,
-                                                       const int32_t* __restrict__ step) {
+                                                       int32_t* __restrict__ status) {
   __shared__ int s_begin[16 * kScanThreads];
   __shared__ long long s_tot[kScanThreads / 64];
-  snapshot_step(step, status);
   block_scan_ranges<kScanThreads>(T, tile_counts, ranges, capacity, status, s_begin, s_tot);
 }
 
@@ -195,9 +193,9 @@ hipError_t launch_count(int C, int order, const float* params, const Segs& S,
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s, const int32_t* fit_step) {
+hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s) {
   k_scan<<<1, kScanThreads, 0, s>>>(S.T, b.tile_counts, reinterpret_cast<int2*>(b.ranges),
-                                    b.capacity, b.status, fit_step);
+                                    b.capacity, b.status);
   return hipGetLastError();
 }
 

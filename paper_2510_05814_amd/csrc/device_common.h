@@ -7,7 +7,6 @@
 
 namespace smoe {
 
-// Status word holding the fit step counter as the step began (written by the scan).
 constexpr int kStepShadow = 4;  // status word: completed steps, copied by the step's first kernel
 constexpr int kStepFlags = 5;   // status words 5, 6: the fit step's overflow flag by step parity
 constexpr int kNonfinite = 7;   // status word: a kernel row with a NaN or infinite parameter was
@@ -290,11 +289,6 @@ __device__ void block_scan_ranges(int T, int32_t* __restrict__ tile_counts,
     status[2] = longest;
     status[kNonfiniteOut] = status[kNonfinite];
   }
-}
-
-// The scan kernel's optional extra for the fit step: snapshot the step counter.
-__device__ __forceinline__ void snapshot_step(const int32_t* step, int32_t* status) {
-  if (step && threadIdx.x == 0) status[kStepShadow] = step[0];
 }
 
 // Sorts one bucket of n distinct kernel ids (seg[0, n)) ascending with the 64 lanes of one

@@ -182,9 +182,7 @@ hipError_t launch_materialize(int K, int C, int order, const float* raw, float* 
 // counters.
 hipError_t launch_count(int C, int order, const float* params, const Segs& S,
                         const smoe_bins& b, hipStream_t s);
-// fit_step (the fit step only): the step counter to snapshot for the step's Adam kernel.
-hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s,
-                       const int32_t* fit_step = nullptr);
+hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s);
 hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s);
 // Copies the first four status words (P needed, overflow, longest list, spare) to out4.
 hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s);
