@@ -415,7 +415,10 @@ struct PixelSeed {
 //   dL/dmu_x = -(bz1/l11 + sum_c g_c w wx_c),  dL/dmu_y = -(bz2/l22 + sum_c g_c w wy_c)
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 // The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
-// 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel.
+// 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel; so
+// is the l21/l22 term of bz1 (sum bz1 = -(z1 sum H + (l21/l22) sum bz2) over a lane's
+// pixels), and the seeds g and sum_c g_c y_c are taken already divided by D, so that pi K
+// itself stands in for w.
 // packed (the fit step): list entries hold kernel id << shift | low, and the partial row of
 // the entry goes to row kSlots j + low for low < kSlots (the block's index in the kernel's
 // rectangle: kernel-major rows), else to row kSlots K + rg.x + low - kSlots (its bucket
@@ -435,6 +438,14 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
   constexpr int PS = partial_stride(NP);
   static_assert(PS <= 16, "16 accumulators per kernel");
   const int lane = threadIdx.x & 63;
+  // the seeds divided by D: g_c / D and sum_c g_c y_c / D
+  float gs[kRows][C], gys[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; ++i) {
+    gys[i] = sd.gy[i] * sd.invD[i];
+#pragma unroll
+    for (int c = 0; c < C; ++c) gs[i][c] = sd.g[i][c] * sd.invD[i];
+  }
   for (int base = rg.x; base < rg.y; base += kChunk) {
     const int n = min(kChunk, rg.y - base);
     const bool reuse = staged && rg.y - rg.x <= kChunk;
@@ -467,13 +478,14 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
                            : r[kRecExpert + c];
       // Per lane, over its four pixels: the sums that do not factor through the lane's
-      // column -- A_c = sum g_c w, Y_c = sum g_c w dy, B1 = sum bz1, B2 = sum bz2,
-      // S2 = sum -bz2 z2, R = sum H.  dx and z1 are the same for the lane's pixels, so
-      // sum g_c w dx = dx A_c, sum bz1 z1 = z1 B1 and sum g_c w wx_c = wx_c A_c.
+      // column -- A_c = sum g_c w, Y_c = sum g_c w dy, B2 = sum bz2, S2 = sum -bz2 z2,
+      // R = sum H.  dx and z1 are the same for the lane's pixels, so sum g_c w dx = dx A_c,
+      // sum bz1 = -(z1 R + (l21/l22) B2), sum bz1 z1 = z1 sum bz1 and
+      // sum g_c w wx_c = wx_c A_c.  With the seeds divided by D, w = pi K / D is e = pi K.
       float A[C], Y[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) A[c] = Y[c] = 0.0f;
-      float B1 = 0.0f, B2 = 0.0f, S2 = 0.0f, R = 0.0f;
+      float B2 = 0.0f, S2 = 0.0f, R = 0.0f;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
         const float dy = px.y[i] - r[1];
@@ -482,28 +494,26 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         const float q = zz1 + z2 * z2;
         if (sd.valid[i] && q <= r2) {
           const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
-          const float w = e * sd.invD[i];
-          float Gs = -sd.gy[i];
+          const float ed = e * dy;
+          float Gs = -gys[i];  // G / D
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             float m = mx[c];
             if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
-            Gs = __builtin_fmaf(sd.g[i][c], m, Gs);
-            const float gw = sd.g[i][c] * w;
+            Gs = __builtin_fmaf(gs[i][c], m, Gs);
             // the first row's terms start the sums (the other lanes keep their zeros): no
             // additions of zero
-            A[c] = i == 0 ? gw : A[c] + gw;
-            if (ORDER == 1) Y[c] = i == 0 ? gw * dy : __builtin_fmaf(gw, dy, Y[c]);
+            A[c] = i == 0 ? gs[i][c] * e : __builtin_fmaf(gs[i][c], e, A[c]);
+            if (ORDER == 1) Y[c] = i == 0 ? gs[i][c] * ed : __builtin_fmaf(gs[i][c], ed, Y[c]);
           }
-          const float Hh = w * Gs;
-          const float bz2 = -Hh * z2;
-          const float bz1 = __builtin_fmaf(-bz2, r[6], -Hh * z1);
-          B1 = i == 0 ? bz1 : B1 + bz1;
-          B2 = i == 0 ? bz2 : B2 + bz2;
-          S2 = i == 0 ? -bz2 * z2 : __builtin_fmaf(-bz2, z2, S2);
+          const float Hh = e * Gs;    // H = w G
+          const float nbz2 = Hh * z2;  // -bz2
+          B2 = i == 0 ? -nbz2 : B2 - nbz2;
+          S2 = i == 0 ? nbz2 * z2 : __builtin_fmaf(nbz2, z2, S2);
           R = i == 0 ? Hh : R + Hh;
         }
       }
+      const float B1 = -__builtin_fmaf(r[6], B2, z1 * R);
       float acc[16];
       float ex = 0.0f, ey = 0.0f;
 #pragma unroll
