@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kWave) void k_backward(BackwardArgs a) {
 
 struct GatherArgs {
   Segs S;
+  const float* __restrict__ records;
   const int4* __restrict__ tile_rects;
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
@@ -76,14 +77,18 @@ struct GatherArgs {
 };
 
 // 16 lanes per kernel (one 16-lane row of the wave); lane i ends with parameter i.
-template <int NP>
+template <int C, int ORDER>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
+  constexpr int NP = num_params(C, ORDER);
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = gid >> 4, i = gid & 15;
+  constexpr int RS = record_stride(C, ORDER);
   const bool live = j < a.S.K;
-  // every lane takes part in the gather's row reduction
-  const float g = gather_param<NP>(j, live && a.status[1] == 0, seg_of_kernel(a.S, live ? j : 0),
+  const float rec = live && i < RS ? a.records[(size_t)j * RS + i] : 0.0f;
+  // every lane takes part in the gather's row reduction and the finishing shuffles
+  const float s = gather_param<NP>(j, live && a.status[1] == 0, seg_of_kernel(a.S, live ? j : 0),
                                    a.tile_rects, a.ranges, a.vals, a.pair_grads);
+  const float g = finish_gradient<C, ORDER, kRecExpert>(s, live, rec);
   if (live && i < NP) a.grads[(size_t)j * NP + i] = g;
 }
 
@@ -113,6 +118,7 @@ hipError_t launch_gather(int C, int order, const Segs& S, const smoe_bins& b, fl
                          hipStream_t s) {
   if (S.K == 0) return hipSuccess;
   GatherArgs a{S,
+               b.records,
                reinterpret_cast<const int4*>(b.tile_rects),
                reinterpret_cast<const int2*>(b.ranges),
                b.vals,
@@ -120,10 +126,10 @@ hipError_t launch_gather(int C, int order, const Segs& S, const smoe_bins& b, fl
                b.status,
                grads};
   const int blocks = (int)(((long long)S.K * 16 + 255) / 256);
-  const int NP = num_params(C, order);
-  if (NP == 7) k_gather<7><<<blocks, 256, 0, s>>>(a);
-  else if (NP == 9) k_gather<9><<<blocks, 256, 0, s>>>(a);  // (C, order) = (1, 1) or (3, 0)
-  else k_gather<15><<<blocks, 256, 0, s>>>(a);
+  if (C == 1 && order == 0) k_gather<1, 0><<<blocks, 256, 0, s>>>(a);
+  else if (C == 1 && order == 1) k_gather<1, 1><<<blocks, 256, 0, s>>>(a);
+  else if (C == 3 && order == 0) k_gather<3, 0><<<blocks, 256, 0, s>>>(a);
+  else k_gather<3, 1><<<blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

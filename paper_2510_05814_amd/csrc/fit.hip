@@ -152,8 +152,10 @@ struct AdamFitArgs {
 // overflow the parameters stay as they are, and the records and rectangles are rewritten
 // from them unchanged.
 constexpr int kAdamThreads = 256;
+// (held to 64 VGPRs: 8 waves per SIMD to overlap the gather's loads)
 template <int C, int ORDER>
-__global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
+__global__ __launch_bounds__(kAdamThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_adam_fit(AdamFitArgs f) {
   constexpr int NP = num_params(C, ORDER);
   constexpr int NE = expert_floats(C, ORDER);
   constexpr int RS = record_stride(C, ORDER);
@@ -214,9 +216,13 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam_fit(AdamFitArgs f) {
   float pm = 0.0f;  // materialized value of parameter i after the step
   if (live && skip && i < NP) pm = f.model[e];
   const bool upd = live && !skip && i < NP;
-  // every lane takes part in the gather's row reduction
-  const float gi = gather_param_fit<NP>(j, live && !skip, sg, rc, f.S.K, f.ranges, f.vals,
-                                        f.pair_grads, f.shift);
+  // Every lane takes part in the gather's row reduction and the finishing shuffles; the
+  // expert slopes are those of the raw row (the render record this step used holds the same
+  // numbers).
+  const float gi = finish_gradient<C, ORDER, 6>(
+      gather_param_fit<NP>(j, live && !skip, sg, rc, f.S.K, f.ranges, f.vals, f.pair_grads,
+                           f.shift),
+      live && !skip, raw0);
   if (upd) {
     const float lr = i < 2 ? lr_mu : (i < 5 ? ad.lr_chol : (i == 5 ? ad.lr_rho : ad.lr_expert));
     const float mi = ad.beta1 * m0 + (1.0f - ad.beta1) * gi;

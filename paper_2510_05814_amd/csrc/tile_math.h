@@ -390,6 +390,27 @@ __device__ __forceinline__ float gather_param_fit(int j, bool live, const SegGri
   return row_reduce16_transposed(v);
 }
 
+// A kernel's gradient from the sums of its partial rows (lane i of the kernel's 16-lane group
+// holds the sum of field i; every lane of the group must call it).  Fields 0 and 1 of a
+// partial row leave out the expert terms of the centre's gradient, which factor through the
+// kernel's slopes and are applied here once per kernel:
+//   dL/dmu_x = field 0 - sum_c wx_c dL/da_c,  dL/dmu_y = field 1 - sum_c wy_c dL/da_c.
+// slopes: a per-lane value whose lane SLOPES + C + c holds wx_c and lane SLOPES + 2C + c
+// holds wy_c (the render record's fields, or the kernel's raw row: the same numbers).
+template <int C, int ORDER, int SLOPES>
+__device__ __forceinline__ float finish_gradient(float s, bool live, float slopes) {
+  if (ORDER == 0) return s;
+  const int i = threadIdx.x & 15;
+  float ex = 0.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float da = __shfl(s, 6 + c, 16);
+    const float slope = __shfl(slopes, SLOPES + ((i == 0) ? 1 : 2) * C + c, 16);
+    ex = __builtin_fmaf(da, slope, ex);
+  }
+  return live && i < 2 ? s - ex : s;
+}
+
 // Adjoint seed of one pixel: dL/dy (g), 1/D, sum_c g_c y_c; `valid` false where D = 0 or the
 // pixel lies outside the raster (no gradient flows there).  With the seed 1/D -> 1 and
 // sum_c g_c y_c -> 0 the same backward is the adjoint of the un-normalised sum of Eq. (1):
@@ -414,6 +435,8 @@ struct PixelSeed {
 //   bz2 = -H z2,  bz1 = -H z1 - bz2 l21/l22                  (through q = z1^2 + z2^2)
 //   dL/dmu_x = -(bz1/l11 + sum_c g_c w wx_c),  dL/dmu_y = -(bz2/l22 + sum_c g_c w wy_c)
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
+// Fields 0 and 1 of the partial row leave out the sum_c g_c w wx_c and sum_c g_c w wy_c
+// terms: the gather applies them per kernel from dL/da_c (finish_gradient).
 // The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
 // 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel; so
 // is the l21/l22 term of bz1 (sum bz1 = -(z1 sum H + (l21/l22) sum bz2) over a lane's
@@ -514,20 +537,18 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         }
       }
       const float B1 = -__builtin_fmaf(r[6], B2, z1 * R);
+      // fields 0 and 1 leave the expert terms of the centre's gradient to finish_gradient
       float acc[16];
-      float ex = 0.0f, ey = 0.0f;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         acc[6 + c] = A[c];
         if (ORDER == 1) {
           acc[6 + C + c] = A[c] * dx;
           acc[6 + 2 * C + c] = Y[c];
-          ex = __builtin_fmaf(A[c], r[kRecExpert + C + c], ex);
-          ey = __builtin_fmaf(A[c], r[kRecExpert + 2 * C + c], ey);
         }
       }
-      acc[0] = -__builtin_fmaf(B1, r[2], ex);
-      acc[1] = -__builtin_fmaf(B2, r[4], ey);
+      acc[0] = -B1 * r[2];
+      acc[1] = -B2 * r[4];
       acc[2] = -B1 * z1;
       acc[3] = -B2 * z1 * r[4];
       acc[4] = S2;
