@@ -501,22 +501,28 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
         mx[c] = ORDER == 1 ? __builtin_fmaf(r[kRecExpert + C + c], dx, r[kRecExpert + c])
                            : r[kRecExpert + c];
       // Per lane, over its four pixels: the sums that do not factor through the lane's
-      // column -- A_c = sum g_c w, Y_c = sum g_c w dy, B2 = sum bz2, S2 = sum -bz2 z2,
+      // column -- A_c = sum g_c w, Y_c = sum g_c w dy, V = sum H (dy - t), S2 = sum H z2^2,
       // R = sum H.  dx and z1 are the same for the lane's pixels, so sum g_c w dx = dx A_c,
-      // sum bz1 = -(z1 R + (l21/l22) B2), sum bz1 z1 = z1 sum bz1 and
-      // sum g_c w wx_c = wx_c A_c.  With the seeds divided by D, w = pi K / D is e = pi K.
+      // sum bz2 = -V / l22 (z2 = (dy - t) / l22), sum bz1 = -(z1 R + (l21/l22) sum bz2),
+      // sum bz1 z1 = z1 sum bz1 and sum g_c w wx_c = wx_c A_c.  With the seeds divided by D,
+      // w = pi K / D is e = pi K.
       float A[C], Y[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) A[c] = Y[c] = 0.0f;
-      float B2 = 0.0f, S2 = 0.0f, R = 0.0f;
+      float V = 0.0f, S2 = 0.0f, R = 0.0f;
 #pragma unroll
       for (int i = 0; i < kRows; ++i) {
         const float dy = px.y[i] - r[1];
         const float w_ = dy - tt;
         const float z2 = w_ * r[4];
-        const float q = zz1 + z2 * z2;
-        if (sd.valid[i] && q <= r2) {
-          const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+        const float z2sq = z2 * z2;
+        const float q = zz1 + z2sq;
+        // the first row runs unmasked with pi K zeroed where it does not take part, so that
+        // it can start the sums without zero-filled accumulators in front of it
+        const bool ok = sd.valid[i] && q <= r2;
+        if (i == 0 || ok) {
+          float e = __builtin_amdgcn_exp2f(__builtin_fmaf(q, -0.5f * kLog2e, r[5]));
+          if (i == 0) e = ok ? e : 0.0f;
           const float ed = e * dy;
           float Gs = -gys[i];  // G / D
 #pragma unroll
@@ -524,18 +530,17 @@ __device__ __forceinline__ void backward_accumulate(const PixelCoords& px, float
             float m = mx[c];
             if (ORDER == 1) m = __builtin_fmaf(r[kRecExpert + 2 * C + c], dy, m);
             Gs = __builtin_fmaf(gs[i][c], m, Gs);
-            // the first row's terms start the sums (the other lanes keep their zeros): no
-            // additions of zero
+            // the first row's terms start the sums: no additions of zero
             A[c] = i == 0 ? gs[i][c] * e : __builtin_fmaf(gs[i][c], e, A[c]);
             if (ORDER == 1) Y[c] = i == 0 ? gs[i][c] * ed : __builtin_fmaf(gs[i][c], ed, Y[c]);
           }
-          const float Hh = e * Gs;    // H = w G
-          const float nbz2 = Hh * z2;  // -bz2
-          B2 = i == 0 ? -nbz2 : B2 - nbz2;
-          S2 = i == 0 ? nbz2 * z2 : __builtin_fmaf(nbz2, z2, S2);
+          const float Hh = e * Gs;  // H = w G
+          V = i == 0 ? Hh * w_ : __builtin_fmaf(Hh, w_, V);
+          S2 = i == 0 ? Hh * z2sq : __builtin_fmaf(Hh, z2sq, S2);
           R = i == 0 ? Hh : R + Hh;
         }
       }
+      const float B2 = -V * r[4];
       const float B1 = -__builtin_fmaf(r[6], B2, z1 * R);
       // fields 0 and 1 leave the expert terms of the centre's gradient to finish_gradient
       float acc[16];
