@@ -365,11 +365,12 @@ typedef struct smoe_fit_state {
  * synchronisation: binning, forward render
  * with the fused squared-error loss, backward, then per kernel the deterministic
  * reduction of its block partials, the Adam update of the raw row and its
- * re-materialization.  The step runs as three kernels: the scatter of the (block, kernel)
- * pairs into block buckets; one kernel that per 16x16 block orders its bucket, renders the
- * block and runs its backward; and Adam, which also records the loss and computes the next
- * step's boxes and records (so the first step, state->prepared == 0, computes those first
- * and then sets state->prepared = 1).  The workspace's pair storage is used as fixed-width
+ * re-materialization.  The step runs as three kernels: the scatter, which computes each
+ * kernel's box from its model row and puts the (block, kernel) pairs into block buckets; one
+ * kernel that per 16x16 block orders its bucket, renders the block and runs its backward;
+ * and Adam, which also records the loss and writes the next step's render records (so the
+ * first step, state->prepared == 0, computes those first and then sets
+ * state->prepared = 1).  The workspace's pair storage is used as fixed-width
  * buckets: each of the T blocks gets floor(bins.capacity / T) entries, so the capacity must
  * cover T times the longest block list; with W = floor(capacity / T) and 16 + W rounded up
  * to a power of two 2^b, the total kernel count must stay below 2^(32 - b) (each bucket entry

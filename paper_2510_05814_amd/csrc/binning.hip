@@ -104,9 +104,14 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
 // for q < kSlots (row kSlots j + q), else kSlots + c (row kSlots K + t W + c).  A bucket that
 // fills up sets the step's overflow flag (status word kStepFlags + parity of the step
 // counter) and drops the entry -- the step then changes nothing.  The cursors start at zero
-// (the fused render resets them).  Thread 0 copies the step counter into the status words
+// (the fused render resets them).  The kernel's block rectangle comes from its model row
+// (kernel_rects, the binning's own rule; a row with a NaN or infinite parameter covers no
+// block) and is stored with its count for the step's Adam kernel, which gathers the
+// kernel's partial rows over it.  Thread 0 copies the step counter into the status words
 // and writes the step's Adam scalars, for the step's later kernels.
-__global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __restrict__ tile_rects,
+__global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const float* __restrict__ model,
+                                                       int np, int4* __restrict__ tile_rects,
+                                                       int32_t* __restrict__ counts,
                                                        int32_t* __restrict__ cursors,
                                                        uint32_t* __restrict__ vals, int width,
                                                        int shift, int32_t* __restrict__ status,
@@ -120,11 +125,27 @@ __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const int4* __res
     adam_step_scalars(adam, t0, scalars);
   }
   const int j = gid / kScatterLanes, q0 = gid % kScatterLanes;
-  if (j >= S.K) return;
-  const int4 rc = tile_rects[j];
-  const int n = rect_count(rc);
-  if (n == 0) return;
+  if (j >= S.K) return;  // (whole groups of kScatterLanes lanes: the shuffles stay inside one)
   const SegGrid sg = seg_of_kernel(S, j);
+  // every lane of the kernel's group reads the geometry; lane q0 also checks parameters
+  // 5 + q0, 5 + q0 + kScatterLanes, ... for finiteness
+  const float* p = model + (size_t)j * np;
+  const float mux = p[0], muy = p[1], l11 = p[2], l21 = p[3], l22 = p[4];
+  bool finite = __builtin_isfinite(mux) && __builtin_isfinite(muy) && __builtin_isfinite(l11) &&
+                __builtin_isfinite(l21) && __builtin_isfinite(l22);
+  for (int k = 5 + q0; k < np; k += kScatterLanes) finite = finite && __builtin_isfinite(p[k]);
+  int bad = finite ? 0 : 1;
+  static_assert(kScatterLanes == 4, "the finiteness vote spans a quad");
+  bad |= __shfl_xor(bad, 1);
+  bad |= __shfl_xor(bad, 2);
+  int4 rc = make_int4(0, 0, -1, -1);
+  if (!bad) rc = kernel_rects(mux, muy, l11, l21, l22, sg, S.r, S.box, S.trunc).tile;
+  const int n = rect_count(rc);
+  if (q0 == 0) {
+    tile_rects[j] = rc;
+    counts[j] = n;
+  }
+  if (n == 0) return;
   const int w = rc.z - rc.x + 1;
   for (int q = q0; q < n; q += kScatterLanes) {
     const int t = sg.tile_offset + (rc.y + q / w) * sg.ntx + rc.x + q % w;
@@ -214,12 +235,12 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
-                                const int32_t* step, const smoe_adam_config& adam,
-                                float* scalars, hipStream_t s) {
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, const float* model, int np,
+                                int width, int shift, const int32_t* step,
+                                const smoe_adam_config& adam, float* scalars, hipStream_t s) {
   k_scatter_fixed<<<max(1, cdiv((long long)S.K * kScatterLanes, 256)), 256, 0, s>>>(
-      S, reinterpret_cast<const int4*>(b.tile_rects), b.tile_counts, b.vals, width, shift,
-      b.status, step, adam, scalars);
+      S, model, np, reinterpret_cast<int4*>(b.tile_rects), b.counts, b.tile_counts, b.vals,
+      width, shift, b.status, step, adam, scalars);
   return hipGetLastError();
 }
 

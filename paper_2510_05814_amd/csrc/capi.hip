@@ -248,7 +248,8 @@ smoe_status fit_step(smoe_fit_state* st, const float* target, float* loss_out,
   if (e == hipSuccess && !st->prepared)
     e = launch_prepare_fit(st->C, st->order, st->model, S, st->bins, s);
   if (e == hipSuccess)
-    e = launch_scatter_fixed(S, st->bins, width, shift, st->step, st->adam, st->scalars, s);
+    e = launch_scatter_fixed(S, st->bins, st->model, num_params(st->C, st->order), width, shift,
+                             st->step, st->adam, st->scalars, s);
   if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_fit_tile(*st, S, width, shift, target, s);
   if (e == hipSuccess) e = mark(2);

@@ -2,13 +2,14 @@
 // parameters, the centre learning rate decaying exponentially).
 //
 // A fit step runs three kernels after the first: the scatter of the (block, kernel) pairs
-// into fixed-width block buckets (binning.hip), then
+// into fixed-width block buckets, over each kernel's block rectangle computed from its model
+// row (binning.hip), then
 //   k_fit_tile: one wave per 16x16 block orders the block's bucket, renders the block
 //     (image, D, squared error) and runs the backward over the same list while the
 //     pixels' y, D and dL/dy are still in its registers -- the backward of a block needs
 //     only that block's pixels, so nothing round-trips through HBM between the two;
 //   k_adam_fit: per kernel, the sum of its block partials, Adam, re-materialization, and
-//     the next step's box and render record.
+//     the next step's render record.
 // Cross-workgroup handoffs happen only at kernel boundaries: the 8 XCD L2 caches are not
 // coherent with each other, so a device-scope fence per workgroup would cost more than a
 // launch.  The step counter is read by every Adam workgroup and advanced by one: the
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kWave) void k_fit_tile(FitTileArgs a) {
 struct AdamFitArgs {
   Segs S;
   int shift;  // bucket entries: kernel id << shift | row of the partial (k_scatter_fixed)
-  const int4* __restrict__ tile_rects_in;
+  const int4* __restrict__ tile_rects;  // the step's block rectangles (from its scatter)
   const int2* __restrict__ ranges;
   const uint32_t* __restrict__ vals;
   const float* __restrict__ pair_grads;
@@ -139,18 +140,15 @@ struct AdamFitArgs {
   float* __restrict__ model;
   float* __restrict__ grads;
   float* __restrict__ records;
-  int4* __restrict__ tile_rects_out;
-  int32_t* __restrict__ counts;
 };
 
 
-// Fit-step Adam fused with the next step's binning front end.  16 lanes per kernel: lane i
-// owns raw parameter i -- its gradient (the sum of the kernel's block partials), Adam with
-// the group's learning rate, the re-materialized value -- and writes field i of the new
-// render record; lane 0 also writes the new block rectangle and count, which the next step
-// scatters.  Block 0 also reduces the per-block squared errors into the loss.  After an
-// overflow the parameters stay as they are, and the records and rectangles are rewritten
-// from them unchanged.
+// Fit-step Adam fused with the re-materialization.  16 lanes per kernel: lane i owns raw
+// parameter i -- its gradient (the sum of the kernel's block partials), Adam with the group's
+// learning rate, the re-materialized value -- and writes field i of the new render record
+// (the next step's scatter derives the block rectangle from the new model row).  Block 0
+// also reduces the per-block squared errors into the loss.  After an overflow the
+// parameters stay as they are, and the records are rewritten from them unchanged.
 constexpr int kAdamThreads = 256;
 // (held to 64 VGPRs: 8 waves per SIMD to overlap the gather's loads)
 template <int C, int ORDER>
@@ -174,7 +172,7 @@ void k_adam_fit(AdamFitArgs f) {
   int4 rc = make_int4(0, 0, -1, -1);
   float m0 = 0.0f, v0 = 0.0f, raw0 = 0.0f;
   if (live) {
-    rc = f.tile_rects_in[j];
+    rc = f.tile_rects[j];
     if (i < NP) {
       m0 = f.m[e];
       v0 = f.v[e];
@@ -258,15 +256,7 @@ void k_adam_fit(AdamFitArgs f) {
       else fld = 0.0f;
       f.records[(size_t)j * RS + i] = fld;
     }
-    if (i == 0) {
-      // (nothing in the fit step reads the native rectangles: at scale 1 and origin 0 the
-      // output blocks are the native blocks; they are not kept up to date)
-      int4 rc = make_int4(0, 0, -1, -1);
-      if (!row_nonfinite) rc = kernel_rects(mux, muy, l11, l21, l22, sg, f.S.r, f.S.box, f.S.trunc).tile;
-      else f.status[kNonfinite] = 1;
-      f.tile_rects_out[j] = rc;
-      f.counts[j] = rect_count(rc);
-    }
+    if (i == 0 && row_nonfinite) f.status[kNonfinite] = 1;
   }
   // The counter itself is written once; every workgroup read the shadow copy instead.  The
   // next step's overflow flag is cleared here: no kernel of this step reads it.
@@ -336,9 +326,7 @@ hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, f
                 st.adam_v,
                 st.model,
                 st.grads,
-                b.records,
-                reinterpret_cast<int4*>(b.tile_rects),
-                b.counts};
+                b.records};
   // at least one workgroup, so that the loss and the step counter advance even for K = 0
   const int blocks = max(1, (int)(((long long)S.K * 16 + kAdamThreads - 1) / kAdamThreads));
   if (st.C == 1 && st.order == 0) k_adam_fit<1, 0><<<blocks, kAdamThreads, 0, s>>>(f);

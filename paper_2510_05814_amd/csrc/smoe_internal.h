@@ -192,9 +192,9 @@ hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs&
                               const smoe_bins& b, hipStream_t s);
 // The fit step's bucket entries: kernel id << shift | the row of the entry's gradient
 // partial (kSlots + width <= 2^shift).
-hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, int width, int shift,
-                                const int32_t* step, const smoe_adam_config& adam,
-                                float* scalars, hipStream_t s);
+hipError_t launch_scatter_fixed(const Segs& S, const smoe_bins& b, const float* model, int np,
+                                int width, int shift, const int32_t* step,
+                                const smoe_adam_config& adam, float* scalars, hipStream_t s);
 hipError_t launch_fit_tile(const smoe_fit_state& st, const Segs& S, int width, int shift,
                            const float* target, hipStream_t s);
 hipError_t launch_adam_fit(const smoe_fit_state& st, const Segs& S, int shift, float* loss_out,
