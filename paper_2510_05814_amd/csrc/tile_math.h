@@ -150,18 +150,33 @@ __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, f
     const float z2 = w * r[4];
     q[i] = zz1 + z2 * z2;
   }
+  // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2), with the render's bound applied
+  // in its compare-free form -- which is the identity, bit for bit, unless some pixel of the
+  // block lies beyond the bound (q > r^2 with the ellipse in the render; an exponent below
+  // -125 otherwise), so the wave applies it only then.
+  float a[kRows];
+  if (TRUNC == SMOE_TRUNC_RENDER) {
+    const float qmax = __builtin_fmaxf(__builtin_fmaxf(q[0], q[1]), __builtin_fmaxf(q[2], q[3]));
+    if (__any(!(qmax <= r2))) {
+#pragma unroll
+      for (int i = 0; i < kRows; ++i)
+        q[i] = __builtin_fmaxf(q[i], __builtin_fmaf(q[i], cut_scale, cut_offset));
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) a[i] = __builtin_fmaf(q[i], -0.5f * kLog2e, r[5]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) a[i] = __builtin_fmaf(q[i], -0.5f * kLog2e, r[5]);
+    const float amin = __builtin_fminf(__builtin_fminf(a[0], a[1]), __builtin_fminf(a[2], a[3]));
+    if (__any(!(amin >= -125.0f))) {
+#pragma unroll
+      for (int i = 0; i < kRows; ++i)
+        a[i] = __builtin_fminf(a[i], __builtin_fmaf(a[i], cut_scale, cut_offset));
+    }
+  }
 #pragma unroll
   for (int i = 0; i < kRows; ++i) {
-    // pi K = exp(rho - q/2) = exp2(rho log2 e - q log2 e / 2)
-    float a;
-    if (TRUNC == SMOE_TRUNC_RENDER) {
-      const float qc = __builtin_fmaxf(q[i], __builtin_fmaf(q[i], cut_scale, cut_offset));
-      a = __builtin_fmaf(qc, -0.5f * kLog2e, r[5]);
-    } else {
-      const float a0 = __builtin_fmaf(q[i], -0.5f * kLog2e, r[5]);
-      a = __builtin_fminf(a0, __builtin_fmaf(a0, cut_scale, cut_offset));
-    }
-    const float e = __builtin_amdgcn_exp2f(a);
+    const float e = __builtin_amdgcn_exp2f(a[i]);
     D[i] += e;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
