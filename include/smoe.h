@@ -221,10 +221,12 @@ typedef struct smoe_bins {
   uint32_t* vals;          /* [capacity] kernel id of each pair, ascending within a block */
   uint32_t* vals_alt;      /* [capacity] scratch for very long block lists */
   float* pair_grads;       /* [16 K + capacity][NP rounded up to a multiple of 4] per-(block,
-                              kernel) gradient partials: the standalone backward's at the
-                              pair's list position; the fit step's at row 16 j + q for block q
-                              (row-major in kernel j's rectangle) when q < 16, else at row
-                              16 K + the pair's bucket slot (NULL in a render-only workspace) */
+                              kernel) gradient partials (the centre's two without their
+                              expert-slope terms, which the gradient gather adds once per
+                              kernel): the standalone backward's at the pair's list position;
+                              the fit step's at row 16 j + q for block q (row-major in kernel
+                              j's rectangle) when q < 16, else at row 16 K + the pair's bucket
+                              slot (NULL in a render-only workspace) */
   float* tile_loss;        /* [max_tiles] per-block squared error */
   int32_t* status;         /* [8]: pairs needed P, overflow flag, longest list, non-finite
                               flag of the last binning, then internal words (the fit step's
