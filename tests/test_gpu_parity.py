@@ -470,3 +470,33 @@ def test_fused_fit_step_equals_standalone_calls(smoe):
         assert torch.equal(st.image, img), k
         assert torch.equal(st.denom, D), k
         assert torch.equal(st.grads, g), k
+
+FUSED_SHAPES = [(1, 0, "smoe", 301), (3, 0, "smoe", 302), (1, 1, "smoe", 303),
+                (3, 1, "rbf", 304), (1, 0, "rbf", 305)]
+
+
+@pytest.mark.parametrize("C_,order,mode,seed", FUSED_SHAPES)
+def test_fused_fit_step_equals_standalone_calls_shapes(smoe, C_, order, mode, seed):
+    """The same bitwise equality for the other expert shapes and the RBF mode: the gather's
+    per-kernel finishing (the centre's expert-slope terms) is shared by the fit step's Adam
+    and the standalone gather, which take the slopes from the raw row and the render record."""
+    import torch
+    say(f"fused vs standalone C={C_} order={order} {mode}")
+    W, H, K = 96, 80, 150
+    m_np = wl.random_model(K, C_, order, W, H, seed, sig_lo=1.5, sig_hi=8.0)
+    raw = m_np.astype(np.float64).copy()
+    raw[:, 2], raw[:, 4] = np.log(m_np[:, 2]), np.log(m_np[:, 4])
+    t = dev(np.random.default_rng(seed).uniform(0, 1, (H, W, C_)).astype(np.float32))
+    st = smoe.FitState(t, dev(raw), order, smoe.AdamConfig(total_steps=100), max_steps=8,
+                       mode=mode)
+    grid = smoe.make_grid(W, H, mode=mode)
+    for k in range(3):
+        model = st.model.clone()
+        img, D, _, b = smoe.render(model, C_, order, grid)
+        g = smoe.render_backward(model, C_, order, grid, b, img, D, target=t)
+        st.step()
+        torch.cuda.synchronize()
+        assert torch.equal(st.image, img), k
+        assert torch.equal(st.denom, D), k
+        assert torch.equal(st.grads, g), k
+
