@@ -1,9 +1,9 @@
 // Fit-step kernels on gfx950 (Sec. VI-B: gradient descent with Adam on all kernel
 // parameters, the centre learning rate decaying exponentially).
 //
-// A fit step runs three kernels after the first: the scatter of the (block, kernel) pairs
-// into fixed-width block buckets, over each kernel's block rectangle computed from its model
-// row (binning.hip), then
+// A fit step runs three kernels (a fit's first step computes the render records first): the
+// scatter of the (block, kernel) pairs into fixed-width block buckets, over each kernel's
+// block rectangle computed from its model row (binning.hip), then
 //   k_fit_tile: one wave per 16x16 block orders the block's bucket, renders the block
 //     (image, D, squared error) and runs the backward over the same list while the
 //     pixels' y, D and dL/dy are still in its registers -- the backward of a block needs

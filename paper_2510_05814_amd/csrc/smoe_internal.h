@@ -176,18 +176,18 @@ hipError_t launch_gather(int C, int order, const Segs& S, const smoe_bins& b, fl
                          hipStream_t s);
 hipError_t launch_materialize(int K, int C, int order, const float* raw, float* model,
                               hipStream_t s);
-// Fit-step pieces: block counters, boxes and records of the current model (fill,
-// preprocess); the scan of the counters into ranges; the scatter into buckets; the fused
-// per-block sort + render + backward; Adam fused with the next step's boxes, records and
-// counters.
+// Binning pieces: block counters, boxes and records of the current model (fill,
+// preprocess); the scan of the counters into ranges; the scatter into the lists.
 hipError_t launch_count(int C, int order, const float* params, const Segs& S,
                         const smoe_bins& b, hipStream_t s);
 hipError_t launch_scan(const Segs& S, const smoe_bins& b, hipStream_t s);
 hipError_t launch_scatter(const Segs& S, const smoe_bins& b, hipStream_t s);
 // Copies the first four status words (P needed, overflow, longest list, spare) to out4.
 hipError_t launch_copy_status(const smoe_bins& b, int32_t* out4, hipStream_t s);
-// Fit step: boxes and records of the current model with zeroed bucket cursors (the first
-// step), and the scatter into fixed-width buckets (every step).
+// Fit step: boxes and records of the current model with zeroed bucket cursors and status
+// words (the first step); then every step the scatter into fixed-width buckets (over each
+// kernel's box, computed from its model row), the fused per-block sort + render + backward,
+// and Adam fused with the re-materialization and the next step's render records.
 hipError_t launch_prepare_fit(int C, int order, const float* params, const Segs& S,
                               const smoe_bins& b, hipStream_t s);
 // The fit step's bucket entries: kernel id << shift | the row of the entry's gradient

@@ -452,9 +452,9 @@ struct PixelSeed {
 //   dL/ds1 = -bz1 z1,  dL/dl21 = -bz2 z1/l22,  dL/ds2 = -bz2 z2
 // Fields 0 and 1 of the partial row leave out the sum_c g_c w wx_c and sum_c g_c w wy_c
 // terms: the gather applies them per kernel from dL/da_c (finish_gradient).
-// The terms that factor through a lane's column (dx, z1) or through the kernel (wx, wy,
-// 1/l11, 1/l22) are applied once per lane to the lane's sums instead of once per pixel; so
-// is the l21/l22 term of bz1 (sum bz1 = -(z1 sum H + (l21/l22) sum bz2) over a lane's
+// The terms that factor through a lane's column (dx, z1) or through the kernel (1/l11,
+// 1/l22) are applied once per lane to the lane's sums instead of once per pixel; so is the
+// l21/l22 term of bz1 (sum bz1 = -(z1 sum H + (l21/l22) sum bz2) over a lane's
 // pixels), and the seeds g and sum_c g_c y_c are taken already divided by D, so that pi K
 // itself stands in for w.
 // packed (the fit step): list entries hold kernel id << shift | low, and the partial row of
