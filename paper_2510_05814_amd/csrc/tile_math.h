@@ -186,7 +186,11 @@ __device__ __forceinline__ bool forward_entry(const PixelCoords& px, float r2, f
     }
   }
   static_assert(kRows == 4, "the ellipse test takes the minimum of four rows");
-  return __builtin_fminf(__builtin_fminf(q[0], q[1]), __builtin_fminf(q[2], q[3])) <= r2;
+  // q >= +0 (a sum of squares, or the bound's larger stand-in), so the order of the floats is
+  // the order of their bit patterns as integers: no NaN handling in the minimum
+  const int qmin = min(min(__float_as_int(q[0]), __float_as_int(q[1])),
+                       min(__float_as_int(q[2]), __float_as_int(q[3])));
+  return __int_as_float(qmin) <= r2;
 }
 
 // A copy of x that the compiler must keep in a vector register: loop-invariant operands of
