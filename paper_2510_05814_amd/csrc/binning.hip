@@ -16,6 +16,18 @@
 namespace smoe {
 namespace {
 
+// The kernel that group g of a binning kernel's lanes (kPreLanes, kScatterLanes) takes: every
+// 8th of 128 consecutive kernel ids (a bijection on each complete run of 128; the ids past
+// the last one keep their order).  Neighbouring ids are neighbours in the image (the grid
+// initialisation's order, which the kernels keep as they move), so a wave's counter and
+// cursor atomics stay within a few blocks; spreading them over eight times as many ids keeps
+// that locality while fewer atomics of one instruction meet on the same counter, where they
+// serialise.  Any order gives the same counts and, up to the order inside a bucket, which
+// the sorts that follow remove, the same buckets.
+__device__ __forceinline__ int binning_kernel(int g, int K) {
+  return (g | 127) < K ? (g & ~127) + ((g & 15) << 3) + ((g >> 4) & 7) : g;
+}
+
 // Four lanes per kernel row (so that a wave covers 16 kernels and a launch has four times the
 // waves to hide its loads): every lane of the quad reads the row and computes the
 // output-block and native-block rectangles; lane 0 writes them and the count, lane q the
@@ -32,8 +44,9 @@ __global__ __launch_bounds__(256) void k_preprocess(int C, int order,
                                                     int32_t* __restrict__ tile_counts,
                                                     int32_t* __restrict__ status) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = gid / kPreLanes, lq = gid % kPreLanes;
-  if (j >= S.K) return;
+  const int g = gid / kPreLanes, lq = gid % kPreLanes;
+  if (g >= S.K) return;
+  const int j = binning_kernel(g, S.K);
   const SegGrid sg = seg_of_kernel(S, j);
   const int ne = expert_floats(C, order);
   const float* p = params + (size_t)(sg.param_offset + (j - sg.kernel_offset)) * (6 + ne);
@@ -76,18 +89,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int T, int32_t* __restric
 // covered blocks q, q + 4, ... (row-major inside its block rectangle), so the cursor
 // atomics of one kernel run in parallel rather than one after another.
 constexpr int kScatterLanes = 4;
-
-// The kernel whose pairs group g of kScatterLanes lanes appends: every 8th of 128
-// consecutive kernel ids (a bijection on each complete run of 128; the ids past the last
-// one keep their order).  Neighbouring ids are neighbours in the image (the grid
-// initialisation's order, which the kernels keep as they move), so a wave's appends stay
-// within a few blocks' cursors and bucket lines; spreading them over eight times as many
-// ids keeps that locality while fewer appends of one atomic instruction meet on the same
-// cursor, where they serialise.  Any order gives the same buckets up to the order inside a
-// bucket, which the sorts that follow remove.
-__device__ __forceinline__ int scatter_kernel(int g, int K) {
-  return (g | 127) < K ? (g & ~127) + ((g & 15) << 3) + ((g >> 4) & 7) : g;
-}
 __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict__ tile_rects,
                                                  const int2* __restrict__ ranges,
                                                  int32_t* __restrict__ cursors,
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(256) void k_scatter(Segs S, const int4* __restrict_
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int g = gid / kScatterLanes, q0 = gid % kScatterLanes;
   if (g >= S.K || status[1] != 0) return;
-  const int j = scatter_kernel(g, S.K);
+  const int j = binning_kernel(g, S.K);
   const int4 rc = tile_rects[j];
   const int n = rect_count(rc);
   if (n == 0) return;
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_scatter_fixed(Segs S, const float* __re
   }
   const int g = gid / kScatterLanes, q0 = gid % kScatterLanes;
   if (g >= S.K) return;  // (whole groups of kScatterLanes lanes: the shuffles stay inside one)
-  const int j = scatter_kernel(g, S.K);
+  const int j = binning_kernel(g, S.K);
   const SegGrid sg = seg_of_kernel(S, j);
   // every lane of the kernel's group reads the geometry; lane q0 also checks parameters
   // 5 + q0, 5 + q0 + kScatterLanes, ... for finiteness
