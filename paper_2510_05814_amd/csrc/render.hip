@@ -30,6 +30,7 @@ struct RenderArgs {
   float* __restrict__ denom;
   const float* __restrict__ target;
   float* __restrict__ tile_loss;
+  const int32_t* __restrict__ status;  // the binning's status words (word 2: longest list)
 };
 
 // Blocks whose list is longer than this go to k_render_wide.
@@ -88,9 +89,10 @@ __global__ __launch_bounds__(kWave) void k_render(RenderArgs a) {
 // Four waves per block for lists longer than kSplitMin.  Each wave stages its own records
 // in its own LDS region; within a wave, LDS stores and loads execute in program order, so
 // the staging needs no workgroup barrier (the waves' chunk counts differ).  A workgroup
-// walks the blocks with a grid stride (at most kWideGroups workgroups, so that a raster
-// without long lists costs only a scan of its ranges); every decision in the walk is the
-// same for the four waves, so each barrier is reached by all of them.
+// walks the blocks with a grid stride (at most kWideGroups workgroups); a raster whose
+// longest list (status word 2 of its binning) is short costs only the launch.  Every
+// decision in the walk is the same for the four waves, so each barrier is reached by all
+// of them.
 constexpr int kWideGroups = 1024;
 
 template <int C, int ORDER, bool RBF, int TRUNC>
@@ -151,6 +153,8 @@ template <int C, int ORDER, bool RBF, int TRUNC>
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_render_wide(RenderArgs a) {
   __shared__ float4 srec[kSplitWaves][kChunk * record_stride(C, ORDER) / 4];
   __shared__ float part[kSplitWaves - 1][kRows * (1 + C)][kWave];
+  // the binning recorded the longest list: without a long one there is nothing to walk
+  if (a.status[2] <= kSplitMin) return;
   for (int tile = blockIdx.x; tile < a.S.T; tile += gridDim.x) {
     const int2 rg = a.ranges[tile];
     if (rg.y - rg.x <= kSplitMin) continue;  // k_render renders this block
@@ -239,7 +243,8 @@ hipError_t launch_render(int C, int order, const Segs& S, const smoe_bins& b, fl
                image,
                denom,
                target,
-               target ? b.tile_loss : nullptr};
+               target ? b.tile_loss : nullptr,
+               b.status};
   with_shape(C, order, S, [&](auto sh) {
     using T = decltype(sh);
     k_render<T::C, T::ORDER, T::RBF, T::TRUNC><<<S.T, kWave, 0, s>>>(a);
