@@ -628,14 +628,36 @@ def run_serving(args):
         plain.serve(wq, realtime=False)
         srv.serve(wq, realtime=True)
         plain.serve(wq, realtime=True)
-    _, out["batched"] = srv.serve(reqs)
-    _, out["plain"] = plain.serve(reqs)
-    # The same rate over independent request streams, the servers alternating, latencies
-    # pooled: the 99th percentile of one 1000-request run rests on its 10 slowest requests.
+    # The two servers on the same request stream, in the order batched, plain, plain,
+    # batched, so that a drift of the GPU's clocks or of the host over the section lands on
+    # both alike; each server's two runs are pooled for the latency percentiles (the
+    # throughput fields are those of its first run).
+    runs = {"batched": [], "plain": []}
+    for name, server in (("batched", srv), ("plain", plain), ("plain", plain), ("batched", srv)):
+        runs[name].append(server.serve(reqs))
+    for name, rs in runs.items():
+        summ = dict(rs[0][1])
+        res = [r for run, _ in rs for r in run]
+        lat = np.array([r.latency for r in res]) * 1e3
+        wait = np.array([r.started - r.request.arrival for r in res]) * 1e3
+        gpu = np.array([r.done - r.started for r in res]) * 1e3
+        summ.update({"runs": len(rs), "order": "batched, plain, plain, batched",
+                     "latencies_pooled": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                     "max_ms": float(lat.max()),
+                     "wait_p50_ms": float(np.percentile(wait, 50)),
+                     "wait_p99_ms": float(np.percentile(wait, 99)),
+                     "gpu_p50_ms": float(np.percentile(gpu, 50)),
+                     "gpu_p99_ms": float(np.percentile(gpu, 99))})
+        out[name] = summ
+    # The same rate over independent request streams, which server goes first alternating
+    # from stream to stream, latencies pooled: the 99th percentile of one 1000-request run
+    # rests on its 10 slowest requests.
     pooled = {"batched": [], "plain": []}
     for rep in range(args.serve_repeats):
         rq = wl.serving_requests(sides, args.serve_requests, rate=200.0, seed=300 + rep)
-        for name, server in (("batched", srv), ("plain", plain)):
+        pair = (("batched", srv), ("plain", plain))
+        for name, server in (pair if rep % 2 == 0 else pair[::-1]):
             res, _ = server.serve(rq)
             pooled[name] += [r.latency * 1e3 for r in res]
     out["pooled_200hz"] = {"streams": args.serve_repeats, "requests_each": args.serve_requests}
@@ -1189,7 +1211,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-saturation", type=int, default=300)
-    ap.add_argument("--serve-repeats", type=int, default=3,
+    ap.add_argument("--serve-repeats", type=int, default=2,
                     help="further independent 200 req/s streams whose latencies are pooled")
     ap.add_argument("--serve-fit-steps", type=int, default=50)
     ap.add_argument("--serve-sweep-requests", type=int, default=600)

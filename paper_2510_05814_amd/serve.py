@@ -391,6 +391,10 @@ class Server:
         self._status = torch.zeros((256, 4), dtype=torch.int32, pin_memory=True)
         self.streams = [sl.stream for sl in self.slots]
         self._models = [model_struct(bank.rows(i), bank.C, bank.order) for i in range(len(bank))]
+        # per request shape (model, size, scale, window origin, sharpening): its kernels,
+        # blocks, pair bound, pixels and bytes -- a request's shape recurs, its bound need
+        # not be recomputed on the path to its launch
+        self._shape_info = {}
         if reserve_for is not None:
             w, h, scales = reserve_for
             t = _tiles(w, h, TILE - 1, TILE - 1)  # the most blocks such a window touches
@@ -401,15 +405,23 @@ class Server:
                     sl.layout(k, bank.C, bank.order, tt, p)
 
     def _info(self, r):
-        """(kernels, blocks, pair bound, pixels, bytes alone) of one request, computed once."""
+        """(kernels, blocks, pair bound, pixels, bytes alone) of one request, computed once per
+        request shape."""
         inf = getattr(r, "_smoe_info", None)
         if inf is None:
-            k, t = self.bank.K[r.model], _tiles(r.width, r.height, r.origin_x, r.origin_y)
-            p = self.bank.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen)
-            n = r.width * r.height
-            nbytes = (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
-                      + n * self.nbytes_px + 64)
-            inf = r._smoe_info = (k, t, p, n, nbytes)
+            key = (r.model, r.scale, r.width, r.height, r.origin_x, r.origin_y, r.sharpen)
+            inf = self._shape_info.get(key)
+            if inf is None:
+                k, t = self.bank.K[r.model], _tiles(r.width, r.height, r.origin_x, r.origin_y)
+                p = self.bank.pair_bound(r.model, r.scale, r.width, r.height, r.sharpen)
+                n = r.width * r.height
+                nbytes = (C.smoe_render_workspace_bytes(k, self.bank.C, self.bank.order, t, p)
+                          + n * self.nbytes_px + 64)
+                inf = (k, t, p, n, nbytes)
+                if len(self._shape_info) >= 4096:
+                    self._shape_info.clear()
+                self._shape_info[key] = inf
+            r._smoe_info = inf
         return inf
 
     def footprint(self, reqs) -> tuple[int, int, int, int]:
@@ -436,9 +448,11 @@ class Server:
                 r = batch.reqs[0]
                 grid = make_grid(r.width, r.height, r.scale, r.origin_x, r.origin_y, b.radius,
                                  r.sharpen, b.box, mode=b.mode, trunc=b.trunc)
-                images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
                 m = self._models[r.model]
+                # the binning goes first, so that the device starts while the host allocates
+                # the output
                 C.smoe_bin(m, grid, bins, st.cuda_stream)
+                images = torch.empty((r.height * r.width, b.C), dtype=torch.float32, device=dev)
                 C.smoe_render(m, grid, bins, images.data_ptr(), None, None, None, st.cuda_stream)
                 slices = [(0, r.height * r.width, r.height, r.width)]
             else:
